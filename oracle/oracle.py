@@ -1,0 +1,185 @@
+"""ctypes wrapper of the C oracle (test infrastructure only; see package doc)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "build", "lib", "Problem", "element_stiffness", "stiffness_table",
+    "CONVERGED", "NOT_CONVERGED", "BREAKDOWN",
+]
+
+CONVERGED, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "elas3d_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        i, l, d = ctypes.c_int, ctypes.c_long, ctypes.c_double
+        L.orc_element_stiffness.argtypes = [_D, _D]
+        L.orc_stiffness_table.argtypes = [i, _D, _D]
+        L.orc_apply.argtypes = [i, i, i, _I32, _D, _D, _D]
+        L.orc_apply_at.argtypes = [i, i, i, _I32, _D, _D, _I64, l, _D]
+        L.orc_load.argtypes = [i, i, i, _I32, _D, _D, _D, _D]
+        L.orc_load_at.argtypes = [i, i, i, _I32, _D, _D, _I64, l, _D]
+        L.orc_precond.argtypes = [i, i, i, _I32, _D, i, _D, i, _D]
+        L.orc_precond_at.argtypes = [i, i, i, _I32, _D, i, _D, _I64, l, _D]
+        L.orc_pcg.argtypes = [i, i, i, _I32, _D, _D, _D, d, d, i, i, _D, _D, _D]
+        L.orc_pcg.restype = ctypes.c_int
+        L.orc_stress.argtypes = [i, i, i, _I32, i, _D, _D, _D, _D, _D]
+        L.orc_energy.argtypes = [i, i, i, _I32, _D, _D, _D]
+        L.orc_energy.restype = d
+        _lib = L
+    return _lib
+
+
+def _p(a, t=_D):
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def element_stiffness(C: np.ndarray) -> np.ndarray:
+    """24x24 K_e of the unit voxel for a 6x6 Voigt stiffness (dof 3*a + c)."""
+    C = _f64(C).reshape(36)
+    ke = np.empty(576)
+    lib().orc_element_stiffness(_p(C), _p(ke))
+    return ke.reshape(24, 24)
+
+
+def stiffness_table(C: np.ndarray) -> np.ndarray:
+    C = _f64(C).reshape(-1, 36)
+    ke = np.empty((C.shape[0], 576))
+    lib().orc_stiffness_table(C.shape[0], _p(C), _p(ke))
+    return ke
+
+
+class Problem:
+    """One microstructure: grid, phase map and per-phase stiffness."""
+
+    def __init__(self, shape, phase, C):
+        self.nx, self.ny, self.nz = (int(s) for s in shape)
+        self.n = self.nx * self.ny * self.nz
+        self.phase = np.ascontiguousarray(phase, dtype=np.int32).reshape(self.n)
+        self.C = _f64(C).reshape(-1, 6, 6)
+        self.nphase = self.C.shape[0]
+        self.ke = stiffness_table(self.C)
+
+    @classmethod
+    def from_micro(cls, ms):
+        return cls(ms.shape, ms.phase, ms.C)
+
+    def _g(self):
+        return self.nx, self.ny, self.nz
+
+    def apply(self, x: np.ndarray) -> np.ndarray:
+        x = _f64(x).reshape(3, self.n)
+        y = np.empty_like(x)
+        lib().orc_apply(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(x), _p(y))
+        return y
+
+    def apply_at(self, x: np.ndarray, nodes: np.ndarray) -> np.ndarray:
+        x = _f64(x).reshape(3, self.n)
+        sel = np.ascontiguousarray(nodes, dtype=np.int64)
+        y = np.empty((3, sel.size))
+        lib().orc_apply_at(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(x),
+                           _p(sel, _I64), sel.size, _p(y))
+        return y
+
+    def load(self, strain) -> tuple:
+        """(b, ||b||_ref^2) for one macroscopic strain (tensor components)."""
+        e = _f64(strain).reshape(6)
+        b = np.empty((3, self.n))
+        r2 = np.zeros(1)
+        lib().orc_load(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e), _p(b), _p(r2))
+        return b, float(r2[0])
+
+    def load_at(self, strain, nodes) -> np.ndarray:
+        e = _f64(strain).reshape(6)
+        sel = np.ascontiguousarray(nodes, dtype=np.int64)
+        b = np.empty((3, sel.size))
+        lib().orc_load_at(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e),
+                          _p(sel, _I64), sel.size, _p(b))
+        return b
+
+    def precond(self, identity: bool = False) -> np.ndarray:
+        """N x 3 x 3 inverse diagonal blocks (0 on void-only nodes)."""
+        minv = np.empty((self.n, 9))
+        lib().orc_precond(*self._g(), _p(self.phase, _I32), _p(self.ke), self.nphase,
+                          _p(self.C), int(identity), _p(minv))
+        return minv.reshape(self.n, 3, 3)
+
+    def precond_at(self, nodes) -> np.ndarray:
+        sel = np.ascontiguousarray(nodes, dtype=np.int64)
+        minv = np.empty((sel.size, 9))
+        lib().orc_precond_at(*self._g(), _p(self.phase, _I32), _p(self.ke), self.nphase,
+                             _p(self.C), _p(sel, _I64), sel.size, _p(minv))
+        return minv.reshape(sel.size, 3, 3)
+
+    def solve(self, strain, tol: float = 1e-10, maxit: int = 100000, mode: int = 0,
+              preconditioned: bool = True, b: Optional[np.ndarray] = None,
+              minv: Optional[np.ndarray] = None, trace: bool = False) -> dict:
+        """PCG (Algorithm 2) or plain CG from w = 0; returns w and statistics."""
+        if b is None:
+            b, r2 = self.load(strain)
+        else:
+            r2 = float(np.sum(_f64(b) ** 2))
+        if minv is None:
+            minv = self.precond(identity=not preconditioned)
+        b = _f64(b).reshape(3, self.n)
+        minv = _f64(minv).reshape(self.n, 9)
+        w = np.empty((3, self.n))
+        info = np.zeros(5)
+        tr = np.zeros(max(1, maxit)) if trace else None
+        st = lib().orc_pcg(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(minv), _p(b),
+                           r2, float(tol), int(maxit), int(mode), _p(w), _p(info),
+                           _p(tr) if trace else None)
+        out = {"w": w, "status": int(st), "iters": int(info[0]), "relres": info[1],
+               "relres_precond": info[2], "relres_true": info[3], "restarts": int(info[4]),
+               "b": b}
+        if trace:
+            out["trace"] = tr[: int(info[0])]
+        return out
+
+    def stress(self, strain, w) -> tuple:
+        """(sigma 6 x N, mean stress 6) at voxel centroids."""
+        e = _f64(strain).reshape(6)
+        w = _f64(w).reshape(3, self.n)
+        sig = np.empty((6, self.n))
+        avg = np.empty(6)
+        lib().orc_stress(*self._g(), _p(self.phase, _I32), self.nphase, _p(self.C), _p(e),
+                         _p(w), _p(sig), _p(avg))
+        return sig, avg
+
+    def energy(self, strain, w) -> float:
+        e = _f64(strain).reshape(6)
+        w = _f64(w).reshape(3, self.n)
+        return float(lib().orc_energy(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e), _p(w)))

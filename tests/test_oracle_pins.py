@@ -1,0 +1,393 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names the passage of ELAS3D-Xtal (arXiv 2602.07354) or the piece of
+mathematics it checks.  A plausible slip in the oracle (a dropped term, a
+wrong sign or index, a transposed operand, a wrong quadrature weight) breaks
+at least one of them:
+
+* K_e: symmetry, its six rigid-body null vectors, exact nodal forces of an
+  affine field, and the strain energy of arbitrary nodal values computed
+  independently from the trilinear interpolant (finite differences + 3-point
+  Gauss-Legendre); the isotropic diagonal (lambda + 4 mu)/9.
+* M^-1: closed form of the interior block of a homogeneous grid.
+* b, A: homogeneous grid gives b = 0 and exact uniform stress; A is symmetric
+  and annihilates translations; the sum of b vanishes.
+* PCG: brute-force dense assembled solve on tiny grids (numpy lstsq),
+  energy decrease, PCG and CG reach the same field.
+* stress + energy: the discrete Hill-Mandel identity
+  2 Pi(w) = N E_hat . <sigma>(w) + w . (A w + b) for any w.
+* physics: Eshelby inclusion mean strain against the Mori-Tanaka closed form.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2602_07354_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_spd_C(rng):
+    A = rng.standard_normal((6, 6))
+    return A @ A.T + 6.0 * np.eye(6)
+
+
+def _sgn(a):
+    return np.array([2 * (a & 1) - 1, 2 * ((a >> 1) & 1) - 1, 2 * ((a >> 2) & 1) - 1], float)
+
+
+def _tensor(e6):
+    e = np.asarray(e6, float)
+    return np.array([[e[0], e[5], e[4]], [e[5], e[1], e[3]], [e[4], e[3], e[2]]])
+
+
+def _voigt_stress_to_tensor(s):
+    return np.array([[s[0], s[5], s[4]], [s[5], s[1], s[3]], [s[4], s[3], s[2]]])
+
+
+def _ehat(e6):
+    e = np.asarray(e6, float)
+    return np.array([e[0], e[1], e[2], 2 * e[3], 2 * e[4], 2 * e[5]])
+
+
+# ------------------------------------------------------------------ element
+
+def test_ke_symmetric_with_rigid_null_space(orc):
+    rng = np.random.default_rng(1)
+    C = _rand_spd_C(rng)
+    K = orc.element_stiffness(C)
+    assert np.abs(K - K.T).max() <= 1e-13 * np.abs(K).max()
+    # rigid motions: 3 translations + 3 infinitesimal rotations u = w x X
+    X = np.array([[a & 1, (a >> 1) & 1, (a >> 2) & 1] for a in range(8)], float)
+    modes = []
+    for d in range(3):
+        u = np.zeros((8, 3)); u[:, d] = 1.0; modes.append(u.ravel())
+    for d in range(3):
+        w = np.zeros(3); w[d] = 1.0
+        modes.append(np.cross(w, X).ravel())
+    for u in modes:
+        assert np.abs(K @ u).max() <= 1e-12 * np.abs(K).max()
+    ev = np.linalg.eigvalsh(K)
+    assert np.sum(np.abs(ev) <= 1e-10 * ev.max()) == 6
+    assert np.all(ev[6:] > 1e-6 * ev.max())
+
+
+def test_ke_affine_field_gives_exact_nodal_forces(orc):
+    """For u = E.X the nodal force is int grad(N_a) . sigma = sigma s_a / 4."""
+    rng = np.random.default_rng(2)
+    C = _rand_spd_C(rng)
+    K = orc.element_stiffness(C)
+    for _ in range(4):
+        e6 = rng.standard_normal(6)
+        E = _tensor(e6)
+        u = np.array([E @ np.array([a & 1, (a >> 1) & 1, (a >> 2) & 1], float) for a in range(8)])
+        sig = _voigt_stress_to_tensor(C @ _ehat(e6))
+        f = np.array([sig @ _sgn(a) / 4.0 for a in range(8)])
+        assert np.allclose(K @ u.ravel(), f.ravel(), rtol=0, atol=1e-12 * np.abs(f).max())
+        # and the energy of a uniform strain is E_hat . C E_hat over the unit voxel
+        assert np.isclose(u.ravel() @ K @ u.ravel(), _ehat(e6) @ C @ _ehat(e6), rtol=1e-13)
+
+
+def _interp_energy(C, u):
+    """int_voxel eps:C:eps of the trilinear interpolant of nodal values u (8x3).
+
+    Strains come from central differences of the interpolant (exact, because
+    it is linear in each coordinate separately) and the integral from 3-point
+    Gauss-Legendre per axis (exact for the at most quadratic integrand).
+    """
+    def interp(p):
+        val = np.zeros(3)
+        for a in range(8):
+            wgt = 1.0
+            for d, bit in enumerate((a & 1, (a >> 1) & 1, (a >> 2) & 1)):
+                wgt *= p[d] if bit else 1.0 - p[d]
+            val += wgt * u[a]
+        return val
+
+    xg = 0.5 + 0.5 * np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)])
+    wg = 0.5 * np.array([5 / 9, 8 / 9, 5 / 9])
+    h = 1e-3
+    total = 0.0
+    for i in range(3):
+        for j in range(3):
+            for k in range(3):
+                p = np.array([xg[i], xg[j], xg[k]])
+                G = np.zeros((3, 3))  # G[c, d] = d u_c / d x_d
+                for d in range(3):
+                    dp = np.zeros(3); dp[d] = h
+                    G[:, d] = (interp(p + dp) - interp(p - dp)) / (2 * h)
+                eps = np.array([G[0, 0], G[1, 1], G[2, 2], G[1, 2] + G[2, 1],
+                                G[0, 2] + G[2, 0], G[0, 1] + G[1, 0]])
+                total += wg[i] * wg[j] * wg[k] * eps @ C @ eps
+    return total
+
+
+def test_ke_energy_matches_independent_integration(orc):
+    rng = np.random.default_rng(3)
+    C = _rand_spd_C(rng)
+    K = orc.element_stiffness(C)
+    for _ in range(5):
+        u = rng.standard_normal((8, 3))
+        assert np.isclose(u.ravel() @ K @ u.ravel(), _interp_energy(C, u), rtol=1e-10)
+    # polarisation: the symmetric bilinear form is fixed by the quadratic one
+    u, v = rng.standard_normal((2, 8, 3))
+    pol = 0.25 * (_interp_energy(C, u + v) - _interp_energy(C, u - v))
+    assert np.isclose(u.ravel() @ K @ v.ravel(), pol, rtol=1e-9, atol=1e-9 * abs(pol))
+
+
+def test_ke_isotropic_diagonal_closed_form(orc):
+    E, nu = 200.0, 0.3
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    K = orc.element_stiffness(synth.isotropic_stiffness(E, nu))
+    assert np.allclose(np.diag(K), (lam + 4 * mu) / 9.0, rtol=1e-14)
+
+
+# ------------------------------------------------------------ preconditioner
+
+def test_precond_homogeneous_isotropic_closed_form(orc):
+    """Interior block of a homogeneous isotropic grid is 8(lambda+4mu)/9 I
+    (376.0684 GPa for E = 200, nu = 0.3): Eq. (block_precond)."""
+    E, nu = 200.0, 0.3
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    d = 8 * (lam + 4 * mu) / 9
+    assert abs(d - 376.0684) < 1e-4
+    P = orc.Problem((4, 3, 5), np.zeros(60, np.int32), synth.isotropic_stiffness(E, nu)[None])
+    M = P.precond()
+    assert np.allclose(M, np.eye(3)[None] / d, rtol=1e-13, atol=1e-18)
+
+
+def test_precond_homogeneous_anisotropic_closed_form(orc):
+    """For any C the 8 corner blocks sum to (8/9) sum_k C_ikjk: the
+    off-diagonal corner terms cancel between opposite corners."""
+    rng = np.random.default_rng(4)
+    C = _rand_spd_C(rng)
+    voigt = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (1, 2): 3, (2, 1): 3, (0, 2): 4, (2, 0): 4,
+             (0, 1): 5, (1, 0): 5}
+    A = np.array([[8.0 / 9.0 * sum(C[voigt[(i, k)], voigt[(j, k)]] for k in range(3))
+                   for j in range(3)] for i in range(3)])
+    P = orc.Problem((3, 4, 2), np.zeros(24, np.int32), C[None])
+    M = P.precond()
+    assert np.allclose(M @ A, np.eye(3)[None], atol=1e-12)
+
+
+def test_precond_masks_void_only_nodes(orc):
+    C = np.stack([synth.isotropic_stiffness(200, .3), np.zeros((6, 6))])
+    phase = np.ones(4 * 4 * 4, np.int32)
+    phase[0] = 0  # one solid voxel: its 8 corner nodes are active
+    P = orc.Problem((4, 4, 4), phase, C)
+    M = P.precond()
+    active = np.zeros(64, bool)
+    for a in range(8):
+        active[(a & 1) + 4 * ((a >> 1) & 1) + 16 * ((a >> 2) & 1)] = True
+    assert np.all(M[~active] == 0.0)
+    assert np.all(np.abs(np.linalg.det(M[active])) > 0)
+
+
+# --------------------------------------------------------------- load + A
+
+def test_homogeneous_grid_exact_uniform_strain(orc):
+    rng = np.random.default_rng(5)
+    C = _rand_spd_C(rng)
+    shape = (5, 4, 3)
+    n = 60
+    P = orc.Problem(shape, np.zeros(n, np.int32), C[None])
+    e6 = rng.standard_normal(6) * 1e-3
+    b, r2 = P.load(e6)
+    assert np.abs(b).max() <= 1e-14 * np.sqrt(r2)
+    res = P.solve(e6, tol=1e-10)
+    assert res["status"] == orc.CONVERGED and res["iters"] == 0
+    sig, avg = P.stress(e6, res["w"])
+    ref = C @ _ehat(e6)
+    assert np.allclose(sig, ref[:, None], rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+    assert np.allclose(avg, ref, rtol=1e-13)
+
+
+def _poly_small(shape, seed, void=True):
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    ng = 4
+    phase = rng.integers(0, ng, n).astype(np.int32)
+    C = [synth.rotate_stiffness(synth.cubic_stiffness(206, 133, 119), synth.random_rotations(rng, 1)[0])
+         for _ in range(ng)]
+    C.append(np.zeros((6, 6)))
+    if void:
+        phase[rng.random(n) < 0.12] = ng
+    return phase, np.array(C)
+
+
+def test_operator_symmetric_and_translation_free(orc):
+    shape = (5, 4, 6)
+    phase, C = _poly_small(shape, 6)
+    P = orc.Problem(shape, phase, C)
+    rng = np.random.default_rng(7)
+    x, y = rng.standard_normal((2, 3, P.n))
+    assert np.isclose(np.sum(x * P.apply(y)), np.sum(P.apply(x) * y), rtol=1e-12)
+    for d in range(3):
+        t = np.zeros((3, P.n)); t[d] = 1.0
+        assert np.abs(P.apply(t)).max() <= 1e-12 * np.abs(C).max()
+    b, _ = P.load([1e-3, -2e-4, 3e-4, 1e-4, -5e-4, 2e-4])
+    assert np.abs(b.sum(axis=1)).max() <= 1e-15 * np.abs(b).sum()
+
+
+def test_sampled_entry_points_match_full_ones(orc):
+    shape = (6, 5, 4)
+    phase, C = _poly_small(shape, 8)
+    P = orc.Problem(shape, phase, C)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((3, P.n))
+    sel = rng.choice(P.n, 17, replace=False)
+    assert np.allclose(P.apply_at(x, sel), P.apply(x)[:, sel], rtol=1e-13, atol=1e-12)
+    e6 = [0, 0, 1e-3, 0, 0, 0]
+    assert np.allclose(P.load_at(e6, sel), P.load(e6)[0][:, sel], rtol=1e-13, atol=1e-16)
+    assert np.allclose(P.precond_at(sel), P.precond()[sel], rtol=1e-13)
+
+
+# ------------------------------------------------------------------ solve
+
+def _dense_operator(P):
+    """Dense A assembled from the element matrices by direct index bookkeeping."""
+    nx, ny, nz, n = P.nx, P.ny, P.nz, P.n
+    A = np.zeros((3 * n, 3 * n))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                e = i + nx * (j + ny * k)
+                K = P.ke[P.phase[e]].reshape(24, 24)
+                dofs = []
+                for a in range(8):
+                    m = ((i + (a & 1)) % nx) + nx * (((j + ((a >> 1) & 1)) % ny) + ny * ((k + (a >> 2)) % nz))
+                    dofs += [c * n + m for c in range(3)]
+                A[np.ix_(dofs, dofs)] += K
+    return A
+
+
+@pytest.mark.parametrize("shape,void", [((4, 4, 4), False), ((4, 3, 5), True), ((4, 4, 4), True)])
+def test_pcg_matches_bruteforce_dense_solve(orc, shape, void):
+    phase, C = _poly_small(shape, 10 + shape[2], void)
+    P = orc.Problem(shape, phase, C)
+    e6 = np.array([1e-3, 0, 0, 0, 2e-4, 0])
+    b, _ = P.load(e6)
+    A = _dense_operator(P)
+    assert np.allclose(A @ np.random.default_rng(0).standard_normal(3 * P.n),
+                       A @ np.random.default_rng(0).standard_normal(3 * P.n))
+    x = np.random.default_rng(11).standard_normal((3, P.n))
+    assert np.allclose(A @ x.ravel(), P.apply(x).ravel(), rtol=1e-12, atol=1e-10)
+    w_ls = np.linalg.lstsq(A, -b.ravel(), rcond=1e-12)[0]  # minimum-norm solution
+    res = P.solve(e6, tol=1e-13, maxit=5000)
+    assert res["status"] == orc.CONVERGED
+    w = res["w"].ravel()
+    # the solutions may differ only by null-space (rigid) motions
+    U, s, Vt = np.linalg.svd(A)
+    rng_basis = Vt[s > 1e-10 * s[0]]
+    w_proj = rng_basis.T @ (rng_basis @ w)
+    assert np.linalg.norm(w_proj - w_ls) <= 1e-9 * np.linalg.norm(w_ls)
+    s1, _ = P.stress(e6, res["w"])
+    s2, _ = P.stress(e6, w_ls.reshape(3, -1))
+    assert np.abs(s1 - s2).max() <= 1e-9 * np.abs(s2).max()
+
+
+def test_pcg_and_cg_reach_same_field_and_energy_decreases(orc):
+    shape = (6, 5, 4)
+    phase, C = _poly_small(shape, 12)
+    P = orc.Problem(shape, phase, C)
+    e6 = [0, 1e-3, 0, 0, 0, 0]
+    r1 = P.solve(e6, tol=1e-13, maxit=5000)
+    r2 = P.solve(e6, tol=1e-13, maxit=5000, preconditioned=False)
+    s1, a1 = P.stress(e6, r1["w"])
+    s2, a2 = P.stress(e6, r2["w"])
+    assert np.abs(s1 - s2).max() <= 1e-9 * np.abs(s1).max()
+    energies = [P.energy(e6, P.solve(e6, tol=0.0, maxit=k)["w"]) for k in range(0, 9)]
+    assert all(b < a for a, b in zip(energies, energies[1:]))
+
+
+def test_paper_mode_stops_on_preconditioned_norm(orc):
+    ms = synth.eshelby_inclusion(12, radius=3.0)
+    P = orc.Problem.from_micro(ms)
+    r = P.solve(ms.strain[0], tol=1e-6, mode=1)
+    assert r["status"] == orc.CONVERGED and r["relres_precond"] < 1e-6
+    r0 = P.solve(ms.strain[0], tol=1e-6, mode=1, maxit=r["iters"] - 1)
+    assert r0["status"] == orc.NOT_CONVERGED and r0["relres_precond"] >= 1e-6
+
+
+def test_hill_mandel_identity_any_field(orc):
+    """2 Pi(w) = N E_hat.<sigma>(w) + w.(A w + b) holds for every w."""
+    shape = (5, 6, 4)
+    phase, C = _poly_small(shape, 13)
+    P = orc.Problem(shape, phase, C)
+    rng = np.random.default_rng(14)
+    for e6 in synth.unit_load_cases():
+        w = rng.standard_normal((3, P.n)) * 1e-4
+        b, _ = P.load(e6)
+        g = P.apply(w) + b
+        _, avg = P.stress(e6, w)
+        lhs = 2.0 * P.energy(e6, w)
+        rhs = P.n * _ehat(e6) @ avg + np.sum(w * g)
+        assert np.isclose(lhs, rhs, rtol=1e-12)
+
+
+def test_eshelby_inclusion_mean_strain_near_mori_tanaka(orc):
+    """Uniform interior strain of an isotropic sphere (Eshelby 1957) corrected
+    for the periodic volume fraction by Mori-Tanaka; voxelisation error
+    shrinks with resolution (Sec. 3.1 validates against Eshelby)."""
+    errs = []
+    for n in (20, 40):
+        ms = synth.eshelby_inclusion(n)
+        P = orc.Problem.from_micro(ms)
+        r = P.solve(ms.strain[0], tol=1e-10)
+        sig, _ = P.stress(ms.strain[0], r["w"])
+        inc = ms.phase == 1
+        e_in = np.linalg.solve(ms.C[1], sig[:, inc].mean(axis=1))
+        f = inc.mean()
+        K = lambda E, v: E / (3 * (1 - 2 * v))
+        G = lambda E, v: E / (2 * (1 + v))
+        Km, Gm, Ki, Gi = K(200, .3), G(200, .3), K(400, .25), G(400, .25)
+        al = 3 * Km / (3 * Km + 4 * Gm)
+        be = 6 * (Km + 2 * Gm) / (5 * (3 * Km + 4 * Gm))
+        Av = 1 / (1 + al * (Ki / Km - 1))
+        Ad = 1 / (1 + be * (Gi / Gm - 1))
+        Av, Ad = Av / (f * Av + 1 - f), Ad / (f * Ad + 1 - f)
+        E = _tensor(ms.strain[0])
+        tr = np.trace(E) / 3
+        mt = Av * tr * np.eye(3) + Ad * (E - tr * np.eye(3))
+        fe = _tensor(np.r_[e_in[:3], e_in[3:] / 2])
+        errs.append(np.linalg.norm(fe - mt) / np.linalg.norm(mt))
+        assert np.abs(fe - np.diag(np.diag(fe))).max() < 1e-3 * np.abs(fe).max()
+    assert errs[0] < 0.08 and errs[1] < errs[0]
+
+
+# ------------------------------------------------------------ golden tables
+
+def test_table5_rotation_keeps_mandel_spectrum():
+    g = json.load(open(os.path.join(GOLD, "table5_ss316l.json")))
+    C0 = synth.cubic_stiffness(g["C11"], g["C12"], g["C44"])
+    W = np.diag([1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)])
+    expect = np.sort([472.0, 73.0, 73.0, 238.0, 238.0, 238.0])
+    rng = synth.rng_for(15)
+    for R in synth.random_rotations(rng, 20):
+        Cr = synth.rotate_stiffness(C0, R)
+        assert np.allclose(np.sort(np.linalg.eigvalsh(W @ Cr @ W)), expect, rtol=1e-12)
+        assert np.allclose(Cr, Cr.T)
+
+
+def test_table3_relations_and_rotation_invariants():
+    g = json.load(open(os.path.join(GOLD, "table3_anisotropy.json")))
+    rng = synth.rng_for(16)
+    for case, A, c11, c12, c44 in g["rows"]:
+        assert abs((c11 + 2 * c12) / 3 - g["baseline_K_GPa"]) < 0.02
+        assert abs(2 * c44 / (c11 - c12) - A) < 0.01
+        C0 = synth.cubic_stiffness(c11, c12, c44)
+        R = synth.random_rotations(rng, 1)[0]
+        Cr = synth.rotate_stiffness(C0, R)
+        # Voigt averages are rotation invariant
+        K0 = (C0[:3, :3].sum()) / 9
+        Kr = (Cr[:3, :3].sum()) / 9
+        G0 = (np.trace(C0[:3, :3]) - C0[0, 1] - C0[0, 2] - C0[1, 2] + 3 * np.trace(C0[3:, 3:])) / 15
+        Gr = (np.trace(Cr[:3, :3]) - Cr[0, 1] - Cr[0, 2] - Cr[1, 2] + 3 * np.trace(Cr[3:, 3:])) / 15
+        assert np.isclose(K0, Kr, rtol=1e-12) and np.isclose(G0, Gr, rtol=1e-12)
+        if case == 3:
+            assert abs(G0 - g["baseline_G_GPa"]) < 0.01
