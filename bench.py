@@ -1,0 +1,202 @@
+"""Benchmark of the PCG hot path on one MI355X.
+
+One step = one pass of the whole path over one synthetic microstructure
+already resident in HBM: elas3d_setup (coefficient tables, load vector,
+block-Jacobi inverse), elas3d_solve to a true relative residual of `tol`,
+elas3d_stress (voxel stress planes, mean stress, energy) and destroy.
+
+Prints one JSON line with the throughput in Gdof*iterations/s over the
+whole step, the roofline of the dominant kernel (the fused
+direction + operator sweep, timed with HIP events on its own stream) and
+the CPU oracle timed on a bounded sample of the same recipe.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# Algorithmic HBM bytes per node of the fused direction+operator sweep:
+# read z, h_old, w and write h_new, w, Ah (6 x 3 doubles) plus the phase id.
+OPERATOR_BYTES_PER_NODE_FP64 = 6 * 24 + 4
+
+WORKLOAD_TEXT = {
+    "poly500": "500^3 periodic Voronoi polycrystal, 8000 rotated cubic SS316L grains "
+               "(C11/C12/C44 = 206/133/119 GPa), 2% pores (spheres, oblate 4:4:1, z-prolate "
+               "keyholes in thirds), eps_zz = 1e-3",
+    "poly300": "300^3 periodic Voronoi polycrystal, 3000 grains, 0.5% spheres + 0.5% oblate pores",
+    "poly100": "100^3 periodic Voronoi polycrystal, 500 grains, 1% spherical pores, eps_xx = 1e-3",
+    "eshelby20": "20^3 isotropic matrix with a stiff spherical inclusion, eps_xx = 1e-3",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="poly500", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--scale", type=int, default=None, help="re-size the workload to scale^3")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=50000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=100, help="edge of the oracle sample grid")
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(workload: str, edge: int, iters: int) -> dict:
+    """The oracle (serial FP64 C) on a bounded sample: the same recipe at edge^3."""
+    import oracle
+    from paper_2602_07354_amd import synth
+
+    ms = synth.workload(workload, scale=edge) if workload != "eshelby20" else synth.workload(workload)
+    P = oracle.Problem.from_micro(ms)
+    b, r2 = P.load(ms.strain[0])
+    minv = P.precond()
+    t0 = time.perf_counter()
+    r = P.solve(ms.strain[0], tol=0.0, maxit=iters, b=b, minv=minv)
+    dt = time.perf_counter() - t0
+    n_it = max(1, r["iters"])
+    return {
+        "value": 3.0 * ms.n * n_it / dt / 1e9,
+        "unit": "Gdof*iter/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"serial FP64 oracle PCG, {n_it} iterations on the {ms.meta['workload']} grid "
+                  f"({ms.n} voxels, same grain density and pore recipe), {dt:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                                   "described in DESIGN.md but not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2602_07354_amd import elas3d as E
+    from paper_2602_07354_amd import synth
+
+    E.lib()
+    t_gen = time.perf_counter()
+    ms = synth.workload(args.workload, scale=args.scale) if args.workload != "eshelby20" \
+        else synth.workload(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# generated {ms.meta.get('workload')} {ms.shape} in {t_gen:.1f} s, "
+          f"void {ms.void_fraction():.4f}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.calib_copy_gib > 0:
+        nbytes = int(args.calib_copy_gib * (1 << 30))
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    phase = torch.from_numpy(ms.phase).to(dev)
+    sigma = torch.empty((6, ms.n), dtype=torch.float64, device=dev)
+    avg = np.empty(6)
+    energy = np.empty(1)
+    stream = torch.cuda.Stream(device=dev)
+    opts = E.options_init(inputs_on_device=1, outputs_on_device=0, timing=1, device=0,
+                          stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+
+    def step(record):
+        h = E.setup(ms.shape, phase, ms.C, ms.strain[:1], opts)
+        try:
+            st, info = E.solve(h, args.tol, args.maxit, 1)
+            # voxel stress planes stay on the device (outputs_on_device context)
+            E.lib().elas3d_stress(h, 0, None, avg.ctypes.data, None, energy.ctypes.data)
+        finally:
+            E.destroy(h)
+        if record is not None:
+            record.append((st, info.as_dict()))
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    iters = [r[1]["iters"][0] for r in recs]
+    t_op = sum(r[1]["t_operator_ms"] for r in recs)
+    n_op = sum(r[1]["n_operator"] for r in recs)
+    t_up = sum(r[1]["t_update_ms"] for r in recs)
+    n_up = sum(r[1]["n_update"] for r in recs)
+    ms_step = 1e3 * dt / args.steps
+    dof_iters = 3.0 * ms.n * float(np.mean(iters))
+    value = dof_iters / (ms_step / 1e3) / 1e9
+    op_ms = t_op / max(1, n_op)
+    op_bytes = OPERATOR_BYTES_PER_NODE_FP64 * ms.n
+    achieved = op_bytes / (op_ms / 1e3) / 1e9
+    out = {
+        "metric": "Gdof*iterations/s of the FP64 block-Jacobi PCG solve to true rel-res 1e-8 "
+                  "(whole step: setup + solve + stress)",
+        "value": round(value, 3),
+        "unit": "Gdof*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ms.meta.get("workload"),
+            "description": WORKLOAD_TEXT.get(args.workload, ""),
+            "grid": list(ms.shape),
+            "nphase": ms.nphase,
+            "void_fraction": round(ms.void_fraction(), 5),
+            "tol": args.tol,
+            "precision": "fp64",
+            "parallelism": "single GPU",
+        },
+        "iters": iters,
+        "status": [r[0] for r in recs],
+        "relres_true": [r[1]["relres_true"][0] for r in recs],
+        "time_to_solution_s": [round(r[1]["t_solve_s"], 4) for r in recs],
+        "operator_ms_avg": round(op_ms, 4),
+        "update_ms_avg": round(t_up / max(1, n_up), 4),
+        "roofline": {
+            "kernel": "op_kernel<16,16,true> (fused direction update + matrix-free operator + h.Ah)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": op_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_iters)
+        except Exception as e:  # the GPU number stands without it
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

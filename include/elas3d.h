@@ -1,0 +1,202 @@
+/*
+ * elas3d.h - C-ABI of the MI355X periodic voxel elasticity solver.
+ *
+ * The library solves the equilibrium problem of ELAS3D-Xtal (arXiv
+ * 2602.07354, Sec. 2.1): a periodic grid of nx*ny*nz voxels, each voxel a
+ * trilinear 8-node hexahedron with 3 displacement dofs per node, carrying
+ * the 6x6 stiffness of its phase (grain or pore).  Under an applied
+ * macroscopic strain E the displacement is u = E.X + w, and w minimises the
+ * quadratic energy of Eq. (quadratic_form), i.e. solves A w + b = 0
+ * (Sec. 2.1.2).  The solve is the matrix-free point-block Jacobi PCG of
+ * Algorithm 2, run entirely by hand-written gfx950 HIP kernels.
+ *
+ * Conventions (all entry points):
+ *   - Grid: voxel / node (i,j,k) is flattened as m = i + nx*(j + ny*k),
+ *     x fastest (Eq. pbc_indices, 0-based).  Node m sits at the lower corner
+ *     of voxel m; voxel m has the nodes ((i+a)%nx, (j+b)%ny, (k+c)%nz),
+ *     a,b,c in {0,1}.  Voxel size is 1, so displacements are in voxel units
+ *     and stresses in the units of C.
+ *   - Stiffness C: per phase a row-major 6x6 Voigt matrix in the order
+ *     (11,22,33,23,13,12) mapping engineering strain to stress (Sec. 2.1.1,
+ *     Eq. (2)-(3) and Eq. (anisotropic_rotation)).  It must be symmetric and
+ *     finite.  A phase whose 36 entries are all zero is a void (pore).
+ *   - Strain: tensor components (E11,E22,E33,E23,E13,E12) (Eq. affine_strain).
+ *   - Node vectors (displacement, load, operator input/output): SoA, three
+ *     planes of N doubles, component c of node m at [c*N + m].
+ *   - Voxel stress: six planes of N doubles, Voigt order, [r*N + m].
+ *
+ * Ownership: setup copies every input, so callers may free or reuse their
+ * arrays on return.  Outputs go to caller-allocated buffers (host memory,
+ * or device memory when elas3d_options.outputs_on_device is set).  The
+ * library owns all device memory of a context and releases it in
+ * elas3d_destroy.  A context is not thread-safe; distinct contexts are
+ * independent.
+ *
+ * Errors: 0 = success.  Positive values are soft results whose outputs are
+ * still valid (ELAS3D_NOT_CONVERGED, ELAS3D_BREAKDOWN).  Negative values are
+ * hard errors with no outputs written; elas3d_last_error gives a message.
+ * Argument validation runs before any device call.
+ */
+#ifndef ELAS3D_H
+#define ELAS3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ELAS3D_OK 0
+#define ELAS3D_NOT_CONVERGED 1  /* maxit reached before the tolerance       */
+#define ELAS3D_BREAKDOWN 2      /* h.Ah <= 0 or not finite (Algorithm 2, B) */
+#define ELAS3D_EBADARG (-1)     /* invalid argument, nothing done           */
+#define ELAS3D_ENOMEM (-2)      /* device memory budget exceeded            */
+#define ELAS3D_EDEVICE (-3)     /* HIP runtime error                        */
+#define ELAS3D_EORDER (-4)      /* call out of order (e.g. stress before solve) */
+
+#define ELAS3D_MAX_RHS 6
+
+/* elas3d_options.precision */
+#define ELAS3D_PREC_FP64 0  /* every vector and reduction in FP64 (the paper's, Sec. 2.1.2) */
+#define ELAS3D_PREC_MIXED 1 /* FP32 inner PCG inside FP64 iterative refinement            */
+
+/* elas3d_options.convergence */
+#define ELAS3D_CONV_RESIDUAL 0 /* stop on ||g||/||b|| <= tol, confirmed by the true residual */
+#define ELAS3D_CONV_PAPER 1    /* stop on sqrt(z.g / z0.g0) < tol (Algorithm 2, D)           */
+
+/* elas3d_options.preconditioner */
+#define ELAS3D_PRECOND_BLOCK_JACOBI 0 /* 3x3 point-block Jacobi, Eq. (block_precond) */
+#define ELAS3D_PRECOND_NONE 1         /* plain CG (M^-1 = I on active nodes)          */
+
+typedef struct elas3d_ctx elas3d_ctx;
+
+typedef struct elas3d_options {
+    int32_t precision;         /* ELAS3D_PREC_*                                      */
+    int32_t convergence;       /* ELAS3D_CONV_*                                      */
+    int32_t preconditioner;    /* ELAS3D_PRECOND_*                                   */
+    int32_t inputs_on_device;  /* nonzero: `phase` of elas3d_setup is a device pointer */
+    int32_t outputs_on_device; /* nonzero: output/input vectors of stress, apply,
+                                  get_* are device pointers                          */
+    int32_t poll_interval;     /* iterations between host checks of the stop flag;
+                                  0 = automatic                                      */
+    int32_t timing;            /* nonzero: time each fused-operator and update
+                                  launch with HIP events (reported in elas3d_info)   */
+    int32_t device;            /* HIP device ordinal, -1 = current device            */
+    double hbm_budget_bytes;   /* device bytes the context may allocate; 0 = 95 %
+                                  of the device's free memory at setup               */
+    void* stream;              /* hipStream_t to run on; NULL = a library stream     */
+    double inner_tol;          /* mixed: relative residual reduction per refinement
+                                  cycle of the FP32 inner PCG (0 = 1e-4)             */
+    int32_t inner_maxit;       /* mixed: iteration cap of one inner solve (0 = auto) */
+    int32_t batched;           /* nonzero: solve all requested RHS in one multi-RHS
+                                  launch sequence sharing the operator               */
+} elas3d_options;
+
+typedef struct elas3d_info {
+    int32_t nrhs;                              /* RHS solved by the call             */
+    int32_t status[ELAS3D_MAX_RHS];            /* per RHS: 0, 1 or 2 (see above)    */
+    int32_t iters[ELAS3D_MAX_RHS];             /* PCG iterations (inner ones in mixed) */
+    int32_t restarts[ELAS3D_MAX_RHS];          /* residual-confirmation restarts /
+                                                  refinement cycles (mixed)          */
+    double relres_true[ELAS3D_MAX_RHS];        /* ||A w + b||_2 / ||b||_2, recomputed */
+    double relres_recursive[ELAS3D_MAX_RHS];   /* ||g||_2 / ||b||_2 of the recursion */
+    double relres_precond[ELAS3D_MAX_RHS];     /* sqrt(z.g / z0.g0)                  */
+    double t_solve_s;                          /* wall time of the call              */
+    double bytes_per_iter;                     /* algorithmic HBM bytes of one PCG
+                                                  iteration (all RHS of the call)   */
+    double t_operator_ms;                      /* summed fused-operator kernel time  */
+    int64_t n_operator;                        /* fused-operator launches timed      */
+    double t_update_ms;                        /* summed update-kernel time          */
+    int64_t n_update;                          /* update launches timed              */
+} elas3d_info;
+
+/* Fill `opt` with the defaults (FP64, residual criterion, block Jacobi,
+ * host pointers, automatic polling, no timing, current device, budget from
+ * free memory, library stream). */
+void elas3d_options_init(elas3d_options* opt);
+
+/*
+ * Create a context: copy the inputs to the device, build the per-phase
+ * coefficient tables, assemble the load vector b of every RHS (the work of
+ * the macroscopic strain, Eq. (discrete_energy)) and the inverse point-block
+ * Jacobi preconditioner M^-1 (Eq. (block_precond)).
+ *   out     receives the context (set to NULL on error).
+ *   nx,ny,nz grid size, each >= 2, N = nx*ny*nz < 2^31.
+ *   phase   N phase ids in [0, nphase), x fastest (host, or device when
+ *           opt->inputs_on_device).
+ *   nphase  number of phases (>= 1).
+ *   C       nphase*36 doubles (host), 6x6 per phase as described above.
+ *   nrhs    number of macroscopic strains, 1..ELAS3D_MAX_RHS.
+ *   strain  nrhs*6 doubles (host), tensor components per RHS.
+ *   opt     NULL for defaults.
+ * Returns 0, ELAS3D_EBADARG (null pointer, bad size, phase id out of range,
+ * non-finite or asymmetric C, non-finite strain), ELAS3D_ENOMEM or
+ * ELAS3D_EDEVICE.
+ */
+int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int32_t* phase,
+                 int32_t nphase, const double* C, int32_t nrhs, const double* strain,
+                 const elas3d_options* opt);
+
+/*
+ * Solve A w_r = -b_r for the first `nrhs` load cases from w_r = 0 by the PCG
+ * of Algorithm 2 (or its mixed-precision refinement) until the criterion of
+ * opt->convergence holds with `tol`, or `maxit` iterations per RHS.
+ * `info` (may be NULL) receives per-RHS statistics.  Returns the worst
+ * per-RHS status (0, ELAS3D_NOT_CONVERGED, ELAS3D_BREAKDOWN) or a negative
+ * error.  The solutions stay on the device for elas3d_stress.
+ */
+int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3d_info* info);
+
+/*
+ * Post-processing of load case `rhs` (Table 1, stress_OpenMP): per voxel the
+ * stress at the voxel centroid sigma = C_p (E_hat + B(1/2,1/2,1/2) w_e),
+ * which is the voxel average of the trilinear field (0 in voids).
+ *   sigma_voxel  6*N doubles or NULL.
+ *   sigma_avg    6 doubles or NULL: mean over all N voxels (voids count 0).
+ *   u_node       3*N doubles or NULL: total displacement u = E.X + w with
+ *                X = (i,j,k) of the node.
+ *   energy       1 double or NULL: total potential energy
+ *                Pi = 1/2 sum_e (u_e)^T K_e (u_e) (Eq. discrete_energy).
+ * Returns 0, ELAS3D_EBADARG, ELAS3D_EORDER (rhs not solved) or ELAS3D_EDEVICE.
+ */
+int elas3d_stress(elas3d_ctx* ctx, int32_t rhs, double* sigma_voxel, double* sigma_avg,
+                  double* u_node, double* energy);
+
+/*
+ * Matrix-free operator y = A x (Algorithm 2, step A: the 27-point coupling
+ * of every node through its 8 voxels), x and y 3*N doubles.  Also the
+ * building block of the true residual.  Returns 0 or a negative error.
+ */
+int elas3d_apply(elas3d_ctx* ctx, const double* x, double* y);
+
+/* Copy the load vector b of case `rhs` (3*N doubles) out of the context. */
+int elas3d_get_load(elas3d_ctx* ctx, int32_t rhs, double* b);
+
+/* Copy the inverse diagonal blocks M^-1 (6*N doubles: planes xx, yy, zz,
+ * yz, xz, xy of the symmetric 3x3 per node; 0 on nodes touched only by
+ * voids) out of the context. */
+int elas3d_get_precond(elas3d_ctx* ctx, double* minv);
+
+/* Copy the fluctuation displacement w of case `rhs` (3*N doubles). */
+int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w);
+
+/* Device bytes a context with these sizes and options would allocate. */
+double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
+                           const elas3d_options* opt);
+
+/* Release every device resource of the context (NULL is a no-op). */
+void elas3d_destroy(elas3d_ctx* ctx);
+
+/* Message of the last error of `ctx`, or of the calling thread's last
+ * context-free call (setup) when ctx is NULL.  Never NULL. */
+const char* elas3d_last_error(const elas3d_ctx* ctx);
+
+/* Library version string. */
+const char* elas3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELAS3D_H */

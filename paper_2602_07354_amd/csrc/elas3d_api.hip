@@ -1,0 +1,727 @@
+// Host runtime and C-ABI of libelas3d: argument validation, device memory
+// budget, per-phase coefficient tables, and the iteration driver of the
+// point-block Jacobi PCG (ELAS3D-Xtal, arXiv 2602.07354, Algorithm 2).
+//
+// The PCG scalars live on the device and are updated by single-block
+// finalize kernels, so iterations are enqueued back to back; the host only
+// reads the stop flag every `poll_interval` iterations, one batch behind
+// the device (a batch enqueued after convergence returns at once).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "elas3d.h"
+#include "elas3d_internal.h"
+
+using e3d::Dims;
+using e3d::Fields;
+using e3d::Scalars;
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+constexpr int kSweepBlocks = 4096;  // grid of the node-wise sweeps
+constexpr int kPartialValues = 8;   // partial sums per block, upper bound
+constexpr int kDefaultPoll = 16;
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+struct elas3d_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Dims d{};
+    int nphase = 0, nrhs = 0;
+    elas3d_options opt{};
+    std::vector<double> strain;  // nrhs * 6
+    e3d::OpGeom geom{};
+
+    int32_t* phase = nullptr;
+    double* coef = nullptr;
+    double* diag = nullptr;
+    uint8_t* solid = nullptr;
+    double* sig = nullptr;
+    double* b = nullptr;     // nrhs * 3N
+    double* w = nullptr;     // nrhs * 3N
+    double* work = nullptr;  // g, z, h0, h1, Ah: 15N
+    double* minv = nullptr;  // 6N
+    double* partials = nullptr;
+    int partial_stride = 0;
+    double* norms = nullptr;  // nrhs * 2: ||b||^2, ||b||_ref^2
+    double* dscratch = nullptr;  // 16 doubles
+    int* dflag = nullptr;
+    Scalars* S = nullptr;
+    Scalars* hS = nullptr;        // pinned, 2 slots
+    double* hscratch = nullptr;   // pinned, 16 doubles
+    std::vector<int> solved;
+    double bytes = 0.0;
+    std::string err;
+
+    std::vector<EventPair> ev_op, ev_up;
+
+    size_t N() const { return (size_t)d.n; }
+    double* plane(double* base, int q) const { return base + (size_t)q * N(); }
+
+    Fields fields(int rhs)
+    {
+        Fields f;
+        for (int c = 0; c < 3; ++c) {
+            f.w[c] = plane(w, 3 * rhs + c);
+            f.b[c] = plane(b, 3 * rhs + c);
+            f.g[c] = plane(work, c);
+            f.z[c] = plane(work, 3 + c);
+            f.h0[c] = plane(work, 6 + c);
+            f.h1[c] = plane(work, 9 + c);
+            f.Ah[c] = plane(work, 12 + c);
+        }
+        return f;
+    }
+    void minv_planes(double* out[6]) const
+    {
+        for (int q = 0; q < 6; ++q) out[q] = minv + (size_t)q * N();
+    }
+    e3d::Tables tables() const { return e3d::Tables{coef, diag, solid}; }
+};
+
+namespace {
+
+int fail(elas3d_ctx* ctx, int code, const std::string& msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_last_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), ELAS3D_EDEVICE,                                                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+    } while (0)
+
+void default_options(elas3d_options* o)
+{
+    std::memset(o, 0, sizeof(*o));
+    o->precision = ELAS3D_PREC_FP64;
+    o->convergence = ELAS3D_CONV_RESIDUAL;
+    o->preconditioner = ELAS3D_PRECOND_BLOCK_JACOBI;
+    o->device = -1;
+}
+
+// Device bytes of a context (kept in one place so the budget check and
+// elas3d_device_bytes agree).
+double plan_bytes(int64_t n, int nphase, int nrhs)
+{
+    const double N = (double)n;
+    double bytes = 0.0;
+    bytes += 4.0 * N;                          // phase ids
+    bytes += 8.0 * 3.0 * N * nrhs * 2.0;       // b and w per case
+    bytes += 8.0 * 15.0 * N;                   // g, z, h0, h1, Ah
+    bytes += 8.0 * 6.0 * N;                    // M^-1 (symmetric 3x3)
+    bytes += (double)nphase * 8.0 * (e3d::kCoefStride + e3d::kDiagStride + 1.0) +
+             (double)nphase * nrhs * 8.0 * e3d::kSigStride;
+    bytes += 8.0 * kPartialValues * 65536.0;   // partial sums
+    bytes += 4096.0;
+    return bytes;
+}
+
+// Voigt index of the tensor pair (i,j).
+int voigt(int i, int j)
+{
+    if (i == j) return i;
+    const int s = i + j;
+    return s == 3 ? 3 : (s == 2 ? 4 : 5);  // (1,2)->3, (0,2)->4, (0,1)->5
+}
+
+int ut(int r, int c)
+{
+    if (r > c) std::swap(r, c);
+    return r * 6 - (r * (r - 1)) / 2 + (c - r);
+}
+
+// Per-phase tables (Sec. 2.1.1: a full stiffness per phase).
+//  coef: packed upper triangle of C.
+//  diag: the corner block of the element stiffness for corner signs s,
+//        (K_e)_aa,ij = sum_kl s_k s_l C_ikjl I_kl with I_kk = 1/9 and
+//        I_kl = 1/12 (k != l) the integrals of products of shape-function
+//        derivatives over the voxel, split as D + sx sy Oxy + sx sz Oxz + sy sz Oyz.
+//  sig:  C E_hat per load case (uniform stress of the affine field).
+void build_tables(const double* C, int nphase, const double* strain, int nrhs,
+                  std::vector<double>& coef, std::vector<double>& diag, std::vector<uint8_t>& solid,
+                  std::vector<double>& sig)
+{
+    coef.assign((size_t)nphase * e3d::kCoefStride, 0.0);
+    diag.assign((size_t)nphase * e3d::kDiagStride, 0.0);
+    solid.assign((size_t)nphase, 0);
+    sig.assign((size_t)nrhs * nphase * e3d::kSigStride, 0.0);
+    const int pij[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    for (int p = 0; p < nphase; ++p) {
+        const double* Cp = C + 36 * (size_t)p;
+        auto T = [&](int i, int j, int k, int l) { return Cp[6 * voigt(i, j) + voigt(k, l)]; };
+        bool any = false;
+        for (int q = 0; q < 36; ++q) any = any || Cp[q] != 0.0;
+        solid[p] = any ? 1 : 0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = r; c < 6; ++c) coef[(size_t)p * e3d::kCoefStride + ut(r, c)] = Cp[6 * r + c];
+        double* dg = diag.data() + (size_t)p * e3d::kDiagStride;
+        for (int q = 0; q < 6; ++q) {
+            const int i = pij[q][0], j = pij[q][1];
+            dg[q] = (T(i, 0, j, 0) + T(i, 1, j, 1) + T(i, 2, j, 2)) / 9.0;
+            dg[6 + q] = (T(i, 0, j, 1) + T(i, 1, j, 0)) / 12.0;   // x-y corner term
+            dg[12 + q] = (T(i, 0, j, 2) + T(i, 2, j, 0)) / 12.0;  // x-z
+            dg[18 + q] = (T(i, 1, j, 2) + T(i, 2, j, 1)) / 12.0;  // y-z
+        }
+        for (int r = 0; r < nrhs; ++r) {
+            const double* E = strain + 6 * r;
+            const double Eh[6] = {E[0], E[1], E[2], 2 * E[3], 2 * E[4], 2 * E[5]};
+            double* s = sig.data() + ((size_t)r * nphase + p) * e3d::kSigStride;
+            for (int a = 0; a < 6; ++a) {
+                double acc = 0.0;
+                for (int b = 0; b < 6; ++b) acc += Cp[6 * a + b] * Eh[b];
+                s[a] = acc;
+            }
+        }
+    }
+}
+
+int validate_options(const elas3d_options* o)
+{
+    if (o->precision != ELAS3D_PREC_FP64 && o->precision != ELAS3D_PREC_MIXED)
+        return fail(nullptr, ELAS3D_EBADARG, "options.precision must be ELAS3D_PREC_FP64 or _MIXED");
+    if (o->convergence != ELAS3D_CONV_RESIDUAL && o->convergence != ELAS3D_CONV_PAPER)
+        return fail(nullptr, ELAS3D_EBADARG, "options.convergence must be RESIDUAL or PAPER");
+    if (o->preconditioner != ELAS3D_PRECOND_BLOCK_JACOBI && o->preconditioner != ELAS3D_PRECOND_NONE)
+        return fail(nullptr, ELAS3D_EBADARG, "options.preconditioner must be BLOCK_JACOBI or NONE");
+    if (o->poll_interval < 0 || o->inner_maxit < 0)
+        return fail(nullptr, ELAS3D_EBADARG, "options.poll_interval / inner_maxit must be >= 0");
+    if (!(o->hbm_budget_bytes >= 0.0) || !std::isfinite(o->hbm_budget_bytes))
+        return fail(nullptr, ELAS3D_EBADARG, "options.hbm_budget_bytes must be finite and >= 0");
+    if (!(o->inner_tol >= 0.0) || !(o->inner_tol < 1.0))
+        return fail(nullptr, ELAS3D_EBADARG, "options.inner_tol must be in [0, 1)");
+    if (o->precision == ELAS3D_PREC_MIXED)
+        return fail(nullptr, ELAS3D_EBADARG, "mixed precision is not available in this build");
+    if (o->batched)
+        return fail(nullptr, ELAS3D_EBADARG, "batched multi-RHS is not available in this build");
+    return 0;
+}
+
+int validate_setup(int32_t nx, int32_t ny, int32_t nz, const int32_t* phase, int32_t nphase,
+                   const double* C, int32_t nrhs, const double* strain, const elas3d_options* o)
+{
+    if (nx < 2 || ny < 2 || nz < 2)
+        return fail(nullptr, ELAS3D_EBADARG, "grid dimensions must each be >= 2");
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (n >= ((int64_t)1 << 31))
+        return fail(nullptr, ELAS3D_EBADARG, "nx*ny*nz must be < 2^31");
+    if (!phase) return fail(nullptr, ELAS3D_EBADARG, "phase is NULL");
+    if (!C) return fail(nullptr, ELAS3D_EBADARG, "C is NULL");
+    if (!strain) return fail(nullptr, ELAS3D_EBADARG, "strain is NULL");
+    if (nphase < 1) return fail(nullptr, ELAS3D_EBADARG, "nphase must be >= 1");
+    if (nrhs < 1 || nrhs > ELAS3D_MAX_RHS)
+        return fail(nullptr, ELAS3D_EBADARG, "nrhs must be in [1, 6]");
+    int rc = validate_options(o);
+    if (rc) return rc;
+    for (int p = 0; p < nphase; ++p) {
+        const double* Cp = C + 36 * (size_t)p;
+        double amax = 0.0;
+        for (int q = 0; q < 36; ++q) {
+            if (!std::isfinite(Cp[q]))
+                return fail(nullptr, ELAS3D_EBADARG, "C of phase " + std::to_string(p) + " is not finite");
+            amax = std::max(amax, std::fabs(Cp[q]));
+        }
+        for (int r = 0; r < 6; ++r)
+            for (int c = r + 1; c < 6; ++c)
+                if (std::fabs(Cp[6 * r + c] - Cp[6 * c + r]) > 1e-12 * amax)
+                    return fail(nullptr, ELAS3D_EBADARG,
+                                "C of phase " + std::to_string(p) + " is not symmetric");
+    }
+    for (int q = 0; q < 6 * nrhs; ++q)
+        if (!std::isfinite(strain[q])) return fail(nullptr, ELAS3D_EBADARG, "strain is not finite");
+    if (!o->inputs_on_device) {
+        for (int64_t m = 0; m < n; ++m)
+            if (phase[m] < 0 || phase[m] >= nphase)
+                return fail(nullptr, ELAS3D_EBADARG,
+                            "phase id out of range at voxel " + std::to_string(m));
+    }
+    return 0;
+}
+
+void free_ctx(elas3d_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    for (void* p : {(void*)c->phase, (void*)c->coef, (void*)c->diag, (void*)c->solid, (void*)c->sig,
+                    (void*)c->b, (void*)c->w, (void*)c->work, (void*)c->minv, (void*)c->partials,
+                    (void*)c->norms, (void*)c->dscratch, (void*)c->dflag, (void*)c->S})
+        if (p) hipFree(p);
+    if (c->hS) hipHostFree(c->hS);
+    if (c->hscratch) hipHostFree(c->hscratch);
+    for (auto& e : c->ev_op) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    for (auto& e : c->ev_up) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int ensure_events(elas3d_ctx* c, std::vector<EventPair>& pool, size_t count)
+{
+    while (pool.size() < count) {
+        EventPair e;
+        HIPCHK(c, hipEventCreate(&e.a));
+        HIPCHK(c, hipEventCreate(&e.b));
+        pool.push_back(e);
+    }
+    return 0;
+}
+
+hipMemcpyKind copy_kind(const elas3d_ctx* c, bool to_device)
+{
+    if (c->opt.outputs_on_device) return hipMemcpyDeviceToDevice;
+    return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+}
+
+// One PCG run on case `rhs`, restarting from w when the recursive residual
+// and the true one disagree (residual criterion only).
+int solve_case(elas3d_ctx* c, int rhs, double tol, int maxit, elas3d_info* info)
+{
+    const Dims& d = c->d;
+    Fields f = c->fields(rhs);
+    double* M[6];
+    c->minv_planes(M);
+    const e3d::Tables t = c->tables();
+    const int poll = c->opt.poll_interval > 0 ? c->opt.poll_interval : kDefaultPoll;
+    const bool timing = c->opt.timing != 0;
+
+    Scalars init{};
+    init.tol = tol;
+    init.maxit = maxit;
+    init.mode = c->opt.convergence;
+    init.it = 0;
+    std::memcpy(&c->hS[0], &init, sizeof(Scalars));
+    HIPCHK(c, hipMemcpyAsync(c->S, &c->hS[0], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, e3d::launch_pcg_init(c->stream, d, f, M, 1, 0, c->S, c->partials, kSweepBlocks,
+                                   c->norms + 2 * rhs));
+    int restarts = 0;
+    double rel_true = 0.0;
+    Scalars fin{};
+    for (;;) {
+        // iterate: batches of `poll` iterations, host one batch behind
+        HIPCHK(c, hipMemcpyAsync(&c->hS[0], c->S, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int it_start = c->hS[0].it;
+        std::vector<int> op_idx;  // timing event slots used, in launch order
+        size_t ev_used = 0;
+        if (!c->hS[0].done) {
+            hipEvent_t batch_ev[2] = {nullptr, nullptr};
+            HIPCHK(c, hipEventCreateWithFlags(&batch_ev[0], hipEventDisableTiming));
+            HIPCHK(c, hipEventCreateWithFlags(&batch_ev[1], hipEventDisableTiming));
+            const long long max_launch = (long long)maxit - it_start + poll;
+            long long launched = 0;
+            int k = 0;
+            bool recorded[2] = {false, false};
+            auto enqueue = [&](int slot) -> int {
+                for (int j = 0; j < poll; ++j) {
+                    if (timing) {
+                        int rc = ensure_events(c, c->ev_op, ev_used + 1);
+                        if (rc) return rc;
+                        rc = ensure_events(c, c->ev_up, ev_used + 1);
+                        if (rc) return rc;
+                        HIPCHK(c, hipEventRecord(c->ev_op[ev_used].a, c->stream));
+                    }
+                    HIPCHK(c, e3d::launch_direction_operator(c->stream, d, c->geom, c->phase, t, f,
+                                                             c->S, c->partials));
+                    if (timing) {
+                        HIPCHK(c, hipEventRecord(c->ev_op[ev_used].b, c->stream));
+                        HIPCHK(c, hipEventRecord(c->ev_up[ev_used].a, c->stream));
+                    }
+                    HIPCHK(c, e3d::launch_update_precond(c->stream, d, f, M, c->S, c->partials,
+                                                         kSweepBlocks));
+                    if (timing) {
+                        HIPCHK(c, hipEventRecord(c->ev_up[ev_used].b, c->stream));
+                        ++ev_used;
+                    }
+                }
+                launched += poll;
+                HIPCHK(c, hipMemcpyAsync(&c->hS[slot], c->S, sizeof(Scalars), hipMemcpyDeviceToHost,
+                                         c->stream));
+                HIPCHK(c, hipEventRecord(batch_ev[slot], c->stream));
+                recorded[slot] = true;
+                return 0;
+            };
+            int rc = enqueue(0);
+            bool stop = false;
+            while (!rc && !stop) {
+                const int slot = k & 1;
+                if (launched < max_launch) rc = enqueue(slot ^ 1);
+                if (rc) break;
+                hipError_t e = hipEventSynchronize(batch_ev[slot]);
+                if (e != hipSuccess) {
+                    rc = fail(c, ELAS3D_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+                    break;
+                }
+                if (c->hS[slot].done) stop = true;
+                if (!stop && launched >= max_launch) {
+                    // the last batch is in flight: wait for it
+                    e = recorded[slot ^ 1] ? hipEventSynchronize(batch_ev[slot ^ 1]) : hipSuccess;
+                    if (e != hipSuccess) {
+                        rc = fail(c, ELAS3D_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+                        break;
+                    }
+                    stop = true;
+                }
+                ++k;
+            }
+            hipStreamSynchronize(c->stream);
+            hipEventDestroy(batch_ev[0]);
+            hipEventDestroy(batch_ev[1]);
+            if (rc) return rc;
+        }
+        HIPCHK(c, e3d::launch_final_update(c->stream, d, f, c->S));
+        // true residual r = A w + b (into g, ready for a restart)
+        const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
+        double* gy[3] = {f.g[0], f.g[1], f.g[2]};
+        HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom, c->phase, t, wx, gy, f.b, c->partials,
+                                    c->dscratch));
+        HIPCHK(c, hipMemcpyAsync(&c->hS[0], c->S, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        fin = c->hS[0];
+        if (timing) {
+            // only the sweeps that ran before the stop flag count
+            const int real = fin.it - it_start + (fin.status == 2 ? 1 : 0);
+            for (int q = 0; q < real && q < (int)ev_used; ++q) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, c->ev_op[q].a, c->ev_op[q].b) == hipSuccess && info) {
+                    info->t_operator_ms += ms;
+                    info->n_operator += 1;
+                }
+                if (q < fin.it - it_start &&
+                    hipEventElapsedTime(&ms, c->ev_up[q].a, c->ev_up[q].b) == hipSuccess && info) {
+                    info->t_update_ms += ms;
+                    info->n_update += 1;
+                }
+            }
+        }
+        const bool zero_load = fin.bnorm2 <= 1e-28 * fin.bref2;
+        rel_true = (zero_load || fin.bnorm2 <= 0.0) ? 0.0 : std::sqrt(c->hscratch[0] / fin.bnorm2);
+        if (c->opt.convergence == ELAS3D_CONV_RESIDUAL && fin.status == 0 && !zero_load &&
+            !(rel_true <= tol)) {
+            if (fin.it >= maxit) {
+                fin.status = 1;
+                break;
+            }
+            ++restarts;
+            HIPCHK(c, e3d::launch_pcg_init(c->stream, d, f, M, 0, 1, c->S, c->partials, kSweepBlocks,
+                                           c->norms + 2 * rhs));
+            continue;
+        }
+        break;
+    }
+    if (info) {
+        info->status[rhs] = fin.status;
+        info->iters[rhs] = fin.it;
+        info->restarts[rhs] = restarts;
+        info->relres_true[rhs] = rel_true;
+        const bool zero_load = fin.bnorm2 <= 1e-28 * fin.bref2;
+        info->relres_recursive[rhs] = (zero_load || fin.bnorm2 <= 0) ? 0.0 : std::sqrt(fin.rr / fin.bnorm2);
+        info->relres_precond[rhs] = (zero_load || fin.gg0 <= 0) ? 0.0 : std::sqrt(std::fabs(fin.gg / fin.gg0));
+    }
+    c->solved[rhs] = 1;
+    return fin.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+void elas3d_options_init(elas3d_options* opt)
+{
+    if (opt) default_options(opt);
+}
+
+const char* elas3d_version(void) { return "elas3d-mi355x 0.1 (gfx950)"; }
+
+const char* elas3d_last_error(const elas3d_ctx* ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_last_error.c_str();
+}
+
+double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
+                           const elas3d_options* opt)
+{
+    (void)opt;
+    return plan_bytes((int64_t)nx * ny * nz, nphase, nrhs);
+}
+
+int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int32_t* phase,
+                 int32_t nphase, const double* C, int32_t nrhs, const double* strain,
+                 const elas3d_options* opt_in)
+{
+    if (!out) return fail(nullptr, ELAS3D_EBADARG, "out is NULL");
+    *out = nullptr;
+    elas3d_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        default_options(&opt);
+    int rc = validate_setup(nx, ny, nz, phase, nphase, C, nrhs, strain, &opt);
+    if (rc) return rc;
+
+    auto t0 = std::chrono::steady_clock::now();
+    // ---- device calls start here
+    int dev = opt.device;
+    if (dev >= 0) {
+        hipError_t e = hipSetDevice(dev);
+        if (e != hipSuccess) return fail(nullptr, ELAS3D_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    } else {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return fail(nullptr, ELAS3D_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    const int64_t n = (int64_t)nx * ny * nz;
+    const double need = plan_bytes(n, nphase, nrhs);
+    double budget = opt.hbm_budget_bytes;
+    if (budget <= 0.0) {
+        size_t free_b = 0, total_b = 0;
+        hipError_t e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) return fail(nullptr, ELAS3D_EDEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+        budget = 0.95 * (double)free_b;
+    }
+    if (need > budget) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "needs %.3f GB of device memory, budget is %.3f GB", need / 1e9,
+                      budget / 1e9);
+        return fail(nullptr, ELAS3D_ENOMEM, buf);
+    }
+
+    elas3d_ctx* c = new elas3d_ctx();
+    c->device = dev;
+    c->opt = opt;
+    c->d = Dims{nx, ny, nz, (int)n};
+    c->nphase = nphase;
+    c->nrhs = nrhs;
+    c->strain.assign(strain, strain + 6 * nrhs);
+    c->solved.assign(nrhs, 0);
+    c->bytes = need;
+    c->geom = e3d::op_geometry(c->d, 0);
+    c->partial_stride = 65536;
+
+    auto bail = [&](hipError_t e, const char* what) {
+        std::string m = std::string(what) + ": " + hipGetErrorString(e);
+        free_ctx(c);
+        return fail(nullptr, ELAS3D_EDEVICE, m);
+    };
+#define SETUPCHK(expr)                          \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return bail(e_, #expr); \
+    } while (0)
+
+    if (opt.stream) {
+        c->stream = (hipStream_t)opt.stream;
+    } else {
+        SETUPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    const size_t N = (size_t)n;
+    SETUPCHK(hipMalloc(&c->phase, 4 * N));
+    SETUPCHK(hipMalloc(&c->coef, 8 * (size_t)nphase * e3d::kCoefStride));
+    SETUPCHK(hipMalloc(&c->diag, 8 * (size_t)nphase * e3d::kDiagStride));
+    SETUPCHK(hipMalloc(&c->solid, (size_t)nphase));
+    SETUPCHK(hipMalloc(&c->sig, 8 * (size_t)nrhs * nphase * e3d::kSigStride));
+    SETUPCHK(hipMalloc(&c->b, 8 * 3 * N * nrhs));
+    SETUPCHK(hipMalloc(&c->w, 8 * 3 * N * nrhs));
+    SETUPCHK(hipMalloc(&c->work, 8 * 15 * N));
+    SETUPCHK(hipMalloc(&c->minv, 8 * 6 * N));
+    SETUPCHK(hipMalloc(&c->partials, 8 * (size_t)kPartialValues * c->partial_stride));
+    SETUPCHK(hipMalloc(&c->norms, 8 * 2 * (size_t)nrhs));
+    SETUPCHK(hipMalloc(&c->dscratch, 8 * 16));
+    SETUPCHK(hipMalloc(&c->dflag, sizeof(int) * 4));
+    SETUPCHK(hipMalloc(&c->S, sizeof(Scalars)));
+    SETUPCHK(hipHostMalloc(&c->hS, 2 * sizeof(Scalars), hipHostMallocDefault));
+    SETUPCHK(hipHostMalloc(&c->hscratch, 16 * sizeof(double), hipHostMallocDefault));
+
+    SETUPCHK(hipMemcpyAsync(c->phase, phase, 4 * N,
+                            opt.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            c->stream));
+    if (opt.inputs_on_device) {
+        SETUPCHK(hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+        SETUPCHK(e3d::launch_phase_check(c->stream, c->phase, (int)n, nphase, c->dflag));
+        int bad = 0;
+        SETUPCHK(hipMemcpyAsync(&bad, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        SETUPCHK(hipStreamSynchronize(c->stream));
+        if (bad) {
+            free_ctx(c);
+            return fail(nullptr, ELAS3D_EBADARG, std::to_string(bad) + " phase ids out of range");
+        }
+    }
+    std::vector<double> coef, diag, sig;
+    std::vector<uint8_t> solid;
+    build_tables(C, nphase, strain, nrhs, coef, diag, solid, sig);
+    SETUPCHK(hipMemcpyAsync(c->coef, coef.data(), 8 * coef.size(), hipMemcpyHostToDevice, c->stream));
+    SETUPCHK(hipMemcpyAsync(c->diag, diag.data(), 8 * diag.size(), hipMemcpyHostToDevice, c->stream));
+    SETUPCHK(hipMemcpyAsync(c->solid, solid.data(), solid.size(), hipMemcpyHostToDevice, c->stream));
+    SETUPCHK(hipMemcpyAsync(c->sig, sig.data(), 8 * sig.size(), hipMemcpyHostToDevice, c->stream));
+    for (int r = 0; r < nrhs; ++r) {
+        double* bp[3] = {c->plane(c->b, 3 * r), c->plane(c->b, 3 * r + 1), c->plane(c->b, 3 * r + 2)};
+        SETUPCHK(e3d::launch_load(c->stream, c->d, c->phase,
+                                  c->sig + (size_t)r * nphase * e3d::kSigStride, bp, c->partials,
+                                  c->norms + 2 * r, kSweepBlocks));
+    }
+    double* M[6];
+    c->minv_planes(M);
+    SETUPCHK(e3d::launch_precond(c->stream, c->d, c->phase, c->tables(),
+                                 opt.preconditioner == ELAS3D_PRECOND_NONE ? 1 : 0, M));
+    // (host input arrays must not be read after return)
+    SETUPCHK(hipStreamSynchronize(c->stream));
+    (void)t0;
+#undef SETUPCHK
+    *out = c;
+    return 0;
+}
+
+int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3d_info* info)
+{
+    if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(ctx, ELAS3D_EBADARG, "tol must be finite and >= 0");
+    if (maxit < 0) return fail(ctx, ELAS3D_EBADARG, "maxit must be >= 0");
+    if (nrhs < 1 || nrhs > ctx->nrhs)
+        return fail(ctx, ELAS3D_EBADARG, "nrhs must be in [1, nrhs of setup]");
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->nrhs = nrhs;
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    auto t0 = std::chrono::steady_clock::now();
+    int worst = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        int rc = solve_case(ctx, r, tol, maxit, info);
+        if (rc < 0) return rc;
+        worst = std::max(worst, rc);
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
+        // two fused sweeps: direction+operator (read z, h, w, phase; write h, w, Ah)
+        // and update+precondition (read g, Ah, M^-1; write g, z)
+        info->bytes_per_iter = (double)ctx->N() * ((6 * 24.0 + 4.0) + (4 * 24.0 + 48.0));
+    }
+    return worst;
+}
+
+int elas3d_stress(elas3d_ctx* ctx, int32_t rhs, double* sigma_voxel, double* sigma_avg,
+                  double* u_node, double* energy)
+{
+    if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (rhs < 0 || rhs >= ctx->nrhs) return fail(ctx, ELAS3D_EBADARG, "rhs out of range");
+    if (!ctx->solved[rhs]) return fail(ctx, ELAS3D_EORDER, "load case not solved yet");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const size_t N = ctx->N();
+    Fields f = ctx->fields(rhs);
+    double* sigd[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (sigma_voxel) {
+        double* base = ctx->opt.outputs_on_device ? sigma_voxel : ctx->work;  // work: 15N >= 6N
+        for (int q = 0; q < 6; ++q) sigd[q] = base + q * N;
+    }
+    HIPCHK(ctx, e3d::launch_stress(ctx->stream, ctx->d, ctx->phase, ctx->tables(),
+                                   ctx->strain.data() + 6 * rhs, f, sigma_voxel ? sigd : nullptr,
+                                   ctx->partials, ctx->dscratch, kSweepBlocks));
+    if (sigma_voxel && !ctx->opt.outputs_on_device)
+        HIPCHK(ctx, hipMemcpyAsync(sigma_voxel, ctx->work, 8 * 6 * N, hipMemcpyDeviceToHost, ctx->stream));
+    if (u_node) {
+        double* base = ctx->opt.outputs_on_device ? u_node : ctx->work + 6 * N;
+        double* ud[3] = {base, base + N, base + 2 * N};
+        HIPCHK(ctx, e3d::launch_total_displacement(ctx->stream, ctx->d, ctx->strain.data() + 6 * rhs, f, ud));
+        if (!ctx->opt.outputs_on_device)
+            HIPCHK(ctx, hipMemcpyAsync(u_node, base, 8 * 3 * N, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hscratch, ctx->dscratch, 8 * 7, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (sigma_avg)
+        for (int q = 0; q < 6; ++q) sigma_avg[q] = ctx->hscratch[q] / (double)N;
+    if (energy) *energy = ctx->hscratch[6];
+    return 0;
+}
+
+int elas3d_apply(elas3d_ctx* ctx, const double* x, double* y)
+{
+    if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (!x || !y) return fail(ctx, ELAS3D_EBADARG, "x or y is NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const size_t N = ctx->N();
+    const double* xd = x;
+    double* yd = y;
+    if (!ctx->opt.outputs_on_device) {
+        HIPCHK(ctx, hipMemcpyAsync(ctx->work, x, 8 * 3 * N, hipMemcpyHostToDevice, ctx->stream));
+        xd = ctx->work;
+        yd = ctx->work + 3 * N;
+    }
+    const double* xp[3] = {xd, xd + N, xd + 2 * N};
+    double* yp[3] = {yd, yd + N, yd + 2 * N};
+    HIPCHK(ctx, e3d::launch_apply(ctx->stream, ctx->d, ctx->geom, ctx->phase, ctx->tables(), xp, yp,
+                                  nullptr, ctx->partials, nullptr));
+    if (!ctx->opt.outputs_on_device)
+        HIPCHK(ctx, hipMemcpyAsync(y, yd, 8 * 3 * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int elas3d_get_load(elas3d_ctx* ctx, int32_t rhs, double* b)
+{
+    if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (rhs < 0 || rhs >= ctx->nrhs || !b) return fail(ctx, ELAS3D_EBADARG, "bad rhs or NULL output");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipMemcpyAsync(b, ctx->plane(ctx->b, 3 * rhs), 8 * 3 * ctx->N(), copy_kind(ctx, false),
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int elas3d_get_precond(elas3d_ctx* ctx, double* minv)
+{
+    if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (!minv) return fail(ctx, ELAS3D_EBADARG, "NULL output");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipMemcpyAsync(minv, ctx->minv, 8 * 6 * ctx->N(), copy_kind(ctx, false), ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w)
+{
+    if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (rhs < 0 || rhs >= ctx->nrhs || !w) return fail(ctx, ELAS3D_EBADARG, "bad rhs or NULL output");
+    if (!ctx->solved[rhs]) return fail(ctx, ELAS3D_EORDER, "load case not solved yet");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipMemcpyAsync(w, ctx->plane(ctx->w, 3 * rhs), 8 * 3 * ctx->N(), copy_kind(ctx, false),
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+void elas3d_destroy(elas3d_ctx* ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    free_ctx(ctx);
+}
+
+}  // extern "C"

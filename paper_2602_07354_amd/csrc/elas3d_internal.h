@@ -1,0 +1,105 @@
+// Internal declarations shared by the kernels and the host runtime of
+// libelas3d.  Not part of the public ABI (include/elas3d.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace e3d {
+
+// Per-phase table strides (doubles).  The operator table holds the 21
+// upper-triangular entries of the phase's 6x6 Voigt stiffness, the
+// preconditioner table the four 3x3 symmetric pieces of the corner block,
+// the load table C_p E_hat for each load case.
+constexpr int kCoefStride = 24;
+constexpr int kDiagStride = 24;
+constexpr int kSigStride = 8;
+
+// Problem size.  N = nx*ny*nz < 2^31, so node indices fit in int.
+struct Dims {
+    int nx, ny, nz;
+    int n;
+};
+
+// Device-resident scalars of one PCG run (Algorithm 2).  Written only by
+// the single-block finalize kernels; read by the sweep kernels.
+struct Scalars {
+    double gg;      // z.g of the current iterate
+    double gg0;     // z0.g0 (reference of the paper's criterion)
+    double hAh;     // h.Ah of the current direction
+    double lambda;  // step size; applied to w lazily by the next direction sweep
+    double gamma;   // Fletcher-Reeves coefficient for the next direction
+    double rr;      // g.g
+    double bnorm2;  // ||b||^2 of the case
+    double bref2;   // sum_e ||K_e u^E_e||^2 (scale for the zero-load test)
+    double tol;
+    double rr_true;  // ||A w + b||^2 from the last residual sweep
+    int it;          // iterations done
+    int maxit;       // iteration cap of this run
+    int done;        // nonzero: every later sweep returns at once
+    int status;      // 0 converged, 1 not converged, 2 breakdown
+    int mode;        // 0 residual criterion, 1 paper criterion
+    int cur;         // which of the two direction buffers holds the current h
+    int pending;     // 1 while w still owes -lambda*h of the last iteration
+    int pad;
+};
+
+// Field pointers of one load case (FP64 SoA planes).
+struct Fields {
+    double* w[3];
+    double* g[3];
+    double* z[3];
+    double* h0[3];
+    double* h1[3];
+    double* Ah[3];
+    const double* b[3];
+};
+
+struct Tables {
+    const double* coef;  // nphase * kCoefStride
+    const double* diag;  // nphase * kDiagStride
+    const uint8_t* solid;  // nphase: 1 if the phase has stiffness
+};
+
+// Kernel launch geometry of the tiled operator sweep.
+struct OpGeom {
+    int tiles_x, tiles_y, zchunks, kz;
+    int blocks;
+};
+
+OpGeom op_geometry(const Dims& d, int kz_hint);
+
+// ---- launchers (elas3d_kernels.hip) -------------------------------------
+// Every launcher enqueues on `st` and returns the hipError_t of the launch.
+
+hipError_t launch_load(hipStream_t st, const Dims& d, const int32_t* phase, const double* sig,
+                       double* const b[3], double* partials, double* out2 /* bnorm2, bref2 */,
+                       int max_blocks);
+hipError_t launch_precond(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
+                          int identity, double* const minv[6]);
+// norms2: device {||b||^2, ||b||_ref^2} of the case (zero-load test).
+hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const Fields& f, double* const minv[6],
+                           int fresh, int from_residual, Scalars* S, double* partials,
+                           int max_blocks, const double* norms2);
+hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
+                                     const int32_t* phase, const Tables& t, const Fields& f,
+                                     Scalars* S, double* partials);
+hipError_t launch_update_precond(hipStream_t st, const Dims& d, const Fields& f,
+                                 double* const minv[6], Scalars* S, double* partials,
+                                 int max_blocks);
+hipError_t launch_final_update(hipStream_t st, const Dims& d, const Fields& f, Scalars* S);
+// y = A x (+ add when add[0] != nullptr); ||y||^2 into *norm2 when norm2 != nullptr.
+hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
+                        const Tables& t, const double* const x[3], double* const y[3],
+                        const double* const add[3], double* partials, double* norm2);
+// sums7: device {sum sigma_r (6), energy}; sig may be nullptr.  Uses f.w.
+hipError_t launch_stress(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
+                         const double* strain6, const Fields& f, double* const sig[6],
+                         double* partials, double* sums7, int max_blocks);
+hipError_t launch_total_displacement(hipStream_t st, const Dims& d, const double* strain6,
+                                     const Fields& f, double* const u[3]);
+// Adds to *bad the number of ids outside [0, nphase).
+hipError_t launch_phase_check(hipStream_t st, const int32_t* phase, int n, int nphase, int* bad);
+
+}  // namespace e3d

@@ -1,0 +1,1053 @@
+// gfx950 kernels of the matrix-free point-block Jacobi PCG for periodic voxel
+// elasticity (ELAS3D-Xtal, arXiv 2602.07354, Sec. 2.1.2, Algorithm 2).
+//
+// Element operator.  For a unit voxel with trilinear shape functions the
+// product K_e u_e (Eq. discrete_energy) is evaluated without forming the
+// 24x24 K_e.  Writing each displacement component in the L2-orthogonal basis
+// {1, X, Y, Z, XY, XZ, YZ, XYZ} (X = x - 1/2, ...) of the voxel, the strain
+// lives in span{1, X, Y, Z, XY, XZ, YZ} with weights 1, 1/12, 1/144, so the
+// element energy splits into seven small quadratic forms of C.  The basis
+// coefficients are an 8-point +-1 transform (butterfly) of the nodal values;
+// the nodal forces are the adjoint transform of the mode stresses.  This is
+// exactly K_e u_e (same bilinear form, 2x2x2 Gauss being exact) at about
+// 330 flops per voxel instead of 1152.
+//
+// Sweep structure.  A workgroup of TX x TY lanes owns an (x,y) column of
+// (TX-1) x (TY-1) nodes and marches through a chunk of z planes.  Lane
+// (tx,ty) evaluates the voxel column whose upper corner is its own node, so
+// one element layer per step; node planes are staged once in LDS and shared
+// by the four voxels around each node (neighbour-plane reuse), forces of the
+// lower face are carried in registers to the next step (z coupling) and the
+// in-plane coupling goes through LDS.  The ring of voxels on the low x/y edge
+// of a column is evaluated by two workgroups.
+//
+// Reductions are two-stage and deterministic: a fixed-order in-block tree
+// writes one partial per block, a single-block kernel sums the partials in
+// fixed order and updates the device-resident PCG scalars.
+#include "elas3d_internal.h"
+
+namespace e3d {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kFinThreads = 256;
+
+// Index of (r,c) in the packed upper triangle of a symmetric 6x6.
+__host__ __device__ constexpr int ut(int r, int c)
+{
+    return r <= c ? r * 6 - (r * (r - 1)) / 2 + (c - r) : c * 6 - (c * (c - 1)) / 2 + (r - c);
+}
+
+// ----------------------------------------------------------------- element
+
+// In-place +-1 transform of 8 corner values (corner a = ax + 2ay + 4az).
+// Output slot mu holds sum_a prod_{d in mu} s_d(a) v_a, s = 2 a_d - 1; slot 1
+// is X, 2 Y, 3 XY, 4 Z, 5 XZ, 6 YZ, 7 XYZ (slot 0, the plain sum, is unused).
+__device__ __forceinline__ void fwd8(double* v)
+{
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            if (!(a & bit)) {
+                const double lo = v[a], hi = v[a | bit];
+                v[a] = lo + hi;
+                v[a | bit] = hi - lo;
+            }
+}
+
+// Adjoint (transpose) of fwd8.
+__device__ __forceinline__ void adj8(double* v)
+{
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            if (!(a & bit)) {
+                const double lo = v[a], hi = v[a | bit];
+                v[a] = lo - hi;
+                v[a | bit] = lo + hi;
+            }
+}
+
+// t = C[sup,sup] e for a support of the 6 Voigt components.
+template <int N>
+__device__ __forceinline__ void contract(const double* Cu, const int (&sup)[N], const double* e,
+                                         double* t)
+{
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double acc = Cu[ut(sup[r], sup[0])] * e[0];
+#pragma unroll
+        for (int c = 1; c < N; ++c) acc = fma(Cu[ut(sup[r], sup[c])], e[c], acc);
+        t[r] = acc;
+    }
+}
+
+enum { MX = 1, MY = 2, MXY = 3, MZ = 4, MXZ = 5, MYZ = 6, MXYZ = 7 };
+
+// f = K_e u for one voxel with packed stiffness Cu (21 entries).  u[c][a] is
+// destroyed.  f[c][a]: force component c on corner a.
+__device__ __forceinline__ void element_force(const double* Cu, double (&u)[3][8], double (&f)[3][8])
+{
+    fwd8(u[0]);
+    fwd8(u[1]);
+    fwd8(u[2]);
+    // Energy weights of the modes folded into the coefficients: the constant
+    // strain mode carries (1/4)^2, the linear ones (1/2)^2/12, the bilinear
+    // ones 1/144 (coefficient scales of the transform times the L2 weights).
+    constexpr double s1 = 1.0 / 16.0, s2 = 1.0 / 48.0, s3 = 1.0 / 144.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        u[c][MX] *= s1;
+        u[c][MY] *= s1;
+        u[c][MZ] *= s1;
+        u[c][MXY] *= s2;
+        u[c][MXZ] *= s2;
+        u[c][MYZ] *= s2;
+        u[c][MXYZ] *= s3;
+    }
+    double g[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) g[c][a] = 0.0;
+
+    // constant mode: full 6-component strain
+    {
+        constexpr int sup[6] = {0, 1, 2, 3, 4, 5};
+        const double e[6] = {u[0][MX], u[1][MY], u[2][MZ], u[1][MZ] + u[2][MY], u[0][MZ] + u[2][MX],
+                             u[0][MY] + u[1][MX]};
+        double t[6];
+        contract<6>(Cu, sup, e, t);
+        g[0][MX] += t[0];
+        g[1][MY] += t[1];
+        g[2][MZ] += t[2];
+        g[1][MZ] += t[3];
+        g[2][MY] += t[3];
+        g[0][MZ] += t[4];
+        g[2][MX] += t[4];
+        g[0][MY] += t[5];
+        g[1][MX] += t[5];
+    }
+    // X mode: (yy, zz, yz, xz, xy)
+    {
+        constexpr int sup[5] = {1, 2, 3, 4, 5};
+        const double e[5] = {u[1][MXY], u[2][MXZ], u[1][MXZ] + u[2][MXY], u[0][MXZ], u[0][MXY]};
+        double t[5];
+        contract<5>(Cu, sup, e, t);
+        g[1][MXY] += t[0];
+        g[2][MXZ] += t[1];
+        g[1][MXZ] += t[2];
+        g[2][MXY] += t[2];
+        g[0][MXZ] += t[3];
+        g[0][MXY] += t[4];
+    }
+    // Y mode: (xx, zz, yz, xz, xy)
+    {
+        constexpr int sup[5] = {0, 2, 3, 4, 5};
+        const double e[5] = {u[0][MXY], u[2][MYZ], u[1][MYZ], u[0][MYZ] + u[2][MXY], u[1][MXY]};
+        double t[5];
+        contract<5>(Cu, sup, e, t);
+        g[0][MXY] += t[0];
+        g[2][MYZ] += t[1];
+        g[1][MYZ] += t[2];
+        g[0][MYZ] += t[3];
+        g[2][MXY] += t[3];
+        g[1][MXY] += t[4];
+    }
+    // Z mode: (xx, yy, yz, xz, xy)
+    {
+        constexpr int sup[5] = {0, 1, 3, 4, 5};
+        const double e[5] = {u[0][MXZ], u[1][MYZ], u[2][MYZ], u[2][MXZ], u[0][MYZ] + u[1][MXZ]};
+        double t[5];
+        contract<5>(Cu, sup, e, t);
+        g[0][MXZ] += t[0];
+        g[1][MYZ] += t[1];
+        g[2][MYZ] += t[2];
+        g[2][MXZ] += t[3];
+        g[0][MYZ] += t[4];
+        g[1][MXZ] += t[4];
+    }
+    // YZ mode: (xx, xz, xy)
+    {
+        constexpr int sup[3] = {0, 4, 5};
+        const double e[3] = {u[0][MXYZ], u[2][MXYZ], u[1][MXYZ]};
+        double t[3];
+        contract<3>(Cu, sup, e, t);
+        g[0][MXYZ] += t[0];
+        g[2][MXYZ] += t[1];
+        g[1][MXYZ] += t[2];
+    }
+    // XZ mode: (yy, yz, xy)
+    {
+        constexpr int sup[3] = {1, 3, 5};
+        const double e[3] = {u[1][MXYZ], u[2][MXYZ], u[0][MXYZ]};
+        double t[3];
+        contract<3>(Cu, sup, e, t);
+        g[1][MXYZ] += t[0];
+        g[2][MXYZ] += t[1];
+        g[0][MXYZ] += t[2];
+    }
+    // XY mode: (zz, yz, xz)
+    {
+        constexpr int sup[3] = {2, 3, 4};
+        const double e[3] = {u[2][MXYZ], u[1][MXYZ], u[0][MXYZ]};
+        double t[3];
+        contract<3>(Cu, sup, e, t);
+        g[2][MXYZ] += t[0];
+        g[1][MXYZ] += t[1];
+        g[0][MXYZ] += t[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        adj8(g[c]);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) f[c][a] = g[c][a];
+    }
+}
+
+__device__ __forceinline__ void load_coef(const double* __restrict__ coef, int p, double (&Cu)[21])
+{
+    const double2* src = reinterpret_cast<const double2*>(coef + (size_t)p * kCoefStride);
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        const double2 v = src[q];
+        Cu[2 * q] = v.x;
+        Cu[2 * q + 1] = v.y;
+    }
+    Cu[20] = coef[(size_t)p * kCoefStride + 20];
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Fixed-order block sum of NV values; thread 0 writes partials[k*stride + bid].
+template <int NV, int NT>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* partials, int stride, int bid)
+{
+    __shared__ double red[NV][NT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) red[k][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = red[k][0];
+            for (int w = 1; w < NT / 64; ++w) s += red[k][w];
+            partials[(size_t)k * stride + bid] = s;
+        }
+    }
+}
+
+enum FinKind { FIN_STORE = 0, FIN_INIT = 1, FIN_DIRECTION = 2, FIN_UPDATE = 3 };
+
+// Sums NV partial vectors (nblocks each) in fixed order, then:
+//   FIN_STORE     out[k] = total[k]
+//   FIN_INIT      start of a PCG run (gg, rr)
+//   FIN_DIRECTION step size from h.Ah (Algorithm 2, B)
+//   FIN_UPDATE    gg, rr after the update; convergence; Fletcher-Reeves gamma (D, E)
+template <int NV>
+__global__ void __launch_bounds__(kFinThreads) finalize_kernel(int kind, const double* partials,
+                                                               int stride, int nblocks, Scalars* S,
+                                                               double* out, const double* norms)
+{
+    __shared__ double red[NV][kFinThreads / 64];
+    // sweeps enqueued after the stop flag was raised did no work: leave the
+    // scalars of the finished run untouched
+    if ((kind == FIN_DIRECTION || kind == FIN_UPDATE) && S->done) return;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kFinThreads) s += partials[(size_t)k * stride + b];
+        v[k] = s;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) red[k][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double tot[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = red[k][0];
+        for (int w = 1; w < kFinThreads / 64; ++w) s += red[k][w];
+        tot[k] = s;
+    }
+    if (kind == FIN_STORE) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] = tot[k];
+        return;
+    }
+    if (kind == FIN_INIT) {
+        // tot = {z.g, g.g}; norms = {||b||^2, ||b||_ref^2} of the case
+        S->gg = tot[0];
+        S->gg0 = tot[0];
+        S->rr = tot[NV > 1 ? 1 : 0];
+        S->bnorm2 = norms[0];
+        S->bref2 = norms[1];
+        S->lambda = 0.0;
+        S->gamma = 0.0;
+        S->cur = 0;
+        S->pending = 0;
+        S->done = 0;
+        S->status = 1;
+        // zero load (homogeneous or all-void grid): nothing to solve
+        if (S->bnorm2 <= 1e-28 * S->bref2) {
+            S->done = 1;
+            S->status = 0;
+        } else if (S->it >= S->maxit) {
+            S->done = 1;
+        }
+        return;
+    }
+    if (kind == FIN_DIRECTION) {
+        const double hAh = tot[0];
+        S->hAh = hAh;
+        S->pending = 0;  // the sweep applied the previous step to w
+        S->cur ^= 1;     // the sweep wrote the new direction to the other buffer
+        if (!(hAh > 0.0) || !isfinite(hAh)) {
+            S->status = 2;
+            S->done = 1;
+            S->lambda = 0.0;
+        } else {
+            S->lambda = S->gg / hAh;
+        }
+        return;
+    }
+    if (kind == FIN_UPDATE) {
+        const double gg_new = tot[0];
+        const double rr = tot[NV > 1 ? 1 : 0];
+        S->it += 1;
+        S->pending = 1;
+        S->rr = rr;
+        const double gg_last = S->gg;
+        S->gg = gg_new;
+        bool conv;
+        if (S->mode == 1)
+            conv = S->gg0 > 0.0 && sqrt(fabs(gg_new / S->gg0)) < S->tol;
+        else
+            conv = rr <= S->tol * S->tol * S->bnorm2;
+        if (!isfinite(gg_new) || !isfinite(rr)) {
+            S->status = 2;
+            S->done = 1;
+        } else if (conv) {
+            S->status = 0;
+            S->done = 1;
+        } else if (S->it >= S->maxit) {
+            S->status = 1;
+            S->done = 1;
+        }
+        S->gamma = gg_new / gg_last;
+        return;
+    }
+}
+
+// ------------------------------------------------------------- node sweeps
+
+__device__ __forceinline__ void node_ijk(int m, const Dims& d, int& i, int& j, int& k)
+{
+    const int plane = d.nx * d.ny;
+    k = m / plane;
+    const int r = m - k * plane;
+    j = r / d.nx;
+    i = r - j * d.nx;
+}
+
+// b_m = sum over the 8 voxels around node m of the force that voxel's
+// uniform stress C_p E_hat exerts on its corner: (sigma s_a)/4, s_a = 2a-1
+// (the element vector K_e u^E_e of the affine field, Eq. affine_strain).
+__global__ void __launch_bounds__(kBlock) load_kernel(Dims d, const int32_t* __restrict__ phase,
+                                                      const double* __restrict__ sig, double* bx,
+                                                      double* by, double* bz, double* partials,
+                                                      int stride)
+{
+    double acc[2] = {0.0, 0.0};
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        int i, j, k;
+        node_ijk(m, d, i, j, k);
+        double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+            const int ii = i - ax < 0 ? d.nx - 1 : i - ax;
+            const int jj = j - ay < 0 ? d.ny - 1 : j - ay;
+            const int kk = k - az < 0 ? d.nz - 1 : k - az;
+            const double* s = sig + (size_t)phase[ii + d.nx * (jj + d.ny * kk)] * kSigStride;
+            const double sx = ax ? 1.0 : -1.0, sy = ay ? 1.0 : -1.0, sz = az ? 1.0 : -1.0;
+            f0 += s[0] * sx + s[5] * sy + s[4] * sz;
+            f1 += s[5] * sx + s[1] * sy + s[3] * sz;
+            f2 += s[4] * sx + s[3] * sy + s[2] * sz;
+        }
+        f0 *= 0.25;
+        f1 *= 0.25;
+        f2 *= 0.25;
+        bx[m] = f0;
+        by[m] = f1;
+        bz[m] = f2;
+        acc[0] += f0 * f0 + f1 * f1 + f2 * f2;
+        // uncancelled element forces of voxel m: sum_a |sigma s_a / 4|^2 = |sigma|_F^2 / 2
+        const double* s = sig + (size_t)phase[m] * kSigStride;
+        acc[1] += 0.5 * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
+                         2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
+    }
+    block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
+}
+
+// Inverse of the assembled diagonal 3x3 block (Eq. block_precond).  The
+// corner block of a phase is D + sx sy Oxy + sx sz Oxz + sy sz Oyz (four
+// symmetric pieces per phase, ordered xx, yy, zz, yz, xz, xy); nodes whose
+// eight voxels are all void get 0, plain CG gets I on the other nodes.
+__global__ void __launch_bounds__(kBlock) precond_kernel(Dims d, const int32_t* __restrict__ phase,
+                                                         const double* __restrict__ diag,
+                                                         const uint8_t* __restrict__ solid,
+                                                         int identity, double* m0, double* m1,
+                                                         double* m2, double* m3, double* m4,
+                                                         double* m5)
+{
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        int i, j, k;
+        node_ijk(m, d, i, j, k);
+        double A[6] = {0, 0, 0, 0, 0, 0};
+        int nsolid = 0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+            const int ii = i - ax < 0 ? d.nx - 1 : i - ax;
+            const int jj = j - ay < 0 ? d.ny - 1 : j - ay;
+            const int kk = k - az < 0 ? d.nz - 1 : k - az;
+            const int p = phase[ii + d.nx * (jj + d.ny * kk)];
+            nsolid += solid[p];
+            const double* t = diag + (size_t)p * kDiagStride;
+            const double sxy = (ax == ay) ? 1.0 : -1.0;
+            const double sxz = (ax == az) ? 1.0 : -1.0;
+            const double syz = (ay == az) ? 1.0 : -1.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) A[q] += t[q] + sxy * t[6 + q] + sxz * t[12 + q] + syz * t[18 + q];
+        }
+        double r[6] = {0, 0, 0, 0, 0, 0};
+        if (nsolid > 0) {
+            if (identity) {
+                r[0] = r[1] = r[2] = 1.0;
+            } else {
+                // symmetric [a b c; b d e; c e f] with a=xx d=yy f=zz e=yz c=xz b=xy
+                const double a_ = A[0], d_ = A[1], f_ = A[2], e_ = A[3], c_ = A[4], b_ = A[5];
+                const double c00 = d_ * f_ - e_ * e_;
+                const double c01 = c_ * e_ - b_ * f_;
+                const double c02 = b_ * e_ - c_ * d_;
+                const double c11 = a_ * f_ - c_ * c_;
+                const double c12 = b_ * c_ - a_ * e_;
+                const double c22 = a_ * d_ - b_ * b_;
+                const double inv = 1.0 / (a_ * c00 + b_ * c01 + c_ * c02);
+                r[0] = c00 * inv;
+                r[1] = c11 * inv;
+                r[2] = c22 * inv;
+                r[3] = c12 * inv;
+                r[4] = c02 * inv;
+                r[5] = c01 * inv;
+            }
+        }
+        m0[m] = r[0];
+        m1[m] = r[1];
+        m2[m] = r[2];
+        m3[m] = r[3];
+        m4[m] = r[4];
+        m5[m] = r[5];
+    }
+}
+
+__device__ __forceinline__ void apply_minv(const double* const* M, int m, double g0, double g1,
+                                           double g2, double& z0, double& z1, double& z2)
+{
+    const double xx = M[0][m], yy = M[1][m], zz = M[2][m], yz = M[3][m], xz = M[4][m], xy = M[5][m];
+    z0 = xx * g0 + xy * g1 + xz * g2;
+    z1 = xy * g0 + yy * g1 + yz * g2;
+    z2 = xz * g0 + yz * g1 + zz * g2;
+}
+
+struct Minv {
+    const double* m[6];
+};
+
+// Start (or restart) of a PCG run: g = b (or the residual already in g),
+// z = M^-1 g, current direction h = 0, w = 0 on a fresh start.
+__global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, Fields f, Minv M, int fresh,
+                                                          int from_residual, double* partials,
+                                                          int stride)
+{
+    double acc[2] = {0.0, 0.0};
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        double g0, g1, g2;
+        if (from_residual) {
+            g0 = f.g[0][m];
+            g1 = f.g[1][m];
+            g2 = f.g[2][m];
+        } else {
+            g0 = f.b[0][m];
+            g1 = f.b[1][m];
+            g2 = f.b[2][m];
+            f.g[0][m] = g0;
+            f.g[1][m] = g1;
+            f.g[2][m] = g2;
+        }
+        double z0, z1, z2;
+        apply_minv(M.m, m, g0, g1, g2, z0, z1, z2);
+        f.z[0][m] = z0;
+        f.z[1][m] = z1;
+        f.z[2][m] = z2;
+        f.h0[0][m] = 0.0;
+        f.h0[1][m] = 0.0;
+        f.h0[2][m] = 0.0;
+        if (fresh) {
+            f.w[0][m] = 0.0;
+            f.w[1][m] = 0.0;
+            f.w[2][m] = 0.0;
+        }
+        acc[0] += z0 * g0 + z1 * g1 + z2 * g2;
+        acc[1] += g0 * g0 + g1 * g1 + g2 * g2;
+    }
+    block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
+}
+
+// Algorithm 2, C-D: g -= lambda Ah, z = M^-1 g, partial z.g and g.g.
+// (w -= lambda h is deferred to the next direction sweep, which reads h anyway.)
+__global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, Fields f, Minv M,
+                                                                const Scalars* S, double* partials,
+                                                                int stride)
+{
+    if (S->done) return;
+    const double lam = S->lambda;
+    double acc[2] = {0.0, 0.0};
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        const double g0 = fma(-lam, f.Ah[0][m], f.g[0][m]);
+        const double g1 = fma(-lam, f.Ah[1][m], f.g[1][m]);
+        const double g2 = fma(-lam, f.Ah[2][m], f.g[2][m]);
+        f.g[0][m] = g0;
+        f.g[1][m] = g1;
+        f.g[2][m] = g2;
+        double z0, z1, z2;
+        apply_minv(M.m, m, g0, g1, g2, z0, z1, z2);
+        f.z[0][m] = z0;
+        f.z[1][m] = z1;
+        f.z[2][m] = z2;
+        acc[0] += z0 * g0 + z1 * g1 + z2 * g2;
+        acc[1] += g0 * g0 + g1 * g1 + g2 * g2;
+    }
+    block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
+}
+
+// The step size of the last iteration still owed to w.
+__global__ void __launch_bounds__(kBlock) final_update_kernel(Dims d, Fields f, const Scalars* S)
+{
+    if (!S->pending) return;
+    const double lam = S->lambda;
+    double* const* h = S->cur ? f.h1 : f.h0;
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f.w[c][m] = fma(-lam, h[c][m], f.w[c][m]);
+    }
+}
+
+// ------------------------------------------------------- tiled operator sweep
+
+struct OpArgs {
+    Dims d;
+    int tiles_x, tiles_y, kz;
+    const int32_t* phase;
+    const double* coef;
+    // operator input: x (apply) or z, h_old (fused direction update)
+    const double* x[3];
+    const double* z[3];
+    double* h0[3];
+    double* h1[3];
+    double* w[3];
+    // output y = A x (+ add)
+    double* y[3];
+    const double* add[3];
+    const Scalars* S;
+    double* partials;
+    int want_norm;
+};
+
+// FUSED = false: y = A x (+ add), optional ||y||^2 partials.
+// FUSED = true : Algorithm 2 steps E and A of one iteration in a single sweep:
+//   h_new = z + gamma h_old (written to the other direction buffer),
+//   w -= lambda h_old (the previous step, deferred), Ah = A h_new and the
+//   partial h_new.Ah.
+template <int TX, int TY, bool FUSED>
+__global__ void __launch_bounds__(TX* TY) op_kernel(OpArgs a)
+{
+    constexpr int NT = TX * TY, LX = TX + 1, LY = TY + 1;
+    __shared__ double sn[3][LY * LX];
+    __shared__ double sf[3][3][NT];
+
+    double gam = 0.0, lam = 0.0;
+    const double* hold[3] = {nullptr, nullptr, nullptr};
+    double* hnew[3] = {nullptr, nullptr, nullptr};
+    if constexpr (FUSED) {
+        if (a.S->done) return;
+        gam = a.S->gamma;
+        lam = a.S->lambda;
+        const int cur = a.S->cur;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            hold[c] = cur ? a.h1[c] : a.h0[c];
+            hnew[c] = cur ? a.h0[c] : a.h1[c];
+        }
+    }
+
+    const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+    const int plane = nx * ny;
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    const int ntiles = a.tiles_x * a.tiles_y;
+    const int bz = blockIdx.x / ntiles, t = blockIdx.x - bz * ntiles;
+    const int by = t / a.tiles_x, bx = t - by * a.tiles_x;
+    const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
+    const int k0 = bz * a.kz;
+    const int kend = min(k0 + a.kz, nz);
+
+    const int gi = i0 + tx, gj = j0 + ty;
+    const int own = (gi % nx) + nx * (gj % ny);
+    const int elem = ((gi + nx - 1) % nx) + nx * ((gj + ny - 1) % ny);
+    const bool out_ok = (tx < TX - 1) && (ty < TY - 1) && (gi < nx) && (gj < ny);
+    const bool has_halo = tid < LX + TY;
+    int hslot = 0, hoff = 0;
+    if (has_halo) {
+        const int hx = tid < LX ? tid : 0;
+        const int hy = tid < LX ? 0 : tid - LX + 1;
+        hslot = hy * LX + hx;
+        hoff = ((i0 - 1 + hx + nx) % nx) + nx * ((j0 - 1 + hy + ny) % ny);
+    }
+    const int oslot = (ty + 1) * LX + (tx + 1);
+
+    double ov[3], hv[3], oh[3], ow[3];
+    auto fetch = [&](int kk) {
+        const int kw = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
+        const int base = kw * plane;
+        if constexpr (FUSED) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                oh[c] = hold[c][base + own];
+                ov[c] = fma(gam, oh[c], a.z[c][base + own]);
+            }
+            if (out_ok && kk >= k0 && kk < kend) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ow[c] = a.w[c][base + own];
+            }
+            if (has_halo) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) hv[c] = fma(gam, hold[c][base + hoff], a.z[c][base + hoff]);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ov[c] = a.x[c][base + own];
+            if (has_halo) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) hv[c] = a.x[c][base + hoff];
+            }
+        }
+    };
+
+    double lo[3][4], carry[3][4];
+    // prologue: node plane k0-1 gives the lower face of element layer k0-1
+    fetch(k0 - 1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        sn[c][oslot] = ov[c];
+        if (has_halo) sn[c][hslot] = hv[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            lo[c][q] = sn[c][(ty + (q >> 1)) * LX + tx + (q & 1)];
+            carry[c][q] = 0.0;
+        }
+    fetch(k0);
+    __syncthreads();
+
+    double dot = 0.0;
+    const int nsteps = kend - k0 + 1;
+    for (int s = 0; s < nsteps; ++s) {
+        const int ku = k0 + s;
+        const int kuw = ku >= nz ? ku - nz : ku;
+        if constexpr (FUSED) {
+            if (out_ok && ku < kend) {
+                const int idx = kuw * plane + own;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    hnew[c][idx] = ov[c];
+                    a.w[c][idx] = fma(-lam, oh[c], ow[c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sn[c][oslot] = ov[c];
+            if (has_halo) sn[c][hslot] = hv[c];
+        }
+        __syncthreads();
+        double u[3][8];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                u[c][q] = lo[c][q];
+                u[c][q + 4] = sn[c][(ty + (q >> 1)) * LX + tx + (q & 1)];
+            }
+        double hprev[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            hprev[c] = lo[c][3];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lo[c][q] = u[c][q + 4];
+        }
+        if (s + 1 < nsteps) fetch(ku + 1);
+
+        const int kl = k0 - 1 + s;
+        const int klw = kl < 0 ? kl + nz : kl;
+        double Cu[21];
+        load_coef(a.coef, a.phase[klw * plane + elem], Cu);
+        double f[3][8];
+        element_force(Cu, u, f);
+
+        double mine[3] = {0.0, 0.0, 0.0};
+        if (s > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                sf[0][c][tid] = carry[c][0] + f[c][0];
+                sf[1][c][tid] = carry[c][1] + f[c][1];
+                sf[2][c][tid] = carry[c][2] + f[c][2];
+                mine[c] = carry[c][3] + f[c][3];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) carry[c][q] = f[c][q + 4];
+        __syncthreads();
+        if (s > 0 && out_ok) {
+            const int idx = klw * plane + own;
+            double yv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double v = mine[c] + sf[2][c][tid + 1];
+                v += sf[1][c][tid + TX];
+                v += sf[0][c][tid + TX + 1];
+                if constexpr (!FUSED) {
+                    if (a.add[0]) v += a.add[c][idx];
+                }
+                yv[c] = v;
+                a.y[c][idx] = v;
+            }
+            if constexpr (FUSED) {
+                dot += hprev[0] * yv[0] + hprev[1] * yv[1] + hprev[2] * yv[2];
+            } else {
+                dot += yv[0] * yv[0] + yv[1] * yv[1] + yv[2] * yv[2];
+            }
+        }
+    }
+    if (FUSED || a.want_norm) {
+        double v[1] = {dot};
+        block_partials<1, NT>(v, a.partials, gridDim.x, blockIdx.x);
+    }
+}
+
+constexpr int kTX = 16, kTY = 16;
+
+// ------------------------------------------------------------ post-process
+
+struct Strain6 {
+    double e[6];  // tensor components E11 E22 E33 E23 E13 E12
+};
+
+struct Sig6 {
+    double* s[6];
+};
+
+// Centroid stress C_p (E_hat + B(1/2) w_e) per voxel, which is the voxel
+// average of the trilinear field, and the element energy
+// 1/2 (u^E + w)_e^T K_e (u^E + w)_e (Eq. discrete_energy).
+__global__ void __launch_bounds__(kBlock) stress_kernel(Dims d, const int32_t* __restrict__ phase,
+                                                        const double* __restrict__ coef, Strain6 E,
+                                                        Fields f, Sig6 out, int store,
+                                                        double* partials, int stride)
+{
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const double Et[3][3] = {{E.e[0], E.e[5], E.e[4]}, {E.e[5], E.e[1], E.e[3]}, {E.e[4], E.e[3], E.e[2]}};
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < d.n; e += gridDim.x * kBlock) {
+        int i, j, k;
+        node_ijk(e, d, i, j, k);
+        const int i1 = i + 1 == d.nx ? 0 : i + 1;
+        const int j1 = j + 1 == d.ny ? 0 : j + 1;
+        const int k1 = k + 1 == d.nz ? 0 : k + 1;
+        const int xs[2] = {i, i1}, ys[2] = {j, j1}, zs[2] = {k, k1};
+        double u[3][8], ut_[3][8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int m = xs[a & 1] + d.nx * (ys[(a >> 1) & 1] + d.ny * zs[a >> 2]);
+            const double xi[3] = {(double)(a & 1), (double)((a >> 1) & 1), (double)(a >> 2)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double wv = f.w[c][m];
+                u[c][a] = wv;
+                ut_[c][a] = wv + Et[c][0] * xi[0] + Et[c][1] * xi[1] + Et[c][2] * xi[2];
+            }
+        }
+        fwd8(u[0]);
+        fwd8(u[1]);
+        fwd8(u[2]);
+        // centroid strain: gradient coefficients are (transform X/Y/Z slots)/4
+        double eps[6] = {E.e[0] + 0.25 * u[0][MX],
+                         E.e[1] + 0.25 * u[1][MY],
+                         E.e[2] + 0.25 * u[2][MZ],
+                         2.0 * E.e[3] + 0.25 * (u[1][MZ] + u[2][MY]),
+                         2.0 * E.e[4] + 0.25 * (u[0][MZ] + u[2][MX]),
+                         2.0 * E.e[5] + 0.25 * (u[0][MY] + u[1][MX])};
+        double Cu[21];
+        load_coef(coef, phase[e], Cu);
+        constexpr int sup[6] = {0, 1, 2, 3, 4, 5};
+        double sg[6];
+        contract<6>(Cu, sup, eps, sg);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            if (store) out.s[r][e] = sg[r];
+            acc[r] += sg[r];
+        }
+        double ff[3][8];
+        double keep[3][8];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < 8; ++a) keep[c][a] = ut_[c][a];
+        element_force(Cu, ut_, ff);
+        double en = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < 8; ++a) en += keep[c][a] * ff[c][a];
+        acc[6] += 0.5 * en;
+    }
+    block_partials<7, kBlock>(acc, partials, stride, blockIdx.x);
+}
+
+// u = E.X + w with X = (i, j, k) of the node.
+__global__ void __launch_bounds__(kBlock) total_displacement_kernel(Dims d, Strain6 E, Fields f,
+                                                                    double* u0, double* u1,
+                                                                    double* u2)
+{
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        int i, j, k;
+        node_ijk(m, d, i, j, k);
+        const double X = i, Y = j, Z = k;
+        u0[m] = f.w[0][m] + E.e[0] * X + E.e[5] * Y + E.e[4] * Z;
+        u1[m] = f.w[1][m] + E.e[5] * X + E.e[1] * Y + E.e[3] * Z;
+        u2[m] = f.w[2][m] + E.e[4] * X + E.e[3] * Y + E.e[2] * Z;
+    }
+}
+
+// Counts phase ids outside [0, nphase) (validation of device-resident input).
+__global__ void __launch_bounds__(kBlock) phase_check_kernel(const int32_t* __restrict__ phase, int n,
+                                                             int nphase, int* bad)
+{
+    int cnt = 0;
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < n; m += gridDim.x * kBlock) {
+        const int p = phase[m];
+        cnt += (p < 0 || p >= nphase) ? 1 : 0;
+    }
+    if (cnt) atomicAdd(bad, cnt);
+}
+
+int sweep_blocks(int n, int max_blocks)
+{
+    long long b = ((long long)n + kBlock - 1) / kBlock;
+    if (b > max_blocks) b = max_blocks;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+
+OpGeom op_geometry(const Dims& d, int kz_hint)
+{
+    OpGeom g;
+    g.tiles_x = (d.nx + kTX - 2) / (kTX - 1);
+    g.tiles_y = (d.ny + kTY - 2) / (kTY - 1);
+    const int ntiles = g.tiles_x * g.tiles_y;
+    int kz = kz_hint;
+    if (kz <= 0) {
+        // enough workgroups to fill 256 CUs several times over
+        const int target = 4096;
+        int chunks = (target + ntiles - 1) / ntiles;
+        if (chunks > d.nz) chunks = d.nz;
+        kz = (d.nz + chunks - 1) / chunks;
+        if (kz < 4 && d.nz >= 4) kz = 4;
+    }
+    if (kz > d.nz) kz = d.nz;
+    g.kz = kz;
+    g.zchunks = (d.nz + kz - 1) / kz;
+    g.blocks = ntiles * g.zchunks;
+    return g;
+}
+
+hipError_t launch_load(hipStream_t st, const Dims& d, const int32_t* phase, const double* sig,
+                       double* const b[3], double* partials, double* out2, int max_blocks)
+{
+    const int nb = sweep_blocks(d.n, max_blocks);
+    hipLaunchKernelGGL(load_kernel, dim3(nb), dim3(kBlock), 0, st, d, phase, sig, b[0], b[1], b[2],
+                       partials, nb);
+    hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
+                       (const double*)partials, nb, nb, (Scalars*)nullptr, out2, (const double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
+                          int identity, double* const minv[6])
+{
+    const int nb = sweep_blocks(d.n, 8192);
+    hipLaunchKernelGGL(precond_kernel, dim3(nb), dim3(kBlock), 0, st, d, phase, t.diag, t.solid,
+                       identity, minv[0], minv[1], minv[2], minv[3], minv[4], minv[5]);
+    return hipGetLastError();
+}
+
+static Minv mk_minv(double* const minv[6])
+{
+    Minv M;
+    for (int q = 0; q < 6; ++q) M.m[q] = minv[q];
+    return M;
+}
+
+hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const Fields& f, double* const minv[6],
+                           int fresh, int from_residual, Scalars* S, double* partials,
+                           int max_blocks, const double* norms2)
+{
+    const int nb = sweep_blocks(d.n, max_blocks);
+    hipLaunchKernelGGL(pcg_init_kernel, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv), fresh,
+                       from_residual, partials, nb);
+    hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_INIT,
+                       (const double*)partials, nb, nb, S, (double*)nullptr, norms2);
+    return hipGetLastError();
+}
+
+hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
+                                     const int32_t* phase, const Tables& t, const Fields& f,
+                                     Scalars* S, double* partials)
+{
+    OpArgs a = {};
+    a.d = d;
+    a.tiles_x = g.tiles_x;
+    a.tiles_y = g.tiles_y;
+    a.kz = g.kz;
+    a.phase = phase;
+    a.coef = t.coef;
+    for (int c = 0; c < 3; ++c) {
+        a.z[c] = f.z[c];
+        a.h0[c] = f.h0[c];
+        a.h1[c] = f.h1[c];
+        a.w[c] = f.w[c];
+        a.y[c] = f.Ah[c];
+    }
+    a.S = S;
+    a.partials = partials;
+    hipLaunchKernelGGL((op_kernel<kTX, kTY, true>), dim3(g.blocks), dim3(kTX * kTY), 0, st, a);
+    hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_DIRECTION,
+                       (const double*)partials, g.blocks, g.blocks, S, (double*)nullptr,
+                       (const double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_precond(hipStream_t st, const Dims& d, const Fields& f,
+                                 double* const minv[6], Scalars* S, double* partials, int max_blocks)
+{
+    const int nb = sweep_blocks(d.n, max_blocks);
+    hipLaunchKernelGGL(update_precond_kernel, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv),
+                       (const Scalars*)S, partials, nb);
+    hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_UPDATE,
+                       (const double*)partials, nb, nb, S, (double*)nullptr, (const double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_update(hipStream_t st, const Dims& d, const Fields& f, Scalars* S)
+{
+    const int nb = sweep_blocks(d.n, 4096);
+    hipLaunchKernelGGL(final_update_kernel, dim3(nb), dim3(kBlock), 0, st, d, f, (const Scalars*)S);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
+                        const Tables& t, const double* const x[3], double* const y[3],
+                        const double* const add[3], double* partials, double* norm2)
+{
+    OpArgs a = {};
+    a.d = d;
+    a.tiles_x = g.tiles_x;
+    a.tiles_y = g.tiles_y;
+    a.kz = g.kz;
+    a.phase = phase;
+    a.coef = t.coef;
+    for (int c = 0; c < 3; ++c) {
+        a.x[c] = x[c];
+        a.y[c] = y[c];
+        a.add[c] = add ? add[c] : nullptr;
+    }
+    a.partials = partials;
+    a.want_norm = norm2 != nullptr;
+    hipLaunchKernelGGL((op_kernel<kTX, kTY, false>), dim3(g.blocks), dim3(kTX * kTY), 0, st, a);
+    if (norm2)
+        hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
+                           (const double*)partials, g.blocks, g.blocks, (Scalars*)nullptr, norm2,
+                           (const double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_stress(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
+                         const double* strain6, const Fields& f, double* const sig[6],
+                         double* partials, double* sums7, int max_blocks)
+{
+    const int nb = sweep_blocks(d.n, max_blocks);
+    Strain6 E;
+    for (int q = 0; q < 6; ++q) E.e[q] = strain6[q];
+    Sig6 o;
+    for (int q = 0; q < 6; ++q) o.s[q] = sig ? sig[q] : nullptr;
+    hipLaunchKernelGGL(stress_kernel, dim3(nb), dim3(kBlock), 0, st, d, phase, t.coef, E, f, o,
+                       sig ? 1 : 0, partials, nb);
+    hipLaunchKernelGGL(finalize_kernel<7>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
+                       (const double*)partials, nb, nb, (Scalars*)nullptr, sums7,
+                       (const double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_check(hipStream_t st, const int32_t* phase, int n, int nphase, int* bad)
+{
+    const int nb = sweep_blocks(n, 2048);
+    hipLaunchKernelGGL(phase_check_kernel, dim3(nb), dim3(kBlock), 0, st, phase, n, nphase, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_total_displacement(hipStream_t st, const Dims& d, const double* strain6,
+                                     const Fields& f, double* const u[3])
+{
+    const int nb = sweep_blocks(d.n, 4096);
+    Strain6 E;
+    for (int q = 0; q < 6; ++q) E.e[q] = strain6[q];
+    hipLaunchKernelGGL(total_displacement_kernel, dim3(nb), dim3(kBlock), 0, st, d, E, f, u[0], u[1],
+                       u[2]);
+    return hipGetLastError();
+}
+
+}  // namespace e3d

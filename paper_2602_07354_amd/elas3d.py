@@ -1,0 +1,321 @@
+"""ctypes binding of libelas3d (C-ABI in include/elas3d.h).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels
+of ``libelas3d.so``.  The functions keep the C names without the ``elas3d_``
+prefix.  Host arrays are numpy; device arrays may be any object with a
+``data_ptr()`` (torch CUDA tensors) when the context was created with
+``inputs_on_device`` / ``outputs_on_device``.
+
+There is no fallback: if the shared library is missing, importing this
+module raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "OK", "NOT_CONVERGED", "BREAKDOWN", "EBADARG", "ENOMEM", "EDEVICE", "EORDER",
+    "PREC_FP64", "PREC_MIXED", "CONV_RESIDUAL", "CONV_PAPER", "PRECOND_BLOCK_JACOBI",
+    "PRECOND_NONE", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
+    "setup", "solve", "stress", "apply", "get_load", "get_precond", "get_solution",
+    "device_bytes", "destroy", "last_error", "version", "Context", "EXPORTS",
+]
+
+OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+EBADARG, ENOMEM, EDEVICE, EORDER = -1, -2, -3, -4
+PREC_FP64, PREC_MIXED = 0, 1
+CONV_RESIDUAL, CONV_PAPER = 0, 1
+PRECOND_BLOCK_JACOBI, PRECOND_NONE = 0, 1
+MAX_RHS = 6
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libelas3d.so")
+
+EXPORTS = (
+    "elas3d_options_init", "elas3d_setup", "elas3d_solve", "elas3d_stress", "elas3d_apply",
+    "elas3d_get_load", "elas3d_get_precond", "elas3d_get_solution", "elas3d_device_bytes",
+    "elas3d_destroy", "elas3d_last_error", "elas3d_version",
+)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("convergence", ctypes.c_int32),
+        ("preconditioner", ctypes.c_int32),
+        ("inputs_on_device", ctypes.c_int32),
+        ("outputs_on_device", ctypes.c_int32),
+        ("poll_interval", ctypes.c_int32),
+        ("timing", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("hbm_budget_bytes", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("inner_tol", ctypes.c_double),
+        ("inner_maxit", ctypes.c_int32),
+        ("batched", ctypes.c_int32),
+    ]
+
+
+_R = MAX_RHS
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("nrhs", ctypes.c_int32),
+        ("status", ctypes.c_int32 * _R),
+        ("iters", ctypes.c_int32 * _R),
+        ("restarts", ctypes.c_int32 * _R),
+        ("relres_true", ctypes.c_double * _R),
+        ("relres_recursive", ctypes.c_double * _R),
+        ("relres_precond", ctypes.c_double * _R),
+        ("t_solve_s", ctypes.c_double),
+        ("bytes_per_iter", ctypes.c_double),
+        ("t_operator_ms", ctypes.c_double),
+        ("n_operator", ctypes.c_int64),
+        ("t_update_ms", ctypes.c_double),
+        ("n_update", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        n = self.nrhs
+        return {
+            "nrhs": n,
+            "status": list(self.status[:n]),
+            "iters": list(self.iters[:n]),
+            "restarts": list(self.restarts[:n]),
+            "relres_true": list(self.relres_true[:n]),
+            "relres_recursive": list(self.relres_recursive[:n]),
+            "relres_precond": list(self.relres_precond[:n]),
+            "t_solve_s": self.t_solve_s,
+            "bytes_per_iter": self.bytes_per_iter,
+            "t_operator_ms": self.t_operator_ms,
+            "n_operator": self.n_operator,
+            "t_update_ms": self.t_update_ms,
+            "n_update": self.n_update,
+        }
+
+
+class Elas3dError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"elas3d error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libelas3d.so (raises if it has not been built).
+
+    PyTorch wheels carry their own HIP runtime with the same soname as the
+    system one.  torch is imported first, when installed, so that the
+    library binds to that runtime: one HIP runtime per process, and torch's
+    device pointers and streams are valid in the library's calls.
+    """
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run python -m paper_2602_07354_amd.build")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.elas3d_options_init.argtypes = [ctypes.POINTER(Options)]
+        L.elas3d_options_init.restype = None
+        L.elas3d_setup.argtypes = [ctypes.POINTER(vp), i32, i32, i32, vp, i32, vp, i32, vp,
+                                   ctypes.POINTER(Options)]
+        L.elas3d_setup.restype = ctypes.c_int
+        L.elas3d_solve.argtypes = [vp, d, i32, i32, ctypes.POINTER(Info)]
+        L.elas3d_solve.restype = ctypes.c_int
+        L.elas3d_stress.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.elas3d_stress.restype = ctypes.c_int
+        L.elas3d_apply.argtypes = [vp, vp, vp]
+        L.elas3d_apply.restype = ctypes.c_int
+        L.elas3d_get_load.argtypes = [vp, i32, vp]
+        L.elas3d_get_load.restype = ctypes.c_int
+        L.elas3d_get_precond.argtypes = [vp, vp]
+        L.elas3d_get_precond.restype = ctypes.c_int
+        L.elas3d_get_solution.argtypes = [vp, i32, vp]
+        L.elas3d_get_solution.restype = ctypes.c_int
+        L.elas3d_device_bytes.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(Options)]
+        L.elas3d_device_bytes.restype = ctypes.c_double
+        L.elas3d_destroy.argtypes = [vp]
+        L.elas3d_destroy.restype = None
+        L.elas3d_last_error.argtypes = [vp]
+        L.elas3d_last_error.restype = ctypes.c_char_p
+        L.elas3d_version.argtypes = []
+        L.elas3d_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(a) -> Optional[int]:
+    """Address of a numpy array (host) or of an object with data_ptr() (device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return a.ctypes.data
+    if hasattr(a, "data_ptr"):
+        return int(a.data_ptr())
+    if isinstance(a, int):
+        return a
+    raise TypeError(f"cannot pass {type(a)} to the C-ABI")
+
+
+def options_init(**kw) -> Options:
+    o = Options()
+    lib().elas3d_options_init(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def last_error(ctx=None) -> str:
+    return lib().elas3d_last_error(ctx).decode()
+
+
+def version() -> str:
+    return lib().elas3d_version().decode()
+
+
+def _check(rc: int, ctx=None, soft_ok: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not soft_ok):
+        raise Elas3dError(rc, last_error(ctx))
+    return rc
+
+
+def setup(shape, phase, C, strain, options: Optional[Options] = None):
+    """elas3d_setup; returns an opaque context handle (int)."""
+    nx, ny, nz = (int(s) for s in shape)
+    C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1, 36)
+    strain = np.ascontiguousarray(strain, dtype=np.float64).reshape(-1, 6)
+    if isinstance(phase, np.ndarray):
+        phase = np.ascontiguousarray(phase, dtype=np.int32)
+    h = ctypes.c_void_p()
+    rc = lib().elas3d_setup(ctypes.byref(h), nx, ny, nz, _ptr(phase), C.shape[0], _ptr(C),
+                            strain.shape[0], _ptr(strain),
+                            ctypes.byref(options) if options is not None else None)
+    _check(rc)
+    return h.value
+
+
+def solve(ctx, tol: float, maxit: int, nrhs: int = 1) -> tuple:
+    """elas3d_solve; returns (status, Info)."""
+    info = Info()
+    rc = lib().elas3d_solve(ctx, float(tol), int(maxit), int(nrhs), ctypes.byref(info))
+    _check(rc, ctx, soft_ok=True)
+    return rc, info
+
+
+def stress(ctx, rhs: int, sigma_voxel=None, sigma_avg=None, u_node=None, energy=None) -> int:
+    return _check(lib().elas3d_stress(ctx, int(rhs), _ptr(sigma_voxel), _ptr(sigma_avg),
+                                      _ptr(u_node), _ptr(energy)), ctx)
+
+
+def apply(ctx, x, y) -> int:
+    return _check(lib().elas3d_apply(ctx, _ptr(x), _ptr(y)), ctx)
+
+
+def get_load(ctx, rhs: int, b) -> int:
+    return _check(lib().elas3d_get_load(ctx, int(rhs), _ptr(b)), ctx)
+
+
+def get_precond(ctx, minv) -> int:
+    return _check(lib().elas3d_get_precond(ctx, _ptr(minv)), ctx)
+
+
+def get_solution(ctx, rhs: int, w) -> int:
+    return _check(lib().elas3d_get_solution(ctx, int(rhs), _ptr(w)), ctx)
+
+
+def device_bytes(shape, nphase: int, nrhs: int, options: Optional[Options] = None) -> float:
+    nx, ny, nz = (int(s) for s in shape)
+    return lib().elas3d_device_bytes(nx, ny, nz, int(nphase), int(nrhs),
+                                     ctypes.byref(options) if options is not None else None)
+
+
+def destroy(ctx) -> None:
+    if ctx:
+        lib().elas3d_destroy(ctx)
+
+
+class Context:
+    """Owning wrapper of one elas3d context (host numpy in/out by default)."""
+
+    def __init__(self, shape, phase, C, strain, **opts):
+        self.shape = tuple(int(s) for s in shape)
+        self.n = int(np.prod(self.shape))
+        self.nrhs = int(np.asarray(strain).reshape(-1, 6).shape[0])
+        self.options = options_init(**opts)
+        self.handle = setup(self.shape, phase, C, strain, self.options)
+
+    @classmethod
+    def from_micro(cls, ms, **opts):
+        return cls(ms.shape, ms.phase, ms.C, ms.strain, **opts)
+
+    def solve(self, tol: float, maxit: int = 100000, nrhs: Optional[int] = None):
+        st, info = solve(self.handle, tol, maxit, self.nrhs if nrhs is None else nrhs)
+        return st, info.as_dict()
+
+    def stress(self, rhs: int = 0, voxel: bool = True, displacement: bool = False) -> dict:
+        sig = np.empty((6, self.n)) if voxel else None
+        avg = np.empty(6)
+        u = np.empty((3, self.n)) if displacement else None
+        en = np.empty(1)
+        stress(self.handle, rhs, sig, avg, u, en)
+        return {"sigma": sig, "avg": avg, "u": u, "energy": float(en[0])}
+
+    def apply(self, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(3, self.n)
+        y = np.empty_like(x)
+        apply(self.handle, x, y)
+        return y
+
+    def load(self, rhs: int = 0) -> np.ndarray:
+        b = np.empty((3, self.n))
+        get_load(self.handle, rhs, b)
+        return b
+
+    def precond(self) -> np.ndarray:
+        """(N, 3, 3) symmetric inverse blocks from the six stored planes."""
+        m = np.empty((6, self.n))
+        get_precond(self.handle, m)
+        out = np.empty((self.n, 3, 3))
+        xx, yy, zz, yz, xz, xy = m
+        out[:, 0, 0], out[:, 1, 1], out[:, 2, 2] = xx, yy, zz
+        out[:, 1, 2] = out[:, 2, 1] = yz
+        out[:, 0, 2] = out[:, 2, 0] = xz
+        out[:, 0, 1] = out[:, 1, 0] = xy
+        return out
+
+    def solution(self, rhs: int = 0) -> np.ndarray:
+        w = np.empty((3, self.n))
+        get_solution(self.handle, rhs, w)
+        return w
+
+    def close(self):
+        if self.handle:
+            destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

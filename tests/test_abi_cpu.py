@@ -1,0 +1,111 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, the ctypes structs match the C layout, and argument
+validation rejects bad input before any device call."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "elas3d.h")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2602_07354_amd import elas3d
+    elas3d.lib()
+    return elas3d
+
+
+def test_library_exports_every_declared_symbol(E):
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(elas3d_[a-z_]+)\s*\(", text))
+    assert declared, "no declarations found"
+    assert declared == set(E.EXPORTS)
+    L = E.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert "gfx950" in E.version()
+
+
+def test_struct_layout_matches_c(E, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "elas3d.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(elas3d_options), offsetof(elas3d_options, hbm_budget_bytes),'
+        " offsetof(elas3d_options, stream), offsetof(elas3d_options, batched),"
+        " sizeof(elas3d_info), offsetof(elas3d_info, relres_true));\n"
+        'printf("%zu %zu\\n", offsetof(elas3d_info, t_operator_ms), offsetof(elas3d_info, n_update));\n'
+        "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    c = [int(v) for v in out]
+    py = [ctypes.sizeof(E.Options), E.Options.hbm_budget_bytes.offset, E.Options.stream.offset,
+          E.Options.batched.offset, ctypes.sizeof(E.Info), E.Info.relres_true.offset,
+          E.Info.t_operator_ms.offset, E.Info.n_update.offset]
+    assert c == py
+
+
+def _good():
+    from paper_2602_07354_amd import synth
+    C = np.stack([synth.isotropic_stiffness(200, .3), np.zeros((6, 6))])
+    phase = np.zeros(4 * 4 * 4, np.int32)
+    strain = np.array([[1e-3, 0, 0, 0, 0, 0]])
+    return (4, 4, 4), phase, C, strain
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda a: a.update(shape=(1, 4, 4)), "grid dimensions"),
+    (lambda a: a.update(phase=None), "phase is NULL"),
+    (lambda a: a.update(C=np.zeros((0, 6, 6))), "nphase"),
+    (lambda a: a.update(strain=np.zeros((7, 6))), "nrhs"),
+    (lambda a: a["phase"].__setitem__(5, 2), "out of range"),
+    (lambda a: a["phase"].__setitem__(5, -1), "out of range"),
+    (lambda a: a["C"].__setitem__((0, 0, 1), np.nan), "not finite"),
+    (lambda a: a["C"].__setitem__((0, 0, 1), 1.0), "not symmetric"),
+    (lambda a: a["strain"].__setitem__((0, 2), np.inf), "strain"),
+])
+def test_setup_rejects_bad_arguments(E, mutate, needle):
+    shape, phase, C, strain = _good()
+    args = {"shape": shape, "phase": phase, "C": C, "strain": strain}
+    mutate(args)
+    if args["phase"] is None:
+        h = ctypes.c_void_p()
+        rc = E.lib().elas3d_setup(ctypes.byref(h), 4, 4, 4, None, 2, args["C"].ctypes.data, 1,
+                                  args["strain"].ctypes.data, None)
+        assert rc == E.EBADARG and needle in E.last_error()
+        return
+    with pytest.raises(E.Elas3dError) as ei:
+        E.setup(args["shape"], args["phase"], args["C"], args["strain"])
+    assert ei.value.code == E.EBADARG
+    assert needle in str(ei.value)
+
+
+def test_setup_rejects_bad_options(E):
+    shape, phase, C, strain = _good()
+    for kw in ({"precision": 7}, {"convergence": 3}, {"preconditioner": -1},
+               {"poll_interval": -2}, {"hbm_budget_bytes": -1.0}, {"inner_tol": 2.0}):
+        with pytest.raises(E.Elas3dError) as ei:
+            E.setup(shape, phase, C, strain, E.options_init(**kw))
+        assert ei.value.code == E.EBADARG
+
+
+def test_null_context_calls_are_rejected(E):
+    L = E.lib()
+    assert L.elas3d_solve(None, 1e-8, 10, 1, None) == E.EBADARG
+    assert L.elas3d_stress(None, 0, None, None, None, None) == E.EBADARG
+    assert L.elas3d_apply(None, None, None) == E.EBADARG
+    L.elas3d_destroy(None)
+    assert "ctx is NULL" in E.last_error()
+
+
+def test_device_bytes_plan(E):
+    b1 = E.device_bytes((500, 500, 500), 8001, 1)
+    assert 25e9 < b1 < 30e9  # ~220 B per node in FP64 with one load case
+    assert E.device_bytes((500, 500, 500), 8001, 6) > b1
