@@ -152,11 +152,11 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
  * Post-processing of load case `rhs` (Table 1, stress_OpenMP): per voxel the
  * stress at the voxel centroid sigma = C_p (E_hat + B(1/2,1/2,1/2) w_e),
  * which is the voxel average of the trilinear field (0 in voids).
- *   sigma_voxel  6*N doubles or NULL.
- *   sigma_avg    6 doubles or NULL: mean over all N voxels (voids count 0).
- *   u_node       3*N doubles or NULL: total displacement u = E.X + w with
- *                X = (i,j,k) of the node.
- *   energy       1 double or NULL: total potential energy
+ *   sigma_voxel  6*N doubles or NULL (device memory when outputs_on_device).
+ *   sigma_avg    6 doubles (host) or NULL: mean over all N voxels (voids count 0).
+ *   u_node       3*N doubles or NULL (device memory when outputs_on_device):
+ *                total displacement u = E.X + w with X = (i,j,k) of the node.
+ *   energy       1 double (host) or NULL: total potential energy
  *                Pi = 1/2 sum_e (u_e)^T K_e (u_e) (Eq. discrete_energy).
  * Returns 0, ELAS3D_EBADARG, ELAS3D_EORDER (rhs not solved) or ELAS3D_EDEVICE.
  */

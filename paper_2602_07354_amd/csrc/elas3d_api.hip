@@ -152,7 +152,8 @@ int ut(int r, int c)
 }
 
 // Per-phase tables (Sec. 2.1.1: a full stiffness per phase).
-//  coef: packed upper triangle of C.
+//  coef: packed upper triangle of C/16 (the weight of the constant strain
+//        mode of the element operator; dividing by a power of two is exact).
 //  diag: the corner block of the element stiffness for corner signs s,
 //        (K_e)_aa,ij = sum_kl s_k s_l C_ikjl I_kl with I_kk = 1/9 and
 //        I_kl = 1/12 (k != l) the integrals of products of shape-function
@@ -174,7 +175,8 @@ void build_tables(const double* C, int nphase, const double* strain, int nrhs,
         for (int q = 0; q < 36; ++q) any = any || Cp[q] != 0.0;
         solid[p] = any ? 1 : 0;
         for (int r = 0; r < 6; ++r)
-            for (int c = r; c < 6; ++c) coef[(size_t)p * e3d::kCoefStride + ut(r, c)] = Cp[6 * r + c];
+            for (int c = r; c < 6; ++c)
+                coef[(size_t)p * e3d::kCoefStride + ut(r, c)] = Cp[6 * r + c] / 16.0;  // exact
         double* dg = diag.data() + (size_t)p * e3d::kDiagStride;
         for (int q = 0; q < 6; ++q) {
             const int i = pij[q][0], j = pij[q][1];

@@ -87,124 +87,182 @@ __device__ __forceinline__ void contract(const double* Cu, const int (&sup)[N], 
 
 enum { MX = 1, MY = 2, MXY = 3, MZ = 4, MXZ = 5, MYZ = 6, MXYZ = 7 };
 
-// f = K_e u for one voxel with packed stiffness Cu (21 entries).  u[c][a] is
-// destroyed.  f[c][a]: force component c on corner a.
-__device__ __forceinline__ void element_force(const double* Cu, double (&u)[3][8], double (&f)[3][8])
+// The stiffness table holds C/16 (exact: a power of two).  With H the +-1
+// transform of the nodal values, the element energy is
+//   1/2 [ (1/16) e1^T C e1 + (1/48) sum_{X,Y,Z} e^T C e + (1/144) sum_{YZ,XZ,XY} e^T C e ]
+// (coefficient scales 1/4, 1/2, 1 of the transform times the L2 weights 1,
+// 1/12, 1/144 of the modes), so with Cs = C/16 the linear modes carry an
+// extra 1/3 and the bilinear ones 1/9.
+//
+// modal_core: H[c][mu] (slots MX..MXYZ, unscaled) -> G[c][mu] = dE/dH (slot 0
+// is not written and must be treated as 0).  H is scaled in place.
+__device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], double (&G)[3][8])
 {
-    fwd8(u[0]);
-    fwd8(u[1]);
-    fwd8(u[2]);
-    // Energy weights of the modes folded into the coefficients: the constant
-    // strain mode carries (1/4)^2, the linear ones (1/2)^2/12, the bilinear
-    // ones 1/144 (coefficient scales of the transform times the L2 weights).
-    constexpr double s1 = 1.0 / 16.0, s2 = 1.0 / 48.0, s3 = 1.0 / 144.0;
+    constexpr double third = 1.0 / 3.0, ninth = 1.0 / 9.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        u[c][MX] *= s1;
-        u[c][MY] *= s1;
-        u[c][MZ] *= s1;
-        u[c][MXY] *= s2;
-        u[c][MXZ] *= s2;
-        u[c][MYZ] *= s2;
-        u[c][MXYZ] *= s3;
+        H[c][MXY] *= third;
+        H[c][MXZ] *= third;
+        H[c][MYZ] *= third;
+        H[c][MXYZ] *= ninth;
     }
-    double g[3][8];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int a = 0; a < 8; ++a) g[c][a] = 0.0;
-
     // constant mode: full 6-component strain
     {
         constexpr int sup[6] = {0, 1, 2, 3, 4, 5};
-        const double e[6] = {u[0][MX], u[1][MY], u[2][MZ], u[1][MZ] + u[2][MY], u[0][MZ] + u[2][MX],
-                             u[0][MY] + u[1][MX]};
+        const double e[6] = {H[0][MX], H[1][MY], H[2][MZ], H[1][MZ] + H[2][MY], H[0][MZ] + H[2][MX],
+                             H[0][MY] + H[1][MX]};
         double t[6];
-        contract<6>(Cu, sup, e, t);
-        g[0][MX] += t[0];
-        g[1][MY] += t[1];
-        g[2][MZ] += t[2];
-        g[1][MZ] += t[3];
-        g[2][MY] += t[3];
-        g[0][MZ] += t[4];
-        g[2][MX] += t[4];
-        g[0][MY] += t[5];
-        g[1][MX] += t[5];
+        contract<6>(Cs, sup, e, t);
+        G[0][MX] = t[0];
+        G[1][MY] = t[1];
+        G[2][MZ] = t[2];
+        G[1][MZ] = t[3];
+        G[2][MY] = t[3];
+        G[0][MZ] = t[4];
+        G[2][MX] = t[4];
+        G[0][MY] = t[5];
+        G[1][MX] = t[5];
     }
     // X mode: (yy, zz, yz, xz, xy)
     {
         constexpr int sup[5] = {1, 2, 3, 4, 5};
-        const double e[5] = {u[1][MXY], u[2][MXZ], u[1][MXZ] + u[2][MXY], u[0][MXZ], u[0][MXY]};
+        const double e[5] = {H[1][MXY], H[2][MXZ], H[1][MXZ] + H[2][MXY], H[0][MXZ], H[0][MXY]};
         double t[5];
-        contract<5>(Cu, sup, e, t);
-        g[1][MXY] += t[0];
-        g[2][MXZ] += t[1];
-        g[1][MXZ] += t[2];
-        g[2][MXY] += t[2];
-        g[0][MXZ] += t[3];
-        g[0][MXY] += t[4];
+        contract<5>(Cs, sup, e, t);
+        G[1][MXY] = t[0];
+        G[2][MXZ] = t[1];
+        G[1][MXZ] = t[2];
+        G[2][MXY] = t[2];
+        G[0][MXZ] = t[3];
+        G[0][MXY] = t[4];
     }
     // Y mode: (xx, zz, yz, xz, xy)
     {
         constexpr int sup[5] = {0, 2, 3, 4, 5};
-        const double e[5] = {u[0][MXY], u[2][MYZ], u[1][MYZ], u[0][MYZ] + u[2][MXY], u[1][MXY]};
+        const double e[5] = {H[0][MXY], H[2][MYZ], H[1][MYZ], H[0][MYZ] + H[2][MXY], H[1][MXY]};
         double t[5];
-        contract<5>(Cu, sup, e, t);
-        g[0][MXY] += t[0];
-        g[2][MYZ] += t[1];
-        g[1][MYZ] += t[2];
-        g[0][MYZ] += t[3];
-        g[2][MXY] += t[3];
-        g[1][MXY] += t[4];
+        contract<5>(Cs, sup, e, t);
+        G[0][MXY] += t[0];
+        G[2][MYZ] = t[1];
+        G[1][MYZ] = t[2];
+        G[0][MYZ] = t[3];
+        G[2][MXY] += t[3];
+        G[1][MXY] += t[4];
     }
     // Z mode: (xx, yy, yz, xz, xy)
     {
         constexpr int sup[5] = {0, 1, 3, 4, 5};
-        const double e[5] = {u[0][MXZ], u[1][MYZ], u[2][MYZ], u[2][MXZ], u[0][MYZ] + u[1][MXZ]};
+        const double e[5] = {H[0][MXZ], H[1][MYZ], H[2][MYZ], H[2][MXZ], H[0][MYZ] + H[1][MXZ]};
         double t[5];
-        contract<5>(Cu, sup, e, t);
-        g[0][MXZ] += t[0];
-        g[1][MYZ] += t[1];
-        g[2][MYZ] += t[2];
-        g[2][MXZ] += t[3];
-        g[0][MYZ] += t[4];
-        g[1][MXZ] += t[4];
+        contract<5>(Cs, sup, e, t);
+        G[0][MXZ] += t[0];
+        G[1][MYZ] += t[1];
+        G[2][MYZ] += t[2];
+        G[2][MXZ] += t[3];
+        G[0][MYZ] += t[4];
+        G[1][MXZ] += t[4];
     }
     // YZ mode: (xx, xz, xy)
     {
         constexpr int sup[3] = {0, 4, 5};
-        const double e[3] = {u[0][MXYZ], u[2][MXYZ], u[1][MXYZ]};
+        const double e[3] = {H[0][MXYZ], H[2][MXYZ], H[1][MXYZ]};
         double t[3];
-        contract<3>(Cu, sup, e, t);
-        g[0][MXYZ] += t[0];
-        g[2][MXYZ] += t[1];
-        g[1][MXYZ] += t[2];
+        contract<3>(Cs, sup, e, t);
+        G[0][MXYZ] = t[0];
+        G[2][MXYZ] = t[1];
+        G[1][MXYZ] = t[2];
     }
     // XZ mode: (yy, yz, xy)
     {
         constexpr int sup[3] = {1, 3, 5};
-        const double e[3] = {u[1][MXYZ], u[2][MXYZ], u[0][MXYZ]};
+        const double e[3] = {H[1][MXYZ], H[2][MXYZ], H[0][MXYZ]};
         double t[3];
-        contract<3>(Cu, sup, e, t);
-        g[1][MXYZ] += t[0];
-        g[2][MXYZ] += t[1];
-        g[0][MXYZ] += t[2];
+        contract<3>(Cs, sup, e, t);
+        G[1][MXYZ] += t[0];
+        G[2][MXYZ] += t[1];
+        G[0][MXYZ] += t[2];
     }
     // XY mode: (zz, yz, xz)
     {
         constexpr int sup[3] = {2, 3, 4};
-        const double e[3] = {u[2][MXYZ], u[1][MXYZ], u[0][MXYZ]};
+        const double e[3] = {H[2][MXYZ], H[1][MXYZ], H[0][MXYZ]};
         double t[3];
-        contract<3>(Cu, sup, e, t);
-        g[2][MXYZ] += t[0];
-        g[1][MXYZ] += t[1];
-        g[0][MXYZ] += t[2];
+        contract<3>(Cs, sup, e, t);
+        G[2][MXYZ] += t[0];
+        G[1][MXYZ] += t[1];
+        G[0][MXYZ] += t[2];
     }
+}
+
+// f = K_e u for one voxel with the scaled packed stiffness Cs.  u[c][a] is
+// destroyed.  f[c][a]: force component c on corner a.
+__device__ __forceinline__ void element_force(const double* Cs, double (&u)[3][8], double (&f)[3][8])
+{
+    fwd8(u[0]);
+    fwd8(u[1]);
+    fwd8(u[2]);
+    double g[3][8];
+    modal_core(Cs, u, g);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+        g[c][0] = 0.0;
         adj8(g[c]);
 #pragma unroll
         for (int a = 0; a < 8; ++a) f[c][a] = g[c][a];
+    }
+}
+
+// 2D transform of a face (corner q = ax + 2ay) into the slots {sum, X, Y, XY}.
+__device__ __forceinline__ void face_fwd(double v0, double v1, double v2, double v3, double (&F)[4])
+{
+    const double p0 = v0 + v1, d0 = v1 - v0, p1 = v2 + v3, d1 = v3 - v2;
+    F[0] = p0 + p1;
+    F[2] = p1 - p0;
+    F[1] = d0 + d1;
+    F[3] = d1 - d0;
+}
+
+// Adjoint of face_fwd: face slots -> corner values.
+__device__ __forceinline__ void face_adj(const double (&F)[4], double (&v)[4])
+{
+    const double o0 = F[0] - F[1], o1 = F[0] + F[1], o2 = F[2] - F[3], o3 = F[2] + F[3];
+    v[0] = o0 - o2;
+    v[2] = o0 + o2;
+    v[1] = o1 - o3;
+    v[3] = o1 + o3;
+}
+
+// Element operator on face spectra: L, U = face_fwd of the lower (z) and
+// upper node planes' corner values; returns the face spectra FL, FU of the
+// lower- and upper-face corner forces (face_adj turns them into forces).
+__device__ __forceinline__ void element_force_faces(const double* Cs, const double (&L)[3][4],
+                                                    const double (&U)[3][4], double (&FL)[3][4],
+                                                    double (&FU)[3][4])
+{
+    double H[3][8], G[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        // z stage: slots without z are sums of the faces, slots with z differences
+        H[c][MX] = U[c][1] + L[c][1];
+        H[c][MY] = U[c][2] + L[c][2];
+        H[c][MXY] = U[c][3] + L[c][3];
+        H[c][MZ] = U[c][0] - L[c][0];
+        H[c][MXZ] = U[c][1] - L[c][1];
+        H[c][MYZ] = U[c][2] - L[c][2];
+        H[c][MXYZ] = U[c][3] - L[c][3];
+    }
+    modal_core(Cs, H, G);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        // adjoint of the z stage (slot 0 of G is zero)
+        FL[c][0] = -G[c][MZ];
+        FU[c][0] = G[c][MZ];
+        FL[c][1] = G[c][MX] - G[c][MXZ];
+        FU[c][1] = G[c][MX] + G[c][MXZ];
+        FL[c][2] = G[c][MY] - G[c][MYZ];
+        FU[c][2] = G[c][MY] + G[c][MYZ];
+        FL[c][3] = G[c][MXY] - G[c][MXYZ];
+        FU[c][3] = G[c][MXY] + G[c][MXYZ];
     }
 }
 
@@ -523,6 +581,19 @@ __global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, Fields f, Minv
 
 // Algorithm 2, C-D: g -= lambda Ah, z = M^-1 g, partial z.g and g.g.
 // (w -= lambda h is deferred to the next direction sweep, which reads h anyway.)
+// Update sweep body for one node (g -= lambda Ah, z = M^-1 g).
+__device__ __forceinline__ void update_node(double lam, const double (&g)[3], const double (&ah)[3],
+                                            const double (&mm)[6], double (&go)[3], double (&zo)[3])
+{
+    go[0] = fma(-lam, ah[0], g[0]);
+    go[1] = fma(-lam, ah[1], g[1]);
+    go[2] = fma(-lam, ah[2], g[2]);
+    const double xx = mm[0], yy = mm[1], zz = mm[2], yz = mm[3], xz = mm[4], xy = mm[5];
+    zo[0] = xx * go[0] + xy * go[1] + xz * go[2];
+    zo[1] = xy * go[0] + yy * go[1] + yz * go[2];
+    zo[2] = xz * go[0] + yz * go[1] + zz * go[2];
+}
+
 __global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, Fields f, Minv M,
                                                                 const Scalars* S, double* partials,
                                                                 int stride)
@@ -531,19 +602,22 @@ __global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, Fields f
     const double lam = S->lambda;
     double acc[2] = {0.0, 0.0};
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        const double g0 = fma(-lam, f.Ah[0][m], f.g[0][m]);
-        const double g1 = fma(-lam, f.Ah[1][m], f.g[1][m]);
-        const double g2 = fma(-lam, f.Ah[2][m], f.g[2][m]);
-        f.g[0][m] = g0;
-        f.g[1][m] = g1;
-        f.g[2][m] = g2;
-        double z0, z1, z2;
-        apply_minv(M.m, m, g0, g1, g2, z0, z1, z2);
-        f.z[0][m] = z0;
-        f.z[1][m] = z1;
-        f.z[2][m] = z2;
-        acc[0] += z0 * g0 + z1 * g1 + z2 * g2;
-        acc[1] += g0 * g0 + g1 * g1 + g2 * g2;
+        double g[3], ah[3], mm[6], go[3], zo[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            g[c] = f.g[c][m];
+            ah[c] = f.Ah[c][m];
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) mm[q] = M.m[q][m];
+        update_node(lam, g, ah, mm, go, zo);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            f.g[c][m] = go[c];
+            f.z[c][m] = zo[c];
+        }
+        acc[0] += zo[0] * go[0] + zo[1] * go[1] + zo[2] * go[2];
+        acc[1] += go[0] * go[0] + go[1] * go[1] + go[2] * go[2];
     }
     block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
 }
@@ -561,6 +635,24 @@ __global__ void __launch_bounds__(kBlock) final_update_kernel(Dims d, Fields f, 
 }
 
 // ------------------------------------------------------- tiled operator sweep
+
+#ifndef E3D_XCD_REMAP
+#define E3D_XCD_REMAP 1
+#endif
+constexpr int kXcds = 8;  // MI355X: 8 accelerator dies, each with its own L2
+
+// Workgroups are handed to the XCDs round-robin (id % 8).  This bijection
+// gives each XCD a contiguous range of logical tiles instead, so that tiles
+// that share halo rows and cache lines run on the same L2 at about the same
+// time.
+__device__ __forceinline__ int xcd_local_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    if (!E3D_XCD_REMAP || nb < kXcds) return b;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int x = b % kXcds, j = b / kXcds;
+    return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
+}
 
 struct OpArgs {
     Dims d;
@@ -586,8 +678,12 @@ struct OpArgs {
 //   h_new = z + gamma h_old (written to the other direction buffer),
 //   w -= lambda h_old (the previous step, deferred), Ah = A h_new and the
 //   partial h_new.Ah.
+#ifndef E3D_OP_MIN_WAVES
+#define E3D_OP_MIN_WAVES 1
+#endif
+
 template <int TX, int TY, bool FUSED>
-__global__ void __launch_bounds__(TX* TY) op_kernel(OpArgs a)
+__global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
 {
     constexpr int NT = TX * TY, LX = TX + 1, LY = TY + 1;
     __shared__ double sn[3][LY * LX];
@@ -612,7 +708,8 @@ __global__ void __launch_bounds__(TX* TY) op_kernel(OpArgs a)
     const int plane = nx * ny;
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     const int ntiles = a.tiles_x * a.tiles_y;
-    const int bz = blockIdx.x / ntiles, t = blockIdx.x - bz * ntiles;
+    const int lb = xcd_local_block();
+    const int bz = lb / ntiles, t = lb - bz * ntiles;
     const int by = t / a.tiles_x, bx = t - by * a.tiles_x;
     const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
     const int k0 = bz * a.kz;
@@ -623,7 +720,9 @@ __global__ void __launch_bounds__(TX* TY) op_kernel(OpArgs a)
     const int elem = ((gi + nx - 1) % nx) + nx * ((gj + ny - 1) % ny);
     const bool out_ok = (tx < TX - 1) && (ty < TY - 1) && (gi < nx) && (gj < ny);
     const bool has_halo = tid < LX + TY;
-    int hslot = 0, hoff = 0;
+    // lanes without a halo node re-read their own node (an L1 hit), so that
+    // every lane issues the same loads and no load sits behind a branch
+    int hslot = 0, hoff = own;
     if (has_halo) {
         const int hx = tid < LX ? tid : 0;
         const int hy = tid < LX ? 0 : tid - LX + 1;
@@ -632,115 +731,130 @@ __global__ void __launch_bounds__(TX* TY) op_kernel(OpArgs a)
     }
     const int oslot = (ty + 1) * LX + (tx + 1);
 
-    double ov[3], hv[3], oh[3], ow[3];
+    // Raw values of the next node plane, prefetched one step ahead and only
+    // combined (h_new = z + gamma h_old) when the step that needs them starts,
+    // so the loads stay in flight across a whole element layer.  All loads
+    // are unconditional: the wait counts of the compiler then never make the
+    // contraction wait on a prefetch.
+    double rz[3], rh[3], rw[3], hz[3], hh[3];
     auto fetch = [&](int kk) {
         const int kw = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
         const int base = kw * plane;
         if constexpr (FUSED) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                oh[c] = hold[c][base + own];
-                ov[c] = fma(gam, oh[c], a.z[c][base + own]);
-            }
-            if (out_ok && kk >= k0 && kk < kend) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) ow[c] = a.w[c][base + own];
-            }
-            if (has_halo) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) hv[c] = fma(gam, hold[c][base + hoff], a.z[c][base + hoff]);
+                rh[c] = hold[c][base + own];
+                rz[c] = a.z[c][base + own];
+                rw[c] = a.w[c][base + own];
+                hh[c] = hold[c][base + hoff];
+                hz[c] = a.z[c][base + hoff];
             }
         } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ov[c] = a.x[c][base + own];
-            if (has_halo) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) hv[c] = a.x[c][base + hoff];
+            for (int c = 0; c < 3; ++c) {
+                rz[c] = a.x[c][base + own];
+                hz[c] = a.x[c][base + hoff];
             }
         }
     };
+    // node values (h_new, or x) of the prefetched plane
+    auto own_value = [&](int c) { return FUSED ? fma(gam, rh[c], rz[c]) : rz[c]; };
+    auto halo_value = [&](int c) { return FUSED ? fma(gam, hh[c], hz[c]) : hz[c]; };
+    auto layer_phase = [&](int kl) {
+        const int klw = kl < 0 ? kl + nz : (kl >= nz ? kl - nz : kl);
+        return a.phase[klw * plane + elem];
+    };
 
+    // Per lane, in face-spectral form (face_fwd slots): lo = lower node plane
+    // of the current element layer, carry = upper-face forces of the previous
+    // layer (they act on the same node plane as this layer's lower face).
     double lo[3][4], carry[3][4];
+    auto read_face = [&](double (&F)[3][4]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            face_fwd(sn[c][ty * LX + tx], sn[c][ty * LX + tx + 1], sn[c][(ty + 1) * LX + tx],
+                     sn[c][(ty + 1) * LX + tx + 1], F[c]);
+    };
     // prologue: node plane k0-1 gives the lower face of element layer k0-1
     fetch(k0 - 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        sn[c][oslot] = ov[c];
-        if (has_halo) sn[c][hslot] = hv[c];
+        sn[c][oslot] = own_value(c);
+        if (has_halo) sn[c][hslot] = halo_value(c);
     }
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            lo[c][q] = sn[c][(ty + (q >> 1)) * LX + tx + (q & 1)];
-            carry[c][q] = 0.0;
-        }
+    read_face(lo);
+    const int nsteps = kend - k0 + 1;
+    // coefficients of the current layer, phase of the next one
+    double Cu[21];
+    load_coef(a.coef, layer_phase(k0 - 1), Cu);
+    int p_next = layer_phase(min(k0, kend - 1));
     fetch(k0);
     __syncthreads();
 
     double dot = 0.0;
-    const int nsteps = kend - k0 + 1;
+    double hprev[3] = {0.0, 0.0, 0.0};  // own node value of the lower plane
     for (int s = 0; s < nsteps; ++s) {
         const int ku = k0 + s;
         const int kuw = ku >= nz ? ku - nz : ku;
+        double ov[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ov[c] = own_value(c);
         if constexpr (FUSED) {
             if (out_ok && ku < kend) {
                 const int idx = kuw * plane + own;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     hnew[c][idx] = ov[c];
-                    a.w[c][idx] = fma(-lam, oh[c], ow[c]);
+                    a.w[c][idx] = fma(-lam, rh[c], rw[c]);
                 }
             }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             sn[c][oslot] = ov[c];
-            if (has_halo) sn[c][hslot] = hv[c];
+            if (has_halo) sn[c][hslot] = halo_value(c);
         }
         __syncthreads();
-        double u[3][8];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                u[c][q] = lo[c][q];
-                u[c][q + 4] = sn[c][(ty + (q >> 1)) * LX + tx + (q & 1)];
-            }
-        double hprev[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            hprev[c] = lo[c][3];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) lo[c][q] = u[c][q + 4];
-        }
-        if (s + 1 < nsteps) fetch(ku + 1);
+        double up[3][4];
+        read_face(up);
+        fetch(min(ku + 1, kend));  // the last step re-reads plane kend (unused)
 
-        const int kl = k0 - 1 + s;
-        const int klw = kl < 0 ? kl + nz : kl;
-        double Cu[21];
-        load_coef(a.coef, a.phase[klw * plane + elem], Cu);
-        double f[3][8];
-        element_force(Cu, u, f);
+        double FL[3][4], FU[3][4];
+        element_force_faces(Cu, lo, up, FL, FU);
+        // The coefficients are dead: start loading the next layer's, and the
+        // phase id of the layer after it (unconditional, with clamped
+        // indices, so that the compiler cannot merge them into the guarded
+        // prefetch and keep two copies of Cu live through the contraction).
+        __builtin_amdgcn_sched_barrier(0);
+        load_coef(a.coef, p_next, Cu);
+        p_next = layer_phase(min(k0 + s + 1, kend - 1));
 
         double mine[3] = {0.0, 0.0, 0.0};
         if (s > 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                sf[0][c][tid] = carry[c][0] + f[c][0];
-                sf[1][c][tid] = carry[c][1] + f[c][1];
-                sf[2][c][tid] = carry[c][2] + f[c][2];
-                mine[c] = carry[c][3] + f[c][3];
+                double F[4], v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) F[q] = carry[c][q] + FL[c][q];
+                face_adj(F, v);
+                sf[0][c][tid] = v[0];
+                sf[1][c][tid] = v[1];
+                sf[2][c][tid] = v[2];
+                mine[c] = v[3];
             }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) carry[c][q] = f[c][q + 4];
+            for (int q = 0; q < 4; ++q) {
+                carry[c][q] = FU[c][q];
+                lo[c][q] = up[c][q];
+            }
         __syncthreads();
         if (s > 0 && out_ok) {
-            const int idx = klw * plane + own;
+            const int kl = k0 - 1 + s;
+            const int idx = (kl < 0 ? kl + nz : kl) * plane + own;
             double yv[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -759,6 +873,8 @@ __global__ void __launch_bounds__(TX* TY) op_kernel(OpArgs a)
                 dot += yv[0] * yv[0] + yv[1] * yv[1] + yv[2] * yv[2];
             }
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hprev[c] = ov[c];
     }
     if (FUSED || a.want_norm) {
         double v[1] = {dot};
@@ -766,7 +882,16 @@ __global__ void __launch_bounds__(TX* TY) op_kernel(OpArgs a)
     }
 }
 
-constexpr int kTX = 16, kTY = 16;
+#ifndef E3D_TX
+#define E3D_TX 32
+#endif
+#ifndef E3D_TY
+#define E3D_TY 8
+#endif
+#ifndef E3D_OP_TARGET_BLOCKS
+#define E3D_OP_TARGET_BLOCKS 4096
+#endif
+constexpr int kTX = E3D_TX, kTY = E3D_TY;
 
 // ------------------------------------------------------------ post-process
 
@@ -818,10 +943,12 @@ __global__ void __launch_bounds__(kBlock) stress_kernel(Dims d, const int32_t* _
                          2.0 * E.e[4] + 0.25 * (u[0][MZ] + u[2][MX]),
                          2.0 * E.e[5] + 0.25 * (u[0][MY] + u[1][MX])};
         double Cu[21];
-        load_coef(coef, phase[e], Cu);
+        load_coef(coef, phase[e], Cu);  // C/16
         constexpr int sup[6] = {0, 1, 2, 3, 4, 5};
         double sg[6];
         contract<6>(Cu, sup, eps, sg);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) sg[r] *= 16.0;
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
             if (store) out.s[r][e] = sg[r];
@@ -892,7 +1019,7 @@ OpGeom op_geometry(const Dims& d, int kz_hint)
     int kz = kz_hint;
     if (kz <= 0) {
         // enough workgroups to fill 256 CUs several times over
-        const int target = 4096;
+        const int target = E3D_OP_TARGET_BLOCKS;
         int chunks = (target + ntiles - 1) / ntiles;
         if (chunks > d.nz) chunks = d.nz;
         kz = (d.nz + chunks - 1) / chunks;
