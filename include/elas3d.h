@@ -109,6 +109,8 @@ typedef struct elas3d_info {
     int64_t n_operator;                        /* fused-operator launches timed      */
     double t_update_ms;                        /* summed update-kernel time          */
     int64_t n_update;                          /* update launches timed              */
+    int32_t fp64_fallback[ELAS3D_MAX_RHS];     /* mixed: 1 if the refinement stalled
+                                                  and the solve finished in FP64    */
 } elas3d_info;
 
 /* Fill `opt` with the defaults (FP64, residual criterion, block Jacobi,

@@ -20,6 +20,7 @@
 using e3d::Dims;
 using e3d::Fields;
 using e3d::Scalars;
+using e3d::FieldsT;
 
 namespace {
 
@@ -54,6 +55,10 @@ struct elas3d_ctx {
     double* w = nullptr;     // nrhs * 3N
     double* work = nullptr;  // g, z, h0, h1, Ah: 15N
     double* minv = nullptr;  // 6N
+    // mixed precision: FP32 g, z, h0, h1, Ah, d (18N floats), M^-1 (6N), table
+    float* work32 = nullptr;
+    float* minv32 = nullptr;
+    float* coef32 = nullptr;
     double* partials = nullptr;
     int partial_stride = 0;
     double* norms = nullptr;  // nrhs * 2: ||b||^2, ||b||_ref^2
@@ -89,7 +94,25 @@ struct elas3d_ctx {
     {
         for (int q = 0; q < 6; ++q) out[q] = minv + (size_t)q * N();
     }
-    e3d::Tables tables() const { return e3d::Tables{coef, diag, solid}; }
+    e3d::FieldsT<float> fields32()
+    {
+        e3d::FieldsT<float> f;
+        for (int c = 0; c < 3; ++c) {
+            f.g[c] = work32 + (size_t)c * N();
+            f.z[c] = work32 + (size_t)(3 + c) * N();
+            f.h0[c] = work32 + (size_t)(6 + c) * N();
+            f.h1[c] = work32 + (size_t)(9 + c) * N();
+            f.Ah[c] = work32 + (size_t)(12 + c) * N();
+            f.w[c] = work32 + (size_t)(15 + c) * N();
+            f.b[c] = nullptr;
+        }
+        return f;
+    }
+    void minv32_planes(float* out[6]) const
+    {
+        for (int q = 0; q < 6; ++q) out[q] = minv32 + (size_t)q * N();
+    }
+    e3d::Tables tables() const { return e3d::Tables{coef, coef32, diag, solid}; }
 };
 
 namespace {
@@ -122,10 +145,11 @@ void default_options(elas3d_options* o)
 
 // Device bytes of a context (kept in one place so the budget check and
 // elas3d_device_bytes agree).
-double plan_bytes(int64_t n, int nphase, int nrhs)
+double plan_bytes(int64_t n, int nphase, int nrhs, bool mixed)
 {
     const double N = (double)n;
     double bytes = 0.0;
+    if (mixed) bytes += 4.0 * 24.0 * N + 4.0 * nphase * e3d::kCoefStride;  // FP32 work, M^-1, table
     bytes += 4.0 * N;                          // phase ids
     bytes += 8.0 * 3.0 * N * nrhs * 2.0;       // b and w per case
     bytes += 8.0 * 15.0 * N;                   // g, z, h0, h1, Ah
@@ -212,8 +236,6 @@ int validate_options(const elas3d_options* o)
         return fail(nullptr, ELAS3D_EBADARG, "options.hbm_budget_bytes must be finite and >= 0");
     if (!(o->inner_tol >= 0.0) || !(o->inner_tol < 1.0))
         return fail(nullptr, ELAS3D_EBADARG, "options.inner_tol must be in [0, 1)");
-    if (o->precision == ELAS3D_PREC_MIXED)
-        return fail(nullptr, ELAS3D_EBADARG, "mixed precision is not available in this build");
     if (o->batched)
         return fail(nullptr, ELAS3D_EBADARG, "batched multi-RHS is not available in this build");
     return 0;
@@ -266,7 +288,8 @@ void free_ctx(elas3d_ctx* c)
     if (c->stream) hipStreamSynchronize(c->stream);
     for (void* p : {(void*)c->phase, (void*)c->coef, (void*)c->diag, (void*)c->solid, (void*)c->sig,
                     (void*)c->b, (void*)c->w, (void*)c->work, (void*)c->minv, (void*)c->partials,
-                    (void*)c->norms, (void*)c->dscratch, (void*)c->dflag, (void*)c->S})
+                    (void*)c->norms, (void*)c->dscratch, (void*)c->dflag, (void*)c->S,
+                    (void*)c->work32, (void*)c->minv32, (void*)c->coef32})
         if (p) hipFree(p);
     if (c->hS) hipHostFree(c->hS);
     if (c->hscratch) hipHostFree(c->hscratch);
@@ -299,129 +322,161 @@ hipMemcpyKind copy_kind(const elas3d_ctx* c, bool to_device)
     return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
 }
 
-// One PCG run on case `rhs`, restarting from w when the recursive residual
-// and the true one disagree (residual criterion only).
-int solve_case(elas3d_ctx* c, int rhs, double tol, int maxit, elas3d_info* info)
+struct RunStats {
+    Scalars fin{};       // device scalars at the end of the run
+    int it_start = 0;    // iteration counter when the run started
+};
+
+// Enqueue PCG iterations (direction+operator sweep, update sweep) in batches
+// of `poll` until the device raises its stop flag; the host looks at the flag
+// of batch k while batch k+1 is already queued.  Optional HIP-event timing of
+// every sweep that did real work.
+template <typename T>
+int iterate(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], int maxit, elas3d_info* info,
+            RunStats& rs)
+{
+    const Dims& d = c->d;
+    const e3d::Tables t = c->tables();
+    const int poll = c->opt.poll_interval > 0 ? c->opt.poll_interval : kDefaultPoll;
+    const bool timing = c->opt.timing != 0;
+    HIPCHK(c, hipMemcpyAsync(&c->hS[0], c->S, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    rs.it_start = c->hS[0].it;
+    size_t ev_used = 0;
+    if (!c->hS[0].done) {
+        hipEvent_t batch_ev[2] = {nullptr, nullptr};
+        HIPCHK(c, hipEventCreateWithFlags(&batch_ev[0], hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&batch_ev[1], hipEventDisableTiming));
+        const long long max_launch = (long long)maxit - rs.it_start + poll;
+        long long launched = 0;
+        bool recorded[2] = {false, false};
+        auto enqueue = [&](int slot) -> int {
+            for (int j = 0; j < poll; ++j) {
+                if (timing) {
+                    int rc = ensure_events(c, c->ev_op, ev_used + 1);
+                    if (rc) return rc;
+                    rc = ensure_events(c, c->ev_up, ev_used + 1);
+                    if (rc) return rc;
+                    HIPCHK(c, hipEventRecord(c->ev_op[ev_used].a, c->stream));
+                }
+                HIPCHK(c, e3d::launch_direction_operator<T>(c->stream, d, c->geom, c->phase, t, f, c->S,
+                                                            c->partials));
+                if (timing) {
+                    HIPCHK(c, hipEventRecord(c->ev_op[ev_used].b, c->stream));
+                    HIPCHK(c, hipEventRecord(c->ev_up[ev_used].a, c->stream));
+                }
+                HIPCHK(c, e3d::launch_update_precond<T>(c->stream, d, f, M, c->S, c->partials,
+                                                        kSweepBlocks));
+                if (timing) {
+                    HIPCHK(c, hipEventRecord(c->ev_up[ev_used].b, c->stream));
+                    ++ev_used;
+                }
+            }
+            launched += poll;
+            HIPCHK(c, hipMemcpyAsync(&c->hS[slot], c->S, sizeof(Scalars), hipMemcpyDeviceToHost,
+                                     c->stream));
+            HIPCHK(c, hipEventRecord(batch_ev[slot], c->stream));
+            recorded[slot] = true;
+            return 0;
+        };
+        int rc = enqueue(0);
+        bool stop = false;
+        int k = 0;
+        while (!rc && !stop) {
+            const int slot = k & 1;
+            if (launched < max_launch) rc = enqueue(slot ^ 1);
+            if (rc) break;
+            hipError_t e = hipEventSynchronize(batch_ev[slot]);
+            if (e != hipSuccess) {
+                rc = fail(c, ELAS3D_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+                break;
+            }
+            if (c->hS[slot].done) stop = true;
+            if (!stop && launched >= max_launch) {
+                // the last batch is in flight: wait for it
+                e = recorded[slot ^ 1] ? hipEventSynchronize(batch_ev[slot ^ 1]) : hipSuccess;
+                if (e != hipSuccess) {
+                    rc = fail(c, ELAS3D_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+                    break;
+                }
+                stop = true;
+            }
+            ++k;
+        }
+        hipStreamSynchronize(c->stream);
+        hipEventDestroy(batch_ev[0]);
+        hipEventDestroy(batch_ev[1]);
+        if (rc) return rc;
+    }
+    HIPCHK(c, e3d::launch_final_update<T>(c->stream, d, f, c->S));
+    HIPCHK(c, hipMemcpyAsync(&c->hS[0], c->S, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    rs.fin = c->hS[0];
+    if (timing && info) {
+        // only the sweeps that ran before the stop flag count
+        const int real = rs.fin.it - rs.it_start + (rs.fin.status == 2 ? 1 : 0);
+        for (int q = 0; q < real && q < (int)ev_used; ++q) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev_op[q].a, c->ev_op[q].b) == hipSuccess) {
+                info->t_operator_ms += ms;
+                info->n_operator += 1;
+            }
+            if (q < rs.fin.it - rs.it_start &&
+                hipEventElapsedTime(&ms, c->ev_up[q].a, c->ev_up[q].b) == hipSuccess) {
+                info->t_update_ms += ms;
+                info->n_update += 1;
+            }
+        }
+    }
+    return 0;
+}
+
+// Start a PCG run: load tol/maxit/mode and the iteration counter into the
+// device scalars, then the init sweep (fresh: w = 0, g = b; otherwise g
+// already holds the residual to continue from).
+template <typename T>
+int start_run(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], double tol, int maxit, int mode,
+              int it0, int fresh, int from_residual, const double* norms2)
+{
+    Scalars init{};
+    init.tol = tol;
+    init.maxit = maxit;
+    init.mode = mode;
+    init.it = it0;
+    std::memcpy(&c->hS[0], &init, sizeof(Scalars));
+    HIPCHK(c, hipMemcpyAsync(c->S, &c->hS[0], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, e3d::launch_pcg_init<T>(c->stream, c->d, f, M, fresh, from_residual, c->S, c->partials,
+                                      kSweepBlocks, norms2));
+    return 0;
+}
+
+// FP64 PCG on case `rhs` (Algorithm 2), from w = 0 or (continue) from the
+// current w with g = A w + b already in place; in residual mode restart from
+// w whenever the recursive and the true residual disagree.
+int solve_fp64(elas3d_ctx* c, int rhs, double tol, int maxit, bool cont, int it0, elas3d_info* info,
+               Scalars& fin, int& restarts, double& rel_true)
 {
     const Dims& d = c->d;
     Fields f = c->fields(rhs);
     double* M[6];
     c->minv_planes(M);
     const e3d::Tables t = c->tables();
-    const int poll = c->opt.poll_interval > 0 ? c->opt.poll_interval : kDefaultPoll;
-    const bool timing = c->opt.timing != 0;
-
-    Scalars init{};
-    init.tol = tol;
-    init.maxit = maxit;
-    init.mode = c->opt.convergence;
-    init.it = 0;
-    std::memcpy(&c->hS[0], &init, sizeof(Scalars));
-    HIPCHK(c, hipMemcpyAsync(c->S, &c->hS[0], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, e3d::launch_pcg_init(c->stream, d, f, M, 1, 0, c->S, c->partials, kSweepBlocks,
-                                   c->norms + 2 * rhs));
-    int restarts = 0;
-    double rel_true = 0.0;
-    Scalars fin{};
+    int rc = start_run<double>(c, f, M, tol, maxit, c->opt.convergence, it0, cont ? 0 : 1,
+                               cont ? 1 : 0, c->norms + 2 * rhs);
+    if (rc) return rc;
     for (;;) {
-        // iterate: batches of `poll` iterations, host one batch behind
-        HIPCHK(c, hipMemcpyAsync(&c->hS[0], c->S, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        const int it_start = c->hS[0].it;
-        std::vector<int> op_idx;  // timing event slots used, in launch order
-        size_t ev_used = 0;
-        if (!c->hS[0].done) {
-            hipEvent_t batch_ev[2] = {nullptr, nullptr};
-            HIPCHK(c, hipEventCreateWithFlags(&batch_ev[0], hipEventDisableTiming));
-            HIPCHK(c, hipEventCreateWithFlags(&batch_ev[1], hipEventDisableTiming));
-            const long long max_launch = (long long)maxit - it_start + poll;
-            long long launched = 0;
-            int k = 0;
-            bool recorded[2] = {false, false};
-            auto enqueue = [&](int slot) -> int {
-                for (int j = 0; j < poll; ++j) {
-                    if (timing) {
-                        int rc = ensure_events(c, c->ev_op, ev_used + 1);
-                        if (rc) return rc;
-                        rc = ensure_events(c, c->ev_up, ev_used + 1);
-                        if (rc) return rc;
-                        HIPCHK(c, hipEventRecord(c->ev_op[ev_used].a, c->stream));
-                    }
-                    HIPCHK(c, e3d::launch_direction_operator(c->stream, d, c->geom, c->phase, t, f,
-                                                             c->S, c->partials));
-                    if (timing) {
-                        HIPCHK(c, hipEventRecord(c->ev_op[ev_used].b, c->stream));
-                        HIPCHK(c, hipEventRecord(c->ev_up[ev_used].a, c->stream));
-                    }
-                    HIPCHK(c, e3d::launch_update_precond(c->stream, d, f, M, c->S, c->partials,
-                                                         kSweepBlocks));
-                    if (timing) {
-                        HIPCHK(c, hipEventRecord(c->ev_up[ev_used].b, c->stream));
-                        ++ev_used;
-                    }
-                }
-                launched += poll;
-                HIPCHK(c, hipMemcpyAsync(&c->hS[slot], c->S, sizeof(Scalars), hipMemcpyDeviceToHost,
-                                         c->stream));
-                HIPCHK(c, hipEventRecord(batch_ev[slot], c->stream));
-                recorded[slot] = true;
-                return 0;
-            };
-            int rc = enqueue(0);
-            bool stop = false;
-            while (!rc && !stop) {
-                const int slot = k & 1;
-                if (launched < max_launch) rc = enqueue(slot ^ 1);
-                if (rc) break;
-                hipError_t e = hipEventSynchronize(batch_ev[slot]);
-                if (e != hipSuccess) {
-                    rc = fail(c, ELAS3D_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
-                    break;
-                }
-                if (c->hS[slot].done) stop = true;
-                if (!stop && launched >= max_launch) {
-                    // the last batch is in flight: wait for it
-                    e = recorded[slot ^ 1] ? hipEventSynchronize(batch_ev[slot ^ 1]) : hipSuccess;
-                    if (e != hipSuccess) {
-                        rc = fail(c, ELAS3D_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
-                        break;
-                    }
-                    stop = true;
-                }
-                ++k;
-            }
-            hipStreamSynchronize(c->stream);
-            hipEventDestroy(batch_ev[0]);
-            hipEventDestroy(batch_ev[1]);
-            if (rc) return rc;
-        }
-        HIPCHK(c, e3d::launch_final_update(c->stream, d, f, c->S));
+        RunStats rs;
+        rc = iterate<double>(c, f, M, maxit, info, rs);
+        if (rc) return rc;
         // true residual r = A w + b (into g, ready for a restart)
         const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
         double* gy[3] = {f.g[0], f.g[1], f.g[2]};
         HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom, c->phase, t, wx, gy, f.b, c->partials,
                                     c->dscratch));
-        HIPCHK(c, hipMemcpyAsync(&c->hS[0], c->S, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        fin = c->hS[0];
-        if (timing) {
-            // only the sweeps that ran before the stop flag count
-            const int real = fin.it - it_start + (fin.status == 2 ? 1 : 0);
-            for (int q = 0; q < real && q < (int)ev_used; ++q) {
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, c->ev_op[q].a, c->ev_op[q].b) == hipSuccess && info) {
-                    info->t_operator_ms += ms;
-                    info->n_operator += 1;
-                }
-                if (q < fin.it - it_start &&
-                    hipEventElapsedTime(&ms, c->ev_up[q].a, c->ev_up[q].b) == hipSuccess && info) {
-                    info->t_update_ms += ms;
-                    info->n_update += 1;
-                }
-            }
-        }
+        fin = rs.fin;
         const bool zero_load = fin.bnorm2 <= 1e-28 * fin.bref2;
         rel_true = (zero_load || fin.bnorm2 <= 0.0) ? 0.0 : std::sqrt(c->hscratch[0] / fin.bnorm2);
         if (c->opt.convergence == ELAS3D_CONV_RESIDUAL && fin.status == 0 && !zero_load &&
@@ -431,19 +486,126 @@ int solve_case(elas3d_ctx* c, int rhs, double tol, int maxit, elas3d_info* info)
                 break;
             }
             ++restarts;
-            HIPCHK(c, e3d::launch_pcg_init(c->stream, d, f, M, 0, 1, c->S, c->partials, kSweepBlocks,
-                                           c->norms + 2 * rhs));
+            rc = start_run<double>(c, f, M, tol, maxit, c->opt.convergence, fin.it, 0, 1,
+                                   c->norms + 2 * rhs);
+            if (rc) return rc;
             continue;
         }
         break;
     }
+    return 0;
+}
+
+// Mixed precision (iterative refinement): the correction d of A d = -r is
+// solved by the FP32 PCG to a relative reduction of the inner tolerance,
+// then w += d and r = A w + b are formed in FP64 in one sweep.  If a cycle
+// does not reduce the true residual, the solve continues in FP64 from w.
+int solve_mixed(elas3d_ctx* c, int rhs, double tol, int maxit, elas3d_info* info, Scalars& fin,
+                int& cycles, double& rel_true)
+{
+    const Dims& d = c->d;
+    Fields f64 = c->fields(rhs);
+    e3d::FieldsT<float> f32 = c->fields32();
+    float* M32[6];
+    c->minv32_planes(M32);
+    const e3d::Tables t = c->tables();
+    double* w[3] = {f64.w[0], f64.w[1], f64.w[2]};
+    const float* dcorr[3] = {f32.w[0], f32.w[1], f32.w[2]};
+    float* r32[3] = {f32.g[0], f32.g[1], f32.g[2]};
+    const double inner_tol = c->opt.inner_tol > 0.0 ? c->opt.inner_tol : 1e-4;
+    // w = 0, d = 0, then r = b (rounded) and ||b||^2 from the refinement sweep
+    for (int q = 0; q < 3; ++q) {
+        HIPCHK(c, hipMemsetAsync(w[q], 0, sizeof(double) * c->N(), c->stream));
+        HIPCHK(c, hipMemsetAsync(f32.w[q], 0, sizeof(float) * c->N(), c->stream));
+    }
+    HIPCHK(c, e3d::launch_refine(c->stream, d, c->geom, c->phase, t, w, dcorr, f64.b, r32, c->partials,
+                                 c->dscratch));
+    HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hscratch + 2, c->norms + 2 * rhs, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double bnorm2 = c->hscratch[2], bref2 = c->hscratch[3];
+    double rnorm2 = c->hscratch[0];
+    fin = Scalars{};
+    fin.bnorm2 = bnorm2;
+    fin.bref2 = bref2;
+    fin.status = 1;
+    int iters = 0;
+    cycles = 0;
+    if (bnorm2 <= 1e-28 * bref2) {  // zero load
+        fin.status = 0;
+        rel_true = 0.0;
+        return 0;
+    }
+    rel_true = std::sqrt(rnorm2 / bnorm2);
+    while (rel_true > tol && iters < maxit) {
+        // inner FP32 PCG from d = 0 on g = r (rounded), relative tolerance:
+        // the cycle's target, not tighter than needed for the outer one
+        const double target = std::max(inner_tol, 0.5 * tol / rel_true);
+        HIPCHK(c, hipMemcpyAsync(c->dscratch + 4, c->dscratch, sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->dscratch + 5, c->dscratch, sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+        int rc = start_run<float>(c, f32, M32, target, maxit - iters, ELAS3D_CONV_RESIDUAL, 0, 1, 1,
+                                  c->dscratch + 4);
+        if (rc) return rc;
+        RunStats rs;
+        rc = iterate<float>(c, f32, M32, maxit - iters, info, rs);
+        if (rc) return rc;
+        iters += rs.fin.it;
+        ++cycles;
+        // w += d, r = A w + b (FP64), stored rounded for the next cycle
+        HIPCHK(c, e3d::launch_refine(c->stream, d, c->geom, c->phase, t, w, dcorr, f64.b, r32,
+                                     c->partials, c->dscratch));
+        HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const double prev = rel_true;
+        rnorm2 = c->hscratch[0];
+        rel_true = std::sqrt(rnorm2 / bnorm2);
+        fin.rr = rs.fin.rr;
+        fin.gg = rs.fin.gg;
+        fin.gg0 = rs.fin.gg0;
+        if (rs.fin.status == 2 || !(rel_true < 0.5 * prev)) {
+            // stagnation or breakdown of the FP32 solve: finish in FP64 from w
+            const double* wx[3] = {w[0], w[1], w[2]};
+            double* gy[3] = {f64.g[0], f64.g[1], f64.g[2]};
+            HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom, c->phase, t, wx, gy, f64.b, c->partials,
+                                        c->dscratch));
+            int restarts = 0;
+            Scalars f64fin{};
+            rc = solve_fp64(c, rhs, tol, maxit, true, iters, info, f64fin, restarts, rel_true);
+            if (rc) return rc;
+            fin = f64fin;
+            cycles += restarts;
+            if (info) info->fp64_fallback[rhs] = 1;
+            return 0;
+        }
+    }
+    fin.it = iters;
+    fin.status = rel_true <= tol ? 0 : 1;
+    return 0;
+}
+
+int solve_case(elas3d_ctx* c, int rhs, double tol, int maxit, elas3d_info* info)
+{
+    Scalars fin{};
+    int restarts = 0;
+    double rel_true = 0.0;
+    int rc;
+    if (c->opt.precision == ELAS3D_PREC_MIXED)
+        rc = solve_mixed(c, rhs, tol, maxit, info, fin, restarts, rel_true);
+    else
+        rc = solve_fp64(c, rhs, tol, maxit, false, 0, info, fin, restarts, rel_true);
+    if (rc) return rc;
     if (info) {
+        const bool zero_load = fin.bnorm2 <= 1e-28 * fin.bref2;
         info->status[rhs] = fin.status;
         info->iters[rhs] = fin.it;
         info->restarts[rhs] = restarts;
         info->relres_true[rhs] = rel_true;
-        const bool zero_load = fin.bnorm2 <= 1e-28 * fin.bref2;
-        info->relres_recursive[rhs] = (zero_load || fin.bnorm2 <= 0) ? 0.0 : std::sqrt(fin.rr / fin.bnorm2);
+        info->relres_recursive[rhs] =
+            (zero_load || fin.bnorm2 <= 0) ? 0.0 : std::sqrt(fin.rr / fin.bnorm2);
         info->relres_precond[rhs] = (zero_load || fin.gg0 <= 0) ? 0.0 : std::sqrt(std::fabs(fin.gg / fin.gg0));
     }
     c->solved[rhs] = 1;
@@ -470,8 +632,8 @@ const char* elas3d_last_error(const elas3d_ctx* ctx)
 double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
                            const elas3d_options* opt)
 {
-    (void)opt;
-    return plan_bytes((int64_t)nx * ny * nz, nphase, nrhs);
+    return plan_bytes((int64_t)nx * ny * nz, nphase, nrhs,
+                      opt && opt->precision == ELAS3D_PREC_MIXED);
 }
 
 int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int32_t* phase,
@@ -499,7 +661,8 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
         if (e != hipSuccess) return fail(nullptr, ELAS3D_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
     const int64_t n = (int64_t)nx * ny * nz;
-    const double need = plan_bytes(n, nphase, nrhs);
+    const bool mixed = opt.precision == ELAS3D_PREC_MIXED;
+    const double need = plan_bytes(n, nphase, nrhs, mixed);
     double budget = opt.hbm_budget_bytes;
     if (budget <= 0.0) {
         size_t free_b = 0, total_b = 0;
@@ -553,6 +716,11 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     SETUPCHK(hipMalloc(&c->w, 8 * 3 * N * nrhs));
     SETUPCHK(hipMalloc(&c->work, 8 * 15 * N));
     SETUPCHK(hipMalloc(&c->minv, 8 * 6 * N));
+    if (mixed) {
+        SETUPCHK(hipMalloc(&c->work32, 4 * 18 * N));
+        SETUPCHK(hipMalloc(&c->minv32, 4 * 6 * N));
+        SETUPCHK(hipMalloc(&c->coef32, 4 * (size_t)nphase * e3d::kCoefStride));
+    }
     SETUPCHK(hipMalloc(&c->partials, 8 * (size_t)kPartialValues * c->partial_stride));
     SETUPCHK(hipMalloc(&c->norms, 8 * 2 * (size_t)nrhs));
     SETUPCHK(hipMalloc(&c->dscratch, 8 * 16));
@@ -579,6 +747,12 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     std::vector<uint8_t> solid;
     build_tables(C, nphase, strain, nrhs, coef, diag, solid, sig);
     SETUPCHK(hipMemcpyAsync(c->coef, coef.data(), 8 * coef.size(), hipMemcpyHostToDevice, c->stream));
+    std::vector<float> coef32;
+    if (mixed) {
+        coef32.assign(coef.begin(), coef.end());  // rounded to FP32
+        SETUPCHK(hipMemcpyAsync(c->coef32, coef32.data(), 4 * coef32.size(), hipMemcpyHostToDevice,
+                                c->stream));
+    }
     SETUPCHK(hipMemcpyAsync(c->diag, diag.data(), 8 * diag.size(), hipMemcpyHostToDevice, c->stream));
     SETUPCHK(hipMemcpyAsync(c->solid, solid.data(), solid.size(), hipMemcpyHostToDevice, c->stream));
     SETUPCHK(hipMemcpyAsync(c->sig, sig.data(), 8 * sig.size(), hipMemcpyHostToDevice, c->stream));
@@ -592,6 +766,8 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->minv_planes(M);
     SETUPCHK(e3d::launch_precond(c->stream, c->d, c->phase, c->tables(),
                                  opt.preconditioner == ELAS3D_PRECOND_NONE ? 1 : 0, M));
+    // mixed: the blocks are inverted in FP64 and stored rounded to FP32
+    if (mixed) SETUPCHK(e3d::launch_to_float(c->stream, c->minv, c->minv32, 6 * N));
     // (host input arrays must not be read after return)
     SETUPCHK(hipStreamSynchronize(c->stream));
     (void)t0;
@@ -624,7 +800,10 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
         info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
         // two fused sweeps: direction+operator (read z, h, w, phase; write h, w, Ah)
         // and update+precondition (read g, Ah, M^-1; write g, z)
-        info->bytes_per_iter = (double)ctx->N() * ((6 * 24.0 + 4.0) + (4 * 24.0 + 48.0));
+        if (ctx->opt.precision == ELAS3D_PREC_MIXED)
+            info->bytes_per_iter = (double)ctx->N() * ((6 * 12.0 + 4.0) + (4 * 12.0 + 24.0));
+        else
+            info->bytes_per_iter = (double)ctx->N() * ((6 * 24.0 + 4.0) + (4 * 24.0 + 48.0));
     }
     return worst;
 }

@@ -45,20 +45,25 @@ struct Scalars {
     int pad;
 };
 
-// Field pointers of one load case (FP64 SoA planes).
-struct Fields {
-    double* w[3];
-    double* g[3];
-    double* z[3];
-    double* h0[3];
-    double* h1[3];
-    double* Ah[3];
-    const double* b[3];
+// Field pointers of one PCG run (SoA planes of T: double for the FP64 solve,
+// float for the inner solve of the mixed-precision refinement, where w is
+// the correction d and g starts as the rounded residual).
+template <typename T>
+struct FieldsT {
+    T* w[3];
+    T* g[3];
+    T* z[3];
+    T* h0[3];
+    T* h1[3];
+    T* Ah[3];
+    const T* b[3];
 };
+using Fields = FieldsT<double>;
 
 struct Tables {
-    const double* coef;  // nphase * kCoefStride
-    const double* diag;  // nphase * kDiagStride
+    const double* coef;    // nphase * kCoefStride: C/16, packed
+    const float* coef32;   // the same rounded to FP32 (mixed precision), or nullptr
+    const double* diag;    // nphase * kDiagStride
     const uint8_t* solid;  // nphase: 1 if the phase has stiffness
 };
 
@@ -78,17 +83,29 @@ hipError_t launch_load(hipStream_t st, const Dims& d, const int32_t* phase, cons
                        int max_blocks);
 hipError_t launch_precond(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
                           int identity, double* const minv[6]);
-// norms2: device {||b||^2, ||b||_ref^2} of the case (zero-load test).
-hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const Fields& f, double* const minv[6],
+// The PCG sweeps exist for T = double (FP64 solve) and T = float (inner
+// solve of the mixed-precision refinement); dot products are FP64 in both.
+// norms2: device {||b||^2, ||b||_ref^2} of the run (zero-load test).
+template <typename T>
+hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, T* const minv[6],
                            int fresh, int from_residual, Scalars* S, double* partials,
                            int max_blocks, const double* norms2);
+template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
-                                     const int32_t* phase, const Tables& t, const Fields& f,
+                                     const int32_t* phase, const Tables& t, const FieldsT<T>& f,
                                      Scalars* S, double* partials);
-hipError_t launch_update_precond(hipStream_t st, const Dims& d, const Fields& f,
-                                 double* const minv[6], Scalars* S, double* partials,
-                                 int max_blocks);
-hipError_t launch_final_update(hipStream_t st, const Dims& d, const Fields& f, Scalars* S);
+template <typename T>
+hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f,
+                                 T* const minv[6], Scalars* S, double* partials, int max_blocks);
+template <typename T>
+hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& f, Scalars* S);
+// Refinement of the mixed-precision solve: r = A (w + d) + b in FP64, stored
+// rounded to FP32, ||r||^2 (FP64) into *norm2; then w += d.
+hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
+                         const Tables& t, double* const w[3], const float* const dcorr[3],
+                         const double* const b[3], float* const r[3], double* partials,
+                         double* norm2);
+hipError_t launch_to_float(hipStream_t st, const double* src, float* dst, size_t n);
 // y = A x (+ add when add[0] != nullptr); ||y||^2 into *norm2 when norm2 != nullptr.
 hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
                         const Tables& t, const double* const x[3], double* const y[3],

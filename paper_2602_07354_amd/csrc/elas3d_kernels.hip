@@ -24,6 +24,8 @@
 // Reductions are two-stage and deterministic: a fixed-order in-block tree
 // writes one partial per block, a single-block kernel sums the partials in
 // fixed order and updates the device-resident PCG scalars.
+#include <type_traits>
+
 #include "elas3d_internal.h"
 
 namespace e3d {
@@ -44,41 +46,42 @@ __host__ __device__ constexpr int ut(int r, int c)
 // In-place +-1 transform of 8 corner values (corner a = ax + 2ay + 4az).
 // Output slot mu holds sum_a prod_{d in mu} s_d(a) v_a, s = 2 a_d - 1; slot 1
 // is X, 2 Y, 3 XY, 4 Z, 5 XZ, 6 YZ, 7 XYZ (slot 0, the plain sum, is unused).
-__device__ __forceinline__ void fwd8(double* v)
+template <typename R>
+__device__ __forceinline__ void fwd8(R* v)
 {
 #pragma unroll
     for (int bit = 1; bit < 8; bit <<= 1)
 #pragma unroll
         for (int a = 0; a < 8; ++a)
             if (!(a & bit)) {
-                const double lo = v[a], hi = v[a | bit];
+                const R lo = v[a], hi = v[a | bit];
                 v[a] = lo + hi;
                 v[a | bit] = hi - lo;
             }
 }
 
 // Adjoint (transpose) of fwd8.
-__device__ __forceinline__ void adj8(double* v)
+template <typename R>
+__device__ __forceinline__ void adj8(R* v)
 {
 #pragma unroll
     for (int bit = 1; bit < 8; bit <<= 1)
 #pragma unroll
         for (int a = 0; a < 8; ++a)
             if (!(a & bit)) {
-                const double lo = v[a], hi = v[a | bit];
+                const R lo = v[a], hi = v[a | bit];
                 v[a] = lo - hi;
                 v[a | bit] = lo + hi;
             }
 }
 
 // t = C[sup,sup] e for a support of the 6 Voigt components.
-template <int N>
-__device__ __forceinline__ void contract(const double* Cu, const int (&sup)[N], const double* e,
-                                         double* t)
+template <int N, typename R>
+__device__ __forceinline__ void contract(const R* Cu, const int (&sup)[N], const R* e, R* t)
 {
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        double acc = Cu[ut(sup[r], sup[0])] * e[0];
+        R acc = Cu[ut(sup[r], sup[0])] * e[0];
 #pragma unroll
         for (int c = 1; c < N; ++c) acc = fma(Cu[ut(sup[r], sup[c])], e[c], acc);
         t[r] = acc;
@@ -96,9 +99,10 @@ enum { MX = 1, MY = 2, MXY = 3, MZ = 4, MXZ = 5, MYZ = 6, MXYZ = 7 };
 //
 // modal_core: H[c][mu] (slots MX..MXYZ, unscaled) -> G[c][mu] = dE/dH (slot 0
 // is not written and must be treated as 0).  H is scaled in place.
-__device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], double (&G)[3][8])
+template <typename R>
+__device__ __forceinline__ void modal_core(const R* Cs, R (&H)[3][8], R (&G)[3][8])
 {
-    constexpr double third = 1.0 / 3.0, ninth = 1.0 / 9.0;
+    const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         H[c][MXY] *= third;
@@ -109,9 +113,9 @@ __device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], 
     // constant mode: full 6-component strain
     {
         constexpr int sup[6] = {0, 1, 2, 3, 4, 5};
-        const double e[6] = {H[0][MX], H[1][MY], H[2][MZ], H[1][MZ] + H[2][MY], H[0][MZ] + H[2][MX],
-                             H[0][MY] + H[1][MX]};
-        double t[6];
+        const R e[6] = {H[0][MX], H[1][MY], H[2][MZ], H[1][MZ] + H[2][MY], H[0][MZ] + H[2][MX],
+                        H[0][MY] + H[1][MX]};
+        R t[6];
         contract<6>(Cs, sup, e, t);
         G[0][MX] = t[0];
         G[1][MY] = t[1];
@@ -126,8 +130,8 @@ __device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], 
     // X mode: (yy, zz, yz, xz, xy)
     {
         constexpr int sup[5] = {1, 2, 3, 4, 5};
-        const double e[5] = {H[1][MXY], H[2][MXZ], H[1][MXZ] + H[2][MXY], H[0][MXZ], H[0][MXY]};
-        double t[5];
+        const R e[5] = {H[1][MXY], H[2][MXZ], H[1][MXZ] + H[2][MXY], H[0][MXZ], H[0][MXY]};
+        R t[5];
         contract<5>(Cs, sup, e, t);
         G[1][MXY] = t[0];
         G[2][MXZ] = t[1];
@@ -139,8 +143,8 @@ __device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], 
     // Y mode: (xx, zz, yz, xz, xy)
     {
         constexpr int sup[5] = {0, 2, 3, 4, 5};
-        const double e[5] = {H[0][MXY], H[2][MYZ], H[1][MYZ], H[0][MYZ] + H[2][MXY], H[1][MXY]};
-        double t[5];
+        const R e[5] = {H[0][MXY], H[2][MYZ], H[1][MYZ], H[0][MYZ] + H[2][MXY], H[1][MXY]};
+        R t[5];
         contract<5>(Cs, sup, e, t);
         G[0][MXY] += t[0];
         G[2][MYZ] = t[1];
@@ -152,8 +156,8 @@ __device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], 
     // Z mode: (xx, yy, yz, xz, xy)
     {
         constexpr int sup[5] = {0, 1, 3, 4, 5};
-        const double e[5] = {H[0][MXZ], H[1][MYZ], H[2][MYZ], H[2][MXZ], H[0][MYZ] + H[1][MXZ]};
-        double t[5];
+        const R e[5] = {H[0][MXZ], H[1][MYZ], H[2][MYZ], H[2][MXZ], H[0][MYZ] + H[1][MXZ]};
+        R t[5];
         contract<5>(Cs, sup, e, t);
         G[0][MXZ] += t[0];
         G[1][MYZ] += t[1];
@@ -165,8 +169,8 @@ __device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], 
     // YZ mode: (xx, xz, xy)
     {
         constexpr int sup[3] = {0, 4, 5};
-        const double e[3] = {H[0][MXYZ], H[2][MXYZ], H[1][MXYZ]};
-        double t[3];
+        const R e[3] = {H[0][MXYZ], H[2][MXYZ], H[1][MXYZ]};
+        R t[3];
         contract<3>(Cs, sup, e, t);
         G[0][MXYZ] = t[0];
         G[2][MXYZ] = t[1];
@@ -175,8 +179,8 @@ __device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], 
     // XZ mode: (yy, yz, xy)
     {
         constexpr int sup[3] = {1, 3, 5};
-        const double e[3] = {H[1][MXYZ], H[2][MXYZ], H[0][MXYZ]};
-        double t[3];
+        const R e[3] = {H[1][MXYZ], H[2][MXYZ], H[0][MXYZ]};
+        R t[3];
         contract<3>(Cs, sup, e, t);
         G[1][MXYZ] += t[0];
         G[2][MXYZ] += t[1];
@@ -185,8 +189,8 @@ __device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], 
     // XY mode: (zz, yz, xz)
     {
         constexpr int sup[3] = {2, 3, 4};
-        const double e[3] = {H[2][MXYZ], H[1][MXYZ], H[0][MXYZ]};
-        double t[3];
+        const R e[3] = {H[2][MXYZ], H[1][MXYZ], H[0][MXYZ]};
+        R t[3];
         contract<3>(Cs, sup, e, t);
         G[2][MXYZ] += t[0];
         G[1][MXYZ] += t[1];
@@ -196,16 +200,17 @@ __device__ __forceinline__ void modal_core(const double* Cs, double (&H)[3][8], 
 
 // f = K_e u for one voxel with the scaled packed stiffness Cs.  u[c][a] is
 // destroyed.  f[c][a]: force component c on corner a.
-__device__ __forceinline__ void element_force(const double* Cs, double (&u)[3][8], double (&f)[3][8])
+template <typename R>
+__device__ __forceinline__ void element_force(const R* Cs, R (&u)[3][8], R (&f)[3][8])
 {
     fwd8(u[0]);
     fwd8(u[1]);
     fwd8(u[2]);
-    double g[3][8];
+    R g[3][8];
     modal_core(Cs, u, g);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        g[c][0] = 0.0;
+        g[c][0] = R(0);
         adj8(g[c]);
 #pragma unroll
         for (int a = 0; a < 8; ++a) f[c][a] = g[c][a];
@@ -213,9 +218,10 @@ __device__ __forceinline__ void element_force(const double* Cs, double (&u)[3][8
 }
 
 // 2D transform of a face (corner q = ax + 2ay) into the slots {sum, X, Y, XY}.
-__device__ __forceinline__ void face_fwd(double v0, double v1, double v2, double v3, double (&F)[4])
+template <typename R>
+__device__ __forceinline__ void face_fwd(R v0, R v1, R v2, R v3, R (&F)[4])
 {
-    const double p0 = v0 + v1, d0 = v1 - v0, p1 = v2 + v3, d1 = v3 - v2;
+    const R p0 = v0 + v1, d0 = v1 - v0, p1 = v2 + v3, d1 = v3 - v2;
     F[0] = p0 + p1;
     F[2] = p1 - p0;
     F[1] = d0 + d1;
@@ -223,9 +229,10 @@ __device__ __forceinline__ void face_fwd(double v0, double v1, double v2, double
 }
 
 // Adjoint of face_fwd: face slots -> corner values.
-__device__ __forceinline__ void face_adj(const double (&F)[4], double (&v)[4])
+template <typename R>
+__device__ __forceinline__ void face_adj(const R (&F)[4], R (&v)[4])
 {
-    const double o0 = F[0] - F[1], o1 = F[0] + F[1], o2 = F[2] - F[3], o3 = F[2] + F[3];
+    const R o0 = F[0] - F[1], o1 = F[0] + F[1], o2 = F[2] - F[3], o3 = F[2] + F[3];
     v[0] = o0 - o2;
     v[2] = o0 + o2;
     v[1] = o1 - o3;
@@ -235,11 +242,11 @@ __device__ __forceinline__ void face_adj(const double (&F)[4], double (&v)[4])
 // Element operator on face spectra: L, U = face_fwd of the lower (z) and
 // upper node planes' corner values; returns the face spectra FL, FU of the
 // lower- and upper-face corner forces (face_adj turns them into forces).
-__device__ __forceinline__ void element_force_faces(const double* Cs, const double (&L)[3][4],
-                                                    const double (&U)[3][4], double (&FL)[3][4],
-                                                    double (&FU)[3][4])
+template <typename R>
+__device__ __forceinline__ void element_force_faces(const R* Cs, const R (&L)[3][4], const R (&U)[3][4],
+                                                    R (&FL)[3][4], R (&FU)[3][4])
 {
-    double H[3][8], G[3][8];
+    R H[3][8], G[3][8];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         // z stage: slots without z are sums of the faces, slots with z differences
@@ -266,6 +273,7 @@ __device__ __forceinline__ void element_force_faces(const double* Cs, const doub
     }
 }
 
+// 21 packed coefficients of phase p (table stride kCoefStride entries).
 __device__ __forceinline__ void load_coef(const double* __restrict__ coef, int p, double (&Cu)[21])
 {
     const double2* src = reinterpret_cast<const double2*>(coef + (size_t)p * kCoefStride);
@@ -274,6 +282,20 @@ __device__ __forceinline__ void load_coef(const double* __restrict__ coef, int p
         const double2 v = src[q];
         Cu[2 * q] = v.x;
         Cu[2 * q + 1] = v.y;
+    }
+    Cu[20] = coef[(size_t)p * kCoefStride + 20];
+}
+
+__device__ __forceinline__ void load_coef(const float* __restrict__ coef, int p, float (&Cu)[21])
+{
+    const float4* src = reinterpret_cast<const float4*>(coef + (size_t)p * kCoefStride);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const float4 v = src[q];
+        Cu[4 * q] = v.x;
+        Cu[4 * q + 1] = v.y;
+        Cu[4 * q + 2] = v.z;
+        Cu[4 * q + 3] = v.w;
     }
     Cu[20] = coef[(size_t)p * kCoefStride + 20];
 }
@@ -526,112 +548,107 @@ __global__ void __launch_bounds__(kBlock) precond_kernel(Dims d, const int32_t* 
     }
 }
 
-__device__ __forceinline__ void apply_minv(const double* const* M, int m, double g0, double g1,
-                                           double g2, double& z0, double& z1, double& z2)
-{
-    const double xx = M[0][m], yy = M[1][m], zz = M[2][m], yz = M[3][m], xz = M[4][m], xy = M[5][m];
-    z0 = xx * g0 + xy * g1 + xz * g2;
-    z1 = xy * g0 + yy * g1 + yz * g2;
-    z2 = xz * g0 + yz * g1 + zz * g2;
-}
-
-struct Minv {
-    const double* m[6];
+template <typename T>
+struct MinvT {
+    const T* m[6];
 };
 
 // Start (or restart) of a PCG run: g = b (or the residual already in g),
-// z = M^-1 g, current direction h = 0, w = 0 on a fresh start.
-__global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, Fields f, Minv M, int fresh,
+// z = M^-1 g, current direction h = 0, w = 0 on a fresh start.  Dots in FP64.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, MinvT<T> M, int fresh,
                                                           int from_residual, double* partials,
                                                           int stride)
 {
     double acc[2] = {0.0, 0.0};
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        double g0, g1, g2;
-        if (from_residual) {
-            g0 = f.g[0][m];
-            g1 = f.g[1][m];
-            g2 = f.g[2][m];
-        } else {
-            g0 = f.b[0][m];
-            g1 = f.b[1][m];
-            g2 = f.b[2][m];
-            f.g[0][m] = g0;
-            f.g[1][m] = g1;
-            f.g[2][m] = g2;
+        T g[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            g[c] = from_residual ? f.g[c][m] : f.b[c][m];
+            if (!from_residual) f.g[c][m] = g[c];
         }
-        double z0, z1, z2;
-        apply_minv(M.m, m, g0, g1, g2, z0, z1, z2);
+        const T xx = M.m[0][m], yy = M.m[1][m], zz = M.m[2][m];
+        const T yz = M.m[3][m], xz = M.m[4][m], xy = M.m[5][m];
+        const T z0 = xx * g[0] + xy * g[1] + xz * g[2];
+        const T z1 = xy * g[0] + yy * g[1] + yz * g[2];
+        const T z2 = xz * g[0] + yz * g[1] + zz * g[2];
         f.z[0][m] = z0;
         f.z[1][m] = z1;
         f.z[2][m] = z2;
-        f.h0[0][m] = 0.0;
-        f.h0[1][m] = 0.0;
-        f.h0[2][m] = 0.0;
-        if (fresh) {
-            f.w[0][m] = 0.0;
-            f.w[1][m] = 0.0;
-            f.w[2][m] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            f.h0[c][m] = T(0);
+            if (fresh) f.w[c][m] = T(0);
         }
-        acc[0] += z0 * g0 + z1 * g1 + z2 * g2;
-        acc[1] += g0 * g0 + g1 * g1 + g2 * g2;
+        acc[0] += (double)z0 * g[0] + (double)z1 * g[1] + (double)z2 * g[2];
+        acc[1] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
     }
     block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
 }
 
-// Algorithm 2, C-D: g -= lambda Ah, z = M^-1 g, partial z.g and g.g.
+// Algorithm 2, C-D: g -= lambda Ah, z = M^-1 g, partial z.g and g.g (FP64).
 // (w -= lambda h is deferred to the next direction sweep, which reads h anyway.)
-// Update sweep body for one node (g -= lambda Ah, z = M^-1 g).
-__device__ __forceinline__ void update_node(double lam, const double (&g)[3], const double (&ah)[3],
-                                            const double (&mm)[6], double (&go)[3], double (&zo)[3])
-{
-    go[0] = fma(-lam, ah[0], g[0]);
-    go[1] = fma(-lam, ah[1], g[1]);
-    go[2] = fma(-lam, ah[2], g[2]);
-    const double xx = mm[0], yy = mm[1], zz = mm[2], yz = mm[3], xz = mm[4], xy = mm[5];
-    zo[0] = xx * go[0] + xy * go[1] + xz * go[2];
-    zo[1] = xy * go[0] + yy * go[1] + yz * go[2];
-    zo[2] = xz * go[0] + yz * go[1] + zz * go[2];
-}
-
-__global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, Fields f, Minv M,
+template <typename T>
+__global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<T> f, MinvT<T> M,
                                                                 const Scalars* S, double* partials,
                                                                 int stride)
 {
     if (S->done) return;
-    const double lam = S->lambda;
+    const T lam = (T)S->lambda;
     double acc[2] = {0.0, 0.0};
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        double g[3], ah[3], mm[6], go[3], zo[3];
+        T g[3], mm[6];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            g[c] = f.g[c][m];
-            ah[c] = f.Ah[c][m];
-        }
+        for (int c = 0; c < 3; ++c) g[c] = fma(-lam, f.Ah[c][m], f.g[c][m]);
 #pragma unroll
         for (int q = 0; q < 6; ++q) mm[q] = M.m[q][m];
-        update_node(lam, g, ah, mm, go, zo);
+        const T xx = mm[0], yy = mm[1], zz = mm[2], yz = mm[3], xz = mm[4], xy = mm[5];
+        const T z0 = xx * g[0] + xy * g[1] + xz * g[2];
+        const T z1 = xy * g[0] + yy * g[1] + yz * g[2];
+        const T z2 = xz * g[0] + yz * g[1] + zz * g[2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            f.g[c][m] = go[c];
-            f.z[c][m] = zo[c];
-        }
-        acc[0] += zo[0] * go[0] + zo[1] * go[1] + zo[2] * go[2];
-        acc[1] += go[0] * go[0] + go[1] * go[1] + go[2] * go[2];
+        for (int c = 0; c < 3; ++c) f.g[c][m] = g[c];
+        f.z[0][m] = z0;
+        f.z[1][m] = z1;
+        f.z[2][m] = z2;
+        acc[0] += (double)z0 * g[0] + (double)z1 * g[1] + (double)z2 * g[2];
+        acc[1] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
     }
     block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
 }
 
 // The step size of the last iteration still owed to w.
-__global__ void __launch_bounds__(kBlock) final_update_kernel(Dims d, Fields f, const Scalars* S)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) final_update_kernel(Dims d, FieldsT<T> f, const Scalars* S)
 {
     if (!S->pending) return;
-    const double lam = S->lambda;
-    double* const* h = S->cur ? f.h1 : f.h0;
+    const T lam = (T)S->lambda;
+    T* const* h = S->cur ? f.h1 : f.h0;
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) f.w[c][m] = fma(-lam, h[c][m], f.w[c][m]);
     }
+}
+
+// w += d (FP64 iterate, FP32 correction), after the refinement sweep.
+__global__ void __launch_bounds__(kBlock) add_correction_kernel(Dims d, double* w0, double* w1,
+                                                                double* w2, const float* d0,
+                                                                const float* d1, const float* d2)
+{
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        w0[m] += (double)d0[m];
+        w1[m] += (double)d1[m];
+        w2[m] += (double)d2[m];
+    }
+}
+
+// dst = (float) src, n elements.
+__global__ void __launch_bounds__(kBlock) to_float_kernel(const double* __restrict__ src,
+                                                          float* __restrict__ dst, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        dst[i] = (float)src[i];
 }
 
 // ------------------------------------------------------- tiled operator sweep
@@ -654,48 +671,61 @@ __device__ __forceinline__ int xcd_local_block()
     return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
 }
 
+// Operator sweep modes.
+enum OpMode { OP_APPLY = 0, OP_FUSED = 1, OP_REFINE = 2 };
+
+template <typename T>
 struct OpArgs {
     Dims d;
     int tiles_x, tiles_y, kz;
     const int32_t* phase;
-    const double* coef;
-    // operator input: x (apply) or z, h_old (fused direction update)
-    const double* x[3];
-    const double* z[3];
-    double* h0[3];
-    double* h1[3];
-    double* w[3];
-    // output y = A x (+ add)
-    double* y[3];
+    const T* coef;  // FUSED: table in T; APPLY / REFINE: FP64 table
+    // APPLY / REFINE input x (FP64); REFINE adds the FP32 correction xd on the
+    // fly (x itself is not written: neighbouring workgroups read it at their
+    // halo nodes during the sweep)
+    double* x[3];
+    const float* xd[3];
+    // FUSED: z, the two direction buffers, w
+    const T* z[3];
+    T* h0[3];
+    T* h1[3];
+    T* w[3];
+    // outputs: y (APPLY: FP64, FUSED: T), yr (REFINE: FP32)
+    T* y[3];
+    double* yd[3];
+    float* yr[3];
     const double* add[3];
     const Scalars* S;
     double* partials;
     int want_norm;
 };
 
-// FUSED = false: y = A x (+ add), optional ||y||^2 partials.
-// FUSED = true : Algorithm 2 steps E and A of one iteration in a single sweep:
-//   h_new = z + gamma h_old (written to the other direction buffer),
-//   w -= lambda h_old (the previous step, deferred), Ah = A h_new and the
-//   partial h_new.Ah.
+// OP_APPLY : y = A x (+ add) in FP64, optional ||y||^2 partials.
+// OP_FUSED : Algorithm 2 steps E and A of one iteration in a single sweep, in
+//            T: h_new = z + gamma h_old (written to the other direction
+//            buffer), w -= lambda h_old (the previous step, deferred),
+//            Ah = A h_new and the partial h_new.Ah (FP64).
+// OP_REFINE: y = A (x + xd) + add in FP64, stored as FP32, ||y||^2.
 #ifndef E3D_OP_MIN_WAVES
 #define E3D_OP_MIN_WAVES 1
 #endif
 
-template <int TX, int TY, bool FUSED>
-__global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
+template <int TX, int TY, int MODE, typename T>
+__global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> a)
 {
+    constexpr bool FUSED = MODE == OP_FUSED;
+    using R = typename std::conditional<FUSED, T, double>::type;  // arithmetic type
     constexpr int NT = TX * TY, LX = TX + 1, LY = TY + 1;
-    __shared__ double sn[3][LY * LX];
-    __shared__ double sf[3][3][NT];
+    __shared__ R sn[3][LY * LX];
+    __shared__ R sf[3][3][NT];
 
-    double gam = 0.0, lam = 0.0;
-    const double* hold[3] = {nullptr, nullptr, nullptr};
-    double* hnew[3] = {nullptr, nullptr, nullptr};
+    R gam = R(0), lam = R(0);
+    const T* hold[3] = {nullptr, nullptr, nullptr};
+    T* hnew[3] = {nullptr, nullptr, nullptr};
     if constexpr (FUSED) {
         if (a.S->done) return;
-        gam = a.S->gamma;
-        lam = a.S->lambda;
+        gam = (R)a.S->gamma;
+        lam = (R)a.S->lambda;
         const int cur = a.S->cur;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -703,6 +733,7 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
             hnew[c] = cur ? a.h0[c] : a.h1[c];
         }
     }
+    const R* coef = reinterpret_cast<const R*>(a.coef);
 
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
     const int plane = nx * ny;
@@ -732,11 +763,11 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
     const int oslot = (ty + 1) * LX + (tx + 1);
 
     // Raw values of the next node plane, prefetched one step ahead and only
-    // combined (h_new = z + gamma h_old) when the step that needs them starts,
-    // so the loads stay in flight across a whole element layer.  All loads
-    // are unconditional: the wait counts of the compiler then never make the
-    // contraction wait on a prefetch.
-    double rz[3], rh[3], rw[3], hz[3], hh[3];
+    // combined (h_new = z + gamma h_old, or x + xd) when the step that needs
+    // them starts, so the loads stay in flight across a whole element layer.
+    // All loads are unconditional: the wait counts of the compiler then never
+    // make the contraction wait on a prefetch.
+    R rz[3], rh[3], rw[3], hz[3], hh[3];
     auto fetch = [&](int kk) {
         const int kw = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
         const int base = kw * plane;
@@ -749,6 +780,14 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
                 hh[c] = hold[c][base + hoff];
                 hz[c] = a.z[c][base + hoff];
             }
+        } else if constexpr (MODE == OP_REFINE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                rz[c] = a.x[c][base + own];
+                rh[c] = a.xd[c][base + own];
+                hz[c] = a.x[c][base + hoff];
+                hh[c] = a.xd[c][base + hoff];
+            }
         } else {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -757,9 +796,17 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
             }
         }
     };
-    // node values (h_new, or x) of the prefetched plane
-    auto own_value = [&](int c) { return FUSED ? fma(gam, rh[c], rz[c]) : rz[c]; };
-    auto halo_value = [&](int c) { return FUSED ? fma(gam, hh[c], hz[c]) : hz[c]; };
+    // node values (h_new, x + xd or x) of the prefetched plane
+    auto own_value = [&](int c) -> R {
+        if constexpr (FUSED) return fma(gam, rh[c], rz[c]);
+        else if constexpr (MODE == OP_REFINE) return rz[c] + rh[c];
+        else return rz[c];
+    };
+    auto halo_value = [&](int c) -> R {
+        if constexpr (FUSED) return fma(gam, hh[c], hz[c]);
+        else if constexpr (MODE == OP_REFINE) return hz[c] + hh[c];
+        else return hz[c];
+    };
     auto layer_phase = [&](int kl) {
         const int klw = kl < 0 ? kl + nz : (kl >= nz ? kl - nz : kl);
         return a.phase[klw * plane + elem];
@@ -768,8 +815,8 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
     // Per lane, in face-spectral form (face_fwd slots): lo = lower node plane
     // of the current element layer, carry = upper-face forces of the previous
     // layer (they act on the same node plane as this layer's lower face).
-    double lo[3][4], carry[3][4];
-    auto read_face = [&](double (&F)[3][4]) {
+    R lo[3][4], carry[3][4];
+    auto read_face = [&](R (&F)[3][4]) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             face_fwd(sn[c][ty * LX + tx], sn[c][ty * LX + tx + 1], sn[c][(ty + 1) * LX + tx],
@@ -786,23 +833,23 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
     read_face(lo);
     const int nsteps = kend - k0 + 1;
     // coefficients of the current layer, phase of the next one
-    double Cu[21];
-    load_coef(a.coef, layer_phase(k0 - 1), Cu);
+    R Cu[21];
+    load_coef(coef, layer_phase(k0 - 1), Cu);
     int p_next = layer_phase(min(k0, kend - 1));
     fetch(k0);
     __syncthreads();
 
     double dot = 0.0;
-    double hprev[3] = {0.0, 0.0, 0.0};  // own node value of the lower plane
+    R hprev[3] = {R(0), R(0), R(0)};  // own node value of the lower plane
     for (int s = 0; s < nsteps; ++s) {
         const int ku = k0 + s;
         const int kuw = ku >= nz ? ku - nz : ku;
-        double ov[3];
+        R ov[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) ov[c] = own_value(c);
-        if constexpr (FUSED) {
-            if (out_ok && ku < kend) {
-                const int idx = kuw * plane + own;
+        if (out_ok && ku < kend) {
+            const int idx = kuw * plane + own;
+            if constexpr (FUSED) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     hnew[c][idx] = ov[c];
@@ -816,25 +863,25 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
             if (has_halo) sn[c][hslot] = halo_value(c);
         }
         __syncthreads();
-        double up[3][4];
+        R up[3][4];
         read_face(up);
         fetch(min(ku + 1, kend));  // the last step re-reads plane kend (unused)
 
-        double FL[3][4], FU[3][4];
+        R FL[3][4], FU[3][4];
         element_force_faces(Cu, lo, up, FL, FU);
         // The coefficients are dead: start loading the next layer's, and the
         // phase id of the layer after it (unconditional, with clamped
         // indices, so that the compiler cannot merge them into the guarded
         // prefetch and keep two copies of Cu live through the contraction).
         __builtin_amdgcn_sched_barrier(0);
-        load_coef(a.coef, p_next, Cu);
+        load_coef(coef, p_next, Cu);
         p_next = layer_phase(min(k0 + s + 1, kend - 1));
 
-        double mine[3] = {0.0, 0.0, 0.0};
+        R mine[3] = {R(0), R(0), R(0)};
         if (s > 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double F[4], v[4];
+                R F[4], v[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) F[q] = carry[c][q] + FL[c][q];
                 face_adj(F, v);
@@ -855,20 +902,22 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs a)
         if (s > 0 && out_ok) {
             const int kl = k0 - 1 + s;
             const int idx = (kl < 0 ? kl + nz : kl) * plane + own;
-            double yv[3];
+            R yv[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double v = mine[c] + sf[2][c][tid + 1];
+                R v = mine[c] + sf[2][c][tid + 1];
                 v += sf[1][c][tid + TX];
                 v += sf[0][c][tid + TX + 1];
                 if constexpr (!FUSED) {
                     if (a.add[0]) v += a.add[c][idx];
                 }
                 yv[c] = v;
-                a.y[c][idx] = v;
+                if constexpr (FUSED) a.y[c][idx] = v;
+                else if constexpr (MODE == OP_REFINE) a.yr[c][idx] = (float)v;
+                else a.yd[c][idx] = v;
             }
             if constexpr (FUSED) {
-                dot += hprev[0] * yv[0] + hprev[1] * yv[1] + hprev[2] * yv[2];
+                dot += (double)hprev[0] * yv[0] + (double)hprev[1] * yv[1] + (double)hprev[2] * yv[2];
             } else {
                 dot += yv[0] * yv[0] + yv[1] * yv[1] + yv[2] * yv[2];
             }
@@ -1052,36 +1101,42 @@ hipError_t launch_precond(hipStream_t st, const Dims& d, const int32_t* phase, c
     return hipGetLastError();
 }
 
-static Minv mk_minv(double* const minv[6])
+template <typename T>
+static MinvT<T> mk_minv(T* const minv[6])
 {
-    Minv M;
+    MinvT<T> M;
     for (int q = 0; q < 6; ++q) M.m[q] = minv[q];
     return M;
 }
 
-hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const Fields& f, double* const minv[6],
+template <typename T>
+hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, T* const minv[6],
                            int fresh, int from_residual, Scalars* S, double* partials,
                            int max_blocks, const double* norms2)
 {
     const int nb = sweep_blocks(d.n, max_blocks);
-    hipLaunchKernelGGL(pcg_init_kernel, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv), fresh,
+    hipLaunchKernelGGL(pcg_init_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv), fresh,
                        from_residual, partials, nb);
     hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_INIT,
                        (const double*)partials, nb, nb, S, (double*)nullptr, norms2);
     return hipGetLastError();
 }
 
+template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
-                                     const int32_t* phase, const Tables& t, const Fields& f,
+                                     const int32_t* phase, const Tables& t, const FieldsT<T>& f,
                                      Scalars* S, double* partials)
 {
-    OpArgs a = {};
+    OpArgs<T> a = {};
     a.d = d;
     a.tiles_x = g.tiles_x;
     a.tiles_y = g.tiles_y;
     a.kz = g.kz;
     a.phase = phase;
-    a.coef = t.coef;
+    if constexpr (std::is_same<T, float>::value)
+        a.coef = t.coef32;
+    else
+        a.coef = t.coef;
     for (int c = 0; c < 3; ++c) {
         a.z[c] = f.z[c];
         a.h0[c] = f.h0[c];
@@ -1091,36 +1146,51 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
     }
     a.S = S;
     a.partials = partials;
-    hipLaunchKernelGGL((op_kernel<kTX, kTY, true>), dim3(g.blocks), dim3(kTX * kTY), 0, st, a);
+    hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_FUSED, T>), dim3(g.blocks), dim3(kTX * kTY), 0, st, a);
     hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_DIRECTION,
                        (const double*)partials, g.blocks, g.blocks, S, (double*)nullptr,
                        (const double*)nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_update_precond(hipStream_t st, const Dims& d, const Fields& f,
-                                 double* const minv[6], Scalars* S, double* partials, int max_blocks)
+template <typename T>
+hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f,
+                                 T* const minv[6], Scalars* S, double* partials, int max_blocks)
 {
     const int nb = sweep_blocks(d.n, max_blocks);
-    hipLaunchKernelGGL(update_precond_kernel, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv),
+    hipLaunchKernelGGL(update_precond_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv),
                        (const Scalars*)S, partials, nb);
     hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_UPDATE,
                        (const double*)partials, nb, nb, S, (double*)nullptr, (const double*)nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_final_update(hipStream_t st, const Dims& d, const Fields& f, Scalars* S)
+template <typename T>
+hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& f, Scalars* S)
 {
     const int nb = sweep_blocks(d.n, 4096);
-    hipLaunchKernelGGL(final_update_kernel, dim3(nb), dim3(kBlock), 0, st, d, f, (const Scalars*)S);
+    hipLaunchKernelGGL(final_update_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, (const Scalars*)S);
     return hipGetLastError();
 }
+
+#define E3D_INSTANTIATE(T)                                                                          \
+    template hipError_t launch_pcg_init<T>(hipStream_t, const Dims&, const FieldsT<T>&, T* const[6],  \
+                                           int, int, Scalars*, double*, int, const double*);         \
+    template hipError_t launch_direction_operator<T>(hipStream_t, const Dims&, const OpGeom&,         \
+                                                     const int32_t*, const Tables&,                  \
+                                                     const FieldsT<T>&, Scalars*, double*);          \
+    template hipError_t launch_update_precond<T>(hipStream_t, const Dims&, const FieldsT<T>&,         \
+                                                 T* const[6], Scalars*, double*, int);               \
+    template hipError_t launch_final_update<T>(hipStream_t, const Dims&, const FieldsT<T>&, Scalars*);
+E3D_INSTANTIATE(double)
+E3D_INSTANTIATE(float)
+#undef E3D_INSTANTIATE
 
 hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
                         const Tables& t, const double* const x[3], double* const y[3],
                         const double* const add[3], double* partials, double* norm2)
 {
-    OpArgs a = {};
+    OpArgs<double> a = {};
     a.d = d;
     a.tiles_x = g.tiles_x;
     a.tiles_y = g.tiles_y;
@@ -1128,17 +1198,58 @@ hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const in
     a.phase = phase;
     a.coef = t.coef;
     for (int c = 0; c < 3; ++c) {
-        a.x[c] = x[c];
-        a.y[c] = y[c];
+        a.x[c] = const_cast<double*>(x[c]);  // read only in this mode
+        a.yd[c] = y[c];
         a.add[c] = add ? add[c] : nullptr;
     }
     a.partials = partials;
     a.want_norm = norm2 != nullptr;
-    hipLaunchKernelGGL((op_kernel<kTX, kTY, false>), dim3(g.blocks), dim3(kTX * kTY), 0, st, a);
+    hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_APPLY, double>), dim3(g.blocks), dim3(kTX * kTY), 0, st,
+                       a);
     if (norm2)
         hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
                            (const double*)partials, g.blocks, g.blocks, (Scalars*)nullptr, norm2,
                            (const double*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
+                         const Tables& t, double* const w[3], const float* const dcorr[3],
+                         const double* const b[3], float* const r[3], double* partials,
+                         double* norm2)
+{
+    OpArgs<double> a = {};
+    a.d = d;
+    a.tiles_x = g.tiles_x;
+    a.tiles_y = g.tiles_y;
+    a.kz = g.kz;
+    a.phase = phase;
+    a.coef = t.coef;
+    for (int c = 0; c < 3; ++c) {
+        a.x[c] = w[c];
+        a.xd[c] = dcorr[c];
+        a.yr[c] = r[c];
+        a.add[c] = b[c];
+    }
+    a.partials = partials;
+    a.want_norm = 1;
+    hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_REFINE, double>), dim3(g.blocks), dim3(kTX * kTY), 0, st,
+                       a);
+    hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
+                       (const double*)partials, g.blocks, g.blocks, (Scalars*)nullptr, norm2,
+                       (const double*)nullptr);
+    const int nb = sweep_blocks(d.n, 4096);
+    hipLaunchKernelGGL(add_correction_kernel, dim3(nb), dim3(kBlock), 0, st, d, w[0], w[1], w[2],
+                       dcorr[0], dcorr[1], dcorr[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_float(hipStream_t st, const double* src, float* dst, size_t n)
+{
+    size_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(to_float_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, src, dst, n);
     return hipGetLastError();
 }
 

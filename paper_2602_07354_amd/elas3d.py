@@ -78,6 +78,7 @@ class Info(ctypes.Structure):
         ("n_operator", ctypes.c_int64),
         ("t_update_ms", ctypes.c_double),
         ("n_update", ctypes.c_int64),
+        ("fp64_fallback", ctypes.c_int32 * _R),
     ]
 
     def as_dict(self) -> dict:
@@ -96,6 +97,7 @@ class Info(ctypes.Structure):
             "n_operator": self.n_operator,
             "t_update_ms": self.t_update_ms,
             "n_update": self.n_update,
+            "fp64_fallback": list(self.fp64_fallback[:n]),
         }
 
 

@@ -40,7 +40,7 @@ def test_struct_layout_matches_c(E, tmp_path):
         'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(elas3d_options), offsetof(elas3d_options, hbm_budget_bytes),'
         " offsetof(elas3d_options, stream), offsetof(elas3d_options, batched),"
         " sizeof(elas3d_info), offsetof(elas3d_info, relres_true));\n"
-        'printf("%zu %zu\\n", offsetof(elas3d_info, t_operator_ms), offsetof(elas3d_info, n_update));\n'
+        'printf("%zu %zu %zu\\n", offsetof(elas3d_info, t_operator_ms), offsetof(elas3d_info, n_update), offsetof(elas3d_info, fp64_fallback));\n'
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -48,7 +48,7 @@ def test_struct_layout_matches_c(E, tmp_path):
     c = [int(v) for v in out]
     py = [ctypes.sizeof(E.Options), E.Options.hbm_budget_bytes.offset, E.Options.stream.offset,
           E.Options.batched.offset, ctypes.sizeof(E.Info), E.Info.relres_true.offset,
-          E.Info.t_operator_ms.offset, E.Info.n_update.offset]
+          E.Info.t_operator_ms.offset, E.Info.n_update.offset, E.Info.fp64_fallback.offset]
     assert c == py
 
 

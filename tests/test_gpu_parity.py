@@ -217,3 +217,42 @@ def test_deterministic_and_device_inputs(E):
     with pytest.raises(E.Elas3dError) as ei:
         E.setup(ms.shape, bad, ms.C, ms.strain, opts)
     assert ei.value.code == E.EBADARG
+
+
+@pytest.mark.parametrize("case", ["eshelby", "poly"])
+def test_mixed_precision_refinement_matches_oracle(E, orc, case):
+    """FP32 inner PCG inside FP64 refinement, driven to a true FP64 residual of
+    1e-12: displacement and stress match the FP64 oracle to the FP64 bar."""
+    say("case: mixed precision", case)
+    ms = synth.eshelby_inclusion(20) if case == "eshelby" else _small_poly((28, 24, 20), 41, grains=16)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    with E.Context.from_micro(ms, precision=E.PREC_MIXED) as ctx:
+        st, info = ctx.solve(1e-12, 20000)
+        say("mixed", info["iters"][0], "inner iterations,", info["restarts"][0], "cycles, fallback",
+            info["fp64_fallback"][0], "oracle", ro["iters"])
+        assert st == E.OK and info["relres_true"][0] <= 1e-12
+        w = ctx.solution(0)
+        out = ctx.stress(0)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    assert _rel(out["sigma"], so) <= 1e-8
+    active = np.any(np.abs(P.precond()).reshape(ms.n, 9) > 0, axis=1)
+    d1 = w[:, active] - w[:, active].mean(axis=1, keepdims=True)
+    d0 = ro["w"][:, active] - ro["w"][:, active].mean(axis=1, keepdims=True)
+    assert _rel(d1, d0) <= 1e-8
+
+
+def test_mixed_precision_metric_tolerance_poly100(E):
+    """Mixed precision at the metric tolerance on the 100^3 polycrystal: the
+    FP64 true residual meets 1e-8 and the stress agrees with the FP64 solve."""
+    say("case: mixed precision poly100")
+    ms = synth.workload("poly100")
+    with E.Context.from_micro(ms) as c64:
+        st, i64 = c64.solve(1e-10, 20000)
+        s64 = c64.stress(0)
+    with E.Context.from_micro(ms, precision=E.PREC_MIXED) as c32:
+        st, i32 = c32.solve(1e-8, 20000)
+        s32 = c32.stress(0)
+    say("fp64 iters", i64["iters"][0], "mixed iters", i32["iters"][0], "cycles", i32["restarts"][0])
+    assert st == E.OK and i32["relres_true"][0] <= 1e-8
+    assert np.allclose(s32["avg"], s64["avg"], rtol=1e-7, atol=1e-12)
