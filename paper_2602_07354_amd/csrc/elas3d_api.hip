@@ -51,22 +51,24 @@ struct elas3d_ctx {
     double* diag = nullptr;
     uint8_t* solid = nullptr;
     double* sig = nullptr;
-    double* b = nullptr;     // nrhs * 3N
-    double* w = nullptr;     // nrhs * 3N
-    double* work = nullptr;  // g, z, h0, h1, Ah: 15N
+    // FP64 fields.  Batched: per RHS one bundle [w 3N | b 3N | g z h0 h1 Ah 15N]
+    // so that every field of RHS r lies r*21N after RHS 0's.  Otherwise the
+    // RHS keep [w | b] (6N each) and share one 15N work area after them.
+    double* bundle64 = nullptr;
     double* minv = nullptr;  // 6N
-    // mixed precision: FP32 g, z, h0, h1, Ah, d (18N floats), M^-1 (6N), table
-    float* work32 = nullptr;
+    // mixed precision: FP32 g, z, h0, h1, Ah, d (18N floats per work slot),
+    // M^-1 (6N), table
+    float* bundle32 = nullptr;
     float* minv32 = nullptr;
     float* coef32 = nullptr;
     double* partials = nullptr;
     int partial_stride = 0;
     double* norms = nullptr;  // nrhs * 2: ||b||^2, ||b||_ref^2
-    double* dscratch = nullptr;  // 16 doubles
+    double* dscratch = nullptr;  // 64 doubles
     int* dflag = nullptr;
     Scalars* S = nullptr;
-    Scalars* hS = nullptr;        // pinned, 2 slots
-    double* hscratch = nullptr;   // pinned, 16 doubles
+    Scalars* hS = nullptr;        // pinned, 2 slots of kMaxRhs
+    double* hscratch = nullptr;   // pinned, 64 doubles
     std::vector<int> solved;
     double bytes = 0.0;
     std::string err;
@@ -76,17 +78,28 @@ struct elas3d_ctx {
     size_t N() const { return (size_t)d.n; }
     double* plane(double* base, int q) const { return base + (size_t)q * N(); }
 
+    bool batched() const { return opt.batched != 0; }
+    size_t rs64() const { return (batched() ? 21 : 6) * N(); }  // RHS stride of the bundles
+    size_t rs32() const { return 18 * N(); }
+    double* wptr(int r) const { return bundle64 + (size_t)r * rs64(); }
+    double* bptr(int r) const { return wptr(r) + 3 * N(); }
+    double* work64(int r) const
+    {
+        return batched() ? wptr(r) + 6 * N() : bundle64 + (size_t)nrhs * 6 * N();
+    }
+    float* work32(int r) const { return bundle32 + (batched() ? (size_t)r * rs32() : 0); }
     Fields fields(int rhs)
     {
         Fields f;
+        double* wk = work64(rhs);
         for (int c = 0; c < 3; ++c) {
-            f.w[c] = plane(w, 3 * rhs + c);
-            f.b[c] = plane(b, 3 * rhs + c);
-            f.g[c] = plane(work, c);
-            f.z[c] = plane(work, 3 + c);
-            f.h0[c] = plane(work, 6 + c);
-            f.h1[c] = plane(work, 9 + c);
-            f.Ah[c] = plane(work, 12 + c);
+            f.w[c] = wptr(rhs) + (size_t)c * N();
+            f.b[c] = bptr(rhs) + (size_t)c * N();
+            f.g[c] = wk + (size_t)c * N();
+            f.z[c] = wk + (size_t)(3 + c) * N();
+            f.h0[c] = wk + (size_t)(6 + c) * N();
+            f.h1[c] = wk + (size_t)(9 + c) * N();
+            f.Ah[c] = wk + (size_t)(12 + c) * N();
         }
         return f;
     }
@@ -94,16 +107,17 @@ struct elas3d_ctx {
     {
         for (int q = 0; q < 6; ++q) out[q] = minv + (size_t)q * N();
     }
-    e3d::FieldsT<float> fields32()
+    e3d::FieldsT<float> fields32(int rhs)
     {
         e3d::FieldsT<float> f;
+        float* wk = work32(rhs);
         for (int c = 0; c < 3; ++c) {
-            f.g[c] = work32 + (size_t)c * N();
-            f.z[c] = work32 + (size_t)(3 + c) * N();
-            f.h0[c] = work32 + (size_t)(6 + c) * N();
-            f.h1[c] = work32 + (size_t)(9 + c) * N();
-            f.Ah[c] = work32 + (size_t)(12 + c) * N();
-            f.w[c] = work32 + (size_t)(15 + c) * N();
+            f.g[c] = wk + (size_t)c * N();
+            f.z[c] = wk + (size_t)(3 + c) * N();
+            f.h0[c] = wk + (size_t)(6 + c) * N();
+            f.h1[c] = wk + (size_t)(9 + c) * N();
+            f.Ah[c] = wk + (size_t)(12 + c) * N();
+            f.w[c] = wk + (size_t)(15 + c) * N();
             f.b[c] = nullptr;
         }
         return f;
@@ -145,14 +159,15 @@ void default_options(elas3d_options* o)
 
 // Device bytes of a context (kept in one place so the budget check and
 // elas3d_device_bytes agree).
-double plan_bytes(int64_t n, int nphase, int nrhs, bool mixed)
+double plan_bytes(int64_t n, int nphase, int nrhs, bool mixed, bool batched)
 {
     const double N = (double)n;
     double bytes = 0.0;
-    if (mixed) bytes += 4.0 * 24.0 * N + 4.0 * nphase * e3d::kCoefStride;  // FP32 work, M^-1, table
+    if (mixed)  // FP32 work, M^-1, table
+        bytes += 4.0 * (18.0 * (batched ? nrhs : 1) + 6.0) * N + 4.0 * nphase * e3d::kCoefStride;
     bytes += 4.0 * N;                          // phase ids
     bytes += 8.0 * 3.0 * N * nrhs * 2.0;       // b and w per case
-    bytes += 8.0 * 15.0 * N;                   // g, z, h0, h1, Ah
+    bytes += 8.0 * 15.0 * N * (batched ? nrhs : 1);  // g, z, h0, h1, Ah
     bytes += 8.0 * 6.0 * N;                    // M^-1 (symmetric 3x3)
     bytes += (double)nphase * 8.0 * (e3d::kCoefStride + e3d::kDiagStride + 1.0) +
              (double)nphase * nrhs * 8.0 * e3d::kSigStride;
@@ -236,8 +251,6 @@ int validate_options(const elas3d_options* o)
         return fail(nullptr, ELAS3D_EBADARG, "options.hbm_budget_bytes must be finite and >= 0");
     if (!(o->inner_tol >= 0.0) || !(o->inner_tol < 1.0))
         return fail(nullptr, ELAS3D_EBADARG, "options.inner_tol must be in [0, 1)");
-    if (o->batched)
-        return fail(nullptr, ELAS3D_EBADARG, "batched multi-RHS is not available in this build");
     return 0;
 }
 
@@ -287,9 +300,9 @@ void free_ctx(elas3d_ctx* c)
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     for (void* p : {(void*)c->phase, (void*)c->coef, (void*)c->diag, (void*)c->solid, (void*)c->sig,
-                    (void*)c->b, (void*)c->w, (void*)c->work, (void*)c->minv, (void*)c->partials,
+                    (void*)c->bundle64, (void*)c->minv, (void*)c->partials,
                     (void*)c->norms, (void*)c->dscratch, (void*)c->dflag, (void*)c->S,
-                    (void*)c->work32, (void*)c->minv32, (void*)c->coef32})
+                    (void*)c->bundle32, (void*)c->minv32, (void*)c->coef32})
         if (p) hipFree(p);
     if (c->hS) hipHostFree(c->hS);
     if (c->hscratch) hipHostFree(c->hscratch);
@@ -327,27 +340,40 @@ struct RunStats {
     int it_start = 0;    // iteration counter when the run started
 };
 
-// Enqueue PCG iterations (direction+operator sweep, update sweep) in batches
-// of `poll` until the device raises its stop flag; the host looks at the flag
-// of batch k while batch k+1 is already queued.  Optional HIP-event timing of
-// every sweep that did real work.
+// Enqueue PCG iterations (direction+operator sweep, update sweep) for the
+// batch of R right-hand sides [r0, r0+R) in batches of `poll`, until the
+// device has raised the stop flag of every RHS; the host looks at the flags of
+// batch k while batch k+1 is already queued.  Optional HIP-event timing of
+// every launch that did real work.  Then the step owed to w is applied.
 template <typename T>
-int iterate(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], int maxit, elas3d_info* info,
-            RunStats& rs)
+int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* const M[6], int maxit,
+            elas3d_info* info, RunStats* rs_out)
 {
     const Dims& d = c->d;
     const e3d::Tables t = c->tables();
     const int poll = c->opt.poll_interval > 0 ? c->opt.poll_interval : kDefaultPoll;
     const bool timing = c->opt.timing != 0;
-    HIPCHK(c, hipMemcpyAsync(&c->hS[0], c->S, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    Scalars* S0 = c->S + r0;
+    Scalars* h0 = c->hS;                      // slot 0
+    Scalars* h1 = c->hS + e3d::kMaxRhs;       // slot 1
+    auto all_done = [&](const Scalars* h) {
+        for (int r = 0; r < R; ++r)
+            if (!h[r].done) return false;
+        return true;
+    };
+    HIPCHK(c, hipMemcpyAsync(h0, S0, R * sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    rs.it_start = c->hS[0].it;
+    int min_start = maxit;
+    for (int r = 0; r < R; ++r) {
+        rs_out[r].it_start = h0[r].it;
+        if (!h0[r].done) min_start = std::min(min_start, h0[r].it);
+    }
     size_t ev_used = 0;
-    if (!c->hS[0].done) {
+    if (!all_done(h0)) {
         hipEvent_t batch_ev[2] = {nullptr, nullptr};
         HIPCHK(c, hipEventCreateWithFlags(&batch_ev[0], hipEventDisableTiming));
         HIPCHK(c, hipEventCreateWithFlags(&batch_ev[1], hipEventDisableTiming));
-        const long long max_launch = (long long)maxit - rs.it_start + poll;
+        const long long max_launch = (long long)maxit - min_start + poll;
         long long launched = 0;
         bool recorded[2] = {false, false};
         auto enqueue = [&](int slot) -> int {
@@ -359,13 +385,13 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], int maxit, elas3d
                     if (rc) return rc;
                     HIPCHK(c, hipEventRecord(c->ev_op[ev_used].a, c->stream));
                 }
-                HIPCHK(c, e3d::launch_direction_operator<T>(c->stream, d, c->geom, c->phase, t, f, c->S,
-                                                            c->partials));
+                HIPCHK(c, e3d::launch_direction_operator<T>(c->stream, d, c->geom, c->phase, t, f0, rs,
+                                                            R, S0, c->partials));
                 if (timing) {
                     HIPCHK(c, hipEventRecord(c->ev_op[ev_used].b, c->stream));
                     HIPCHK(c, hipEventRecord(c->ev_up[ev_used].a, c->stream));
                 }
-                HIPCHK(c, e3d::launch_update_precond<T>(c->stream, d, f, M, c->S, c->partials,
+                HIPCHK(c, e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials,
                                                         kSweepBlocks));
                 if (timing) {
                     HIPCHK(c, hipEventRecord(c->ev_up[ev_used].b, c->stream));
@@ -373,7 +399,7 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], int maxit, elas3d
                 }
             }
             launched += poll;
-            HIPCHK(c, hipMemcpyAsync(&c->hS[slot], c->S, sizeof(Scalars), hipMemcpyDeviceToHost,
+            HIPCHK(c, hipMemcpyAsync(slot ? h1 : h0, S0, R * sizeof(Scalars), hipMemcpyDeviceToHost,
                                      c->stream));
             HIPCHK(c, hipEventRecord(batch_ev[slot], c->stream));
             recorded[slot] = true;
@@ -391,7 +417,7 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], int maxit, elas3d
                 rc = fail(c, ELAS3D_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
                 break;
             }
-            if (c->hS[slot].done) stop = true;
+            if (all_done(slot ? h1 : h0)) stop = true;
             if (!stop && launched >= max_launch) {
                 // the last batch is in flight: wait for it
                 e = recorded[slot ^ 1] ? hipEventSynchronize(batch_ev[slot ^ 1]) : hipSuccess;
@@ -408,21 +434,23 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], int maxit, elas3d
         hipEventDestroy(batch_ev[1]);
         if (rc) return rc;
     }
-    HIPCHK(c, e3d::launch_final_update<T>(c->stream, d, f, c->S));
-    HIPCHK(c, hipMemcpyAsync(&c->hS[0], c->S, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    for (int r = 0; r < R; ++r)
+        HIPCHK(c, e3d::launch_final_update<T>(c->stream, d, e3d::shifted(f0, (size_t)r * rs), S0 + r));
+    HIPCHK(c, hipMemcpyAsync(h0, S0, R * sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    rs.fin = c->hS[0];
+    int real = 0;  // launches before the last RHS of the batch stopped
+    for (int r = 0; r < R; ++r) {
+        rs_out[r].fin = h0[r];
+        real = std::max(real, h0[r].it - rs_out[r].it_start + (h0[r].status == 2 ? 1 : 0));
+    }
     if (timing && info) {
-        // only the sweeps that ran before the stop flag count
-        const int real = rs.fin.it - rs.it_start + (rs.fin.status == 2 ? 1 : 0);
         for (int q = 0; q < real && q < (int)ev_used; ++q) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, c->ev_op[q].a, c->ev_op[q].b) == hipSuccess) {
                 info->t_operator_ms += ms;
                 info->n_operator += 1;
             }
-            if (q < rs.fin.it - rs.it_start &&
-                hipEventElapsedTime(&ms, c->ev_up[q].a, c->ev_up[q].b) == hipSuccess) {
+            if (hipEventElapsedTime(&ms, c->ev_up[q].a, c->ev_up[q].b) == hipSuccess) {
                 info->t_update_ms += ms;
                 info->n_update += 1;
             }
@@ -431,12 +459,12 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], int maxit, elas3d
     return 0;
 }
 
-// Start a PCG run: load tol/maxit/mode and the iteration counter into the
-// device scalars, then the init sweep (fresh: w = 0, g = b; otherwise g
-// already holds the residual to continue from).
+// Start a PCG run of RHS r: load tol/maxit/mode and the iteration counter
+// into its device scalars, then the init sweep (fresh: w = 0, g = b;
+// otherwise g already holds the residual to continue from).
 template <typename T>
-int start_run(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], double tol, int maxit, int mode,
-              int it0, int fresh, int from_residual, const double* norms2)
+int start_run(elas3d_ctx* c, int r, const FieldsT<T>& f, T* const M[6], double tol, int maxit,
+              int mode, int it0, int fresh, int from_residual, const double* norms2)
 {
     Scalars init{};
     init.tol = tol;
@@ -444,172 +472,243 @@ int start_run(elas3d_ctx* c, const FieldsT<T>& f, T* const M[6], double tol, int
     init.mode = mode;
     init.it = it0;
     std::memcpy(&c->hS[0], &init, sizeof(Scalars));
-    HIPCHK(c, hipMemcpyAsync(c->S, &c->hS[0], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, e3d::launch_pcg_init<T>(c->stream, c->d, f, M, fresh, from_residual, c->S, c->partials,
-                                      kSweepBlocks, norms2));
+    HIPCHK(c, hipMemcpyAsync(c->S + r, &c->hS[0], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, e3d::launch_pcg_init<T>(c->stream, c->d, f, M, fresh, from_residual, c->S + r,
+                                      c->partials, kSweepBlocks, norms2));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // the pinned staging slot is reused
     return 0;
 }
 
-// FP64 PCG on case `rhs` (Algorithm 2), from w = 0 or (continue) from the
-// current w with g = A w + b already in place; in residual mode restart from
-// w whenever the recursive and the true residual disagree.
-int solve_fp64(elas3d_ctx* c, int rhs, double tol, int maxit, bool cont, int it0, elas3d_info* info,
-               Scalars& fin, int& restarts, double& rel_true)
+// Mark RHS r of the next batch as finished (its sweeps return at once).
+int park(elas3d_ctx* c, int r, const Scalars& fin)
+{
+    Scalars q = fin;
+    q.done = 1;
+    q.pending = 0;
+    std::memcpy(&c->hS[0], &q, sizeof(Scalars));
+    HIPCHK(c, hipMemcpyAsync(c->S + r, &c->hS[0], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+struct CaseResult {
+    Scalars fin{};
+    int restarts = 0;
+    double rel_true = 0.0;
+    int fallback = 0;
+};
+
+// FP64 PCG (Algorithm 2) on the RHS [r0, r0+R) in lockstep (R = 1 unless the
+// context is batched), from w = 0, or continuing from the current w when
+// `cont` (g = A w + b already in place).  In residual mode every RHS whose
+// recursive and true residual disagree restarts from its w.
+int solve_fp64(elas3d_ctx* c, int r0, int R, double tol, int maxit, bool cont, int it0,
+               elas3d_info* info, CaseResult* res)
 {
     const Dims& d = c->d;
-    Fields f = c->fields(rhs);
     double* M[6];
     c->minv_planes(M);
     const e3d::Tables t = c->tables();
-    int rc = start_run<double>(c, f, M, tol, maxit, c->opt.convergence, it0, cont ? 0 : 1,
-                               cont ? 1 : 0, c->norms + 2 * rhs);
-    if (rc) return rc;
-    for (;;) {
-        RunStats rs;
-        rc = iterate<double>(c, f, M, maxit, info, rs);
+    std::vector<int> running(R, 1);
+    for (int q = 0; q < R; ++q) {
+        int rc = start_run<double>(c, r0 + q, c->fields(r0 + q), M, tol, maxit, c->opt.convergence, it0,
+                                   cont ? 0 : 1, cont ? 1 : 0, c->norms + 2 * (r0 + q));
         if (rc) return rc;
-        // true residual r = A w + b (into g, ready for a restart)
+    }
+    std::vector<RunStats> rs(R);
+    for (;;) {
+        int rc = iterate<double>(c, c->fields(r0), c->rs64(), r0, R, M, maxit, info, rs.data());
+        if (rc) return rc;
+        bool again = false;
+        for (int q = 0; q < R; ++q) {
+            if (!running[q]) continue;
+            Fields f = c->fields(r0 + q);
+            // true residual r = A w + b (into g, ready for a restart)
+            const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
+            double* gy[3] = {f.g[0], f.g[1], f.g[2]};
+            HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom, c->phase, t, wx, gy, f.b, c->partials,
+                                        c->dscratch));
+            HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost,
+                                     c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            CaseResult& cr = res[q];
+            cr.fin = rs[q].fin;
+            const bool zero_load = cr.fin.bnorm2 <= 1e-28 * cr.fin.bref2;
+            cr.rel_true = (zero_load || cr.fin.bnorm2 <= 0.0) ? 0.0
+                                                             : std::sqrt(c->hscratch[0] / cr.fin.bnorm2);
+            if (c->opt.convergence == ELAS3D_CONV_RESIDUAL && cr.fin.status == 0 && !zero_load &&
+                !(cr.rel_true <= tol)) {
+                if (cr.fin.it >= maxit) {
+                    cr.fin.status = 1;
+                    running[q] = 0;
+                    continue;
+                }
+                ++cr.restarts;
+                rc = start_run<double>(c, r0 + q, f, M, tol, maxit, c->opt.convergence, cr.fin.it, 0, 1,
+                                       c->norms + 2 * (r0 + q));
+                if (rc) return rc;
+                again = true;
+            } else {
+                running[q] = 0;
+            }
+        }
+        if (!again) break;
+        // RHS that are finished keep their raised stop flags
+    }
+    return 0;
+}
+
+// Mixed precision (iterative refinement) on the RHS [r0, r0+R): the
+// corrections d of A d = -r are solved by the FP32 PCG in lockstep to a
+// relative reduction of the inner tolerance, then for each RHS w += d and
+// r = A w + b are formed in FP64.  A RHS whose cycle does not halve its true
+// residual continues in FP64 PCG from its w.
+int solve_mixed(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info* info,
+                CaseResult* res)
+{
+    const Dims& d = c->d;
+    float* M32[6];
+    c->minv32_planes(M32);
+    const e3d::Tables t = c->tables();
+    const double inner_tol = c->opt.inner_tol > 0.0 ? c->opt.inner_tol : 1e-4;
+    std::vector<double> bnorm2(R), bref2(R), rel(R);
+    std::vector<int> iters(R, 0), active(R, 0), fallback(R, 0);
+    auto refine = [&](int q) -> int {
+        const int r = r0 + q;
+        Fields f64 = c->fields(r);
+        e3d::FieldsT<float> f32 = c->fields32(r);
+        double* w[3] = {f64.w[0], f64.w[1], f64.w[2]};
+        const float* dc[3] = {f32.w[0], f32.w[1], f32.w[2]};
+        float* r32[3] = {f32.g[0], f32.g[1], f32.g[2]};
+        HIPCHK(c, e3d::launch_refine(c->stream, d, c->geom, c->phase, t, w, dc, f64.b, r32, c->partials,
+                                     c->dscratch + 4 + 2 * q));
+        // {||r||^2, ||r||^2}: the norms of the next inner run
+        HIPCHK(c, hipMemcpyAsync(c->dscratch + 5 + 2 * q, c->dscratch + 4 + 2 * q, sizeof(double),
+                                 hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch + 4 + 2 * q, sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        rel[q] = std::sqrt(c->hscratch[0] / bnorm2[q]);
+        return 0;
+    };
+    for (int q = 0; q < R; ++q) {
+        const int r = r0 + q;
+        Fields f64 = c->fields(r);
+        e3d::FieldsT<float> f32 = c->fields32(r);
+        for (int k = 0; k < 3; ++k) {  // w = 0, d = 0
+            HIPCHK(c, hipMemsetAsync(f64.w[k], 0, sizeof(double) * c->N(), c->stream));
+            HIPCHK(c, hipMemsetAsync(f32.w[k], 0, sizeof(float) * c->N(), c->stream));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->hscratch + 2, c->norms + 2 * r, 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bnorm2[q] = c->hscratch[2];
+        bref2[q] = c->hscratch[3];
+        res[q] = CaseResult{};
+        res[q].fin.bnorm2 = bnorm2[q];
+        res[q].fin.bref2 = bref2[q];
+        if (bnorm2[q] <= 1e-28 * bref2[q]) {  // zero load: converged
+            res[q].fin.status = 0;
+            continue;
+        }
+        int rc = refine(q);  // r = b, rounded
+        if (rc) return rc;
+        active[q] = rel[q] > tol;
+        if (!active[q]) res[q].fin.status = 0;
+    }
+    std::vector<RunStats> rs(R);
+    for (;;) {
+        bool any = false;
+        for (int q = 0; q < R; ++q)
+            if (active[q] && iters[q] < maxit) any = true;
+        if (!any) break;
+        for (int q = 0; q < R; ++q) {
+            const int r = r0 + q;
+            if (active[q] && iters[q] < maxit) {
+                // inner FP32 PCG from d = 0 on g = r (rounded); relative target:
+                // the cycle's, not tighter than the outer tolerance needs
+                const double target = std::max(inner_tol, 0.5 * tol / rel[q]);
+                int rc = start_run<float>(c, r, c->fields32(r), M32, target, maxit - iters[q],
+                                          ELAS3D_CONV_RESIDUAL, 0, 1, 1, c->dscratch + 4 + 2 * q);
+                if (rc) return rc;
+            } else {
+                int rc = park(c, r, Scalars{});
+                if (rc) return rc;
+            }
+        }
+        int rc = iterate<float>(c, c->fields32(r0), c->rs32(), r0, R, M32, maxit, info, rs.data());
+        if (rc) return rc;
+        for (int q = 0; q < R; ++q) {
+            if (!(active[q] && iters[q] < maxit)) continue;
+            iters[q] += rs[q].fin.it;
+            ++res[q].restarts;
+            const double prev = rel[q];
+            rc = refine(q);  // w += d, r = A w + b
+            if (rc) return rc;
+            res[q].fin.rr = rs[q].fin.rr;
+            res[q].fin.gg = rs[q].fin.gg;
+            res[q].fin.gg0 = rs[q].fin.gg0;
+            if (rel[q] <= tol) {
+                active[q] = 0;
+            } else if (rs[q].fin.status == 2 || !(rel[q] < 0.5 * prev)) {
+                active[q] = 0;  // stagnation or breakdown of the FP32 solve
+                fallback[q] = 1;
+            }
+        }
+    }
+    for (int q = 0; q < R; ++q) {
+        const int r = r0 + q;
+        res[q].fin.it = iters[q];
+        res[q].rel_true = (bnorm2[q] <= 1e-28 * bref2[q]) ? 0.0 : rel[q];
+        res[q].fin.status = res[q].rel_true <= tol ? 0 : 1;
+        if (!fallback[q]) continue;
+        // finish in FP64 from w: g = A w + b, then PCG continuing the count
+        Fields f = c->fields(r);
         const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
         double* gy[3] = {f.g[0], f.g[1], f.g[2]};
         HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom, c->phase, t, wx, gy, f.b, c->partials,
                                     c->dscratch));
-        HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost,
-                                 c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        fin = rs.fin;
-        const bool zero_load = fin.bnorm2 <= 1e-28 * fin.bref2;
-        rel_true = (zero_load || fin.bnorm2 <= 0.0) ? 0.0 : std::sqrt(c->hscratch[0] / fin.bnorm2);
-        if (c->opt.convergence == ELAS3D_CONV_RESIDUAL && fin.status == 0 && !zero_load &&
-            !(rel_true <= tol)) {
-            if (fin.it >= maxit) {
-                fin.status = 1;
-                break;
-            }
-            ++restarts;
-            rc = start_run<double>(c, f, M, tol, maxit, c->opt.convergence, fin.it, 0, 1,
-                                   c->norms + 2 * rhs);
-            if (rc) return rc;
-            continue;
-        }
-        break;
+        CaseResult fr;
+        int rc = solve_fp64(c, r, 1, tol, maxit, true, iters[q], info, &fr);
+        if (rc) return rc;
+        const int cycles = res[q].restarts;
+        res[q] = fr;
+        res[q].restarts += cycles;
+        res[q].fallback = 1;
     }
     return 0;
 }
 
-// Mixed precision (iterative refinement): the correction d of A d = -r is
-// solved by the FP32 PCG to a relative reduction of the inner tolerance,
-// then w += d and r = A w + b are formed in FP64 in one sweep.  If a cycle
-// does not reduce the true residual, the solve continues in FP64 from w.
-int solve_mixed(elas3d_ctx* c, int rhs, double tol, int maxit, elas3d_info* info, Scalars& fin,
-                int& cycles, double& rel_true)
+// Solve RHS [r0, r0+R) and record per-RHS statistics.
+int solve_batch(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info* info)
 {
-    const Dims& d = c->d;
-    Fields f64 = c->fields(rhs);
-    e3d::FieldsT<float> f32 = c->fields32();
-    float* M32[6];
-    c->minv32_planes(M32);
-    const e3d::Tables t = c->tables();
-    double* w[3] = {f64.w[0], f64.w[1], f64.w[2]};
-    const float* dcorr[3] = {f32.w[0], f32.w[1], f32.w[2]};
-    float* r32[3] = {f32.g[0], f32.g[1], f32.g[2]};
-    const double inner_tol = c->opt.inner_tol > 0.0 ? c->opt.inner_tol : 1e-4;
-    // w = 0, d = 0, then r = b (rounded) and ||b||^2 from the refinement sweep
-    for (int q = 0; q < 3; ++q) {
-        HIPCHK(c, hipMemsetAsync(w[q], 0, sizeof(double) * c->N(), c->stream));
-        HIPCHK(c, hipMemsetAsync(f32.w[q], 0, sizeof(float) * c->N(), c->stream));
-    }
-    HIPCHK(c, e3d::launch_refine(c->stream, d, c->geom, c->phase, t, w, dcorr, f64.b, r32, c->partials,
-                                 c->dscratch));
-    HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->hscratch + 2, c->norms + 2 * rhs, 2 * sizeof(double),
-                             hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    const double bnorm2 = c->hscratch[2], bref2 = c->hscratch[3];
-    double rnorm2 = c->hscratch[0];
-    fin = Scalars{};
-    fin.bnorm2 = bnorm2;
-    fin.bref2 = bref2;
-    fin.status = 1;
-    int iters = 0;
-    cycles = 0;
-    if (bnorm2 <= 1e-28 * bref2) {  // zero load
-        fin.status = 0;
-        rel_true = 0.0;
-        return 0;
-    }
-    rel_true = std::sqrt(rnorm2 / bnorm2);
-    while (rel_true > tol && iters < maxit) {
-        // inner FP32 PCG from d = 0 on g = r (rounded), relative tolerance:
-        // the cycle's target, not tighter than needed for the outer one
-        const double target = std::max(inner_tol, 0.5 * tol / rel_true);
-        HIPCHK(c, hipMemcpyAsync(c->dscratch + 4, c->dscratch, sizeof(double), hipMemcpyDeviceToDevice,
-                                 c->stream));
-        HIPCHK(c, hipMemcpyAsync(c->dscratch + 5, c->dscratch, sizeof(double), hipMemcpyDeviceToDevice,
-                                 c->stream));
-        int rc = start_run<float>(c, f32, M32, target, maxit - iters, ELAS3D_CONV_RESIDUAL, 0, 1, 1,
-                                  c->dscratch + 4);
-        if (rc) return rc;
-        RunStats rs;
-        rc = iterate<float>(c, f32, M32, maxit - iters, info, rs);
-        if (rc) return rc;
-        iters += rs.fin.it;
-        ++cycles;
-        // w += d, r = A w + b (FP64), stored rounded for the next cycle
-        HIPCHK(c, e3d::launch_refine(c->stream, d, c->geom, c->phase, t, w, dcorr, f64.b, r32,
-                                     c->partials, c->dscratch));
-        HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost,
-                                 c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        const double prev = rel_true;
-        rnorm2 = c->hscratch[0];
-        rel_true = std::sqrt(rnorm2 / bnorm2);
-        fin.rr = rs.fin.rr;
-        fin.gg = rs.fin.gg;
-        fin.gg0 = rs.fin.gg0;
-        if (rs.fin.status == 2 || !(rel_true < 0.5 * prev)) {
-            // stagnation or breakdown of the FP32 solve: finish in FP64 from w
-            const double* wx[3] = {w[0], w[1], w[2]};
-            double* gy[3] = {f64.g[0], f64.g[1], f64.g[2]};
-            HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom, c->phase, t, wx, gy, f64.b, c->partials,
-                                        c->dscratch));
-            int restarts = 0;
-            Scalars f64fin{};
-            rc = solve_fp64(c, rhs, tol, maxit, true, iters, info, f64fin, restarts, rel_true);
-            if (rc) return rc;
-            fin = f64fin;
-            cycles += restarts;
-            if (info) info->fp64_fallback[rhs] = 1;
-            return 0;
-        }
-    }
-    fin.it = iters;
-    fin.status = rel_true <= tol ? 0 : 1;
-    return 0;
-}
-
-int solve_case(elas3d_ctx* c, int rhs, double tol, int maxit, elas3d_info* info)
-{
-    Scalars fin{};
-    int restarts = 0;
-    double rel_true = 0.0;
+    CaseResult res[e3d::kMaxRhs];
     int rc;
     if (c->opt.precision == ELAS3D_PREC_MIXED)
-        rc = solve_mixed(c, rhs, tol, maxit, info, fin, restarts, rel_true);
+        rc = solve_mixed(c, r0, R, tol, maxit, info, res);
     else
-        rc = solve_fp64(c, rhs, tol, maxit, false, 0, info, fin, restarts, rel_true);
+        rc = solve_fp64(c, r0, R, tol, maxit, false, 0, info, res);
     if (rc) return rc;
-    if (info) {
-        const bool zero_load = fin.bnorm2 <= 1e-28 * fin.bref2;
-        info->status[rhs] = fin.status;
-        info->iters[rhs] = fin.it;
-        info->restarts[rhs] = restarts;
-        info->relres_true[rhs] = rel_true;
-        info->relres_recursive[rhs] =
-            (zero_load || fin.bnorm2 <= 0) ? 0.0 : std::sqrt(fin.rr / fin.bnorm2);
-        info->relres_precond[rhs] = (zero_load || fin.gg0 <= 0) ? 0.0 : std::sqrt(std::fabs(fin.gg / fin.gg0));
+    int worst = 0;
+    for (int q = 0; q < R; ++q) {
+        const int r = r0 + q;
+        const Scalars& fin = res[q].fin;
+        if (info) {
+            const bool zero_load = fin.bnorm2 <= 1e-28 * fin.bref2;
+            info->status[r] = fin.status;
+            info->iters[r] = fin.it;
+            info->restarts[r] = res[q].restarts;
+            info->relres_true[r] = res[q].rel_true;
+            info->relres_recursive[r] =
+                (zero_load || fin.bnorm2 <= 0) ? 0.0 : std::sqrt(fin.rr / fin.bnorm2);
+            info->relres_precond[r] =
+                (zero_load || fin.gg0 <= 0) ? 0.0 : std::sqrt(std::fabs(fin.gg / fin.gg0));
+            info->fp64_fallback[r] = res[q].fallback;
+        }
+        c->solved[r] = 1;
+        worst = std::max(worst, fin.status);
     }
-    c->solved[rhs] = 1;
-    return fin.status;
+    return worst;
 }
 
 }  // namespace
@@ -633,7 +732,7 @@ double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, i
                            const elas3d_options* opt)
 {
     return plan_bytes((int64_t)nx * ny * nz, nphase, nrhs,
-                      opt && opt->precision == ELAS3D_PREC_MIXED);
+                      opt && opt->precision == ELAS3D_PREC_MIXED, opt && opt->batched);
 }
 
 int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int32_t* phase,
@@ -662,7 +761,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     }
     const int64_t n = (int64_t)nx * ny * nz;
     const bool mixed = opt.precision == ELAS3D_PREC_MIXED;
-    const double need = plan_bytes(n, nphase, nrhs, mixed);
+    const double need = plan_bytes(n, nphase, nrhs, mixed, opt.batched != 0);
     double budget = opt.hbm_budget_bytes;
     if (budget <= 0.0) {
         size_t free_b = 0, total_b = 0;
@@ -712,22 +811,20 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     SETUPCHK(hipMalloc(&c->diag, 8 * (size_t)nphase * e3d::kDiagStride));
     SETUPCHK(hipMalloc(&c->solid, (size_t)nphase));
     SETUPCHK(hipMalloc(&c->sig, 8 * (size_t)nrhs * nphase * e3d::kSigStride));
-    SETUPCHK(hipMalloc(&c->b, 8 * 3 * N * nrhs));
-    SETUPCHK(hipMalloc(&c->w, 8 * 3 * N * nrhs));
-    SETUPCHK(hipMalloc(&c->work, 8 * 15 * N));
+    SETUPCHK(hipMalloc(&c->bundle64, 8 * N * (opt.batched ? 21 * (size_t)nrhs : 6 * (size_t)nrhs + 15)));
     SETUPCHK(hipMalloc(&c->minv, 8 * 6 * N));
     if (mixed) {
-        SETUPCHK(hipMalloc(&c->work32, 4 * 18 * N));
+        SETUPCHK(hipMalloc(&c->bundle32, 4 * 18 * N * (opt.batched ? (size_t)nrhs : 1)));
         SETUPCHK(hipMalloc(&c->minv32, 4 * 6 * N));
         SETUPCHK(hipMalloc(&c->coef32, 4 * (size_t)nphase * e3d::kCoefStride));
     }
     SETUPCHK(hipMalloc(&c->partials, 8 * (size_t)kPartialValues * c->partial_stride));
     SETUPCHK(hipMalloc(&c->norms, 8 * 2 * (size_t)nrhs));
-    SETUPCHK(hipMalloc(&c->dscratch, 8 * 16));
+    SETUPCHK(hipMalloc(&c->dscratch, 8 * 64));
     SETUPCHK(hipMalloc(&c->dflag, sizeof(int) * 4));
-    SETUPCHK(hipMalloc(&c->S, sizeof(Scalars)));
-    SETUPCHK(hipHostMalloc(&c->hS, 2 * sizeof(Scalars), hipHostMallocDefault));
-    SETUPCHK(hipHostMalloc(&c->hscratch, 16 * sizeof(double), hipHostMallocDefault));
+    SETUPCHK(hipMalloc(&c->S, e3d::kMaxRhs * sizeof(Scalars)));
+    SETUPCHK(hipHostMalloc(&c->hS, 2 * e3d::kMaxRhs * sizeof(Scalars), hipHostMallocDefault));
+    SETUPCHK(hipHostMalloc(&c->hscratch, 64 * sizeof(double), hipHostMallocDefault));
 
     SETUPCHK(hipMemcpyAsync(c->phase, phase, 4 * N,
                             opt.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -757,7 +854,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     SETUPCHK(hipMemcpyAsync(c->solid, solid.data(), solid.size(), hipMemcpyHostToDevice, c->stream));
     SETUPCHK(hipMemcpyAsync(c->sig, sig.data(), 8 * sig.size(), hipMemcpyHostToDevice, c->stream));
     for (int r = 0; r < nrhs; ++r) {
-        double* bp[3] = {c->plane(c->b, 3 * r), c->plane(c->b, 3 * r + 1), c->plane(c->b, 3 * r + 2)};
+        double* bp[3] = {c->bptr(r), c->bptr(r) + N, c->bptr(r) + 2 * N};
         SETUPCHK(e3d::launch_load(c->stream, c->d, c->phase,
                                   c->sig + (size_t)r * nphase * e3d::kSigStride, bp, c->partials,
                                   c->norms + 2 * r, kSweepBlocks));
@@ -790,20 +887,29 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
     HIPCHK(ctx, hipSetDevice(ctx->device));
     auto t0 = std::chrono::steady_clock::now();
     int worst = 0;
-    for (int r = 0; r < nrhs; ++r) {
-        int rc = solve_case(ctx, r, tol, maxit, info);
+    if (ctx->batched()) {
+        int rc = solve_batch(ctx, 0, nrhs, tol, maxit, info);
         if (rc < 0) return rc;
-        worst = std::max(worst, rc);
+        worst = rc;
+    } else {
+        for (int r = 0; r < nrhs; ++r) {
+            int rc = solve_batch(ctx, r, 1, tol, maxit, info);
+            if (rc < 0) return rc;
+            worst = std::max(worst, rc);
+        }
     }
     auto t1 = std::chrono::steady_clock::now();
     if (info) {
         info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
         // two fused sweeps: direction+operator (read z, h, w, phase; write h, w, Ah)
         // and update+precondition (read g, Ah, M^-1; write g, z)
+        // per RHS: fused sweep 6 vectors + phase, update sweep 4 vectors + M^-1
+        // (M^-1 read once per node for a batch)
+        const int rb = ctx->batched() ? nrhs : 1;
         if (ctx->opt.precision == ELAS3D_PREC_MIXED)
-            info->bytes_per_iter = (double)ctx->N() * ((6 * 12.0 + 4.0) + (4 * 12.0 + 24.0));
+            info->bytes_per_iter = (double)ctx->N() * rb * ((6 * 12.0 + 4.0) + (4 * 12.0 + 24.0 / rb));
         else
-            info->bytes_per_iter = (double)ctx->N() * ((6 * 24.0 + 4.0) + (4 * 24.0 + 48.0));
+            info->bytes_per_iter = (double)ctx->N() * rb * ((6 * 24.0 + 4.0) + (4 * 24.0 + 48.0 / rb));
     }
     return worst;
 }
@@ -819,16 +925,17 @@ int elas3d_stress(elas3d_ctx* ctx, int32_t rhs, double* sigma_voxel, double* sig
     Fields f = ctx->fields(rhs);
     double* sigd[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (sigma_voxel) {
-        double* base = ctx->opt.outputs_on_device ? sigma_voxel : ctx->work;  // work: 15N >= 6N
+        double* base = ctx->opt.outputs_on_device ? sigma_voxel : ctx->work64(0);  // 15N >= 6N
         for (int q = 0; q < 6; ++q) sigd[q] = base + q * N;
     }
     HIPCHK(ctx, e3d::launch_stress(ctx->stream, ctx->d, ctx->phase, ctx->tables(),
                                    ctx->strain.data() + 6 * rhs, f, sigma_voxel ? sigd : nullptr,
                                    ctx->partials, ctx->dscratch, kSweepBlocks));
     if (sigma_voxel && !ctx->opt.outputs_on_device)
-        HIPCHK(ctx, hipMemcpyAsync(sigma_voxel, ctx->work, 8 * 6 * N, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(sigma_voxel, ctx->work64(0), 8 * 6 * N, hipMemcpyDeviceToHost,
+                                   ctx->stream));
     if (u_node) {
-        double* base = ctx->opt.outputs_on_device ? u_node : ctx->work + 6 * N;
+        double* base = ctx->opt.outputs_on_device ? u_node : ctx->work64(0) + 6 * N;
         double* ud[3] = {base, base + N, base + 2 * N};
         HIPCHK(ctx, e3d::launch_total_displacement(ctx->stream, ctx->d, ctx->strain.data() + 6 * rhs, f, ud));
         if (!ctx->opt.outputs_on_device)
@@ -851,9 +958,9 @@ int elas3d_apply(elas3d_ctx* ctx, const double* x, double* y)
     const double* xd = x;
     double* yd = y;
     if (!ctx->opt.outputs_on_device) {
-        HIPCHK(ctx, hipMemcpyAsync(ctx->work, x, 8 * 3 * N, hipMemcpyHostToDevice, ctx->stream));
-        xd = ctx->work;
-        yd = ctx->work + 3 * N;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->work64(0), x, 8 * 3 * N, hipMemcpyHostToDevice, ctx->stream));
+        xd = ctx->work64(0);
+        yd = ctx->work64(0) + 3 * N;
     }
     const double* xp[3] = {xd, xd + N, xd + 2 * N};
     double* yp[3] = {yd, yd + N, yd + 2 * N};
@@ -870,7 +977,7 @@ int elas3d_get_load(elas3d_ctx* ctx, int32_t rhs, double* b)
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
     if (rhs < 0 || rhs >= ctx->nrhs || !b) return fail(ctx, ELAS3D_EBADARG, "bad rhs or NULL output");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, hipMemcpyAsync(b, ctx->plane(ctx->b, 3 * rhs), 8 * 3 * ctx->N(), copy_kind(ctx, false),
+    HIPCHK(ctx, hipMemcpyAsync(b, ctx->bptr(rhs), 8 * 3 * ctx->N(), copy_kind(ctx, false),
                                ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return 0;
@@ -892,7 +999,7 @@ int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w)
     if (rhs < 0 || rhs >= ctx->nrhs || !w) return fail(ctx, ELAS3D_EBADARG, "bad rhs or NULL output");
     if (!ctx->solved[rhs]) return fail(ctx, ELAS3D_EORDER, "load case not solved yet");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, hipMemcpyAsync(w, ctx->plane(ctx->w, 3 * rhs), 8 * 3 * ctx->N(), copy_kind(ctx, false),
+    HIPCHK(ctx, hipMemcpyAsync(w, ctx->wptr(rhs), 8 * 3 * ctx->N(), copy_kind(ctx, false),
                                ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return 0;

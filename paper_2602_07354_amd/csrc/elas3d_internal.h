@@ -60,6 +60,25 @@ struct FieldsT {
 };
 using Fields = FieldsT<double>;
 
+constexpr int kMaxRhs = 6;
+
+// The same fields for RHS r of a batch whose buffers lie `rs` elements apart.
+template <typename T>
+__host__ __device__ inline FieldsT<T> shifted(const FieldsT<T>& f, size_t off)
+{
+    FieldsT<T> g;
+    for (int c = 0; c < 3; ++c) {
+        g.w[c] = f.w[c] ? f.w[c] + off : nullptr;
+        g.g[c] = f.g[c] ? f.g[c] + off : nullptr;
+        g.z[c] = f.z[c] ? f.z[c] + off : nullptr;
+        g.h0[c] = f.h0[c] ? f.h0[c] + off : nullptr;
+        g.h1[c] = f.h1[c] ? f.h1[c] + off : nullptr;
+        g.Ah[c] = f.Ah[c] ? f.Ah[c] + off : nullptr;
+        g.b[c] = f.b[c] ? f.b[c] + off : nullptr;
+    }
+    return g;
+}
+
 struct Tables {
     const double* coef;    // nphase * kCoefStride: C/16, packed
     const float* coef32;   // the same rounded to FP32 (mixed precision), or nullptr
@@ -90,13 +109,17 @@ template <typename T>
 hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, T* const minv[6],
                            int fresh, int from_residual, Scalars* S, double* partials,
                            int max_blocks, const double* norms2);
+// The two iteration sweeps run a batch of nrhs right-hand sides in lockstep:
+// f describes RHS 0, RHS r lies r*rs elements further in every field, and S
+// points to nrhs consecutive scalar sets (a RHS whose flag is done is skipped).
 template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
                                      const int32_t* phase, const Tables& t, const FieldsT<T>& f,
-                                     Scalars* S, double* partials);
+                                     size_t rs, int nrhs, Scalars* S, double* partials);
 template <typename T>
-hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f,
-                                 T* const minv[6], Scalars* S, double* partials, int max_blocks);
+hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f, size_t rs,
+                                 int nrhs, T* const minv[6], Scalars* S, double* partials,
+                                 int max_blocks);
 template <typename T>
 hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& f, Scalars* S);
 // Refinement of the mixed-precision solve: r = A (w + d) + b in FP64, stored

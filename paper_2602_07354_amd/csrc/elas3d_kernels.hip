@@ -336,9 +336,13 @@ enum FinKind { FIN_STORE = 0, FIN_INIT = 1, FIN_DIRECTION = 2, FIN_UPDATE = 3 };
 template <int NV>
 __global__ void __launch_bounds__(kFinThreads) finalize_kernel(int kind, const double* partials,
                                                                int stride, int nblocks, Scalars* S,
-                                                               double* out, const double* norms)
+                                                               double* out, const double* norms,
+                                                               int rhs_stride)
 {
     __shared__ double red[NV][kFinThreads / 64];
+    // block r finalizes RHS r of a batch
+    partials += (size_t)blockIdx.x * rhs_stride;
+    if (S) S += blockIdx.x;
     // sweeps enqueued after the stop flag was raised did no work: leave the
     // scalars of the finished run untouched
     if ((kind == FIN_DIRECTION || kind == FIN_UPDATE) && S->done) return;
@@ -587,35 +591,54 @@ __global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, 
     block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
 }
 
-// Algorithm 2, C-D: g -= lambda Ah, z = M^-1 g, partial z.g and g.g (FP64).
+// Algorithm 2, C-D for a batch of RHS sharing M^-1 (loaded once per node):
+// g -= lambda Ah, z = M^-1 g, partials z.g and g.g (FP64) per RHS.
 // (w -= lambda h is deferred to the next direction sweep, which reads h anyway.)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<T> f, MinvT<T> M,
+__global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<T> f, size_t rs,
+                                                                int nrhs, MinvT<T> M,
                                                                 const Scalars* S, double* partials,
                                                                 int stride)
 {
-    if (S->done) return;
-    const T lam = (T)S->lambda;
-    double acc[2] = {0.0, 0.0};
-    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        T g[3], mm[6];
+    unsigned active = 0;
+    T lam[kMaxRhs];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) g[c] = fma(-lam, f.Ah[c][m], f.g[c][m]);
+    for (int r = 0; r < kMaxRhs; ++r) {
+        lam[r] = T(0);
+        if (r < nrhs && !S[r].done) {
+            active |= 1u << r;
+            lam[r] = (T)S[r].lambda;
+        }
+    }
+    if (!active) return;
+    double acc[2 * kMaxRhs];
+#pragma unroll
+    for (int k = 0; k < 2 * kMaxRhs; ++k) acc[k] = 0.0;
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        T mm[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) mm[q] = M.m[q][m];
         const T xx = mm[0], yy = mm[1], zz = mm[2], yz = mm[3], xz = mm[4], xy = mm[5];
-        const T z0 = xx * g[0] + xy * g[1] + xz * g[2];
-        const T z1 = xy * g[0] + yy * g[1] + yz * g[2];
-        const T z2 = xz * g[0] + yz * g[1] + zz * g[2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) f.g[c][m] = g[c];
-        f.z[0][m] = z0;
-        f.z[1][m] = z1;
-        f.z[2][m] = z2;
-        acc[0] += (double)z0 * g[0] + (double)z1 * g[1] + (double)z2 * g[2];
-        acc[1] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+        for (int r = 0; r < kMaxRhs; ++r) {
+            if (!(active & (1u << r))) continue;
+            const size_t o = (size_t)r * rs + m;
+            T g[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g[c] = fma(-lam[r], f.Ah[c][o], f.g[c][o]);
+            const T z0 = xx * g[0] + xy * g[1] + xz * g[2];
+            const T z1 = xy * g[0] + yy * g[1] + yz * g[2];
+            const T z2 = xz * g[0] + yz * g[1] + zz * g[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f.g[c][o] = g[c];
+            f.z[0][o] = z0;
+            f.z[1][o] = z1;
+            f.z[2][o] = z2;
+            acc[2 * r] += (double)z0 * g[0] + (double)z1 * g[1] + (double)z2 * g[2];
+            acc[2 * r + 1] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
+        }
     }
-    block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
+    block_partials<2 * kMaxRhs, kBlock>(acc, partials, stride, blockIdx.x);
 }
 
 // The step size of the last iteration still owed to w.
@@ -698,6 +721,8 @@ struct OpArgs {
     const Scalars* S;
     double* partials;
     int want_norm;
+    size_t rs;  // FUSED: elements between consecutive RHS of the batch
+    int nrhs;   // FUSED: RHS in the batch (workgroup -> (tile, rhs))
 };
 
 // OP_APPLY : y = A x (+ add) in FP64, optional ||y||^2 partials.
@@ -719,18 +744,31 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
     __shared__ R sn[3][LY * LX];
     __shared__ R sf[3][3][NT];
 
+    // logical workgroup -> (tile block, RHS); the RHS of one tile are
+    // neighbours in the XCD-local order, so they share phase ids and
+    // coefficients through L2
+    const int nr = FUSED ? a.nrhs : 1;
+    const int lbr = xcd_local_block();
+    const int rhs = lbr % nr;
+    const int lb = lbr / nr;
+    const int ntb = gridDim.x / nr;  // tile blocks per RHS
     R gam = R(0), lam = R(0);
     const T* hold[3] = {nullptr, nullptr, nullptr};
     T* hnew[3] = {nullptr, nullptr, nullptr};
     if constexpr (FUSED) {
-        if (a.S->done) return;
-        gam = (R)a.S->gamma;
-        lam = (R)a.S->lambda;
-        const int cur = a.S->cur;
+        const Scalars* S = a.S + rhs;
+        if (S->done) return;
+        gam = (R)S->gamma;
+        lam = (R)S->lambda;
+        const int cur = S->cur;
+        const size_t off = (size_t)rhs * a.rs;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            hold[c] = cur ? a.h1[c] : a.h0[c];
-            hnew[c] = cur ? a.h0[c] : a.h1[c];
+            hold[c] = (cur ? a.h1[c] : a.h0[c]) + off;
+            hnew[c] = (cur ? a.h0[c] : a.h1[c]) + off;
+            a.z[c] += off;
+            a.w[c] += off;
+            a.y[c] += off;
         }
     }
     const R* coef = reinterpret_cast<const R*>(a.coef);
@@ -739,7 +777,6 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
     const int plane = nx * ny;
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     const int ntiles = a.tiles_x * a.tiles_y;
-    const int lb = xcd_local_block();
     const int bz = lb / ntiles, t = lb - bz * ntiles;
     const int by = t / a.tiles_x, bx = t - by * a.tiles_x;
     const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
@@ -927,7 +964,7 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
     }
     if (FUSED || a.want_norm) {
         double v[1] = {dot};
-        block_partials<1, NT>(v, a.partials, gridDim.x, blockIdx.x);
+        block_partials<1, NT>(v, a.partials + (size_t)rhs * ntb, ntb, lb);
     }
 }
 
@@ -1088,7 +1125,7 @@ hipError_t launch_load(hipStream_t st, const Dims& d, const int32_t* phase, cons
     hipLaunchKernelGGL(load_kernel, dim3(nb), dim3(kBlock), 0, st, d, phase, sig, b[0], b[1], b[2],
                        partials, nb);
     hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
-                       (const double*)partials, nb, nb, (Scalars*)nullptr, out2, (const double*)nullptr);
+                       (const double*)partials, nb, nb, (Scalars*)nullptr, out2, (const double*)nullptr, 0);
     return hipGetLastError();
 }
 
@@ -1118,14 +1155,14 @@ hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, T
     hipLaunchKernelGGL(pcg_init_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv), fresh,
                        from_residual, partials, nb);
     hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_INIT,
-                       (const double*)partials, nb, nb, S, (double*)nullptr, norms2);
+                       (const double*)partials, nb, nb, S, (double*)nullptr, norms2, 0);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
                                      const int32_t* phase, const Tables& t, const FieldsT<T>& f,
-                                     Scalars* S, double* partials)
+                                     size_t rs, int nrhs, Scalars* S, double* partials)
 {
     OpArgs<T> a = {};
     a.d = d;
@@ -1146,22 +1183,27 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
     }
     a.S = S;
     a.partials = partials;
-    hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_FUSED, T>), dim3(g.blocks), dim3(kTX * kTY), 0, st, a);
-    hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_DIRECTION,
+    a.rs = rs;
+    a.nrhs = nrhs;
+    hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_FUSED, T>), dim3(g.blocks * nrhs), dim3(kTX * kTY), 0,
+                       st, a);
+    hipLaunchKernelGGL(finalize_kernel<1>, dim3(nrhs), dim3(kFinThreads), 0, st, (int)FIN_DIRECTION,
                        (const double*)partials, g.blocks, g.blocks, S, (double*)nullptr,
-                       (const double*)nullptr);
+                       (const double*)nullptr, g.blocks);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f,
-                                 T* const minv[6], Scalars* S, double* partials, int max_blocks)
+hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f, size_t rs,
+                                 int nrhs, T* const minv[6], Scalars* S, double* partials,
+                                 int max_blocks)
 {
     const int nb = sweep_blocks(d.n, max_blocks);
-    hipLaunchKernelGGL(update_precond_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv),
-                       (const Scalars*)S, partials, nb);
-    hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_UPDATE,
-                       (const double*)partials, nb, nb, S, (double*)nullptr, (const double*)nullptr);
+    hipLaunchKernelGGL(update_precond_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, rs, nrhs,
+                       mk_minv(minv), (const Scalars*)S, partials, nb);
+    hipLaunchKernelGGL(finalize_kernel<2>, dim3(nrhs), dim3(kFinThreads), 0, st, (int)FIN_UPDATE,
+                       (const double*)partials, nb, nb, S, (double*)nullptr, (const double*)nullptr,
+                       2 * nb);
     return hipGetLastError();
 }
 
@@ -1178,9 +1220,10 @@ hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& 
                                            int, int, Scalars*, double*, int, const double*);         \
     template hipError_t launch_direction_operator<T>(hipStream_t, const Dims&, const OpGeom&,         \
                                                      const int32_t*, const Tables&,                  \
-                                                     const FieldsT<T>&, Scalars*, double*);          \
-    template hipError_t launch_update_precond<T>(hipStream_t, const Dims&, const FieldsT<T>&,         \
-                                                 T* const[6], Scalars*, double*, int);               \
+                                                     const FieldsT<T>&, size_t, int, Scalars*,        \
+                                                     double*);                                       \
+    template hipError_t launch_update_precond<T>(hipStream_t, const Dims&, const FieldsT<T>&, size_t, \
+                                                 int, T* const[6], Scalars*, double*, int);          \
     template hipError_t launch_final_update<T>(hipStream_t, const Dims&, const FieldsT<T>&, Scalars*);
 E3D_INSTANTIATE(double)
 E3D_INSTANTIATE(float)
@@ -1209,7 +1252,7 @@ hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const in
     if (norm2)
         hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
                            (const double*)partials, g.blocks, g.blocks, (Scalars*)nullptr, norm2,
-                           (const double*)nullptr);
+                           (const double*)nullptr, 0);
     return hipGetLastError();
 }
 
@@ -1237,7 +1280,7 @@ hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const i
                        a);
     hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
                        (const double*)partials, g.blocks, g.blocks, (Scalars*)nullptr, norm2,
-                       (const double*)nullptr);
+                       (const double*)nullptr, 0);
     const int nb = sweep_blocks(d.n, 4096);
     hipLaunchKernelGGL(add_correction_kernel, dim3(nb), dim3(kBlock), 0, st, d, w[0], w[1], w[2],
                        dcorr[0], dcorr[1], dcorr[2]);
@@ -1266,7 +1309,7 @@ hipError_t launch_stress(hipStream_t st, const Dims& d, const int32_t* phase, co
                        sig ? 1 : 0, partials, nb);
     hipLaunchKernelGGL(finalize_kernel<7>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
                        (const double*)partials, nb, nb, (Scalars*)nullptr, sums7,
-                       (const double*)nullptr);
+                       (const double*)nullptr, 0);
     return hipGetLastError();
 }
 

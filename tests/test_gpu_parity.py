@@ -256,3 +256,39 @@ def test_mixed_precision_metric_tolerance_poly100(E):
     say("fp64 iters", i64["iters"][0], "mixed iters", i32["iters"][0], "cycles", i32["restarts"][0])
     assert st == E.OK and i32["relres_true"][0] <= 1e-8
     assert np.allclose(s32["avg"], s64["avg"], rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_six_load_cases_equal_sequential(E, precision):
+    """The six homogenisation load cases solved in one lockstep batch give
+    bit-identical fields to six sequential solves; C_eff is symmetric."""
+    say("case: batched multi-RHS, precision", precision)
+    ms = _small_poly((24, 20, 18), 77, grains=10)
+    ms.strain = synth.unit_load_cases()
+    with E.Context.from_micro(ms, precision=precision) as cs:
+        st, i_seq = cs.solve(1e-10, 20000)
+        w_seq = [cs.solution(r) for r in range(6)]
+        avg = np.array([cs.stress(r, voxel=False)["avg"] for r in range(6)])
+    with E.Context.from_micro(ms, precision=precision, batched=1) as cb:
+        st, i_bat = cb.solve(1e-10, 20000)
+        w_bat = [cb.solution(r) for r in range(6)]
+    say("iters seq", i_seq["iters"], "batched", i_bat["iters"])
+    assert st == E.OK and max(i_bat["relres_true"]) <= 1e-10
+    assert i_seq["iters"] == i_bat["iters"]
+    for r in range(6):
+        assert np.array_equal(w_seq[r], w_bat[r]), r
+    Ceff = avg.T / 1e-3  # column j: mean stress of unit strain j
+    assert np.abs(Ceff - Ceff.T).max() <= 1e-6 * np.abs(Ceff).max()
+
+
+def test_homogeneous_effective_stiffness_is_C(E):
+    say("case: homogeneous C_eff")
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((6, 6))
+    C = A @ A.T + 6 * np.eye(6)
+    with E.Context((6, 5, 4), np.zeros(120, np.int32), C[None], synth.unit_load_cases(),
+                   batched=1) as ctx:
+        st, info = ctx.solve(1e-10, 100)
+        avg = np.array([ctx.stress(r, voxel=False)["avg"] for r in range(6)])
+    assert st == E.OK and info["iters"] == [0] * 6
+    assert np.allclose(avg.T / 1e-3, C, rtol=1e-12)
