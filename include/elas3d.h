@@ -91,6 +91,9 @@ typedef struct elas3d_options {
     int32_t inner_maxit;       /* mixed: iteration cap of one inner solve (0 = auto) */
     int32_t batched;           /* nonzero: solve all requested RHS in one multi-RHS
                                   launch sequence sharing the operator               */
+    int32_t graphs;            /* nonzero: replay each batch of poll_interval
+                                  iterations as a captured HIP graph (ignored
+                                  when timing is on); default 1                      */
 } elas3d_options;
 
 typedef struct elas3d_info {
@@ -115,7 +118,7 @@ typedef struct elas3d_info {
 
 /* Fill `opt` with the defaults (FP64, residual criterion, block Jacobi,
  * host pointers, automatic polling, no timing, current device, budget from
- * free memory, library stream). */
+ * free memory, library stream, not batched, graphs on). */
 void elas3d_options_init(elas3d_options* opt);
 
 /*

@@ -74,6 +74,13 @@ struct elas3d_ctx {
     std::string err;
 
     std::vector<EventPair> ev_op, ev_up;
+    // captured iteration batches, keyed by (element size, first RHS, RHS count)
+    struct GraphEntry {
+        int key[3];
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
 
     size_t N() const { return (size_t)d.n; }
     double* plane(double* base, int q) const { return base + (size_t)q * N(); }
@@ -155,6 +162,7 @@ void default_options(elas3d_options* o)
     o->convergence = ELAS3D_CONV_RESIDUAL;
     o->preconditioner = ELAS3D_PRECOND_BLOCK_JACOBI;
     o->device = -1;
+    o->graphs = 1;
 }
 
 // Device bytes of a context (kept in one place so the budget check and
@@ -306,6 +314,10 @@ void free_ctx(elas3d_ctx* c)
         if (p) hipFree(p);
     if (c->hS) hipHostFree(c->hS);
     if (c->hscratch) hipHostFree(c->hscratch);
+    for (auto& g : c->graphs) {
+        hipGraphExecDestroy(g.exec);
+        hipGraphDestroy(g.graph);
+    }
     for (auto& e : c->ev_op) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
@@ -376,8 +388,35 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* co
         const long long max_launch = (long long)maxit - min_start + poll;
         long long launched = 0;
         bool recorded[2] = {false, false};
+        // a captured batch of `poll` iterations (no timing events inside)
+        hipGraphExec_t exec = nullptr;
+        if (c->opt.graphs && !timing) {
+            const int key[3] = {(int)sizeof(T), r0, R};
+            for (auto& g : c->graphs)
+                if (g.key[0] == key[0] && g.key[1] == key[1] && g.key[2] == key[2]) exec = g.exec;
+            if (!exec) {
+                elas3d_ctx::GraphEntry ge{{key[0], key[1], key[2]}, nullptr, nullptr};
+                HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e1 = hipSuccess;
+                for (int j = 0; j < poll && e1 == hipSuccess; ++j) {
+                    e1 = e3d::launch_direction_operator<T>(c->stream, d, c->geom, c->phase, t, f0, rs, R,
+                                                           S0, c->partials);
+                    if (e1 == hipSuccess)
+                        e1 = e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials,
+                                                           kSweepBlocks);
+                }
+                hipError_t e2 = hipStreamEndCapture(c->stream, &ge.graph);
+                if (e1 != hipSuccess || e2 != hipSuccess)
+                    return fail(c, ELAS3D_EDEVICE, std::string("graph capture: ") +
+                                                       hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+                HIPCHK(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+                c->graphs.push_back(ge);
+                exec = ge.exec;
+            }
+        }
         auto enqueue = [&](int slot) -> int {
-            for (int j = 0; j < poll; ++j) {
+            if (exec) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+            for (int j = 0; j < poll && !exec; ++j) {
                 if (timing) {
                     int rc = ensure_events(c, c->ev_op, ev_used + 1);
                     if (rc) return rc;

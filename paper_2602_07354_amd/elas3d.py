@@ -57,6 +57,7 @@ class Options(ctypes.Structure):
         ("inner_tol", ctypes.c_double),
         ("inner_maxit", ctypes.c_int32),
         ("batched", ctypes.c_int32),
+        ("graphs", ctypes.c_int32),
     ]
 
 

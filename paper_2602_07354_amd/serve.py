@@ -1,0 +1,245 @@
+"""Solve service with continuous batching of uneven requests on one GPU.
+
+Requests are independent periodic voxel elasticity solves (their own grid,
+phase map, stiffnesses and 1-6 load cases).  A dispatcher admits queued
+requests as soon as the device-memory budget and the concurrency cap allow,
+so requests that arrive while others are on the GPU join as slots and memory
+free up.  Each admitted request runs on a worker thread with its own HIP
+stream: elas3d_setup -> elas3d_solve (all load cases as one lockstep batch,
+mixed precision by default) -> elas3d_stress -> elas3d_destroy.  The ctypes
+calls release the GIL, so the solves of different requests overlap on the
+device.  Every kernel is deterministic, so a result is bit-identical whether
+its request runs alone or in the mix.
+
+``python -m paper_2602_07354_amd.serve`` measures the saturation throughput
+and then p50/p99 latency under Poisson arrivals at fractions of it.
+"""
+
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import sys
+import threading
+import time
+from collections import deque
+from typing import List, Optional
+
+import numpy as np
+
+from . import elas3d as E
+from . import synth
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    micro: synth.Microstructure
+    tol: float = 1e-8
+    precision: int = E.PREC_MIXED
+    arrival: float = 0.0  # seconds after the stream start
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    shape: tuple
+    nrhs: int
+    status: int
+    iters: list
+    relres_true: list
+    sigma_avg: np.ndarray  # (nrhs, 6)
+    t_arrival: float
+    t_start: float
+    t_end: float
+    error: Optional[str] = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_end - self.t_arrival
+
+
+def request_bytes(req: Request) -> float:
+    o = E.options_init(precision=req.precision, batched=1)
+    return E.device_bytes(req.micro.shape, req.micro.nphase, req.micro.nrhs, o)
+
+
+def solve_one(req: Request, t_arrival: float = 0.0, t0: float = 0.0, device: int = 0) -> Result:
+    """Run one request to completion on the calling thread (own HIP stream)."""
+    ms = req.micro
+    t_start = time.perf_counter() - t0
+    try:
+        opts = E.options_init(precision=req.precision, batched=1, device=device)
+        h = E.setup(ms.shape, ms.phase, ms.C, ms.strain, opts)
+        try:
+            st, info = E.solve(h, req.tol, 50000, ms.nrhs)
+            avg = np.empty((ms.nrhs, 6))
+            for r in range(ms.nrhs):
+                a = np.empty(6)
+                E.stress(h, r, None, a, None, None)
+                avg[r] = a
+        finally:
+            E.destroy(h)
+        d = info.as_dict()
+        return Result(req.rid, ms.shape, ms.nrhs, st, d["iters"], d["relres_true"], avg, t_arrival,
+                      t_start, time.perf_counter() - t0)
+    except E.Elas3dError as e:
+        return Result(req.rid, ms.shape, ms.nrhs, e.code, [], [], np.zeros((ms.nrhs, 6)), t_arrival,
+                      t_start, time.perf_counter() - t0, str(e))
+
+
+class Server:
+    """Admission by memory budget and concurrency; workers overlap on the GPU."""
+
+    def __init__(self, budget_bytes: Optional[float] = None, max_concurrency: int = 8,
+                 device: int = 0):
+        if budget_bytes is None:
+            import torch
+
+            free, _ = torch.cuda.mem_get_info(device)
+            budget_bytes = 0.8 * free
+        self.budget = float(budget_bytes)
+        self.max_conc = int(max_concurrency)
+        self.device = device
+        self._lock = threading.Condition()
+        self._queue: deque = deque()
+        self._in_flight_bytes = 0.0
+        self._in_flight = 0
+        self._results: List[Result] = []
+        self._stop = False
+        self._t0 = time.perf_counter()
+        self._dispatcher = threading.Thread(target=self._dispatch, daemon=True)
+        self._dispatcher.start()
+
+    def now(self) -> float:
+        return time.perf_counter() - self._t0
+
+    def submit(self, req: Request) -> None:
+        nbytes = request_bytes(req)
+        if nbytes > self.budget:
+            raise ValueError(f"request {req.rid} needs {nbytes/1e9:.2f} GB, over the budget")
+        with self._lock:
+            self._queue.append((req, nbytes, self.now()))
+            self._lock.notify_all()
+
+    def _dispatch(self):
+        while True:
+            with self._lock:
+                while not self._stop and not self._admissible():
+                    self._lock.wait()
+                if self._stop and not self._queue:
+                    return
+                if not self._admissible():
+                    continue
+                req, nbytes, t_arr = self._queue.popleft()  # FIFO: no overtaking
+                self._in_flight_bytes += nbytes
+                self._in_flight += 1
+            threading.Thread(target=self._work, args=(req, nbytes, t_arr), daemon=True).start()
+
+    def _admissible(self) -> bool:
+        if not self._queue or self._in_flight >= self.max_conc:
+            return False
+        nbytes = self._queue[0][1]
+        return self._in_flight_bytes + nbytes <= self.budget
+
+    def _work(self, req: Request, nbytes: float, t_arr: float):
+        res = solve_one(req, t_arr, self._t0, self.device)
+        with self._lock:
+            self._results.append(res)
+            self._in_flight_bytes -= nbytes
+            self._in_flight -= 1
+            self._lock.notify_all()
+
+    def drain(self) -> List[Result]:
+        with self._lock:
+            while self._queue or self._in_flight:
+                self._lock.wait()
+            out = sorted(self._results, key=lambda r: r.rid)
+            self._results = []
+            return out
+
+    def close(self):
+        with self._lock:
+            self._stop = True
+            self._lock.notify_all()
+        self._dispatcher.join(timeout=5)
+
+
+def run_stream(requests: List[Request], server: Server) -> List[Result]:
+    """Submit requests at their arrival offsets (seconds) and wait for all."""
+    start = server.now()
+    for req in sorted(requests, key=lambda r: r.arrival):
+        delay = start + req.arrival - server.now()
+        if delay > 0:
+            time.sleep(delay)
+        server.submit(req)
+    return server.drain()
+
+
+def latency_stats(results: List[Result], wall: float) -> dict:
+    lat = np.array([r.latency for r in results])
+    return {
+        "n": len(results),
+        "p50_s": float(np.percentile(lat, 50)),
+        "p99_s": float(np.percentile(lat, 99)),
+        "mean_s": float(lat.mean()),
+        "solves_per_s": len(results) / wall,
+        "failed": int(sum(1 for r in results if r.status != 0)),
+    }
+
+
+def make_pool(n: int, seed0: int = 0, precision: int = E.PREC_MIXED, tol: float = 1e-8):
+    """A pool of distinct seeded serving requests (grid 32^3..128^3, 1-6 cases)."""
+    return [Request(i, synth.serving_request(seed0 + i), tol, precision) for i in range(n)]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--pool", type=int, default=16, help="distinct requests, cycled")
+    ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate")
+    ap.add_argument("--rates", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.1])
+    ap.add_argument("--concurrency", type=int, default=8)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--seed", type=int, default=4000)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    torch.cuda.set_device(0)
+    E.lib()
+    prec = E.PREC_MIXED if args.precision == "mixed" else E.PREC_FP64
+    pool = make_pool(args.pool, args.seed, prec)
+    print(f"# pool of {len(pool)} requests: edges {[r.micro.shape[0] for r in pool]}, "
+          f"cases {[r.micro.nrhs for r in pool]}", file=sys.stderr, flush=True)
+    srv = Server(max_concurrency=args.concurrency)
+    # warm-up and saturation: closed loop, everything queued at t = 0
+    run_stream([dataclasses.replace(r, rid=i, arrival=0.0) for i, r in enumerate(pool)], srv)
+    nsat = max(len(pool), args.requests // 2)
+    t0 = time.perf_counter()
+    sat = run_stream([dataclasses.replace(pool[i % len(pool)], rid=i, arrival=0.0)
+                      for i in range(nsat)], srv)
+    sat_rate = len(sat) / (time.perf_counter() - t0)
+    out = {"metric": "p50/p99 solve latency under Poisson arrivals (continuous batching)",
+           "precision": args.precision, "tol": pool[0].tol, "concurrency": args.concurrency,
+           "saturation_solves_per_s": round(sat_rate, 3), "rates": []}
+    rng = np.random.default_rng(args.seed)
+    for frac in args.rates:
+        lam = frac * sat_rate
+        gaps = rng.exponential(1.0 / lam, args.requests)
+        arr = np.cumsum(gaps) - gaps[0]
+        reqs = [dataclasses.replace(pool[i % len(pool)], rid=i, arrival=float(arr[i]))
+                for i in range(args.requests)]
+        t0 = time.perf_counter()
+        res = run_stream(reqs, srv)
+        st = latency_stats(res, time.perf_counter() - t0)
+        st["arrival_rate_frac"] = frac
+        st["arrival_rate_per_s"] = round(lam, 3)
+        out["rates"].append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})
+        print(json.dumps(out["rates"][-1]), file=sys.stderr, flush=True)
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -38,7 +38,7 @@ def test_struct_layout_matches_c(E, tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "elas3d.h"\n'
         "int main(void){\n"
         'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(elas3d_options), offsetof(elas3d_options, hbm_budget_bytes),'
-        " offsetof(elas3d_options, stream), offsetof(elas3d_options, batched),"
+        " offsetof(elas3d_options, stream), offsetof(elas3d_options, graphs),"
         " sizeof(elas3d_info), offsetof(elas3d_info, relres_true));\n"
         'printf("%zu %zu %zu\\n", offsetof(elas3d_info, t_operator_ms), offsetof(elas3d_info, n_update), offsetof(elas3d_info, fp64_fallback));\n'
         "return 0;}\n")
@@ -47,7 +47,7 @@ def test_struct_layout_matches_c(E, tmp_path):
     out = subprocess.check_output([str(exe)]).decode().split()
     c = [int(v) for v in out]
     py = [ctypes.sizeof(E.Options), E.Options.hbm_budget_bytes.offset, E.Options.stream.offset,
-          E.Options.batched.offset, ctypes.sizeof(E.Info), E.Info.relres_true.offset,
+          E.Options.graphs.offset, ctypes.sizeof(E.Info), E.Info.relres_true.offset,
           E.Info.t_operator_ms.offset, E.Info.n_update.offset, E.Info.fp64_fallback.offset]
     assert c == py
 

@@ -292,3 +292,38 @@ def test_homogeneous_effective_stiffness_is_C(E):
         avg = np.array([ctx.stress(r, voxel=False)["avg"] for r in range(6)])
     assert st == E.OK and info["iters"] == [0] * 6
     assert np.allclose(avg.T / 1e-3, C, rtol=1e-12)
+
+
+def test_serving_results_same_alone_and_in_the_mix(E):
+    """Continuous batching: requests of uneven size solved concurrently (own
+    streams, admitted by memory budget) give bit-identical results to the
+    same requests solved alone."""
+    say("case: serving mix vs alone")
+    from paper_2602_07354_amd import serve
+    pool = [r for r in serve.make_pool(12, seed0=900) if r.micro.shape[0] <= 96][:5]
+    alone = [serve.solve_one(r) for r in pool]
+    srv = serve.Server(max_concurrency=4)
+    try:
+        # all queued at once (concurrent), then a staggered stream
+        mixed = serve.run_stream(pool, srv)
+        import dataclasses
+        stag = serve.run_stream([dataclasses.replace(r, arrival=0.01 * i) for i, r in enumerate(pool)], srv)
+    finally:
+        srv.close()
+    for a, m, s in zip(alone, mixed, stag):
+        assert a.status == 0 and max(a.relres_true) <= 1e-8
+        assert a.iters == m.iters == s.iters
+        assert np.array_equal(a.sigma_avg, m.sigma_avg) and np.array_equal(a.sigma_avg, s.sigma_avg)
+
+
+def test_graph_replay_matches_eager_launches(E):
+    """Iteration batches replayed from a captured HIP graph give the same
+    iterates as eager launches (many replays per solve, host syncs between)."""
+    say("case: graphs vs eager")
+    ms = _small_poly((20, 18, 16), 5)
+    out = []
+    for graphs in (0, 1):
+        with E.Context.from_micro(ms, graphs=graphs, poll_interval=4) as ctx:
+            st, info = ctx.solve(1e-10, 5000)
+            out.append((info["iters"], ctx.solution(0)))
+    assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
