@@ -127,7 +127,7 @@ void elas3d_options_init(elas3d_options* opt);
  * the macroscopic strain, Eq. (discrete_energy)) and the inverse point-block
  * Jacobi preconditioner M^-1 (Eq. (block_precond)).
  *   out     receives the context (set to NULL on error).
- *   nx,ny,nz grid size, each >= 2, N = nx*ny*nz < 2^31.
+ *   nx,ny,nz grid size, each >= 2, 3*N < 2^31 (N = nx*ny*nz <= 715827882).
  *   phase   N phase ids in [0, nphase), x fastest (host, or device when
  *           opt->inputs_on_device).
  *   nphase  number of phases (>= 1).

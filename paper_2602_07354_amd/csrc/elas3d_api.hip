@@ -83,7 +83,9 @@ struct elas3d_ctx {
     std::vector<GraphEntry> graphs;
 
     size_t N() const { return (size_t)d.n; }
-    double* plane(double* base, int q) const { return base + (size_t)q * N(); }
+    // component c (or M^-1 entry q) of a field starting at base
+    template <typename P>
+    P* comp(P* base, int c) const { return base + e3d::comp_offset(c, N()); }
 
     bool batched() const { return opt.batched != 0; }
     size_t rs64() const { return (batched() ? 21 : 6) * N(); }  // RHS stride of the bundles
@@ -100,38 +102,38 @@ struct elas3d_ctx {
         Fields f;
         double* wk = work64(rhs);
         for (int c = 0; c < 3; ++c) {
-            f.w[c] = wptr(rhs) + (size_t)c * N();
-            f.b[c] = bptr(rhs) + (size_t)c * N();
-            f.g[c] = wk + (size_t)c * N();
-            f.z[c] = wk + (size_t)(3 + c) * N();
-            f.h0[c] = wk + (size_t)(6 + c) * N();
-            f.h1[c] = wk + (size_t)(9 + c) * N();
-            f.Ah[c] = wk + (size_t)(12 + c) * N();
+            f.w[c] = comp(wptr(rhs), c);
+            f.b[c] = comp(bptr(rhs), c);
+            f.g[c] = comp(wk, c);
+            f.z[c] = comp(wk + 3 * N(), c);
+            f.h0[c] = comp(wk + 6 * N(), c);
+            f.h1[c] = comp(wk + 9 * N(), c);
+            f.Ah[c] = comp(wk + 12 * N(), c);
         }
         return f;
     }
     void minv_planes(double* out[6]) const
     {
-        for (int q = 0; q < 6; ++q) out[q] = minv + (size_t)q * N();
+        for (int q = 0; q < 6; ++q) out[q] = comp(minv, q);
     }
     e3d::FieldsT<float> fields32(int rhs)
     {
         e3d::FieldsT<float> f;
         float* wk = work32(rhs);
         for (int c = 0; c < 3; ++c) {
-            f.g[c] = wk + (size_t)c * N();
-            f.z[c] = wk + (size_t)(3 + c) * N();
-            f.h0[c] = wk + (size_t)(6 + c) * N();
-            f.h1[c] = wk + (size_t)(9 + c) * N();
-            f.Ah[c] = wk + (size_t)(12 + c) * N();
-            f.w[c] = wk + (size_t)(15 + c) * N();
+            f.g[c] = comp(wk, c);
+            f.z[c] = comp(wk + 3 * N(), c);
+            f.h0[c] = comp(wk + 6 * N(), c);
+            f.h1[c] = comp(wk + 9 * N(), c);
+            f.Ah[c] = comp(wk + 12 * N(), c);
+            f.w[c] = comp(wk + 15 * N(), c);
             f.b[c] = nullptr;
         }
         return f;
     }
     void minv32_planes(float* out[6]) const
     {
-        for (int q = 0; q < 6; ++q) out[q] = minv32 + (size_t)q * N();
+        for (int q = 0; q < 6; ++q) out[q] = comp(minv32, q);
     }
     e3d::Tables tables() const { return e3d::Tables{coef, coef32, diag, solid}; }
 };
@@ -268,8 +270,8 @@ int validate_setup(int32_t nx, int32_t ny, int32_t nz, const int32_t* phase, int
     if (nx < 2 || ny < 2 || nz < 2)
         return fail(nullptr, ELAS3D_EBADARG, "grid dimensions must each be >= 2");
     const int64_t n = (int64_t)nx * ny * nz;
-    if (n >= ((int64_t)1 << 31))
-        return fail(nullptr, ELAS3D_EBADARG, "nx*ny*nz must be < 2^31");
+    if (3 * n >= ((int64_t)1 << 31))
+        return fail(nullptr, ELAS3D_EBADARG, "3*nx*ny*nz must be < 2^31");
     if (!phase) return fail(nullptr, ELAS3D_EBADARG, "phase is NULL");
     if (!C) return fail(nullptr, ELAS3D_EBADARG, "C is NULL");
     if (!strain) return fail(nullptr, ELAS3D_EBADARG, "strain is NULL");
@@ -341,10 +343,19 @@ int ensure_events(elas3d_ctx* c, std::vector<EventPair>& pool, size_t count)
     return 0;
 }
 
-hipMemcpyKind copy_kind(const elas3d_ctx* c, bool to_device)
+// Copy a device field of ncomp entries per node out as SoA planes (ncomp*N
+// doubles) to the caller's buffer: device memory when outputs_on_device,
+// else host memory, staged through the work area.  The work area of RHS 0
+// is scratch outside a solve.
+int export_field(elas3d_ctx* c, const double* field, int ncomp, double* out)
 {
-    if (c->opt.outputs_on_device) return hipMemcpyDeviceToDevice;
-    return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+    const size_t N = c->N();
+    double* dst = c->opt.outputs_on_device ? out : c->work64(0);
+    HIPCHK(c, e3d::launch_relayout(c->stream, field, dst, ncomp, N, 1));
+    if (!c->opt.outputs_on_device)
+        HIPCHK(c, hipMemcpyAsync(out, dst, 8 * (size_t)ncomp * N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
 }
 
 struct RunStats {
@@ -634,10 +645,9 @@ int solve_mixed(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info
         const int r = r0 + q;
         Fields f64 = c->fields(r);
         e3d::FieldsT<float> f32 = c->fields32(r);
-        for (int k = 0; k < 3; ++k) {  // w = 0, d = 0
-            HIPCHK(c, hipMemsetAsync(f64.w[k], 0, sizeof(double) * c->N(), c->stream));
-            HIPCHK(c, hipMemsetAsync(f32.w[k], 0, sizeof(float) * c->N(), c->stream));
-        }
+        // w = 0, d = 0 (each field is 3N contiguous elements from component 0)
+        HIPCHK(c, hipMemsetAsync(f64.w[0], 0, sizeof(double) * 3 * c->N(), c->stream));
+        HIPCHK(c, hipMemsetAsync(f32.w[0], 0, sizeof(float) * 3 * c->N(), c->stream));
         HIPCHK(c, hipMemcpyAsync(c->hscratch + 2, c->norms + 2 * r, 2 * sizeof(double),
                                  hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -893,7 +903,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     SETUPCHK(hipMemcpyAsync(c->solid, solid.data(), solid.size(), hipMemcpyHostToDevice, c->stream));
     SETUPCHK(hipMemcpyAsync(c->sig, sig.data(), 8 * sig.size(), hipMemcpyHostToDevice, c->stream));
     for (int r = 0; r < nrhs; ++r) {
-        double* bp[3] = {c->bptr(r), c->bptr(r) + N, c->bptr(r) + 2 * N};
+        double* bp[3] = {c->comp(c->bptr(r), 0), c->comp(c->bptr(r), 1), c->comp(c->bptr(r), 2)};
         SETUPCHK(e3d::launch_load(c->stream, c->d, c->phase,
                                   c->sig + (size_t)r * nphase * e3d::kSigStride, bp, c->partials,
                                   c->norms + 2 * r, kSweepBlocks));
@@ -994,19 +1004,24 @@ int elas3d_apply(elas3d_ctx* ctx, const double* x, double* y)
     if (!x || !y) return fail(ctx, ELAS3D_EBADARG, "x or y is NULL");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     const size_t N = ctx->N();
-    const double* xd = x;
-    double* yd = y;
-    if (!ctx->opt.outputs_on_device) {
-        HIPCHK(ctx, hipMemcpyAsync(ctx->work64(0), x, 8 * 3 * N, hipMemcpyHostToDevice, ctx->stream));
-        xd = ctx->work64(0);
-        yd = ctx->work64(0) + 3 * N;
+    // work area (15N): [x planes | x device layout | y device layout | y planes]
+    double* xs = ctx->work64(0);
+    double* xd = xs + 3 * N;
+    double* yd = xs + 6 * N;
+    double* ys = ctx->opt.outputs_on_device ? y : xs + 9 * N;
+    if (ctx->opt.outputs_on_device)
+        HIPCHK(ctx, e3d::launch_relayout(ctx->stream, x, xd, 3, N, 0));
+    else {
+        HIPCHK(ctx, hipMemcpyAsync(xs, x, 8 * 3 * N, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, e3d::launch_relayout(ctx->stream, xs, xd, 3, N, 0));
     }
-    const double* xp[3] = {xd, xd + N, xd + 2 * N};
-    double* yp[3] = {yd, yd + N, yd + 2 * N};
+    const double* xp[3] = {ctx->comp(xd, 0), ctx->comp(xd, 1), ctx->comp(xd, 2)};
+    double* yp[3] = {ctx->comp(yd, 0), ctx->comp(yd, 1), ctx->comp(yd, 2)};
     HIPCHK(ctx, e3d::launch_apply(ctx->stream, ctx->d, ctx->geom, ctx->phase, ctx->tables(), xp, yp,
                                   nullptr, ctx->partials, nullptr));
+    HIPCHK(ctx, e3d::launch_relayout(ctx->stream, yd, ys, 3, N, 1));
     if (!ctx->opt.outputs_on_device)
-        HIPCHK(ctx, hipMemcpyAsync(y, yd, 8 * 3 * N, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(y, ys, 8 * 3 * N, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return 0;
 }
@@ -1016,10 +1031,7 @@ int elas3d_get_load(elas3d_ctx* ctx, int32_t rhs, double* b)
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
     if (rhs < 0 || rhs >= ctx->nrhs || !b) return fail(ctx, ELAS3D_EBADARG, "bad rhs or NULL output");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, hipMemcpyAsync(b, ctx->bptr(rhs), 8 * 3 * ctx->N(), copy_kind(ctx, false),
-                               ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return 0;
+    return export_field(ctx, ctx->bptr(rhs), 3, b);
 }
 
 int elas3d_get_precond(elas3d_ctx* ctx, double* minv)
@@ -1027,9 +1039,7 @@ int elas3d_get_precond(elas3d_ctx* ctx, double* minv)
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
     if (!minv) return fail(ctx, ELAS3D_EBADARG, "NULL output");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, hipMemcpyAsync(minv, ctx->minv, 8 * 6 * ctx->N(), copy_kind(ctx, false), ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return 0;
+    return export_field(ctx, ctx->minv, 6, minv);
 }
 
 int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w)
@@ -1038,10 +1048,7 @@ int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w)
     if (rhs < 0 || rhs >= ctx->nrhs || !w) return fail(ctx, ELAS3D_EBADARG, "bad rhs or NULL output");
     if (!ctx->solved[rhs]) return fail(ctx, ELAS3D_EORDER, "load case not solved yet");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, hipMemcpyAsync(w, ctx->wptr(rhs), 8 * 3 * ctx->N(), copy_kind(ctx, false),
-                               ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return 0;
+    return export_field(ctx, ctx->wptr(rhs), 3, w);
 }
 
 void elas3d_destroy(elas3d_ctx* ctx)

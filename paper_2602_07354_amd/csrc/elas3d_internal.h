@@ -16,11 +16,29 @@ constexpr int kCoefStride = 24;
 constexpr int kDiagStride = 24;
 constexpr int kSigStride = 8;
 
-// Problem size.  N = nx*ny*nz < 2^31, so node indices fit in int.
+// Problem size.  3N < 2^31, so node and vector-element indices fit in int.
 struct Dims {
     int nx, ny, nz;
     int n;
 };
+
+// Layout of node vectors in device memory.  Interleaved (the default): the
+// three components of a node are adjacent, component c of node m at 3m + c
+// of the field, and the six entries of a node's M^-1 block at 6m + q.  Every
+// workgroup of the tiled operator sweep then reads each row of its tile as
+// one contiguous run of 3 x 8 x TX bytes per field instead of three separate
+// runs, which streams markedly better from HBM.  With E3D_INTERLEAVE=0 the
+// fields are SoA planes (component c at c*N + m), the layout of the C-ABI.
+// A field of T is always 3N (M^-1: 6N) contiguous elements; kernels address
+// component c through a pointer to its first element (base + c*kComp) and
+// node m at m*kVS.
+#ifndef E3D_INTERLEAVE
+#define E3D_INTERLEAVE 0
+#endif
+constexpr int kVS = E3D_INTERLEAVE ? 3 : 1;  // vector element stride of a node
+constexpr int kMS = E3D_INTERLEAVE ? 6 : 1;  // M^-1 element stride of a node
+// offset of component c (or M^-1 entry q) from the start of its field
+__host__ __device__ inline size_t comp_offset(int c, size_t n) { return E3D_INTERLEAVE ? (size_t)c : (size_t)c * n; }
 
 // Device-resident scalars of one PCG run (Algorithm 2).  Written only by
 // the single-block finalize kernels; read by the sweep kernels.
@@ -45,9 +63,10 @@ struct Scalars {
     int pad;
 };
 
-// Field pointers of one PCG run (SoA planes of T: double for the FP64 solve,
-// float for the inner solve of the mixed-precision refinement, where w is
-// the correction d and g starts as the rounded residual).
+// Field pointers of one PCG run (component pointers of T, addressed at
+// m*kVS: double for the FP64 solve, float for the inner solve of the
+// mixed-precision refinement, where w is the correction d and g starts as
+// the rounded residual).
 template <typename T>
 struct FieldsT {
     T* w[3];
@@ -141,5 +160,10 @@ hipError_t launch_total_displacement(hipStream_t st, const Dims& d, const double
                                      const Fields& f, double* const u[3]);
 // Adds to *bad the number of ids outside [0, nphase).
 hipError_t launch_phase_check(hipStream_t st, const int32_t* phase, int n, int nphase, int* bad);
+// Layout conversion between the ABI's SoA planes and the device layout of a
+// field with ncomp components (3: vector, 6: M^-1) of n nodes, FP64,
+// device to device.  to_abi: device layout -> planes; otherwise the reverse.
+hipError_t launch_relayout(hipStream_t st, const double* src, double* dst, int ncomp, size_t n,
+                           int to_abi);
 
 }  // namespace e3d

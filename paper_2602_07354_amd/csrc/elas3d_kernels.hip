@@ -478,9 +478,10 @@ __global__ void __launch_bounds__(kBlock) load_kernel(Dims d, const int32_t* __r
         f0 *= 0.25;
         f1 *= 0.25;
         f2 *= 0.25;
-        bx[m] = f0;
-        by[m] = f1;
-        bz[m] = f2;
+        const size_t mv = (size_t)m * kVS;
+        bx[mv] = f0;
+        by[mv] = f1;
+        bz[mv] = f2;
         acc[0] += f0 * f0 + f1 * f1 + f2 * f2;
         // uncancelled element forces of voxel m: sum_a |sigma s_a / 4|^2 = |sigma|_F^2 / 2
         const double* s = sig + (size_t)phase[m] * kSigStride;
@@ -543,12 +544,13 @@ __global__ void __launch_bounds__(kBlock) precond_kernel(Dims d, const int32_t* 
                 r[5] = c01 * inv;
             }
         }
-        m0[m] = r[0];
-        m1[m] = r[1];
-        m2[m] = r[2];
-        m3[m] = r[3];
-        m4[m] = r[4];
-        m5[m] = r[5];
+        const size_t mq = (size_t)m * kMS;
+        m0[mq] = r[0];
+        m1[mq] = r[1];
+        m2[mq] = r[2];
+        m3[mq] = r[3];
+        m4[mq] = r[4];
+        m5[mq] = r[5];
     }
 }
 
@@ -566,24 +568,26 @@ __global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, 
 {
     double acc[2] = {0.0, 0.0};
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        const int mv = m * kVS;
+        const size_t mq = (size_t)m * kMS;
         T g[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            g[c] = from_residual ? f.g[c][m] : f.b[c][m];
-            if (!from_residual) f.g[c][m] = g[c];
+            g[c] = from_residual ? f.g[c][mv] : f.b[c][mv];
+            if (!from_residual) f.g[c][mv] = g[c];
         }
-        const T xx = M.m[0][m], yy = M.m[1][m], zz = M.m[2][m];
-        const T yz = M.m[3][m], xz = M.m[4][m], xy = M.m[5][m];
+        const T xx = M.m[0][mq], yy = M.m[1][mq], zz = M.m[2][mq];
+        const T yz = M.m[3][mq], xz = M.m[4][mq], xy = M.m[5][mq];
         const T z0 = xx * g[0] + xy * g[1] + xz * g[2];
         const T z1 = xy * g[0] + yy * g[1] + yz * g[2];
         const T z2 = xz * g[0] + yz * g[1] + zz * g[2];
-        f.z[0][m] = z0;
-        f.z[1][m] = z1;
-        f.z[2][m] = z2;
+        f.z[0][mv] = z0;
+        f.z[1][mv] = z1;
+        f.z[2][mv] = z2;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            f.h0[c][m] = T(0);
-            if (fresh) f.w[c][m] = T(0);
+            f.h0[c][mv] = T(0);
+            if (fresh) f.w[c][mv] = T(0);
         }
         acc[0] += (double)z0 * g[0] + (double)z1 * g[1] + (double)z2 * g[2];
         acc[1] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
@@ -617,12 +621,12 @@ __global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
         T mm[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) mm[q] = M.m[q][m];
+        for (int q = 0; q < 6; ++q) mm[q] = M.m[q][(size_t)m * kMS];
         const T xx = mm[0], yy = mm[1], zz = mm[2], yz = mm[3], xz = mm[4], xy = mm[5];
 #pragma unroll
         for (int r = 0; r < kMaxRhs; ++r) {
             if (!(active & (1u << r))) continue;
-            const size_t o = (size_t)r * rs + m;
+            const size_t o = (size_t)r * rs + (size_t)m * kVS;
             T g[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) g[c] = fma(-lam[r], f.Ah[c][o], f.g[c][o]);
@@ -650,7 +654,7 @@ __global__ void __launch_bounds__(kBlock) final_update_kernel(Dims d, FieldsT<T>
     T* const* h = S->cur ? f.h1 : f.h0;
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) f.w[c][m] = fma(-lam, h[c][m], f.w[c][m]);
+        for (int c = 0; c < 3; ++c) f.w[c][m * kVS] = fma(-lam, h[c][m * kVS], f.w[c][m * kVS]);
     }
 }
 
@@ -660,9 +664,10 @@ __global__ void __launch_bounds__(kBlock) add_correction_kernel(Dims d, double* 
                                                                 const float* d1, const float* d2)
 {
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        w0[m] += (double)d0[m];
-        w1[m] += (double)d1[m];
-        w2[m] += (double)d2[m];
+        const int mv = m * kVS;
+        w0[mv] += (double)d0[mv];
+        w1[mv] += (double)d1[mv];
+        w2[mv] += (double)d2[mv];
     }
 }
 
@@ -808,28 +813,29 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
     auto fetch = [&](int kk) {
         const int kw = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
         const int base = kw * plane;
+        const int io = (base + own) * kVS, ih = (base + hoff) * kVS;
         if constexpr (FUSED) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                rh[c] = hold[c][base + own];
-                rz[c] = a.z[c][base + own];
-                rw[c] = a.w[c][base + own];
-                hh[c] = hold[c][base + hoff];
-                hz[c] = a.z[c][base + hoff];
+                rh[c] = hold[c][io];
+                rz[c] = a.z[c][io];
+                rw[c] = a.w[c][io];
+                hh[c] = hold[c][ih];
+                hz[c] = a.z[c][ih];
             }
         } else if constexpr (MODE == OP_REFINE) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                rz[c] = a.x[c][base + own];
-                rh[c] = a.xd[c][base + own];
-                hz[c] = a.x[c][base + hoff];
-                hh[c] = a.xd[c][base + hoff];
+                rz[c] = a.x[c][io];
+                rh[c] = a.xd[c][io];
+                hz[c] = a.x[c][ih];
+                hh[c] = a.xd[c][ih];
             }
         } else {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                rz[c] = a.x[c][base + own];
-                hz[c] = a.x[c][base + hoff];
+                rz[c] = a.x[c][io];
+                hz[c] = a.x[c][ih];
             }
         }
     };
@@ -885,7 +891,7 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
 #pragma unroll
         for (int c = 0; c < 3; ++c) ov[c] = own_value(c);
         if (out_ok && ku < kend) {
-            const int idx = kuw * plane + own;
+            const int idx = (kuw * plane + own) * kVS;
             if constexpr (FUSED) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -938,7 +944,7 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
         __syncthreads();
         if (s > 0 && out_ok) {
             const int kl = k0 - 1 + s;
-            const int idx = (kl < 0 ? kl + nz : kl) * plane + own;
+            const int idx = ((kl < 0 ? kl + nz : kl) * plane + own) * kVS;
             R yv[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -1013,7 +1019,7 @@ __global__ void __launch_bounds__(kBlock) stress_kernel(Dims d, const int32_t* _
             const double xi[3] = {(double)(a & 1), (double)((a >> 1) & 1), (double)(a >> 2)};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double wv = f.w[c][m];
+                const double wv = f.w[c][m * kVS];
                 u[c][a] = wv;
                 ut_[c][a] = wv + Et[c][0] * xi[0] + Et[c][1] * xi[1] + Et[c][2] * xi[2];
             }
@@ -1066,9 +1072,31 @@ __global__ void __launch_bounds__(kBlock) total_displacement_kernel(Dims d, Stra
         int i, j, k;
         node_ijk(m, d, i, j, k);
         const double X = i, Y = j, Z = k;
-        u0[m] = f.w[0][m] + E.e[0] * X + E.e[5] * Y + E.e[4] * Z;
-        u1[m] = f.w[1][m] + E.e[5] * X + E.e[1] * Y + E.e[3] * Z;
-        u2[m] = f.w[2][m] + E.e[4] * X + E.e[3] * Y + E.e[2] * Z;
+        const int mv = m * kVS;
+        u0[m] = f.w[0][mv] + E.e[0] * X + E.e[5] * Y + E.e[4] * Z;
+        u1[m] = f.w[1][mv] + E.e[5] * X + E.e[1] * Y + E.e[3] * Z;
+        u2[m] = f.w[2][mv] + E.e[4] * X + E.e[3] * Y + E.e[2] * Z;
+    }
+}
+
+// Between SoA planes (entry q of node m at q*n + m) and the device layout
+// (q*kComp + m*kStride), for a field of ncomp entries per node.
+__global__ void __launch_bounds__(kBlock) relayout_kernel(const double* __restrict__ src,
+                                                          double* __restrict__ dst, int ncomp, size_t n,
+                                                          int to_abi)
+{
+    const size_t total = (size_t)ncomp * n;
+    const size_t node_stride = E3D_INTERLEAVE ? (size_t)ncomp : 1;
+    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (size_t)gridDim.x * kBlock) {
+        // t enumerates the device layout; its ABI position is q*n + m
+        const size_t m = E3D_INTERLEAVE ? t / ncomp : t % n;
+        const size_t q = E3D_INTERLEAVE ? t - m * ncomp : t / n;
+        const size_t dev = comp_offset((int)q, n) + m * node_stride;
+        const size_t abi = q * n + m;
+        if (to_abi)
+            dst[abi] = src[dev];
+        else
+            dst[dev] = src[abi];
     }
 }
 
@@ -1317,6 +1345,17 @@ hipError_t launch_phase_check(hipStream_t st, const int32_t* phase, int n, int n
 {
     const int nb = sweep_blocks(n, 2048);
     hipLaunchKernelGGL(phase_check_kernel, dim3(nb), dim3(kBlock), 0, st, phase, n, nphase, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_relayout(hipStream_t st, const double* src, double* dst, int ncomp, size_t n,
+                           int to_abi)
+{
+    size_t nb = ((size_t)ncomp * n + kBlock - 1) / kBlock;
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(relayout_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, src, dst, ncomp, n,
+                       to_abi);
     return hipGetLastError();
 }
 
