@@ -94,6 +94,18 @@ typedef struct elas3d_options {
     int32_t graphs;            /* nonzero: replay each batch of poll_interval
                                   iterations as a captured HIP graph (ignored
                                   when timing is on); default 1                      */
+    int32_t autotune;          /* nonzero: before the first iteration of each
+                                  precision, time the candidate workgroup shapes
+                                  and chunkings of the direction+operator sweep and
+                                  the grid of the update sweep on the live problem,
+                                  keep the fastest (cached per process by grid,
+                                  precision and RHS count).  The reduction order
+                                  then follows the chosen geometry, so results match
+                                  the default geometry's to rounding, not bitwise.
+                                  Default 0                                          */
+    int32_t tile;              /* workgroup shape of the direction+operator sweep
+                                  when not autotuned: 0 = 32x8 lanes (default),
+                                  1 = 16x16, 2 = 64x4, 3 = 32x16                     */
 } elas3d_options;
 
 typedef struct elas3d_info {
@@ -114,11 +126,15 @@ typedef struct elas3d_info {
     int64_t n_update;                          /* update launches timed              */
     int32_t fp64_fallback[ELAS3D_MAX_RHS];     /* mixed: 1 if the refinement stalled
                                                   and the solve finished in FP64    */
+    int32_t op_tile[3];                        /* workgroup lanes in x, y and z-chunk
+                                                  length of the direction+operator
+                                                  sweep (of the inner solve in mixed) */
+    int32_t update_blocks;                     /* grid of the update sweep           */
 } elas3d_info;
 
 /* Fill `opt` with the defaults (FP64, residual criterion, block Jacobi,
  * host pointers, automatic polling, no timing, current device, budget from
- * free memory, library stream, not batched, graphs on). */
+ * free memory, library stream, not batched, graphs on, no autotuning). */
 void elas3d_options_init(elas3d_options* opt);
 
 /*
@@ -186,7 +202,8 @@ int elas3d_get_precond(elas3d_ctx* ctx, double* minv);
 /* Copy the fluctuation displacement w of case `rhs` (3*N doubles). */
 int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w);
 
-/* Device bytes a context with these sizes and options would allocate. */
+/* Device bytes a context with these sizes and options would allocate (0 for
+ * sizes that elas3d_setup would reject). */
 double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
                            const elas3d_options* opt);
 

@@ -7,10 +7,13 @@
 // reads the stop flag every `poll_interval` iterations, one batch behind
 // the device (a batch enqueued after convergence returns at once).
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,6 +30,10 @@ namespace {
 thread_local std::string g_last_error = "";
 
 constexpr int kSweepBlocks = 4096;  // grid of the node-wise sweeps
+// autotuning candidates: workgroup targets of the operator sweep (every tile
+// shape) and grids of the update sweep
+constexpr int kTuneTargets[3] = {2048, 4096, 8192};
+constexpr int kTuneUpdate[5] = {1024, 2048, 4096, 8192, 16384};
 constexpr int kPartialValues = 8;   // partial sums per block, upper bound
 constexpr int kDefaultPoll = 16;
 
@@ -44,7 +51,12 @@ struct elas3d_ctx {
     int nphase = 0, nrhs = 0;
     elas3d_options opt{};
     std::vector<double> strain;  // nrhs * 6
-    e3d::OpGeom geom{};
+    e3d::OpGeom geom{};  // APPLY / REFINE sweeps (tile shape 0)
+    // direction+operator sweep and update grid per precision (0 FP64, 1 FP32),
+    // the defaults or the autotuned choice
+    e3d::OpGeom geom_sweep[2]{};
+    int upd_blocks[2] = {0, 0};
+    int tuned[2] = {0, 0};
 
     int32_t* phase = nullptr;
     double* coef = nullptr;
@@ -169,8 +181,20 @@ void default_options(elas3d_options* o)
 
 // Device bytes of a context (kept in one place so the budget check and
 // elas3d_device_bytes agree).
-double plan_bytes(int64_t n, int nphase, int nrhs, bool mixed, bool batched)
+// Partial sums per value slot: one per workgroup (and RHS) of the largest
+// grid any sweep or autotuning candidate can launch.
+int partial_slots(const Dims& d, int nrhs)
 {
+    long long most = 65536;
+    for (int tile = 0; tile < e3d::kNumTiles; ++tile)
+        for (int target : kTuneTargets)
+            most = std::max(most, (long long)e3d::op_geometry(d, 0, tile, target).blocks * nrhs);
+    return (int)most;
+}
+
+double plan_bytes(int32_t nx, int32_t ny, int32_t nz, int nphase, int nrhs, bool mixed, bool batched)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
     const double N = (double)n;
     double bytes = 0.0;
     if (mixed)  // FP32 work, M^-1, table
@@ -181,7 +205,7 @@ double plan_bytes(int64_t n, int nphase, int nrhs, bool mixed, bool batched)
     bytes += 8.0 * 6.0 * N;                    // M^-1 (symmetric 3x3)
     bytes += (double)nphase * 8.0 * (e3d::kCoefStride + e3d::kDiagStride + 1.0) +
              (double)nphase * nrhs * 8.0 * e3d::kSigStride;
-    bytes += 8.0 * kPartialValues * 65536.0;   // partial sums
+    bytes += 8.0 * kPartialValues * partial_slots(Dims{nx, ny, nz, (int)n}, nrhs);  // partial sums
     bytes += 4096.0;
     return bytes;
 }
@@ -261,6 +285,8 @@ int validate_options(const elas3d_options* o)
         return fail(nullptr, ELAS3D_EBADARG, "options.hbm_budget_bytes must be finite and >= 0");
     if (!(o->inner_tol >= 0.0) || !(o->inner_tol < 1.0))
         return fail(nullptr, ELAS3D_EBADARG, "options.inner_tol must be in [0, 1)");
+    if (o->tile < 0 || o->tile >= e3d::kNumTiles)
+        return fail(nullptr, ELAS3D_EBADARG, "options.tile must be in [0, 3]");
     return 0;
 }
 
@@ -358,6 +384,88 @@ int export_field(elas3d_ctx* c, const double* field, int ncomp, double* out)
     return 0;
 }
 
+// Process-wide autotuning results: (device, nx, ny, nz, element size, RHS)
+// -> (operator sweep geometry, update grid).
+std::mutex g_tune_mu;
+std::map<std::array<int, 6>, std::pair<e3d::OpGeom, int>> g_tune_cache;
+
+// Time every candidate geometry of the two iteration sweeps on the live
+// fields and keep the fastest.  Runs right after the start of a run, where
+// lambda = gamma = 0 and h_old = 0: the operator sweep then writes
+// h_new = z (which the first iteration writes again) and Ah, leaves w as it
+// is, and the update sweep leaves g as it is and rewrites z = M^-1 g; no
+// finalize kernel runs, so the scalars are untouched.
+template <typename T>
+int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* const M[6])
+{
+    const int pi = sizeof(T) == sizeof(double) ? 0 : 1;
+    const std::array<int, 6> key = {c->device, c->d.nx, c->d.ny, c->d.nz, (int)sizeof(T), R};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            c->geom_sweep[pi] = it->second.first;
+            c->upd_blocks[pi] = it->second.second;
+            c->tuned[pi] = 1;
+            return 0;
+        }
+    }
+    const Dims& d = c->d;
+    const e3d::Tables t = c->tables();
+    Scalars* S0 = c->S + r0;
+    hipEvent_t ev[2];
+    HIPCHK(c, hipEventCreate(&ev[0]));
+    HIPCHK(c, hipEventCreate(&ev[1]));
+    auto time_it = [&](auto launch, float& ms) -> int {
+        HIPCHK(c, launch());  // warm-up
+        HIPCHK(c, hipEventRecord(ev[0], c->stream));
+        for (int k = 0; k < 3; ++k) HIPCHK(c, launch());
+        HIPCHK(c, hipEventRecord(ev[1], c->stream));
+        HIPCHK(c, hipEventSynchronize(ev[1]));
+        HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+        return 0;
+    };
+    int rc = 0;
+    float best = 1e30f;
+    e3d::OpGeom best_g = c->geom_sweep[pi];
+    for (int tile = 0; tile < e3d::kNumTiles && !rc; ++tile)
+        for (int target : kTuneTargets) {
+            const e3d::OpGeom g = e3d::op_geometry(d, 0, tile, target);
+            float ms = 0.f;
+            rc = time_it([&] {
+                return e3d::launch_direction_operator<T>(c->stream, d, g, c->phase, t, f0, rs, R, S0,
+                                                         c->partials, false);
+            }, ms);
+            if (rc) break;
+            if (ms < best) {
+                best = ms;
+                best_g = g;
+            }
+        }
+    float best_u = 1e30f;
+    int best_nb = c->upd_blocks[pi];
+    for (int nb : kTuneUpdate) {
+        if (rc) break;
+        float ms = 0.f;
+        rc = time_it([&] {
+            return e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials, nb, false);
+        }, ms);
+        if (!rc && ms < best_u) {
+            best_u = ms;
+            best_nb = nb;
+        }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (rc) return rc;
+    c->geom_sweep[pi] = best_g;
+    c->upd_blocks[pi] = best_nb;
+    c->tuned[pi] = 1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {best_g, best_nb};
+    return 0;
+}
+
 struct RunStats {
     Scalars fin{};       // device scalars at the end of the run
     int it_start = 0;    // iteration counter when the run started
@@ -376,6 +484,13 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* co
     const e3d::Tables t = c->tables();
     const int poll = c->opt.poll_interval > 0 ? c->opt.poll_interval : kDefaultPoll;
     const bool timing = c->opt.timing != 0;
+    const int pi = sizeof(T) == sizeof(double) ? 0 : 1;
+    if (c->opt.autotune && !c->tuned[pi]) {
+        int rc = autotune<T>(c, f0, rs, r0, R, M);
+        if (rc) return rc;
+    }
+    const e3d::OpGeom geom = c->geom_sweep[pi];
+    const int upd_blocks = c->upd_blocks[pi];
     Scalars* S0 = c->S + r0;
     Scalars* h0 = c->hS;                      // slot 0
     Scalars* h1 = c->hS + e3d::kMaxRhs;       // slot 1
@@ -410,11 +525,11 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* co
                 HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
                 hipError_t e1 = hipSuccess;
                 for (int j = 0; j < poll && e1 == hipSuccess; ++j) {
-                    e1 = e3d::launch_direction_operator<T>(c->stream, d, c->geom, c->phase, t, f0, rs, R,
+                    e1 = e3d::launch_direction_operator<T>(c->stream, d, geom, c->phase, t, f0, rs, R,
                                                            S0, c->partials);
                     if (e1 == hipSuccess)
                         e1 = e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials,
-                                                           kSweepBlocks);
+                                                           upd_blocks);
                 }
                 hipError_t e2 = hipStreamEndCapture(c->stream, &ge.graph);
                 if (e1 != hipSuccess || e2 != hipSuccess)
@@ -435,14 +550,14 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* co
                     if (rc) return rc;
                     HIPCHK(c, hipEventRecord(c->ev_op[ev_used].a, c->stream));
                 }
-                HIPCHK(c, e3d::launch_direction_operator<T>(c->stream, d, c->geom, c->phase, t, f0, rs,
+                HIPCHK(c, e3d::launch_direction_operator<T>(c->stream, d, geom, c->phase, t, f0, rs,
                                                             R, S0, c->partials));
                 if (timing) {
                     HIPCHK(c, hipEventRecord(c->ev_op[ev_used].b, c->stream));
                     HIPCHK(c, hipEventRecord(c->ev_up[ev_used].a, c->stream));
                 }
                 HIPCHK(c, e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials,
-                                                        kSweepBlocks));
+                                                        upd_blocks));
                 if (timing) {
                     HIPCHK(c, hipEventRecord(c->ev_up[ev_used].b, c->stream));
                     ++ev_used;
@@ -753,6 +868,12 @@ int solve_batch(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info
             info->relres_precond[r] =
                 (zero_load || fin.gg0 <= 0) ? 0.0 : std::sqrt(std::fabs(fin.gg / fin.gg0));
             info->fp64_fallback[r] = res[q].fallback;
+            const int pi = c->opt.precision == ELAS3D_PREC_MIXED ? 1 : 0;
+            const e3d::OpGeom& g = c->geom_sweep[pi];
+            info->op_tile[0] = e3d::kTileShapes[g.tile].tx;
+            info->op_tile[1] = e3d::kTileShapes[g.tile].ty;
+            info->op_tile[2] = g.kz;
+            info->update_blocks = c->upd_blocks[pi];
         }
         c->solved[r] = 1;
         worst = std::max(worst, fin.status);
@@ -780,8 +901,10 @@ const char* elas3d_last_error(const elas3d_ctx* ctx)
 double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
                            const elas3d_options* opt)
 {
-    return plan_bytes((int64_t)nx * ny * nz, nphase, nrhs,
-                      opt && opt->precision == ELAS3D_PREC_MIXED, opt && opt->batched);
+    if (nx < 1 || ny < 1 || nz < 1 || 3 * (int64_t)nx * ny * nz >= ((int64_t)1 << 31) || nrhs < 1)
+        return 0.0;
+    return plan_bytes(nx, ny, nz, nphase, nrhs, opt && opt->precision == ELAS3D_PREC_MIXED,
+                      opt && opt->batched);
 }
 
 int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int32_t* phase,
@@ -810,7 +933,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     }
     const int64_t n = (int64_t)nx * ny * nz;
     const bool mixed = opt.precision == ELAS3D_PREC_MIXED;
-    const double need = plan_bytes(n, nphase, nrhs, mixed, opt.batched != 0);
+    const double need = plan_bytes(nx, ny, nz, nphase, nrhs, mixed, opt.batched != 0);
     double budget = opt.hbm_budget_bytes;
     if (budget <= 0.0) {
         size_t free_b = 0, total_b = 0;
@@ -835,7 +958,11 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->solved.assign(nrhs, 0);
     c->bytes = need;
     c->geom = e3d::op_geometry(c->d, 0);
-    c->partial_stride = 65536;
+    for (int q = 0; q < 2; ++q) {
+        c->geom_sweep[q] = e3d::op_geometry(c->d, 0, opt.tile);
+        c->upd_blocks[q] = kSweepBlocks;
+    }
+    c->partial_stride = partial_slots(c->d, nrhs);
 
     auto bail = [&](hipError_t e, const char* what) {
         std::string m = std::string(what) + ": " + hipGetErrorString(e);

@@ -105,13 +105,25 @@ struct Tables {
     const uint8_t* solid;  // nphase: 1 if the phase has stiffness
 };
 
+// Workgroup shapes (lanes in x and y) of the tiled operator sweep.  Shape 0
+// is the default of every sweep; the fused direction + operator sweep can be
+// autotuned over all of them.
+constexpr int kNumTiles = 4;
+struct TileShape {
+    int tx, ty;
+};
+constexpr TileShape kTileShapes[kNumTiles] = {{32, 8}, {16, 16}, {64, 4}, {32, 16}};
+
 // Kernel launch geometry of the tiled operator sweep.
 struct OpGeom {
+    int tile;  // index into kTileShapes
     int tiles_x, tiles_y, zchunks, kz;
     int blocks;
 };
 
-OpGeom op_geometry(const Dims& d, int kz_hint);
+// kz_hint > 0 fixes the z chunk; otherwise the chunks are cut so that about
+// target_blocks workgroups (0: the default, 4096) cover the grid.
+OpGeom op_geometry(const Dims& d, int kz_hint, int tile = 0, int target_blocks = 0);
 
 // ---- launchers (elas3d_kernels.hip) -------------------------------------
 // Every launcher enqueues on `st` and returns the hipError_t of the launch.
@@ -131,14 +143,17 @@ hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, T
 // The two iteration sweeps run a batch of nrhs right-hand sides in lockstep:
 // f describes RHS 0, RHS r lies r*rs elements further in every field, and S
 // points to nrhs consecutive scalar sets (a RHS whose flag is done is skipped).
+// finalize = false launches the sweep alone (autotuning at the start of a
+// run, where lambda = gamma = 0 leave the iterate unchanged).
 template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
                                      const int32_t* phase, const Tables& t, const FieldsT<T>& f,
-                                     size_t rs, int nrhs, Scalars* S, double* partials);
+                                     size_t rs, int nrhs, Scalars* S, double* partials,
+                                     bool finalize = true);
 template <typename T>
 hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f, size_t rs,
                                  int nrhs, T* const minv[6], Scalars* S, double* partials,
-                                 int max_blocks);
+                                 int max_blocks, bool finalize = true);
 template <typename T>
 hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& f, Scalars* S);
 // Refinement of the mixed-precision solve: r = A (w + d) + b in FP64, stored
@@ -149,6 +164,7 @@ hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const i
                          double* norm2);
 hipError_t launch_to_float(hipStream_t st, const double* src, float* dst, size_t n);
 // y = A x (+ add when add[0] != nullptr); ||y||^2 into *norm2 when norm2 != nullptr.
+// APPLY and REFINE run with tile shape 0 only.
 hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
                         const Tables& t, const double* const x[3], double* const y[3],
                         const double* const add[3], double* partials, double* norm2);

@@ -974,16 +974,31 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
     }
 }
 
-#ifndef E3D_TX
-#define E3D_TX 32
-#endif
-#ifndef E3D_TY
-#define E3D_TY 8
-#endif
 #ifndef E3D_OP_TARGET_BLOCKS
 #define E3D_OP_TARGET_BLOCKS 4096
 #endif
-constexpr int kTX = E3D_TX, kTY = E3D_TY;
+constexpr int kTX = kTileShapes[0].tx, kTY = kTileShapes[0].ty;
+
+// Launch of the operator sweep with the workgroup shape of g.tile.
+template <int MODE, typename T>
+hipError_t launch_op_tiled(hipStream_t st, const OpGeom& g, unsigned grid, const OpArgs<T>& a)
+{
+#define E3D_OP_CASE(I)                                                                        \
+    case I:                                                                                   \
+        hipLaunchKernelGGL((op_kernel<kTileShapes[I].tx, kTileShapes[I].ty, MODE, T>), dim3(grid), \
+                           dim3(kTileShapes[I].tx * kTileShapes[I].ty), 0, st, a);             \
+        break;
+    switch (g.tile) {
+        E3D_OP_CASE(0)
+        E3D_OP_CASE(1)
+        E3D_OP_CASE(2)
+        E3D_OP_CASE(3)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef E3D_OP_CASE
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------ post-process
 
@@ -1124,16 +1139,18 @@ int sweep_blocks(int n, int max_blocks)
 
 // ------------------------------------------------------------- launchers
 
-OpGeom op_geometry(const Dims& d, int kz_hint)
+OpGeom op_geometry(const Dims& d, int kz_hint, int tile, int target_blocks)
 {
     OpGeom g;
-    g.tiles_x = (d.nx + kTX - 2) / (kTX - 1);
-    g.tiles_y = (d.ny + kTY - 2) / (kTY - 1);
+    g.tile = (tile >= 0 && tile < kNumTiles) ? tile : 0;
+    const int tx = kTileShapes[g.tile].tx, ty = kTileShapes[g.tile].ty;
+    g.tiles_x = (d.nx + tx - 2) / (tx - 1);
+    g.tiles_y = (d.ny + ty - 2) / (ty - 1);
     const int ntiles = g.tiles_x * g.tiles_y;
     int kz = kz_hint;
     if (kz <= 0) {
         // enough workgroups to fill 256 CUs several times over
-        const int target = E3D_OP_TARGET_BLOCKS;
+        const int target = target_blocks > 0 ? target_blocks : E3D_OP_TARGET_BLOCKS;
         int chunks = (target + ntiles - 1) / ntiles;
         if (chunks > d.nz) chunks = d.nz;
         kz = (d.nz + chunks - 1) / chunks;
@@ -1190,7 +1207,7 @@ hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, T
 template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
                                      const int32_t* phase, const Tables& t, const FieldsT<T>& f,
-                                     size_t rs, int nrhs, Scalars* S, double* partials)
+                                     size_t rs, int nrhs, Scalars* S, double* partials, bool finalize)
 {
     OpArgs<T> a = {};
     a.d = d;
@@ -1213,8 +1230,8 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
     a.partials = partials;
     a.rs = rs;
     a.nrhs = nrhs;
-    hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_FUSED, T>), dim3(g.blocks * nrhs), dim3(kTX * kTY), 0,
-                       st, a);
+    hipError_t e = launch_op_tiled<OP_FUSED, T>(st, g, (unsigned)(g.blocks * nrhs), a);
+    if (e != hipSuccess || !finalize) return e;
     hipLaunchKernelGGL(finalize_kernel<1>, dim3(nrhs), dim3(kFinThreads), 0, st, (int)FIN_DIRECTION,
                        (const double*)partials, g.blocks, g.blocks, S, (double*)nullptr,
                        (const double*)nullptr, g.blocks);
@@ -1224,11 +1241,12 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
 template <typename T>
 hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f, size_t rs,
                                  int nrhs, T* const minv[6], Scalars* S, double* partials,
-                                 int max_blocks)
+                                 int max_blocks, bool finalize)
 {
     const int nb = sweep_blocks(d.n, max_blocks);
     hipLaunchKernelGGL(update_precond_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, rs, nrhs,
                        mk_minv(minv), (const Scalars*)S, partials, nb);
+    if (!finalize) return hipGetLastError();
     hipLaunchKernelGGL(finalize_kernel<2>, dim3(nrhs), dim3(kFinThreads), 0, st, (int)FIN_UPDATE,
                        (const double*)partials, nb, nb, S, (double*)nullptr, (const double*)nullptr,
                        2 * nb);
@@ -1249,9 +1267,9 @@ hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& 
     template hipError_t launch_direction_operator<T>(hipStream_t, const Dims&, const OpGeom&,         \
                                                      const int32_t*, const Tables&,                  \
                                                      const FieldsT<T>&, size_t, int, Scalars*,        \
-                                                     double*);                                       \
+                                                     double*, bool);                                 \
     template hipError_t launch_update_precond<T>(hipStream_t, const Dims&, const FieldsT<T>&, size_t, \
-                                                 int, T* const[6], Scalars*, double*, int);          \
+                                                 int, T* const[6], Scalars*, double*, int, bool);    \
     template hipError_t launch_final_update<T>(hipStream_t, const Dims&, const FieldsT<T>&, Scalars*);
 E3D_INSTANTIATE(double)
 E3D_INSTANTIATE(float)
@@ -1275,6 +1293,7 @@ hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const in
     }
     a.partials = partials;
     a.want_norm = norm2 != nullptr;
+    if (g.tile != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_APPLY, double>), dim3(g.blocks), dim3(kTX * kTY), 0, st,
                        a);
     if (norm2)
@@ -1304,6 +1323,7 @@ hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const i
     }
     a.partials = partials;
     a.want_norm = 1;
+    if (g.tile != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_REFINE, double>), dim3(g.blocks), dim3(kTX * kTY), 0, st,
                        a);
     hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,

@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EBADARG", "ENOMEM", "EDEVICE", "EORDER",
     "PREC_FP64", "PREC_MIXED", "CONV_RESIDUAL", "CONV_PAPER", "PRECOND_BLOCK_JACOBI",
-    "PRECOND_NONE", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
+    "PRECOND_NONE", "TILE_SHAPES", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
     "setup", "solve", "stress", "apply", "get_load", "get_precond", "get_solution",
     "device_bytes", "destroy", "last_error", "version", "Context", "EXPORTS",
 ]
@@ -32,6 +32,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 CONV_RESIDUAL, CONV_PAPER = 0, 1
 PRECOND_BLOCK_JACOBI, PRECOND_NONE = 0, 1
 MAX_RHS = 6
+# workgroup shapes (lanes in x, y) of the direction+operator sweep, by options.tile
+TILE_SHAPES = ((32, 8), (16, 16), (64, 4), (32, 16))
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libelas3d.so")
 
@@ -58,6 +60,8 @@ class Options(ctypes.Structure):
         ("inner_maxit", ctypes.c_int32),
         ("batched", ctypes.c_int32),
         ("graphs", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
     ]
 
 
@@ -80,6 +84,8 @@ class Info(ctypes.Structure):
         ("t_update_ms", ctypes.c_double),
         ("n_update", ctypes.c_int64),
         ("fp64_fallback", ctypes.c_int32 * _R),
+        ("op_tile", ctypes.c_int32 * 3),
+        ("update_blocks", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -99,6 +105,8 @@ class Info(ctypes.Structure):
             "t_update_ms": self.t_update_ms,
             "n_update": self.n_update,
             "fp64_fallback": list(self.fp64_fallback[:n]),
+            "op_tile": list(self.op_tile),
+            "update_blocks": self.update_blocks,
         }
 
 

@@ -40,7 +40,9 @@ def test_struct_layout_matches_c(E, tmp_path):
         'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(elas3d_options), offsetof(elas3d_options, hbm_budget_bytes),'
         " offsetof(elas3d_options, stream), offsetof(elas3d_options, graphs),"
         " sizeof(elas3d_info), offsetof(elas3d_info, relres_true));\n"
-        'printf("%zu %zu %zu\\n", offsetof(elas3d_info, t_operator_ms), offsetof(elas3d_info, n_update), offsetof(elas3d_info, fp64_fallback));\n'
+        'printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(elas3d_info, t_operator_ms), offsetof(elas3d_info, n_update),'
+        ' offsetof(elas3d_info, fp64_fallback), offsetof(elas3d_info, op_tile),'
+        ' offsetof(elas3d_info, update_blocks), offsetof(elas3d_options, autotune));\n'
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -48,7 +50,8 @@ def test_struct_layout_matches_c(E, tmp_path):
     c = [int(v) for v in out]
     py = [ctypes.sizeof(E.Options), E.Options.hbm_budget_bytes.offset, E.Options.stream.offset,
           E.Options.graphs.offset, ctypes.sizeof(E.Info), E.Info.relres_true.offset,
-          E.Info.t_operator_ms.offset, E.Info.n_update.offset, E.Info.fp64_fallback.offset]
+          E.Info.t_operator_ms.offset, E.Info.n_update.offset, E.Info.fp64_fallback.offset,
+          E.Info.op_tile.offset, E.Info.update_blocks.offset, E.Options.autotune.offset]
     assert c == py
 
 
@@ -90,7 +93,8 @@ def test_setup_rejects_bad_arguments(E, mutate, needle):
 def test_setup_rejects_bad_options(E):
     shape, phase, C, strain = _good()
     for kw in ({"precision": 7}, {"convergence": 3}, {"preconditioner": -1},
-               {"poll_interval": -2}, {"hbm_budget_bytes": -1.0}, {"inner_tol": 2.0}):
+               {"poll_interval": -2}, {"hbm_budget_bytes": -1.0}, {"inner_tol": 2.0},
+               {"tile": 4}, {"tile": -1}):
         with pytest.raises(E.Elas3dError) as ei:
             E.setup(shape, phase, C, strain, E.options_init(**kw))
         assert ei.value.code == E.EBADARG
@@ -109,3 +113,8 @@ def test_device_bytes_plan(E):
     b1 = E.device_bytes((500, 500, 500), 8001, 1)
     assert 25e9 < b1 < 30e9  # ~220 B per node in FP64 with one load case
     assert E.device_bytes((500, 500, 500), 8001, 6) > b1
+    # a flat grid has far more workgroups than z chunks: the partial sums grow
+    flat = E.device_bytes((6000, 6000, 2), 2, 1)
+    assert flat > 220 * 6000 * 6000 * 2
+    # sizes setup would reject
+    assert E.device_bytes((1000, 1000, 1000), 2, 1) == 0.0

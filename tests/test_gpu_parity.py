@@ -327,3 +327,50 @@ def test_graph_replay_matches_eager_launches(E):
             st, info = ctx.solve(1e-10, 5000)
             out.append((info["iters"], ctx.solution(0)))
     assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_every_sweep_tile_shape_matches_oracle(E, orc, tile):
+    """Each workgroup shape of the fused direction+operator sweep (the
+    autotuner's candidates) solves to the oracle's solution; ragged sizes so
+    that every shape has partial tiles in x and y."""
+    say("case: sweep tile shape", tile)
+    ms = _small_poly((37, 29, 21), 41, grains=15)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    for precision in (E.PREC_FP64, E.PREC_MIXED):
+        with E.Context.from_micro(ms, tile=tile, precision=precision) as ctx:
+            st, info = ctx.solve(1e-12 if precision == E.PREC_FP64 else 1e-10, 20000)
+            assert st == E.OK
+            assert info["op_tile"][:2] == list(E.TILE_SHAPES[tile])
+            if precision == E.PREC_FP64:
+                assert abs(info["iters"][0] - ro["iters"]) <= 2
+            out = ctx.stress(0)
+        so, _ = P.stress(ms.strain[0], ro["w"])
+        assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
+
+
+def test_autotuned_geometry_solves_and_is_cached(E, orc):
+    """Autotuning picks one of the candidate geometries, solves to the same
+    answer (to rounding) as the default geometry, and a second context of the
+    same size reuses the choice."""
+    say("case: autotune")
+    ms = _small_poly((45, 38, 30), 43, grains=18)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    infos = []
+    for _ in range(2):
+        with E.Context.from_micro(ms, autotune=1) as ctx:
+            st, info = ctx.solve(1e-12, 20000)
+            assert st == E.OK and info["relres_true"][0] <= 1e-12
+            assert tuple(info["op_tile"][:2]) in E.TILE_SHAPES
+            assert info["update_blocks"] in (1024, 2048, 4096, 8192, 16384)
+            assert abs(info["iters"][0] - ro["iters"]) <= 2
+            assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
+            infos.append(info)
+    assert infos[0]["op_tile"] == infos[1]["op_tile"]
+    assert infos[0]["update_blocks"] == infos[1]["update_blocks"]
+    with E.Context.from_micro(ms, autotune=1, precision=E.PREC_MIXED) as ctx:
+        st, info = ctx.solve(1e-10, 20000)
+        assert st == E.OK and info["relres_true"][0] <= 1e-10
