@@ -202,6 +202,57 @@ int elas3d_get_precond(elas3d_ctx* ctx, double* minv);
 /* Copy the fluctuation displacement w of case `rhs` (3*N doubles). */
 int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w);
 
+/*
+ * Von Mises equivalent stress of load case `rhs` per voxel (Sec. 2.1.3,
+ * Table 1, stress_fullfield): from the centroid stress sigma of
+ * elas3d_stress, sqrt(((s11-s22)^2 + (s22-s33)^2 + (s33-s11)^2)/2
+ * + 3 (s23^2 + s13^2 + s12^2)); 0 in voids.
+ *   vm       N doubles or NULL (device memory when outputs_on_device).
+ *   vm_max   1 double (host) or NULL: the largest value.
+ *   argmax   1 int64 (host) or NULL: the lowest voxel index holding it.
+ * Returns 0, ELAS3D_EBADARG, ELAS3D_EORDER (rhs not solved) or ELAS3D_EDEVICE.
+ */
+int elas3d_von_mises(elas3d_ctx* ctx, int32_t rhs, double* vm, double* vm_max, int64_t* argmax);
+
+/*
+ * Microstructure generator (Sec. 2.2), context-free.  opt (NULL = defaults)
+ * supplies device, stream and outputs_on_device: when set, `phase` is device
+ * memory, otherwise host memory.  Errors: ELAS3D_EBADARG (message in
+ * elas3d_last_error(NULL)), ELAS3D_EDEVICE.  Seeds and pores are host
+ * arrays and are copied.
+ *
+ * Grain assignment (Sec. 2.2.2, Eq. ellipsoid_dist): voxel (i,j,k), centre
+ * x = (i+1/2, j+1/2, k+1/2), gets the grain g minimising
+ *   D^2 = (dx^2 + dy^2) / rt_g^2 + dz^2 / rl_g^2
+ * over all ngrain grains, d the periodic minimum-image offset of x from seed
+ * g (x - s, or (x -+ L) - s when |x - s| > L/2), evaluated in FP64 in that
+ * order; the lowest index wins a tie.  The result is exact (the search is cut
+ * by a proven distance bound, not by a candidate radius).
+ *   seeds  3*ngrain doubles, seed g at (x, y, z), each in [0, n_d).
+ *   semi   2*ngrain doubles (rt_g, rl_g > 0), or NULL for all 1 (plain
+ *          periodic Voronoi).
+ *   phase  N int32 written with grain ids 0..ngrain-1.
+ */
+int elas3d_generate_grains(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, const double* seeds,
+                           const double* semi, int32_t* phase, const elas3d_options* opt);
+
+/*
+ * Pore overwrite (Sec. 2.2.3): pores p = 0, 1, ... are carved in order,
+ * setting to void_id every voxel whose centre they cover, until the number of
+ * void voxels reaches `target` (target < 0: carve all; none is carved when
+ * the count already reaches it).  Pore p is 15 doubles: centre (3, in
+ * [0, n_d)), semi-axes a (3, > 0), R (9, row-major, columns = the pore's
+ * axes in the sample frame); it covers x when
+ *   sum_j (e_j / a_j)^2 <= 1 + 1e-12,  e_j = (d0 R0j + d1 R1j) + d2 R2j,
+ * d the minimum-image offset of x from the centre (as above), in FP64.
+ *   phase   N int32, read and updated in place.
+ *   used    (host, may be NULL) pores carved.
+ *   nvoid   (host, may be NULL) void voxels afterwards.
+ */
+int elas3d_carve_pores(int32_t nx, int32_t ny, int32_t nz, int32_t* phase, int32_t void_id, int32_t npore,
+                       const double* pores, double target, int32_t* used, int64_t* nvoid,
+                       const elas3d_options* opt);
+
 /* Device bytes a context with these sizes and options would allocate (0 for
  * sizes that elas3d_setup would reject). */
 double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
@@ -211,7 +262,7 @@ double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, i
 void elas3d_destroy(elas3d_ctx* ctx);
 
 /* Message of the last error of `ctx`, or of the calling thread's last
- * context-free call (setup) when ctx is NULL.  Never NULL. */
+ * context-free call (setup, generator) when ctx is NULL.  Never NULL. */
 const char* elas3d_last_error(const elas3d_ctx* ctx);
 
 /* Library version string. */

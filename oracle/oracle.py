@@ -11,13 +11,14 @@ import numpy as np
 
 __all__ = [
     "build", "lib", "Problem", "element_stiffness", "stiffness_table",
-    "CONVERGED", "NOT_CONVERGED", "BREAKDOWN",
+    "CONVERGED", "NOT_CONVERGED", "BREAKDOWN", "grains", "grains_at", "carve", "covered_at", "von_mises",
 ]
 
 CONVERGED, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "elas3d_oracle.c")
+_SRC_GEN = os.path.join(_HERE, "microstructure_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -26,11 +27,19 @@ _I32 = ctypes.POINTER(ctypes.c_int32)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 
 
+def _stale() -> bool:
+    if not os.path.exists(_LIB):
+        return True
+    t = os.path.getmtime(_LIB)
+    return any(t < os.path.getmtime(src) for src in (_SRC, _SRC_GEN))
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction)."""
+    if force or _stale():
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp,
+                               _SRC, _SRC_GEN, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -38,7 +47,7 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         i, l, d = ctypes.c_int, ctypes.c_long, ctypes.c_double
@@ -55,6 +64,12 @@ def lib():
         L.orc_stress.argtypes = [i, i, i, _I32, i, _D, _D, _D, _D, _D]
         L.orc_energy.argtypes = [i, i, i, _I32, _D, _D, _D]
         L.orc_energy.restype = d
+        L.orc_grains.argtypes = [i, i, i, i, _D, _D, _I32]
+        L.orc_carve.argtypes = [i, i, i, _I32, ctypes.c_int32, i, _D, d, _I64]
+        L.orc_carve.restype = ctypes.c_int
+        L.orc_von_mises.argtypes = [l, _D, _D]
+        L.orc_grains_at.argtypes = [i, i, i, i, _D, _D, _I64, l, _I32]
+        L.orc_covered_at.argtypes = [i, i, i, i, _D, _I64, l, _I32]
         _lib = L
     return _lib
 
@@ -183,3 +198,59 @@ class Problem:
         e = _f64(strain).reshape(6)
         w = _f64(w).reshape(3, self.n)
         return float(lib().orc_energy(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e), _p(w)))
+
+
+# ------------------------------------------------------------ generator
+
+
+def grains(shape, seeds, semi=None) -> np.ndarray:
+    """Grain id per voxel: smallest ellipsoidal distance over all grains
+    (Sec. 2.2.2, Eq. ellipsoid_dist), brute force."""
+    nx, ny, nz = (int(s) for s in shape)
+    seeds = _f64(seeds).reshape(-1, 3)
+    semi = np.ones((seeds.shape[0], 2)) if semi is None else _f64(semi).reshape(-1, 2)
+    out = np.empty(nx * ny * nz, dtype=np.int32)
+    lib().orc_grains(nx, ny, nz, seeds.shape[0], _p(seeds), _p(semi), _p(out, _I32))
+    return out
+
+
+def grains_at(shape, seeds, semi, idx) -> np.ndarray:
+    """grains() at the voxels idx only."""
+    nx, ny, nz = (int(s) for s in shape)
+    seeds = _f64(seeds).reshape(-1, 3)
+    semi = np.ones((seeds.shape[0], 2)) if semi is None else _f64(semi).reshape(-1, 2)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(idx.size, dtype=np.int32)
+    lib().orc_grains_at(nx, ny, nz, seeds.shape[0], _p(seeds), _p(semi), _p(idx, _I64), idx.size,
+                        _p(out, _I32))
+    return out
+
+
+def covered_at(shape, pores, idx) -> np.ndarray:
+    """1 where any of the pores covers voxel idx[t] (the pore-overwrite test)."""
+    nx, ny, nz = (int(s) for s in shape)
+    pores = _f64(pores).reshape(-1, 15)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(idx.size, dtype=np.int32)
+    lib().orc_covered_at(nx, ny, nz, pores.shape[0], _p(pores), _p(idx, _I64), idx.size, _p(out, _I32))
+    return out
+
+
+def carve(shape, phase, void_id: int, pores, target: float = -1.0) -> tuple:
+    """Pore overwrite in order until the void count reaches target (Sec. 2.2.3);
+    returns (new phase, pores used, void voxels)."""
+    nx, ny, nz = (int(s) for s in shape)
+    ph = np.array(phase, dtype=np.int32, copy=True)
+    pores = _f64(pores).reshape(-1, 15)
+    nvoid = np.zeros(1, dtype=np.int64)
+    used = lib().orc_carve(nx, ny, nz, _p(ph, _I32), int(void_id), pores.shape[0], _p(pores), float(target),
+                           _p(nvoid, _I64))
+    return ph, int(used), int(nvoid[0])
+
+
+def von_mises(sigma) -> np.ndarray:
+    """Von Mises equivalent stress of Voigt stress planes (6 x N)."""
+    sigma = _f64(sigma).reshape(6, -1)
+    vm = np.empty(sigma.shape[1])
+    lib().orc_von_mises(sigma.shape[1], _p(sigma), _p(vm))
+    return vm

@@ -152,6 +152,12 @@ struct elas3d_ctx {
 
 namespace {
 
+}  // namespace
+
+void e3d::set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
 int fail(elas3d_ctx* ctx, int code, const std::string& msg)
 {
     if (ctx)
@@ -1122,6 +1128,26 @@ int elas3d_stress(elas3d_ctx* ctx, int32_t rhs, double* sigma_voxel, double* sig
     if (sigma_avg)
         for (int q = 0; q < 6; ++q) sigma_avg[q] = ctx->hscratch[q] / (double)N;
     if (energy) *energy = ctx->hscratch[6];
+    return 0;
+}
+
+int elas3d_von_mises(elas3d_ctx* ctx, int32_t rhs, double* vm, double* vm_max, int64_t* argmax)
+{
+    if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (rhs < 0 || rhs >= ctx->nrhs) return fail(ctx, ELAS3D_EBADARG, "rhs out of range");
+    if (!ctx->solved[rhs]) return fail(ctx, ELAS3D_EORDER, "load case not solved yet");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const size_t N = ctx->N();
+    double* dvm = vm ? (ctx->opt.outputs_on_device ? vm : ctx->work64(0)) : nullptr;  // 15N >= N
+    HIPCHK(ctx, e3d::launch_von_mises(ctx->stream, ctx->d, ctx->phase, ctx->tables(),
+                                      ctx->strain.data() + 6 * rhs, ctx->fields(rhs), dvm, ctx->partials,
+                                      ctx->dscratch, kSweepBlocks));
+    if (vm && !ctx->opt.outputs_on_device)
+        HIPCHK(ctx, hipMemcpyAsync(vm, dvm, 8 * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hscratch, ctx->dscratch, 8 * 2, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (vm_max) *vm_max = ctx->hscratch[0];
+    if (argmax) *argmax = (int64_t)ctx->hscratch[1];
     return 0;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 namespace e3d {
 
@@ -172,10 +173,19 @@ hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const in
 hipError_t launch_stress(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
                          const double* strain6, const Fields& f, double* const sig[6],
                          double* partials, double* sums7, int max_blocks);
+// Von Mises stress per voxel into vm (may be nullptr) and {max, argmax}
+// (argmax as a double) into the device pair out2.  Uses f.w.
+hipError_t launch_von_mises(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
+                            const double* strain6, const Fields& f, double* vm, double* partials,
+                            double* out2, int max_blocks);
 hipError_t launch_total_displacement(hipStream_t st, const Dims& d, const double* strain6,
                                      const Fields& f, double* const u[3]);
 // Adds to *bad the number of ids outside [0, nphase).
 hipError_t launch_phase_check(hipStream_t st, const int32_t* phase, int n, int nphase, int* bad);
+// Message returned by elas3d_last_error(NULL) on this thread (context-free
+// entry points).
+void set_last_error(const std::string& msg);
+
 // Layout conversion between the ABI's SoA planes and the device layout of a
 // field with ncomp components (3: vector, 6: M^-1) of n nodes, FP64,
 // device to device.  to_abi: device layout -> planes; otherwise the reverse.

@@ -1013,14 +1013,14 @@ struct Sig6 {
 // Centroid stress C_p (E_hat + B(1/2) w_e) per voxel, which is the voxel
 // average of the trilinear field, and the element energy
 // 1/2 (u^E + w)_e^T K_e (u^E + w)_e (Eq. discrete_energy).
-__global__ void __launch_bounds__(kBlock) stress_kernel(Dims d, const int32_t* __restrict__ phase,
-                                                        const double* __restrict__ coef, Strain6 E,
-                                                        Fields f, Sig6 out, int store,
-                                                        double* partials, int stride)
+// Centroid stress sg of voxel e and, with ENERGY, its element energy en.
+template <bool ENERGY>
+__device__ __forceinline__ void voxel_stress(const Dims& d, const int32_t* __restrict__ phase,
+                                             const double* __restrict__ coef, const Strain6& E,
+                                             const Fields& f, int e, double (&sg)[6], double& en)
 {
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     const double Et[3][3] = {{E.e[0], E.e[5], E.e[4]}, {E.e[5], E.e[1], E.e[3]}, {E.e[4], E.e[3], E.e[2]}};
-    for (int e = blockIdx.x * kBlock + threadIdx.x; e < d.n; e += gridDim.x * kBlock) {
+    {
         int i, j, k;
         node_ijk(e, d, i, j, k);
         const int i1 = i + 1 == d.nx ? 0 : i + 1;
@@ -1052,30 +1052,131 @@ __global__ void __launch_bounds__(kBlock) stress_kernel(Dims d, const int32_t* _
         double Cu[21];
         load_coef(coef, phase[e], Cu);  // C/16
         constexpr int sup[6] = {0, 1, 2, 3, 4, 5};
-        double sg[6];
         contract<6>(Cu, sup, eps, sg);
 #pragma unroll
         for (int r = 0; r < 6; ++r) sg[r] *= 16.0;
+        en = 0.0;
+        if constexpr (ENERGY) {
+            double ff[3][8];
+            double keep[3][8];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < 8; ++a) keep[c][a] = ut_[c][a];
+            element_force(Cu, ut_, ff);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < 8; ++a) en += keep[c][a] * ff[c][a];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) stress_kernel(Dims d, const int32_t* __restrict__ phase,
+                                                        const double* __restrict__ coef, Strain6 E,
+                                                        Fields f, Sig6 out, int store,
+                                                        double* partials, int stride)
+{
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < d.n; e += gridDim.x * kBlock) {
+        double sg[6], en;
+        voxel_stress<true>(d, phase, coef, E, f, e, sg, en);
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
             if (store) out.s[r][e] = sg[r];
             acc[r] += sg[r];
         }
-        double ff[3][8];
-        double keep[3][8];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int a = 0; a < 8; ++a) keep[c][a] = ut_[c][a];
-        element_force(Cu, ut_, ff);
-        double en = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int a = 0; a < 8; ++a) en += keep[c][a] * ff[c][a];
         acc[6] += 0.5 * en;
     }
     block_partials<7, kBlock>(acc, partials, stride, blockIdx.x);
+}
+
+// (value, index) pair order of the von Mises maximum: larger value, then
+// lower index.
+__device__ __forceinline__ bool vm_better(double v, double i, double bv, double bi)
+{
+    return v > bv || (v == bv && i < bi);
+}
+
+// Von Mises stress of every voxel (optional store) and the block's largest
+// value with its lowest voxel index: partials[b] (value), partials[stride+b]
+// (index, exact in a double).
+__global__ void __launch_bounds__(kBlock) von_mises_kernel(Dims d, const int32_t* __restrict__ phase,
+                                                           const double* __restrict__ coef, Strain6 E,
+                                                           Fields f, double* vm, double* partials,
+                                                           int stride)
+{
+    double best = -1.0, bidx = 0.0;
+    for (int e = blockIdx.x * kBlock + threadIdx.x; e < d.n; e += gridDim.x * kBlock) {
+        double sg[6], en;
+        voxel_stress<false>(d, phase, coef, E, f, e, sg, en);
+        const double a = sg[0] - sg[1], b = sg[1] - sg[2], c = sg[2] - sg[0];
+        const double v = sqrt(0.5 * (a * a + b * b + c * c) + 3.0 * (sg[3] * sg[3] + sg[4] * sg[4] + sg[5] * sg[5]));
+        if (vm) vm[e] = v;
+        if (vm_better(v, (double)e, best, bidx)) {
+            best = v;
+            bidx = (double)e;
+        }
+    }
+    __shared__ double rv[kBlock / 64], ri[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off), oi = __shfl_xor(bidx, off);
+        if (vm_better(ov, oi, best, bidx)) {
+            best = ov;
+            bidx = oi;
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        rv[wid] = best;
+        ri[wid] = bidx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bv = rv[0], bi = ri[0];
+        for (int w = 1; w < kBlock / 64; ++w)
+            if (vm_better(rv[w], ri[w], bv, bi)) {
+                bv = rv[w];
+                bi = ri[w];
+            }
+        partials[blockIdx.x] = bv;
+        partials[stride + blockIdx.x] = bi;
+    }
+}
+
+__global__ void __launch_bounds__(kFinThreads) von_mises_finalize(const double* partials, int stride,
+                                                                  int nblocks, double* out2)
+{
+    __shared__ double rv[kFinThreads / 64], ri[kFinThreads / 64];
+    double best = -1.0, bidx = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kFinThreads)
+        if (vm_better(partials[b], partials[stride + b], best, bidx)) {
+            best = partials[b];
+            bidx = partials[stride + b];
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off), oi = __shfl_xor(bidx, off);
+        if (vm_better(ov, oi, best, bidx)) {
+            best = ov;
+            bidx = oi;
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        rv[wid] = best;
+        ri[wid] = bidx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bv = rv[0], bi = ri[0];
+        for (int w = 1; w < kFinThreads / 64; ++w)
+            if (vm_better(rv[w], ri[w], bv, bi)) {
+                bv = rv[w];
+                bi = ri[w];
+            }
+        out2[0] = bv;
+        out2[1] = bi;
+    }
 }
 
 // u = E.X + w with X = (i, j, k) of the node.
@@ -1358,6 +1459,20 @@ hipError_t launch_stress(hipStream_t st, const Dims& d, const int32_t* phase, co
     hipLaunchKernelGGL(finalize_kernel<7>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
                        (const double*)partials, nb, nb, (Scalars*)nullptr, sums7,
                        (const double*)nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_von_mises(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
+                           const double* strain6, const Fields& f, double* vm, double* partials,
+                           double* out2, int max_blocks)
+{
+    const int nb = sweep_blocks(d.n, max_blocks);
+    Strain6 E;
+    for (int q = 0; q < 6; ++q) E.e[q] = strain6[q];
+    hipLaunchKernelGGL(von_mises_kernel, dim3(nb), dim3(kBlock), 0, st, d, phase, t.coef, E, f, vm, partials,
+                       nb);
+    hipLaunchKernelGGL(von_mises_finalize, dim3(1), dim3(kFinThreads), 0, st, (const double*)partials, nb, nb,
+                       out2);
     return hipGetLastError();
 }
 

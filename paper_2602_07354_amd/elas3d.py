@@ -23,7 +23,8 @@ __all__ = [
     "PREC_FP64", "PREC_MIXED", "CONV_RESIDUAL", "CONV_PAPER", "PRECOND_BLOCK_JACOBI",
     "PRECOND_NONE", "TILE_SHAPES", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
     "setup", "solve", "stress", "apply", "get_load", "get_precond", "get_solution",
-    "device_bytes", "destroy", "last_error", "version", "Context", "EXPORTS",
+    "device_bytes", "destroy", "last_error", "version", "Context", "EXPORTS", "von_mises",
+    "generate_grains", "carve_pores", "PORE_STRIDE",
 ]
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
@@ -34,13 +35,16 @@ PRECOND_BLOCK_JACOBI, PRECOND_NONE = 0, 1
 MAX_RHS = 6
 # workgroup shapes (lanes in x, y) of the direction+operator sweep, by options.tile
 TILE_SHAPES = ((32, 8), (16, 16), (64, 4), (32, 16))
+# doubles per pore of elas3d_carve_pores: centre 3, semi-axes 3, R row-major 9
+PORE_STRIDE = 15
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libelas3d.so")
 
 EXPORTS = (
     "elas3d_options_init", "elas3d_setup", "elas3d_solve", "elas3d_stress", "elas3d_apply",
     "elas3d_get_load", "elas3d_get_precond", "elas3d_get_solution", "elas3d_device_bytes",
-    "elas3d_destroy", "elas3d_last_error", "elas3d_version",
+    "elas3d_destroy", "elas3d_last_error", "elas3d_version", "elas3d_von_mises",
+    "elas3d_generate_grains", "elas3d_carve_pores",
 )
 
 
@@ -162,6 +166,13 @@ def lib():
         L.elas3d_last_error.restype = ctypes.c_char_p
         L.elas3d_version.argtypes = []
         L.elas3d_version.restype = ctypes.c_char_p
+        L.elas3d_von_mises.argtypes = [vp, i32, vp, vp, vp]
+        L.elas3d_von_mises.restype = ctypes.c_int
+        L.elas3d_generate_grains.argtypes = [i32, i32, i32, i32, vp, vp, vp, ctypes.POINTER(Options)]
+        L.elas3d_generate_grains.restype = ctypes.c_int
+        L.elas3d_carve_pores.argtypes = [i32, i32, i32, vp, i32, i32, vp, d, vp, vp,
+                                         ctypes.POINTER(Options)]
+        L.elas3d_carve_pores.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -249,6 +260,45 @@ def get_solution(ctx, rhs: int, w) -> int:
     return _check(lib().elas3d_get_solution(ctx, int(rhs), _ptr(w)), ctx)
 
 
+def von_mises(ctx, rhs: int, vm=None) -> tuple:
+    """elas3d_von_mises; fills vm (N doubles or None), returns (max, argmax)."""
+    mx = np.empty(1)
+    am = np.empty(1, dtype=np.int64)
+    _check(lib().elas3d_von_mises(ctx, int(rhs), _ptr(vm), _ptr(mx), _ptr(am)), ctx)
+    return float(mx[0]), int(am[0])
+
+
+def generate_grains(shape, seeds, semi=None, phase=None, options: Optional[Options] = None):
+    """elas3d_generate_grains.  Host phase (returned) unless options has
+    outputs_on_device and `phase` is a device buffer of N int32."""
+    nx, ny, nz = (int(s) for s in shape)
+    seeds = np.ascontiguousarray(seeds, dtype=np.float64).reshape(-1, 3)
+    if semi is not None:
+        semi = np.ascontiguousarray(semi, dtype=np.float64).reshape(-1, 2)
+        if semi.shape[0] != seeds.shape[0]:
+            raise ValueError("semi must have one row per seed")
+    if phase is None:
+        phase = np.empty(nx * ny * nz, dtype=np.int32)
+    rc = lib().elas3d_generate_grains(nx, ny, nz, seeds.shape[0], _ptr(seeds), _ptr(semi), _ptr(phase),
+                                      ctypes.byref(options) if options is not None else None)
+    _check(rc)
+    return phase
+
+
+def carve_pores(shape, phase, void_id: int, pores, target: float = -1.0,
+                options: Optional[Options] = None) -> tuple:
+    """elas3d_carve_pores on `phase` in place; returns (pores used, void voxels)."""
+    nx, ny, nz = (int(s) for s in shape)
+    pores = np.ascontiguousarray(pores, dtype=np.float64).reshape(-1, PORE_STRIDE)
+    used = np.zeros(1, dtype=np.int32)
+    nvoid = np.zeros(1, dtype=np.int64)
+    rc = lib().elas3d_carve_pores(nx, ny, nz, _ptr(phase), int(void_id), pores.shape[0],
+                                  _ptr(pores) if pores.shape[0] else None, float(target), _ptr(used),
+                                  _ptr(nvoid), ctypes.byref(options) if options is not None else None)
+    _check(rc)
+    return int(used[0]), int(nvoid[0])
+
+
 def device_bytes(shape, nphase: int, nrhs: int, options: Optional[Options] = None) -> float:
     nx, ny, nz = (int(s) for s in shape)
     return lib().elas3d_device_bytes(nx, ny, nz, int(nphase), int(nrhs),
@@ -308,6 +358,11 @@ class Context:
         out[:, 0, 2] = out[:, 2, 0] = xz
         out[:, 0, 1] = out[:, 1, 0] = xy
         return out
+
+    def von_mises(self, rhs: int = 0, field: bool = True) -> dict:
+        vm = np.empty(self.n) if field else None
+        mx, am = von_mises(self.handle, rhs, vm)
+        return {"vm": vm, "max": mx, "argmax": am}
 
     def solution(self, rhs: int = 0) -> np.ndarray:
         w = np.empty((3, self.n))

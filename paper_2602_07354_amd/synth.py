@@ -50,7 +50,7 @@ __all__ = [
     "rotate_stiffness",
     "random_rotations",
     "periodic_voronoi",
-    "carve_spheres",
+    "carve_spheres", "draw_pore", "workload_recipe",
     "carve_ellipsoids",
     "eshelby_inclusion",
     "polycrystal",
@@ -226,22 +226,23 @@ def periodic_voronoi(shape: Sequence[int], seeds: np.ndarray,
     return out
 
 
+def _min_image(x: np.ndarray, s: float, L: int) -> np.ndarray:
+    """Minimum-image offset of voxel centres x from s, rounded once:
+    x - s, or (x -+ L) - s when |x - s| > L/2."""
+    d = x - s
+    return np.where(d > 0.5 * L, (x - L) - s, np.where(d < -0.5 * L, (x + L) - s, d))
+
+
 def _box_offsets(shape, centre, half):
-    """Index ranges (wrapped) and minimum-image offsets of voxel centres near a point."""
+    """Voxel indices (wrapped) near a point and the minimum-image offsets of
+    their centres."""
     axes = []
     for d in range(3):
         n = shape[d]
         lo = int(math.floor(centre[d] - half[d] - 0.5))
         hi = int(math.ceil(centre[d] + half[d] - 0.5))
-        if hi - lo + 1 >= n:
-            idx = np.arange(n)
-            off = idx + 0.5 - centre[d]
-            off = off - n * np.round(off / n)
-        else:
-            raw = np.arange(lo, hi + 1)
-            off = raw + 0.5 - centre[d]
-            idx = np.mod(raw, n)
-        axes.append((idx, off))
+        idx = np.arange(n) if hi - lo + 1 >= n else np.mod(np.arange(lo, hi + 1), n)
+        axes.append((idx, _min_image(idx + 0.5, float(centre[d]), n)))
     return axes
 
 
@@ -262,10 +263,15 @@ def carve_ellipsoids(phase: np.ndarray, shape: Sequence[int], centres: np.ndarra
         ax = np.asarray(semi_axes[p], dtype=np.float64)
         half = np.full(3, ax.max())
         (ix, dx), (iy, dy), (iz, dz) = _box_offsets((nx, ny, nz), c, half)
-        D = np.stack(np.meshgrid(dz, dy, dx, indexing="ij"), axis=-1)[..., ::-1]
-        if rotations is not None:
-            D = D @ rotations[p]  # components in the ellipsoid frame
-        inside = np.sum((D / ax) ** 2, axis=-1) <= 1.0 + 1e-12
+        d0, d1, d2 = np.meshgrid(dx, dy, dz, indexing="ij")  # [x, y, z]
+        R = np.eye(3) if rotations is None else np.asarray(rotations[p], dtype=np.float64)
+        # offsets in the ellipsoid's own axes, each product and sum rounded on
+        # its own (the order fixed by the pore-overwrite definition)
+        s = None
+        for j in range(3):
+            q = ((d0 * R[0, j] + d1 * R[1, j]) + d2 * R[2, j]) / ax[j]
+            s = q * q if s is None else s + q * q
+        inside = (s <= 1.0 + 1e-12).transpose(2, 1, 0)  # [z, y, x]
         if inside.any():
             sub = view[np.ix_(iz, iy, ix)]
             fresh += int(np.count_nonzero(sub[inside] != void_id))
@@ -317,6 +323,23 @@ def _lognormal_radii(rng, median, sigma, n):
     return median * np.exp(sigma * rng.standard_normal(n))
 
 
+def draw_pore(rng: np.random.Generator, pop: dict, box: np.ndarray):
+    """Next pore of a population: (centre, semi-axes, rotation or None).
+
+    The draws (centre, then the shape's own) are the whole random stream of
+    a pore, so a generator that carves on the device can replay it."""
+    kind = pop["kind"]
+    c = rng.random(3) * box
+    if kind == "sphere":
+        r = float(_lognormal_radii(rng, pop.get("median", 2.0), pop.get("sigma", 0.4), 1)[0])
+        return c, np.array([r, r, r]), None
+    if kind == "oblate":
+        return c, np.asarray(pop.get("axes", (4.0, 4.0, 1.0)), dtype=np.float64), random_rotations(rng, 1)[0]
+    if kind == "prolate_z":
+        return c, np.asarray(pop.get("axes", (5.0 / 3.0, 5.0 / 3.0, 5.0)), dtype=np.float64), None
+    raise ValueError(f"unknown pore kind {kind!r}")
+
+
 def polycrystal(shape: Sequence[int], n_grains: int, seed: int,
                 pores: Sequence[dict] = (), strain: Optional[np.ndarray] = None,
                 cubic: Sequence[float] = SS316L_CUBIC) -> Microstructure:
@@ -347,21 +370,9 @@ def polycrystal(shape: Sequence[int], n_grains: int, seed: int,
         kind = pop["kind"]
         added = 0
         while n_void < target * N:
-            c = rng.random(3) * box
-            if kind == "sphere":
-                r = _lognormal_radii(rng, pop.get("median", 2.0), pop.get("sigma", 0.4), 1)
-                n_void += carve_spheres(phase, (nx, ny, nz), c[None], r, void_id)
-            elif kind == "oblate":
-                a = pop.get("axes", (4.0, 4.0, 1.0))
-                Q = random_rotations(rng, 1)
-                n_void += carve_ellipsoids(phase, (nx, ny, nz), c[None], np.array([a]), Q,
-                                           void_id)
-            elif kind == "prolate_z":
-                a = pop.get("axes", (5.0 / 3.0, 5.0 / 3.0, 5.0))
-                n_void += carve_ellipsoids(phase, (nx, ny, nz), c[None], np.array([a]), None,
-                                           void_id)
-            else:
-                raise ValueError(f"unknown pore kind {kind!r}")
+            c, a, Q = draw_pore(rng, pop, box)
+            n_void += carve_ellipsoids(phase, (nx, ny, nz), c[None], a[None],
+                                       None if Q is None else Q[None], void_id)
             added += 1
         counts[kind] = counts.get(kind, 0) + added
     if strain is None:
@@ -398,17 +409,24 @@ def _poly_recipe(name: str):
 WORKLOADS = ("eshelby20", "poly100", "poly300", "poly500", "poly800")
 
 
-def workload(name: str, scale: Optional[int] = None, nrhs: Optional[int] = None) -> Microstructure:
-    """Named synthetic workload; ``scale`` re-sizes a polycrystal to ``scale``^3
-    voxels keeping its grain density and pore recipe (for bounded samples)."""
-    if name == "eshelby20":
-        return eshelby_inclusion(20)
+def workload_recipe(name: str, scale: Optional[int] = None) -> dict:
+    """Recipe of a polycrystal workload; ``scale`` re-sizes it to ``scale``^3
+    voxels keeping its grain density and pore recipe."""
     rec = _poly_recipe(name)
     if scale is not None:
         n0 = rec["shape"][0]
         rec["n_grains"] = max(1, int(round(rec["n_grains"] * (scale / n0) ** 3)))
         rec["shape"] = (scale, scale, scale)
         rec["seed"] = rec["seed"] + scale
+    return rec
+
+
+def workload(name: str, scale: Optional[int] = None, nrhs: Optional[int] = None) -> Microstructure:
+    """Named synthetic workload; ``scale`` re-sizes a polycrystal to ``scale``^3
+    voxels keeping its grain density and pore recipe (for bounded samples)."""
+    if name == "eshelby20":
+        return eshelby_inclusion(20)
+    rec = workload_recipe(name, scale)
     strain = np.array(rec["strain"], dtype=np.float64)
     if nrhs is not None:
         strain = strain[:nrhs]

@@ -118,3 +118,30 @@ def test_device_bytes_plan(E):
     assert flat > 220 * 6000 * 6000 * 2
     # sizes setup would reject
     assert E.device_bytes((1000, 1000, 1000), 2, 1) == 0.0
+
+
+def test_generator_rejects_bad_arguments(E):
+    seeds = np.array([[1.0, 1.0, 1.0], [2.5, 0.5, 3.9]])
+    bad = [
+        dict(seeds=np.array([[1.0, 1.0, 4.0]])),              # outside [0, n)
+        dict(seeds=np.array([[-0.1, 1.0, 1.0]])),
+        dict(seeds=np.empty((0, 3))),                        # no grains
+        dict(seeds=seeds, semi=np.array([[1.0, 0.0], [1.0, 1.0]])),
+        dict(seeds=seeds, semi=np.array([[1.0, np.nan], [1.0, 1.0]])),
+    ]
+    for kw in bad:
+        with pytest.raises(E.Elas3dError) as ei:
+            E.generate_grains((4, 4, 4), kw["seeds"], kw.get("semi"))
+        assert ei.value.code == E.EBADARG
+    pore = np.concatenate([[1.0, 1.0, 1.0], [1.0, 1.0, 1.0], np.eye(3).ravel()])
+    phase = np.zeros(64, np.int32)
+    for mutate in (lambda p: p.__setitem__(0, 4.0), lambda p: p.__setitem__(4, 0.0),
+                   lambda p: p.__setitem__(8, np.inf)):
+        p = pore.copy()
+        mutate(p)
+        with pytest.raises(E.Elas3dError) as ei:
+            E.carve_pores((4, 4, 4), phase, 1, p[None])
+        assert ei.value.code == E.EBADARG
+    with pytest.raises(E.Elas3dError):
+        E.carve_pores((4, 4, 4), phase, 1, pore[None], float("nan"))
+    assert E.lib().elas3d_von_mises(None, 0, None, None, None) == E.EBADARG

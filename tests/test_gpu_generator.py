@@ -1,0 +1,168 @@
+"""GPU microstructure generator and von Mises output against the oracle.
+
+Integer outputs (grain ids, void flags, pore counts) are compared bit for bit;
+von Mises values within the stress tolerance of the solve parity tests."""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_07354_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2602_07354_amd import elas3d
+    elas3d.lib()
+    return elas3d
+
+
+def _semi(rng, n, sigma_d=0.35, mu_a=1.6, sigma_a=0.25):
+    # lognormal diameters and aspect ratios, r_l = alpha r_t (Sec. 2.2.1)
+    rt = 0.5 * np.exp(sigma_d * rng.standard_normal(n))
+    alpha = mu_a * np.exp(sigma_a * rng.standard_normal(n))
+    return np.stack([rt, alpha * rt], axis=1)
+
+
+GRAIN_CASES = [
+    ((37, 29, 21), 40, False),
+    ((37, 29, 21), 40, True),
+    ((2, 3, 5), 1, False),
+    ((5, 4, 3), 200, True),      # more grains than voxels
+    ((64, 48, 40), 300, True),
+    ((1, 40, 33), 25, False),    # a flat grid
+]
+
+
+@pytest.mark.parametrize("shape,ngrain,weighted", GRAIN_CASES)
+def test_grains_match_oracle_bit_for_bit(E, shape, ngrain, weighted):
+    say("case: grains", shape, ngrain, weighted)
+    rng = np.random.default_rng(ngrain + shape[0])
+    seeds = rng.random((ngrain, 3)) * np.array(shape)
+    semi = _semi(rng, ngrain) if weighted else None
+    gpu = E.generate_grains(shape, seeds, semi)
+    assert np.array_equal(gpu, oracle.grains(shape, seeds, semi))
+
+
+def _pores(rng, shape, n):
+    rows = []
+    for q in range(n):
+        c = rng.random(3) * np.array(shape)
+        kind = q % 3
+        if kind == 0:
+            r = 0.6 + 2.5 * rng.random()
+            rows.append(np.concatenate([c, [r, r, r], np.eye(3).ravel()]))
+        elif kind == 1:
+            R = synth.random_rotations(rng, 1)[0]
+            rows.append(np.concatenate([c, [4.0, 3.0, 1.0], R.ravel()]))
+        else:
+            rows.append(np.concatenate([c, [5 / 3, 5 / 3, 5.0], np.eye(3).ravel()]))
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("target_frac", [-1.0, 0.03, 0.2, 0.9])
+def test_pore_carving_matches_oracle_bit_for_bit(E, target_frac):
+    say("case: carve", target_frac)
+    shape = (33, 26, 19)
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(7)
+    phase = E.generate_grains(shape, rng.random((30, 3)) * np.array(shape))
+    phase[:50] = 30  # void before carving
+    pores = _pores(rng, shape, 60)
+    # a pore larger than the grid in one dimension, and one across a corner
+    pores[5, 3:6] = [12.0, 3.0, 11.0]
+    pores[6, 0:3] = [0.05, 25.9, 18.95]
+    target = target_frac * n if target_frac >= 0 else -1.0
+    ref, used_o, nvoid_o = oracle.carve(shape, phase, 30, pores, target)
+    gpu = phase.copy()
+    used, nvoid = E.carve_pores(shape, gpu, 30, pores, target)
+    assert (used, nvoid) == (used_o, nvoid_o)
+    assert np.array_equal(gpu, ref)
+    if target_frac == 0.9:
+        assert used == len(pores) and nvoid < target  # ran out of pores
+    elif target_frac > 0:
+        assert used < len(pores) and nvoid >= target
+
+
+def test_carving_with_no_pores_and_reached_target(E):
+    shape = (8, 8, 8)
+    phase = np.zeros(512, np.int32)
+    phase[:10] = 3
+    assert E.carve_pores(shape, phase, 3, np.empty((0, 15)), 5.0) == (0, 10)
+    pores = _pores(np.random.default_rng(1), shape, 4)
+    assert E.carve_pores(shape, phase, 3, pores, 10.0) == (0, 10)
+
+
+def test_device_recipe_equals_host_recipe(E):
+    """The device generator replays the host recipe's random stream: the same
+    grain map, pores and void fraction as synth (poly100 at 60^3)."""
+    say("case: device vs host recipe")
+    from paper_2602_07354_amd import generate
+    host = synth.workload("poly100", scale=60)
+    dev = generate.workload("poly100", scale=60)
+    assert np.array_equal(dev.phase, host.phase)
+    assert dev.meta["pores"] == host.meta["pores"]
+    assert dev.meta["void_fraction"] == host.meta["void_fraction"]
+    assert np.array_equal(dev.C, host.C)
+
+
+def test_full_size_generator_sampled_against_oracle(E):
+    """poly500 (500^3, 8000 grains, 2% pores in three shapes) generated on the
+    device; sampled voxels checked against the oracle's brute force."""
+    import torch
+    from paper_2602_07354_amd import generate
+    say("case: generator 500^3 sampled")
+    rec = synth.workload_recipe("poly500")
+    n = int(np.prod(rec["shape"]))
+    phase = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    t0 = time.perf_counter()
+    ms = generate.polycrystal(rec["shape"], rec["n_grains"], rec["seed"], rec["pores"], rec["strain"],
+                              phase=phase)
+    torch.cuda.synchronize()
+    say("  generated in %.2f s, void %.5f, pores %s" % (time.perf_counter() - t0, ms.meta["void_fraction"],
+                                                        ms.meta["pores"]))
+    assert ms.meta["void_fraction"] >= 0.02
+    idx = np.random.default_rng(11).choice(n, 3000, replace=False).astype(np.int64)
+    ph = phase.cpu().numpy()[idx]
+    void = ph == rec["n_grains"]
+    covered = oracle.covered_at(rec["shape"], ms.meta["pores_carved"], idx)
+    assert np.array_equal(void, covered == 1)
+    grains = oracle.grains_at(rec["shape"], ms.meta["seeds"], None, idx)
+    assert np.array_equal(ph[~void], grains[~void])
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_von_mises_matches_oracle(E):
+    say("case: von Mises")
+    ms = synth.polycrystal((30, 26, 22), 20, 77, [dict(kind="sphere", fraction=0.02, median=1.5, sigma=0.3)],
+                           np.array([[0, 0, 1e-3, 0, 0, 0]]))
+    P = oracle.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    vo = oracle.von_mises(so)
+    with E.Context.from_micro(ms) as ctx:
+        st, info = ctx.solve(1e-12, 20000)
+        assert st == E.OK
+        out = ctx.von_mises(0)
+        sig = ctx.stress(0)["sigma"]
+        none = ctx.von_mises(0, field=False)
+    assert _rel(out["vm"], vo) <= 1e-8
+    # the same formula on the GPU's own stress
+    assert np.allclose(out["vm"], oracle.von_mises(sig), rtol=1e-13, atol=1e-15)
+    assert np.isclose(out["max"], vo.max(), rtol=1e-8)
+    assert np.isclose(vo[out["argmax"]], vo.max(), rtol=1e-8)
+    assert out["vm"][out["argmax"]] == out["max"] == out["vm"].max()
+    assert out["argmax"] == int(np.argmax(out["vm"]))  # lowest index of the max
+    assert (none["max"], none["argmax"]) == (out["max"], out["argmax"])
+    assert np.all(out["vm"][ms.phase == ms.nphase - 1] == 0.0)  # voids carry no stress
