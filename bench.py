@@ -9,11 +9,17 @@ Prints one JSON line with the throughput in Gdof*iterations/s over the
 whole step, the roofline of the dominant kernel (the fused
 direction + operator sweep, timed with HIP events on its own stream) and
 the CPU oracle timed on a bounded sample of the same recipe.
+
+The microstructure is generated on the device (same recipe and random
+stream as the host generator) before anything is timed.  The measured HBM
+traffic of the dominant kernel comes from the committed rocprofv3 counter
+summary when that summary was taken on the current kernel source (else null).
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+COUNTERS = os.path.join(ROOT, "profiles", "op_kernel_poly500_fp64_counters.txt")
+KERNEL_SOURCES = ("paper_2602_07354_amd/csrc/elas3d_kernels.hip", "paper_2602_07354_amd/csrc/elas3d_internal.h")
 # Algorithmic HBM bytes per node of the fused direction+operator sweep:
 # read z, h_old, w and write h_new, w, Ah (6 x 3 doubles) plus the phase id.
 OPERATOR_BYTES_PER_NODE_FP64 = 6 * 24 + 4
@@ -50,13 +58,63 @@ def parse():
     ap.add_argument("--maxit", type=int, default=50000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=100, help="edge of the oracle sample grid")
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--autotune", action="store_true", help="autotune the sweep geometry")
+    ap.add_argument("--host-generator", action="store_true",
+                    help="generate the microstructure on the host instead of the device")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
                     help="fp64: the paper's FP64 PCG; mixed: FP32 inner PCG in FP64 refinement; "
                          "both: time both (the headline value is FP64)")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str) -> dict:
+    """HBM bytes per launch of the fused sweep from the committed counter
+    summary, if it was taken on this kernel source and workload."""
+    out = {"bytes": None, "source": None}
+    if not os.path.exists(COUNTERS):
+        return out
+    kv = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload:
+        out["source"] = "stale (kernel or workload changed since the counters were taken)"
+        return out
+    out["bytes"] = float(kv["op_traffic_bytes_per_dispatch"])
+    out["source"] = os.path.relpath(COUNTERS, ROOT)
+    return out
+
+
+def copy_bandwidth(torch, dev, gib: float = 4.0) -> float:
+    """Device-to-device copy rate (read + write bytes / s), GB/s: the
+    practical HBM ceiling beside the datasheet peak."""
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbs = 5 * 2 * 8 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def cpu_baseline(workload: str, edge: int, iters: int) -> dict:
@@ -85,8 +143,8 @@ def cpu_baseline(workload: str, edge: int, iters: int) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; sharding the solve over "
+                                   "several GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -95,15 +153,26 @@ def main():
     from paper_2602_07354_amd import synth
 
     E.lib()
-    t_gen = time.perf_counter()
-    ms = synth.workload(args.workload, scale=args.scale) if args.workload != "eshelby20" \
-        else synth.workload(args.workload)
-    t_gen = time.perf_counter() - t_gen
-    print(f"# generated {ms.meta.get('workload')} {ms.shape} in {t_gen:.1f} s, "
-          f"void {ms.void_fraction():.4f}", file=sys.stderr, flush=True)
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    if args.workload == "eshelby20" or args.host_generator:
+        ms = synth.workload(args.workload, scale=args.scale) if args.workload != "eshelby20" \
+            else synth.workload(args.workload)
+        phase = torch.from_numpy(ms.phase).to(dev)
+        void_fraction = ms.void_fraction()
+    else:
+        from paper_2602_07354_amd import generate
+        rec = synth.workload_recipe(args.workload, args.scale)
+        phase = torch.empty(int(np.prod(rec["shape"])), dtype=torch.int32, device=dev)
+        ms = generate.workload(args.workload, scale=args.scale, phase=phase)
+        void_fraction = ms.meta["void_fraction"]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    print(f"# generated {ms.meta.get('workload')} {ms.shape} in {t_gen:.1f} s "
+          f"({'host' if ms.meta.get('generated_on') != 'device' else 'device'}), void {void_fraction:.4f}",
+          file=sys.stderr, flush=True)
+    copy_gbs = copy_bandwidth(torch, dev)
     if args.calib_copy_gib > 0:
         # a plain elementwise kernel that reads and writes exactly this many
         # bytes once (HBM-counter calibration under rocprofv3 --pmc)
@@ -115,7 +184,6 @@ def main():
         torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    phase = torch.from_numpy(ms.phase).to(dev)
     sigma = torch.empty((6, ms.n), dtype=torch.float64, device=dev)
     avg = np.empty(6)
     energy = np.empty(1)
@@ -124,7 +192,7 @@ def main():
 
     def step(record, precision):
         opts = E.options_init(inputs_on_device=1, outputs_on_device=1, timing=1, device=0,
-                              stream=stream.cuda_stream,
+                              stream=stream.cuda_stream, autotune=1 if args.autotune else 0,
                               precision=E.PREC_MIXED if precision == "mixed" else E.PREC_FP64)
         h = E.setup(ms.shape, phase, ms.C, ms.strain[:1], opts)
         try:
@@ -181,6 +249,7 @@ def main():
     op_ms = t_op / max(1, n_op)
     op_bytes = (OPERATOR_BYTES_PER_NODE_FP64 if head == "fp64" else 6 * 12 + 4) * ms.n
     achieved = op_bytes / (op_ms / 1e3) / 1e9
+    traffic = measured_traffic(ms.meta.get("workload")) if head == "fp64" else {"bytes": None, "source": None}
     out = {
         "metric": "Gdof*iterations/s of the block-Jacobi PCG solve to true rel-res 1e-8 "
                   "(whole step: setup + solve + stress); FP64 vs mixed time-to-solution beside it",
@@ -200,7 +269,8 @@ def main():
             "description": WORKLOAD_TEXT.get(args.workload, ""),
             "grid": list(ms.shape),
             "nphase": ms.nphase,
-            "void_fraction": round(ms.void_fraction(), 5),
+            "void_fraction": round(void_fraction, 5),
+            "generator": ms.meta.get("generated_on", "host"),
             "tol": args.tol,
             "precision": head,
             "parallelism": "single GPU",
@@ -223,8 +293,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic["bytes"],
+            "traffic_source": traffic["source"],
             "bytes_per_launch": op_bytes,
+            "copy_GBs_measured": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
+            "op_tile": recs[0][1]["op_tile"],
         },
     }
     if not args.no_cpu_baseline:
