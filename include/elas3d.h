@@ -70,6 +70,7 @@ extern "C" {
 #define ELAS3D_PRECOND_NONE 1         /* plain CG (M^-1 = I on active nodes)          */
 
 typedef struct elas3d_ctx elas3d_ctx;
+typedef struct elas3d_group elas3d_group;
 
 typedef struct elas3d_options {
     int32_t precision;         /* ELAS3D_PREC_*                                      */
@@ -252,6 +253,51 @@ int elas3d_generate_grains(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, c
 int elas3d_carve_pores(int32_t nx, int32_t ny, int32_t nz, int32_t* phase, int32_t void_id, int32_t npore,
                        const double* pores, double target, int32_t* used, int64_t* nvoid,
                        const elas3d_options* opt);
+
+/*
+ * Groups: continuous batching of independent solves.  A group advances the
+ * PCG of every member context (its own grid, phases, stiffnesses and load
+ * cases, set up with elas3d_setup) in lockstep, with one launch per sweep
+ * for many members: the direction + operator sweep (one launch per 8
+ * members), the update sweep and their finalizes each run over a work list
+ * of (member, workgroup) entries, so four launches per iteration serve up to
+ * 8 requests, and one more per further 8.  Members join
+ * (elas3d_group_add) and leave (when converged) between batches of
+ * iterations.  Each member follows its own precision option exactly as
+ * elas3d_solve would (FP64 PCG with true-residual restarts, or FP32 inner
+ * PCG cycles with FP64 refinement and FP64 fallback, Algorithm 2); the
+ * group changes only which launches carry its sweeps, so a member's result
+ * is bitwise the same alone and in any mix.  Sweeps run with workgroup
+ * shape 0 and the default chunking (no autotuning inside a group).
+ */
+
+/* Create a group.  opt (NULL = defaults): device, stream (NULL = a library
+ * stream).  Returns 0, ELAS3D_EBADARG or ELAS3D_EDEVICE. */
+int elas3d_group_create(elas3d_group** out, const elas3d_options* opt);
+
+/* Admit ctx (all of its load cases) with the stopping data of elas3d_solve.
+ * The context must be on the group's device, not in another group, and set
+ * up with options.batched when it has more than one load case.  Until it is
+ * returned by elas3d_group_run it runs on the group's stream and must not be
+ * used or destroyed by the caller.  A member with nothing to solve (zero
+ * load) finishes at once.  Returns 0, ELAS3D_EBADARG, ELAS3D_EORDER (already
+ * in a group) or ELAS3D_EDEVICE. */
+int elas3d_group_add(elas3d_group* g, elas3d_ctx* ctx, double tol, int32_t maxit);
+
+/* Run `iters` lockstep iterations (>= 1) of every member, then settle the
+ * members whose runs ended (refinement, restarts, completion).  Up to `cap`
+ * finished contexts are returned in done[] with their statistics in
+ * infos[] (as elas3d_solve's info; t_solve_s is the time since
+ * elas3d_group_add); more wait for the next call.  A returned context is
+ * solved (elas3d_stress works) and back on its own stream.  *ndone receives
+ * the count; *nactive (may be NULL) the members still running.  Returns 0,
+ * ELAS3D_EBADARG or ELAS3D_EDEVICE. */
+int elas3d_group_run(elas3d_group* g, int32_t iters, elas3d_ctx** done, elas3d_info* infos, int32_t cap,
+                     int32_t* ndone, int32_t* nactive);
+
+/* Release the group.  Members still running are abandoned (their contexts
+ * stay valid, unsolved, on their own streams). */
+void elas3d_group_destroy(elas3d_group* g);
 
 /* Device bytes a context with these sizes and options would allocate (0 for
  * sizes that elas3d_setup would reject). */

@@ -19,144 +19,19 @@
 
 #include "elas3d.h"
 #include "elas3d_internal.h"
+#include "elas3d_runtime.h"
 
-using e3d::Dims;
-using e3d::Fields;
-using e3d::Scalars;
-using e3d::FieldsT;
+using namespace e3d::rt;
 
 namespace {
 
 thread_local std::string g_last_error = "";
 
-constexpr int kSweepBlocks = 4096;  // grid of the node-wise sweeps
-// autotuning candidates: workgroup targets of the operator sweep (every tile
-// shape) and grids of the update sweep
-constexpr int kTuneTargets[3] = {2048, 4096, 8192};
-constexpr int kTuneUpdate[5] = {1024, 2048, 4096, 8192, 16384};
-constexpr int kPartialValues = 8;   // partial sums per block, upper bound
-constexpr int kDefaultPoll = 16;
-
-struct EventPair {
-    hipEvent_t a = nullptr, b = nullptr;
-};
-
-}  // namespace
-
-struct elas3d_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    Dims d{};
-    int nphase = 0, nrhs = 0;
-    elas3d_options opt{};
-    std::vector<double> strain;  // nrhs * 6
-    e3d::OpGeom geom{};  // APPLY / REFINE sweeps (tile shape 0)
-    // direction+operator sweep and update grid per precision (0 FP64, 1 FP32),
-    // the defaults or the autotuned choice
-    e3d::OpGeom geom_sweep[2]{};
-    int upd_blocks[2] = {0, 0};
-    int tuned[2] = {0, 0};
-
-    int32_t* phase = nullptr;
-    double* coef = nullptr;
-    double* diag = nullptr;
-    uint8_t* solid = nullptr;
-    double* sig = nullptr;
-    // FP64 fields.  Batched: per RHS one bundle [w 3N | b 3N | g z h0 h1 Ah 15N]
-    // so that every field of RHS r lies r*21N after RHS 0's.  Otherwise the
-    // RHS keep [w | b] (6N each) and share one 15N work area after them.
-    double* bundle64 = nullptr;
-    double* minv = nullptr;  // 6N
-    // mixed precision: FP32 g, z, h0, h1, Ah, d (18N floats per work slot),
-    // M^-1 (6N), table
-    float* bundle32 = nullptr;
-    float* minv32 = nullptr;
-    float* coef32 = nullptr;
-    double* partials = nullptr;
-    int partial_stride = 0;
-    double* norms = nullptr;  // nrhs * 2: ||b||^2, ||b||_ref^2
-    double* dscratch = nullptr;  // 64 doubles
-    int* dflag = nullptr;
-    Scalars* S = nullptr;
-    Scalars* hS = nullptr;        // pinned, 2 slots of kMaxRhs
-    double* hscratch = nullptr;   // pinned, 64 doubles
-    std::vector<int> solved;
-    double bytes = 0.0;
-    std::string err;
-
-    std::vector<EventPair> ev_op, ev_up;
-    // captured iteration batches, keyed by (element size, first RHS, RHS count)
-    struct GraphEntry {
-        int key[3];
-        hipGraph_t graph;
-        hipGraphExec_t exec;
-    };
-    std::vector<GraphEntry> graphs;
-
-    size_t N() const { return (size_t)d.n; }
-    // component c (or M^-1 entry q) of a field starting at base
-    template <typename P>
-    P* comp(P* base, int c) const { return base + e3d::comp_offset(c, N()); }
-
-    bool batched() const { return opt.batched != 0; }
-    size_t rs64() const { return (batched() ? 21 : 6) * N(); }  // RHS stride of the bundles
-    size_t rs32() const { return 18 * N(); }
-    double* wptr(int r) const { return bundle64 + (size_t)r * rs64(); }
-    double* bptr(int r) const { return wptr(r) + 3 * N(); }
-    double* work64(int r) const
-    {
-        return batched() ? wptr(r) + 6 * N() : bundle64 + (size_t)nrhs * 6 * N();
-    }
-    float* work32(int r) const { return bundle32 + (batched() ? (size_t)r * rs32() : 0); }
-    Fields fields(int rhs)
-    {
-        Fields f;
-        double* wk = work64(rhs);
-        for (int c = 0; c < 3; ++c) {
-            f.w[c] = comp(wptr(rhs), c);
-            f.b[c] = comp(bptr(rhs), c);
-            f.g[c] = comp(wk, c);
-            f.z[c] = comp(wk + 3 * N(), c);
-            f.h0[c] = comp(wk + 6 * N(), c);
-            f.h1[c] = comp(wk + 9 * N(), c);
-            f.Ah[c] = comp(wk + 12 * N(), c);
-        }
-        return f;
-    }
-    void minv_planes(double* out[6]) const
-    {
-        for (int q = 0; q < 6; ++q) out[q] = comp(minv, q);
-    }
-    e3d::FieldsT<float> fields32(int rhs)
-    {
-        e3d::FieldsT<float> f;
-        float* wk = work32(rhs);
-        for (int c = 0; c < 3; ++c) {
-            f.g[c] = comp(wk, c);
-            f.z[c] = comp(wk + 3 * N(), c);
-            f.h0[c] = comp(wk + 6 * N(), c);
-            f.h1[c] = comp(wk + 9 * N(), c);
-            f.Ah[c] = comp(wk + 12 * N(), c);
-            f.w[c] = comp(wk + 15 * N(), c);
-            f.b[c] = nullptr;
-        }
-        return f;
-    }
-    void minv32_planes(float* out[6]) const
-    {
-        for (int q = 0; q < 6; ++q) out[q] = comp(minv32, q);
-    }
-    e3d::Tables tables() const { return e3d::Tables{coef, coef32, diag, solid}; }
-};
-
-namespace {
-
 }  // namespace
 
 void e3d::set_last_error(const std::string& msg) { g_last_error = msg; }
 
-namespace {
+namespace e3d::rt {
 
 int fail(elas3d_ctx* ctx, int code, const std::string& msg)
 {
@@ -166,14 +41,6 @@ int fail(elas3d_ctx* ctx, int code, const std::string& msg)
         g_last_error = msg;
     return code;
 }
-
-#define HIPCHK(ctx, expr)                                                                       \
-    do {                                                                                        \
-        hipError_t e_ = (expr);                                                                 \
-        if (e_ != hipSuccess)                                                                   \
-            return fail((ctx), ELAS3D_EDEVICE,                                                  \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));                     \
-    } while (0)
 
 void default_options(elas3d_options* o)
 {
@@ -472,11 +339,6 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* c
     return 0;
 }
 
-struct RunStats {
-    Scalars fin{};       // device scalars at the end of the run
-    int it_start = 0;    // iteration counter when the run started
-};
-
 // Enqueue PCG iterations (direction+operator sweep, update sweep) for the
 // batch of R right-hand sides [r0, r0+R) in batches of `poll`, until the
 // device has raised the stop flag of every RHS; the host looks at the flags of
@@ -642,13 +504,19 @@ int start_run(elas3d_ctx* c, int r, const FieldsT<T>& f, T* const M[6], double t
     init.maxit = maxit;
     init.mode = mode;
     init.it = it0;
-    std::memcpy(&c->hS[0], &init, sizeof(Scalars));
-    HIPCHK(c, hipMemcpyAsync(c->S + r, &c->hS[0], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+    // pinned staging slot r: nothing else writes it before the stream passes
+    // this copy (every caller synchronises before the next start of RHS r)
+    std::memcpy(&c->hS[r], &init, sizeof(Scalars));
+    HIPCHK(c, hipMemcpyAsync(c->S + r, &c->hS[r], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, e3d::launch_pcg_init<T>(c->stream, c->d, f, M, fresh, from_residual, c->S + r,
                                       c->partials, kSweepBlocks, norms2));
-    HIPCHK(c, hipStreamSynchronize(c->stream));  // the pinned staging slot is reused
     return 0;
 }
+
+template int start_run<double>(elas3d_ctx*, int, const FieldsT<double>&, double* const[6], double, int, int,
+                               int, int, int, const double*);
+template int start_run<float>(elas3d_ctx*, int, const FieldsT<float>&, float* const[6], double, int, int, int,
+                              int, int, const double*);
 
 // Mark RHS r of the next batch as finished (its sweeps return at once).
 int park(elas3d_ctx* c, int r, const Scalars& fin)
@@ -656,18 +524,10 @@ int park(elas3d_ctx* c, int r, const Scalars& fin)
     Scalars q = fin;
     q.done = 1;
     q.pending = 0;
-    std::memcpy(&c->hS[0], &q, sizeof(Scalars));
-    HIPCHK(c, hipMemcpyAsync(c->S + r, &c->hS[0], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(&c->hS[r], &q, sizeof(Scalars));  // staging slot r, as start_run
+    HIPCHK(c, hipMemcpyAsync(c->S + r, &c->hS[r], sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
     return 0;
 }
-
-struct CaseResult {
-    Scalars fin{};
-    int restarts = 0;
-    double rel_true = 0.0;
-    int fallback = 0;
-};
 
 // FP64 PCG (Algorithm 2) on the RHS [r0, r0+R) in lockstep (R = 1 unless the
 // context is batched), from w = 0, or continuing from the current w when
@@ -695,18 +555,13 @@ int solve_fp64(elas3d_ctx* c, int r0, int R, double tol, int maxit, bool cont, i
             if (!running[q]) continue;
             Fields f = c->fields(r0 + q);
             // true residual r = A w + b (into g, ready for a restart)
-            const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
-            double* gy[3] = {f.g[0], f.g[1], f.g[2]};
-            HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom, c->phase, t, wx, gy, f.b, c->partials,
-                                        c->dscratch));
-            HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost,
-                                     c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
+            double rr = 0.0;
+            rc = true_residual(c, r0 + q, &rr);
+            if (rc) return rc;
             CaseResult& cr = res[q];
             cr.fin = rs[q].fin;
             const bool zero_load = cr.fin.bnorm2 <= 1e-28 * cr.fin.bref2;
-            cr.rel_true = (zero_load || cr.fin.bnorm2 <= 0.0) ? 0.0
-                                                             : std::sqrt(c->hscratch[0] / cr.fin.bnorm2);
+            cr.rel_true = (zero_load || cr.fin.bnorm2 <= 0.0) ? 0.0 : std::sqrt(rr / cr.fin.bnorm2);
             if (c->opt.convergence == ELAS3D_CONV_RESIDUAL && cr.fin.status == 0 && !zero_load &&
                 !(cr.rel_true <= tol)) {
                 if (cr.fin.it >= maxit) {
@@ -729,6 +584,55 @@ int solve_fp64(elas3d_ctx* c, int r0, int R, double tol, int maxit, bool cont, i
     return 0;
 }
 
+int refine_launch(elas3d_ctx* c, int r, int q)
+{
+    Fields f64 = c->fields(r);
+    e3d::FieldsT<float> f32 = c->fields32(r);
+    double* w[3] = {f64.w[0], f64.w[1], f64.w[2]};
+    const float* dc[3] = {f32.w[0], f32.w[1], f32.w[2]};
+    float* r32[3] = {f32.g[0], f32.g[1], f32.g[2]};
+    HIPCHK(c, e3d::launch_refine(c->stream, c->d, c->geom, c->phase, c->tables(), w, dc, f64.b, r32,
+                                 c->partials, c->dscratch + 4 + 2 * q));
+    // {||r||^2, ||r||^2}: the norms of the next inner run
+    HIPCHK(c, hipMemcpyAsync(c->dscratch + 5 + 2 * q, c->dscratch + 4 + 2 * q, sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    return 0;
+}
+
+int residual_launch(elas3d_ctx* c, int r, double* norm2)
+{
+    Fields f = c->fields(r);
+    const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
+    double* gy[3] = {f.g[0], f.g[1], f.g[2]};
+    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom, c->phase, c->tables(), wx, gy, f.b, c->partials,
+                                norm2));
+    return 0;
+}
+
+int refine_step(elas3d_ctx* c, int r, int q, double bnorm2, double* rel)
+{
+    int rc = refine_launch(c, r, q);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch + 4 + 2 * q, sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *rel = std::sqrt(c->hscratch[0] / bnorm2);
+    return 0;
+}
+
+int true_residual(elas3d_ctx* c, int r, double* rr)
+{
+    Fields f = c->fields(r);
+    const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
+    double* gy[3] = {f.g[0], f.g[1], f.g[2]};
+    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom, c->phase, c->tables(), wx, gy, f.b, c->partials,
+                                c->dscratch));
+    HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *rr = c->hscratch[0];
+    return 0;
+}
+
 // Mixed precision (iterative refinement) on the RHS [r0, r0+R): the
 // corrections d of A d = -r are solved by the FP32 PCG in lockstep to a
 // relative reduction of the inner tolerance, then for each RHS w += d and
@@ -744,24 +648,7 @@ int solve_mixed(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info
     const double inner_tol = c->opt.inner_tol > 0.0 ? c->opt.inner_tol : 1e-4;
     std::vector<double> bnorm2(R), bref2(R), rel(R);
     std::vector<int> iters(R, 0), active(R, 0), fallback(R, 0);
-    auto refine = [&](int q) -> int {
-        const int r = r0 + q;
-        Fields f64 = c->fields(r);
-        e3d::FieldsT<float> f32 = c->fields32(r);
-        double* w[3] = {f64.w[0], f64.w[1], f64.w[2]};
-        const float* dc[3] = {f32.w[0], f32.w[1], f32.w[2]};
-        float* r32[3] = {f32.g[0], f32.g[1], f32.g[2]};
-        HIPCHK(c, e3d::launch_refine(c->stream, d, c->geom, c->phase, t, w, dc, f64.b, r32, c->partials,
-                                     c->dscratch + 4 + 2 * q));
-        // {||r||^2, ||r||^2}: the norms of the next inner run
-        HIPCHK(c, hipMemcpyAsync(c->dscratch + 5 + 2 * q, c->dscratch + 4 + 2 * q, sizeof(double),
-                                 hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch + 4 + 2 * q, sizeof(double),
-                                 hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        rel[q] = std::sqrt(c->hscratch[0] / bnorm2[q]);
-        return 0;
-    };
+    auto refine = [&](int q) -> int { return refine_step(c, r0 + q, q, bnorm2[q], &rel[q]); };
     for (int q = 0; q < R; ++q) {
         const int r = r0 + q;
         Fields f64 = c->fields(r);
@@ -859,6 +746,11 @@ int solve_batch(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info
     else
         rc = solve_fp64(c, r0, R, tol, maxit, false, 0, info, res);
     if (rc) return rc;
+    return record_results(c, r0, R, res, info);
+}
+
+int record_results(elas3d_ctx* c, int r0, int R, const CaseResult* res, elas3d_info* info)
+{
     int worst = 0;
     for (int q = 0; q < R; ++q) {
         const int r = r0 + q;
@@ -887,7 +779,7 @@ int solve_batch(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info
     return worst;
 }
 
-}  // namespace
+}  // namespace e3d::rt
 
 extern "C" {
 
@@ -1062,6 +954,7 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
     if (maxit < 0) return fail(ctx, ELAS3D_EBADARG, "maxit must be >= 0");
     if (nrhs < 1 || nrhs > ctx->nrhs)
         return fail(ctx, ELAS3D_EBADARG, "nrhs must be in [1, nrhs of setup]");
+    if (ctx->group) return fail(ctx, ELAS3D_EORDER, "context is a member of a group");
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->nrhs = nrhs;

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 namespace e3d {
 
@@ -182,6 +183,50 @@ hipError_t launch_total_displacement(hipStream_t st, const Dims& d, const double
                                      const Fields& f, double* const u[3]);
 // Adds to *bad the number of ids outside [0, nphase).
 hipError_t launch_phase_check(hipStream_t st, const int32_t* phase, int n, int nphase, int* bad);
+// ---- groups of independent problems in one launch per sweep -------------
+// One member of a group: a problem (its own grid, tables and fields) with
+// nrhs right-hand sides in lockstep; its sweeps use workgroup shape 0 and
+// the geometry g, its update sweep upd_blocks workgroups.
+template <typename T>
+struct GroupMember {
+    Dims d;
+    OpGeom g;
+    const int32_t* phase;
+    Tables t;
+    FieldsT<T> f;
+    size_t rs;
+    int nrhs;
+    T* minv[6];
+    Scalars* S;
+    double* partials;
+    int upd_blocks;
+};
+
+// Work lists of a group (built by group_prepare): the direction+operator
+// sweep's members in kernel-argument packs of up to 8 (one launch each),
+// the update sweep's and the finalizes' lists in device memory.
+struct GroupPlan {
+    char* dev = nullptr;
+    int n = 0, nfin = 0, upd_blocks = 0;
+    std::vector<uint8_t> packs;    // the packs, by value
+    std::vector<int> pack_blocks;  // workgroups of each pack's launch
+    size_t off_upd = 0, off_updfirst = 0, off_findir = 0, off_finupd = 0;
+};
+
+// Bytes of the work lists of n members with nfin (member, RHS) pairs.
+template <typename T>
+size_t group_plan_bytes(int n, int nfin);
+// Writes the work lists to `staging` (pinned host memory of
+// group_plan_bytes) and enqueues their copy to `dev` on st.
+template <typename T>
+hipError_t group_prepare(hipStream_t st, const GroupMember<T>* m, int n, char* staging, char* dev,
+                         GroupPlan* plan);
+// One PCG iteration (direction + operator sweep, update sweep and their
+// finalizes) of every member of the plan: four launches for up to 8
+// members, one more per further 8.
+template <typename T>
+hipError_t launch_group_iteration(hipStream_t st, const GroupPlan& plan);
+
 // Message returned by elas3d_last_error(NULL) on this thread (context-free
 // entry points).
 void set_last_error(const std::string& msg);

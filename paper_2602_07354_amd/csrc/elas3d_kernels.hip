@@ -334,15 +334,10 @@ enum FinKind { FIN_STORE = 0, FIN_INIT = 1, FIN_DIRECTION = 2, FIN_UPDATE = 3 };
 //   FIN_DIRECTION step size from h.Ah (Algorithm 2, B)
 //   FIN_UPDATE    gg, rr after the update; convergence; Fletcher-Reeves gamma (D, E)
 template <int NV>
-__global__ void __launch_bounds__(kFinThreads) finalize_kernel(int kind, const double* partials,
-                                                               int stride, int nblocks, Scalars* S,
-                                                               double* out, const double* norms,
-                                                               int rhs_stride)
+__device__ __forceinline__ void finalize_body(int kind, const double* partials, int stride, int nblocks,
+                                              Scalars* S, double* out, const double* norms)
 {
     __shared__ double red[NV][kFinThreads / 64];
-    // block r finalizes RHS r of a batch
-    partials += (size_t)blockIdx.x * rhs_stride;
-    if (S) S += blockIdx.x;
     // sweeps enqueued after the stop flag was raised did no work: leave the
     // scalars of the finished run untouched
     if ((kind == FIN_DIRECTION || kind == FIN_UPDATE) && S->done) return;
@@ -437,6 +432,31 @@ __global__ void __launch_bounds__(kFinThreads) finalize_kernel(int kind, const d
         S->gamma = gg_new / gg_last;
         return;
     }
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kFinThreads) finalize_kernel(int kind, const double* partials,
+                                                               int stride, int nblocks, Scalars* S,
+                                                               double* out, const double* norms,
+                                                               int rhs_stride)
+{
+    // block r finalizes RHS r of a batch
+    finalize_body<NV>(kind, partials + (size_t)blockIdx.x * rhs_stride, stride, nblocks,
+                      S ? S + blockIdx.x : nullptr, out, norms);
+}
+
+// One (problem, RHS) of a group's finalize.
+struct FinItem {
+    const double* partials;
+    int stride, nblocks;
+    Scalars* S;
+};
+
+template <int NV>
+__global__ void __launch_bounds__(kFinThreads) finalize_group_kernel(int kind, const FinItem* __restrict__ items)
+{
+    const FinItem it = items[blockIdx.x];
+    finalize_body<NV>(kind, it.partials, it.stride, it.nblocks, it.S, nullptr, nullptr);
 }
 
 // ------------------------------------------------------------- node sweeps
@@ -598,11 +618,11 @@ __global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, 
 // Algorithm 2, C-D for a batch of RHS sharing M^-1 (loaded once per node):
 // g -= lambda Ah, z = M^-1 g, partials z.g and g.g (FP64) per RHS.
 // (w -= lambda h is deferred to the next direction sweep, which reads h anyway.)
+// (by value: the fields stay in scalar registers)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<T> f, size_t rs,
-                                                                int nrhs, MinvT<T> M,
-                                                                const Scalars* S, double* partials,
-                                                                int stride)
+__device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, const size_t rs, const int nrhs,
+                                            const MinvT<T> M, const Scalars* S, double* partials,
+                                            const int stride, const int bid, const int nblk)
 {
     unsigned active = 0;
     T lam[kMaxRhs];
@@ -618,7 +638,10 @@ __global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<
     double acc[2 * kMaxRhs];
 #pragma unroll
     for (int k = 0; k < 2 * kMaxRhs; ++k) acc[k] = 0.0;
-    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+    // the unsigned step (as gridDim.x * kBlock) keeps the compiler from
+    // strength-reducing every field address into its own 64-bit induction
+    // variable, which triples the register count
+    for (int m = bid * kBlock + threadIdx.x; m < d.n; m += (unsigned)nblk * kBlock) {
         T mm[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) mm[q] = M.m[q][(size_t)m * kMS];
@@ -642,7 +665,16 @@ __global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<
             acc[2 * r + 1] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
         }
     }
-    block_partials<2 * kMaxRhs, kBlock>(acc, partials, stride, blockIdx.x);
+    block_partials<2 * kMaxRhs, kBlock>(acc, partials, stride, bid);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<T> f, size_t rs,
+                                                                int nrhs, MinvT<T> M,
+                                                                const Scalars* S, double* partials,
+                                                                int stride)
+{
+    update_body<T>(d, f, rs, nrhs, M, S, partials, stride, blockIdx.x, gridDim.x);
 }
 
 // The step size of the last iteration still owed to w.
@@ -740,8 +772,9 @@ struct OpArgs {
 #define E3D_OP_MIN_WAVES 1
 #endif
 
+// Workgroup lbr (logical, of nblocks) of an operator sweep over a.
 template <int TX, int TY, int MODE, typename T>
-__global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> a)
+__device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nblocks)
 {
     constexpr bool FUSED = MODE == OP_FUSED;
     using R = typename std::conditional<FUSED, T, double>::type;  // arithmetic type
@@ -755,8 +788,7 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
     // vectors (interleaving the RHS of one tile instead measured about 11 %
     // slower on six load cases)
     const int nr = FUSED ? a.nrhs : 1;
-    const int lbr = xcd_local_block();
-    const int ntb = gridDim.x / nr;  // tile blocks per RHS
+    const int ntb = nblocks / nr;  // tile blocks per RHS
     const int rhs = lbr / ntb;
     const int lb = lbr - rhs * ntb;
     R gam = R(0), lam = R(0);
@@ -974,6 +1006,91 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
         double v[1] = {dot};
         block_partials<1, NT>(v, a.partials + (size_t)rhs * ntb, ntb, lb);
     }
+}
+
+template <int TX, int TY, int MODE, typename T>
+__global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> a)
+{
+    op_body<TX, TY, MODE, T>(a, xcd_local_block(), gridDim.x);
+}
+
+// Copy of a work-list entry held in scalar registers: the entry is the same
+// for the whole workgroup, and reading it word by word through readfirstlane
+// keeps its pointers out of the vector registers of the sweep.
+template <typename A>
+__device__ __forceinline__ A load_uniform(const A* __restrict__ p)
+{
+    static_assert(sizeof(A) % 4 == 0, "work-list entries are whole words");
+    A out;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(A) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return out;
+}
+
+// Index p of the work-list entry with first[p] <= b < first[p+1].  b is the
+// same in every lane; so is the result, which is made explicit so that the
+// entry's arguments load into scalar registers.
+__device__ __forceinline__ int find_entry(const int* __restrict__ first, int n, int b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Up to kGroupPack problems of a group in one kernel argument: the
+// arguments stay in the constant kernel-argument segment, which the compiler
+// reads with scalar loads wherever a field is used, as for a single-problem
+// sweep (the same entries read from a global-memory list end up in vector
+// registers and halve the occupancy of the FP64 sweep).
+constexpr int kGroupPack = 8;
+template <typename T>
+struct OpPack {
+    OpArgs<T> m[kGroupPack];
+    int first[kGroupPack + 1];
+    int n;
+};
+
+// Fused sweep over a pack of independent problems: problem p owns the
+// logical workgroups [first[p], first[p+1]) and runs exactly the workgroups
+// its own sweep would.
+template <int TX, int TY, typename T>
+__global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_group_kernel(OpPack<T> pk)
+{
+    const int b = xcd_local_block();
+    const int p = find_entry(pk.first, pk.n, b);
+    op_body<TX, TY, OP_FUSED, T>(pk.m[p], b - pk.first[p], pk.first[p + 1] - pk.first[p]);
+}
+
+template <typename T>
+struct UpdArgs {
+    Dims d;
+    FieldsT<T> f;
+    size_t rs;
+    int nrhs;
+    MinvT<T> M;
+    const Scalars* S;
+    double* partials;
+};
+
+// Update sweep over a group's work list: problem p owns workgroups
+// [first[p], first[p+1]) and runs them as its own sweep would.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) update_group_kernel(const UpdArgs<T>* __restrict__ list,
+                                                              const int* __restrict__ first, int n)
+{
+    const int b = blockIdx.x;
+    const int p = find_entry(first, n, b);
+    const int nb = first[p + 1] - first[p];
+    const UpdArgs<T> u = load_uniform(list + p);
+    update_body<T>(u.d, u.f, u.rs, u.nrhs, u.M, u.S, u.partials, nb, b - first[p], nb);
 }
 
 #ifndef E3D_OP_TARGET_BLOCKS
@@ -1364,6 +1481,134 @@ hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ groups
+
+namespace {
+
+template <typename T>
+struct PlanLayout {
+    size_t upd, updfirst, findir, finupd, bytes;
+};
+
+template <typename T>
+PlanLayout<T> plan_layout(int n, int nfin)
+{
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    PlanLayout<T> L;
+    L.upd = 0;
+    L.updfirst = up(L.upd + sizeof(UpdArgs<T>) * n);
+    L.findir = up(L.updfirst + sizeof(int) * (n + 1));
+    L.finupd = up(L.findir + sizeof(FinItem) * nfin);
+    L.bytes = up(L.finupd + sizeof(FinItem) * nfin);
+    return L;
+}
+
+}  // namespace
+
+template <typename T>
+size_t group_plan_bytes(int n, int nfin)
+{
+    return plan_layout<T>(n, nfin).bytes;
+}
+
+template <typename T>
+hipError_t group_prepare(hipStream_t st, const GroupMember<T>* m, int n, char* staging, char* dev,
+                         GroupPlan* plan)
+{
+    int nfin = 0;
+    for (int i = 0; i < n; ++i) nfin += m[i].nrhs;
+    const PlanLayout<T> L = plan_layout<T>(n, nfin);
+    const int npacks = (n + kGroupPack - 1) / kGroupPack;
+    plan->packs.assign(sizeof(OpPack<T>) * npacks, 0);
+    plan->pack_blocks.assign(npacks, 0);
+    OpPack<T>* packs = reinterpret_cast<OpPack<T>*>(plan->packs.data());
+    UpdArgs<T>* up = reinterpret_cast<UpdArgs<T>*>(staging + L.upd);
+    int* updfirst = reinterpret_cast<int*>(staging + L.updfirst);
+    FinItem* fd = reinterpret_cast<FinItem*>(staging + L.findir);
+    FinItem* fu = reinterpret_cast<FinItem*>(staging + L.finupd);
+    long long ub = 0;
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+        const GroupMember<T>& g = m[i];
+        if (g.g.tile != 0) return hipErrorInvalidValue;  // groups run workgroup shape 0
+        OpArgs<T> a = {};
+        a.d = g.d;
+        a.tiles_x = g.g.tiles_x;
+        a.tiles_y = g.g.tiles_y;
+        a.kz = g.g.kz;
+        a.phase = g.phase;
+        if constexpr (std::is_same<T, float>::value)
+            a.coef = g.t.coef32;
+        else
+            a.coef = g.t.coef;
+        for (int c = 0; c < 3; ++c) {
+            a.z[c] = g.f.z[c];
+            a.h0[c] = g.f.h0[c];
+            a.h1[c] = g.f.h1[c];
+            a.w[c] = g.f.w[c];
+            a.y[c] = g.f.Ah[c];
+        }
+        a.S = g.S;
+        a.partials = g.partials;
+        a.rs = g.rs;
+        a.nrhs = g.nrhs;
+        OpPack<T>& pk = packs[i / kGroupPack];
+        const int j = i % kGroupPack;
+        pk.m[j] = a;
+        pk.first[j] = (int)plan->pack_blocks[i / kGroupPack];
+        const long long ob = (long long)pk.first[j] + (long long)g.g.blocks * g.nrhs;
+        if (ob >= (1LL << 31)) return hipErrorInvalidValue;
+        pk.first[j + 1] = (int)ob;
+        pk.n = j + 1;
+        plan->pack_blocks[i / kGroupPack] = (int)ob;
+        const int nb = sweep_blocks(g.d.n, g.upd_blocks);
+        UpdArgs<T> u;
+        u.d = g.d;
+        u.f = g.f;
+        u.rs = g.rs;
+        u.nrhs = g.nrhs;
+        u.M = mk_minv(g.minv);
+        u.S = g.S;
+        u.partials = g.partials;
+        up[i] = u;
+        updfirst[i] = (int)ub;
+        ub += nb;
+        for (int r = 0; r < g.nrhs; ++r, ++k) {
+            fd[k] = FinItem{g.partials + (size_t)r * g.g.blocks, g.g.blocks, g.g.blocks, g.S + r};
+            fu[k] = FinItem{g.partials + (size_t)r * 2 * nb, nb, nb, g.S + r};
+        }
+    }
+    if (ub >= (1LL << 31)) return hipErrorInvalidValue;
+    updfirst[n] = (int)ub;
+    plan->dev = dev;
+    plan->n = n;
+    plan->nfin = nfin;
+    plan->upd_blocks = (int)ub;
+    plan->off_upd = L.upd;
+    plan->off_updfirst = L.updfirst;
+    plan->off_findir = L.findir;
+    plan->off_finupd = L.finupd;
+    return hipMemcpyAsync(dev, staging, L.bytes, hipMemcpyHostToDevice, st);
+}
+
+template <typename T>
+hipError_t launch_group_iteration(hipStream_t st, const GroupPlan& p)
+{
+    if (p.n == 0) return hipSuccess;
+    const OpPack<T>* packs = reinterpret_cast<const OpPack<T>*>(p.packs.data());
+    for (size_t k = 0; k < p.pack_blocks.size(); ++k)
+        hipLaunchKernelGGL((op_group_kernel<kTX, kTY, T>), dim3(p.pack_blocks[k]), dim3(kTX * kTY), 0, st,
+                           packs[k]);
+    hipLaunchKernelGGL(finalize_group_kernel<1>, dim3(p.nfin), dim3(kFinThreads), 0, st, (int)FIN_DIRECTION,
+                       reinterpret_cast<const FinItem*>(p.dev + p.off_findir));
+    hipLaunchKernelGGL(update_group_kernel<T>, dim3(p.upd_blocks), dim3(kBlock), 0, st,
+                       reinterpret_cast<const UpdArgs<T>*>(p.dev + p.off_upd),
+                       reinterpret_cast<const int*>(p.dev + p.off_updfirst), p.n);
+    hipLaunchKernelGGL(finalize_group_kernel<2>, dim3(p.nfin), dim3(kFinThreads), 0, st, (int)FIN_UPDATE,
+                       reinterpret_cast<const FinItem*>(p.dev + p.off_finupd));
+    return hipGetLastError();
+}
+
 #define E3D_INSTANTIATE(T)                                                                          \
     template hipError_t launch_pcg_init<T>(hipStream_t, const Dims&, const FieldsT<T>&, T* const[6],  \
                                            int, int, Scalars*, double*, int, const double*);         \
@@ -1373,7 +1618,11 @@ hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& 
                                                      double*, bool);                                 \
     template hipError_t launch_update_precond<T>(hipStream_t, const Dims&, const FieldsT<T>&, size_t, \
                                                  int, T* const[6], Scalars*, double*, int, bool);    \
-    template hipError_t launch_final_update<T>(hipStream_t, const Dims&, const FieldsT<T>&, Scalars*);
+    template hipError_t launch_final_update<T>(hipStream_t, const Dims&, const FieldsT<T>&, Scalars*);     \
+    template size_t group_plan_bytes<T>(int, int);                                                   \
+    template hipError_t group_prepare<T>(hipStream_t, const GroupMember<T>*, int, char*, char*,       \
+                                         GroupPlan*);                                                \
+    template hipError_t launch_group_iteration<T>(hipStream_t, const GroupPlan&);
 E3D_INSTANTIATE(double)
 E3D_INSTANTIATE(float)
 #undef E3D_INSTANTIATE

@@ -1,0 +1,194 @@
+// Host runtime shared by the C-ABI translation units of libelas3d: the
+// context of one problem and the solver steps that both elas3d_solve and
+// the group engine (elas3d_group_*) drive.  Not part of the public ABI.
+#pragma once
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "elas3d.h"
+#include "elas3d_internal.h"
+
+namespace e3d::rt {
+
+constexpr int kSweepBlocks = 4096;  // grid of the node-wise sweeps
+// autotuning candidates: workgroup targets of the operator sweep (every tile
+// shape) and grids of the update sweep
+constexpr int kTuneTargets[3] = {2048, 4096, 8192};
+constexpr int kTuneUpdate[5] = {1024, 2048, 4096, 8192, 16384};
+constexpr int kPartialValues = 8;   // partial sums per block, upper bound
+constexpr int kDefaultPoll = 16;
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace e3d::rt
+
+using e3d::Dims;
+using e3d::Fields;
+using e3d::FieldsT;
+using e3d::Scalars;
+
+struct elas3d_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Dims d{};
+    int nphase = 0, nrhs = 0;
+    elas3d_options opt{};
+    std::vector<double> strain;  // nrhs * 6
+    e3d::OpGeom geom{};  // APPLY / REFINE sweeps (tile shape 0)
+    // direction+operator sweep and update grid per precision (0 FP64, 1 FP32),
+    // the defaults or the autotuned choice
+    e3d::OpGeom geom_sweep[2]{};
+    int upd_blocks[2] = {0, 0};
+    int tuned[2] = {0, 0};
+
+    int32_t* phase = nullptr;
+    double* coef = nullptr;
+    double* diag = nullptr;
+    uint8_t* solid = nullptr;
+    double* sig = nullptr;
+    // FP64 fields.  Batched: per RHS one bundle [w 3N | b 3N | g z h0 h1 Ah 15N]
+    // so that every field of RHS r lies r*21N after RHS 0's.  Otherwise the
+    // RHS keep [w | b] (6N each) and share one 15N work area after them.
+    double* bundle64 = nullptr;
+    double* minv = nullptr;  // 6N
+    // mixed precision: FP32 g, z, h0, h1, Ah, d (18N floats per work slot),
+    // M^-1 (6N), table
+    float* bundle32 = nullptr;
+    float* minv32 = nullptr;
+    float* coef32 = nullptr;
+    double* partials = nullptr;
+    int partial_stride = 0;
+    double* norms = nullptr;  // nrhs * 2: ||b||^2, ||b||_ref^2
+    double* dscratch = nullptr;  // 64 doubles
+    int* dflag = nullptr;
+    Scalars* S = nullptr;
+    Scalars* hS = nullptr;        // pinned, 2 slots of kMaxRhs
+    double* hscratch = nullptr;   // pinned, 64 doubles
+    std::vector<int> solved;
+    elas3d_group* group = nullptr;  // group the context is solved in, if any
+    double bytes = 0.0;
+    std::string err;
+
+    std::vector<e3d::rt::EventPair> ev_op, ev_up;
+    // captured iteration batches, keyed by (element size, first RHS, RHS count)
+    struct GraphEntry {
+        int key[3];
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+
+    size_t N() const { return (size_t)d.n; }
+    // component c (or M^-1 entry q) of a field starting at base
+    template <typename P>
+    P* comp(P* base, int c) const { return base + e3d::comp_offset(c, N()); }
+
+    bool batched() const { return opt.batched != 0; }
+    size_t rs64() const { return (batched() ? 21 : 6) * N(); }  // RHS stride of the bundles
+    size_t rs32() const { return 18 * N(); }
+    double* wptr(int r) const { return bundle64 + (size_t)r * rs64(); }
+    double* bptr(int r) const { return wptr(r) + 3 * N(); }
+    double* work64(int r) const
+    {
+        return batched() ? wptr(r) + 6 * N() : bundle64 + (size_t)nrhs * 6 * N();
+    }
+    float* work32(int r) const { return bundle32 + (batched() ? (size_t)r * rs32() : 0); }
+    Fields fields(int rhs)
+    {
+        Fields f;
+        double* wk = work64(rhs);
+        for (int c = 0; c < 3; ++c) {
+            f.w[c] = comp(wptr(rhs), c);
+            f.b[c] = comp(bptr(rhs), c);
+            f.g[c] = comp(wk, c);
+            f.z[c] = comp(wk + 3 * N(), c);
+            f.h0[c] = comp(wk + 6 * N(), c);
+            f.h1[c] = comp(wk + 9 * N(), c);
+            f.Ah[c] = comp(wk + 12 * N(), c);
+        }
+        return f;
+    }
+    void minv_planes(double* out[6]) const
+    {
+        for (int q = 0; q < 6; ++q) out[q] = comp(minv, q);
+    }
+    e3d::FieldsT<float> fields32(int rhs)
+    {
+        e3d::FieldsT<float> f;
+        float* wk = work32(rhs);
+        for (int c = 0; c < 3; ++c) {
+            f.g[c] = comp(wk, c);
+            f.z[c] = comp(wk + 3 * N(), c);
+            f.h0[c] = comp(wk + 6 * N(), c);
+            f.h1[c] = comp(wk + 9 * N(), c);
+            f.Ah[c] = comp(wk + 12 * N(), c);
+            f.w[c] = comp(wk + 15 * N(), c);
+            f.b[c] = nullptr;
+        }
+        return f;
+    }
+    void minv32_planes(float* out[6]) const
+    {
+        for (int q = 0; q < 6; ++q) out[q] = comp(minv32, q);
+    }
+    e3d::Tables tables() const { return e3d::Tables{coef, coef32, diag, solid}; }
+};
+
+
+namespace e3d::rt {
+
+// Records msg as the error of ctx (or of the thread when ctx is NULL) and
+// returns code.
+int fail(elas3d_ctx* ctx, int code, const std::string& msg);
+
+#define HIPCHK(ctx, expr)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return e3d::rt::fail((ctx), ELAS3D_EDEVICE,                                         \
+                                 std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+struct RunStats {
+    Scalars fin{};     // device scalars at the end of the run
+    int it_start = 0;  // iteration counter when the run started
+};
+
+struct CaseResult {
+    Scalars fin{};
+    int restarts = 0;
+    double rel_true = 0.0;
+    int fallback = 0;
+};
+
+// Start a PCG run of RHS r (device scalars and the init sweep), enqueued on
+// the context's stream through pinned staging slot r of c->hS.
+template <typename T>
+int start_run(elas3d_ctx* c, int r, const FieldsT<T>& f, T* const M[6], double tol, int maxit, int mode,
+              int it0, int fresh, int from_residual, const double* norms2);
+// Mark RHS r finished for the sweeps that follow (enqueued, staging slot r).
+int park(elas3d_ctx* c, int r, const Scalars& fin);
+// FP64 PCG of RHS [r0, r0+R) (see elas3d_api.hip).
+int solve_fp64(elas3d_ctx* c, int r0, int R, double tol, int maxit, bool cont, int it0, elas3d_info* info,
+               CaseResult* res);
+// Mixed precision: w += d, then r = A w + b in FP64 stored as the FP32
+// residual of the next inner run (and as its norms); *rel = ||r|| / ||b||.
+int refine_step(elas3d_ctx* c, int r, int q, double bnorm2, double* rel);
+// The refinement sweep of refine_step, enqueued only: ||r||^2 lands in
+// c->dscratch[4 + 2q] (and [5 + 2q]).
+int refine_launch(elas3d_ctx* c, int r, int q);
+// The residual sweep of true_residual, enqueued only: ||g||^2 into the
+// device double norm2.
+int residual_launch(elas3d_ctx* c, int r, double* norm2);
+// FP64 true residual of RHS r: g = A w + b, returns ||g||^2 in *rr.
+int true_residual(elas3d_ctx* c, int r, double* rr);
+// Per-RHS statistics of a finished solve into info (may be NULL); marks the
+// RHS solved; returns the worst status.
+int record_results(elas3d_ctx* c, int r0, int R, const CaseResult* res, elas3d_info* info);
+
+}  // namespace e3d::rt

@@ -24,7 +24,7 @@ __all__ = [
     "PRECOND_NONE", "TILE_SHAPES", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
     "setup", "solve", "stress", "apply", "get_load", "get_precond", "get_solution",
     "device_bytes", "destroy", "last_error", "version", "Context", "EXPORTS", "von_mises",
-    "generate_grains", "carve_pores", "PORE_STRIDE",
+    "generate_grains", "carve_pores", "PORE_STRIDE", "Group",
 ]
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
@@ -44,7 +44,8 @@ EXPORTS = (
     "elas3d_options_init", "elas3d_setup", "elas3d_solve", "elas3d_stress", "elas3d_apply",
     "elas3d_get_load", "elas3d_get_precond", "elas3d_get_solution", "elas3d_device_bytes",
     "elas3d_destroy", "elas3d_last_error", "elas3d_version", "elas3d_von_mises",
-    "elas3d_generate_grains", "elas3d_carve_pores",
+    "elas3d_generate_grains", "elas3d_carve_pores", "elas3d_group_create", "elas3d_group_add",
+    "elas3d_group_run", "elas3d_group_destroy",
 )
 
 
@@ -173,6 +174,15 @@ def lib():
         L.elas3d_carve_pores.argtypes = [i32, i32, i32, vp, i32, i32, vp, d, vp, vp,
                                          ctypes.POINTER(Options)]
         L.elas3d_carve_pores.restype = ctypes.c_int
+        L.elas3d_group_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Options)]
+        L.elas3d_group_create.restype = ctypes.c_int
+        L.elas3d_group_add.argtypes = [vp, vp, d, i32]
+        L.elas3d_group_add.restype = ctypes.c_int
+        L.elas3d_group_run.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(Info), i32,
+                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.elas3d_group_run.restype = ctypes.c_int
+        L.elas3d_group_destroy.argtypes = [vp]
+        L.elas3d_group_destroy.restype = None
         _lib = L
     return _lib
 
@@ -385,3 +395,41 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+class Group:
+    """Continuous batching of independent solves (elas3d_group_*): members
+    advance in lockstep with one launch per sweep for all of them."""
+
+    def __init__(self, options: Optional[Options] = None):
+        h = ctypes.c_void_p()
+        _check(lib().elas3d_group_create(ctypes.byref(h), ctypes.byref(options) if options is not None else None))
+        self.handle = h.value
+
+    def add(self, ctx, tol: float, maxit: int = 100000) -> None:
+        """Admit a context handle (all its load cases)."""
+        _check(lib().elas3d_group_add(self.handle, ctx, float(tol), int(maxit)))
+
+    def run(self, iters: int, cap: int = 64) -> tuple:
+        """Run `iters` lockstep iterations; returns ([(ctx, status, info dict)], active)."""
+        done = (ctypes.c_void_p * max(cap, 1))()
+        infos = (Info * max(cap, 1))()
+        nd, na = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().elas3d_group_run(self.handle, int(iters), done, infos, int(cap), ctypes.byref(nd),
+                                      ctypes.byref(na)))
+        out = []
+        for k in range(nd.value):
+            info = infos[k].as_dict()
+            out.append((done[k], max(info["status"]), info))
+        return out, na.value
+
+    def close(self):
+        if self.handle:
+            lib().elas3d_group_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

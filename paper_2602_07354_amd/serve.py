@@ -1,15 +1,23 @@
 """Solve service with continuous batching of uneven requests on one GPU.
 
 Requests are independent periodic voxel elasticity solves (their own grid,
-phase map, stiffnesses and 1-6 load cases).  A dispatcher admits queued
-requests as soon as the device-memory budget and the concurrency cap allow,
-so requests that arrive while others are on the GPU join as slots and memory
-free up.  Each admitted request runs on a worker thread with its own HIP
-stream: elas3d_setup -> elas3d_solve (all load cases as one lockstep batch,
-mixed precision by default) -> elas3d_stress -> elas3d_destroy.  The ctypes
-calls release the GIL, so the solves of different requests overlap on the
-device.  Every kernel is deterministic, so a result is bit-identical whether
-its request runs alone or in the mix.
+phase map, stiffnesses and 1-6 load cases).  Queued requests are admitted as
+soon as the device-memory budget and the concurrency cap allow, so requests
+that arrive while others are on the GPU join as slots and memory free up.
+
+Two engines:
+
+* ``GroupServer`` (the default): one engine thread owns an elas3d group.
+  Admitted requests are set up and added to it; every batch of iterations
+  advances all of them with one launch per sweep over a work list of
+  (request, workgroup) entries (four launches per PCG iteration for up to 8
+  requests); finished requests leave between batches, new ones join.
+* ``Server``: each admitted request runs elas3d_solve on a worker thread with
+  its own HIP stream, and the solves overlap on the device.
+
+Every kernel is deterministic and a request's sweeps are the same in either
+engine, so a result is bit-identical whether its request runs alone or in the
+mix.
 
 ``python -m paper_2602_07354_amd.serve`` measures the saturation throughput
 and then p50/p99 latency under Poisson arrivals at fractions of it.
@@ -24,6 +32,7 @@ import sys
 import threading
 import time
 from collections import deque
+from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait
 from typing import List, Optional
 
 import numpy as np
@@ -166,7 +175,135 @@ class Server:
         self._dispatcher.join(timeout=5)
 
 
-def run_stream(requests: List[Request], server: Server) -> List[Result]:
+class GroupServer:
+    """Continuous batching through an elas3d group: one engine thread runs the
+    group; set-ups (copies, tables, load and preconditioner sweeps on each
+    context's own stream) run on worker threads meanwhile."""
+
+    def __init__(self, budget_bytes: Optional[float] = None, max_concurrency: int = 64,
+                 poll: int = 8, device: int = 0, setup_workers: int = 4):
+        if budget_bytes is None:
+            import torch
+
+            free, _ = torch.cuda.mem_get_info(device)
+            budget_bytes = 0.8 * free
+        self.budget = float(budget_bytes)
+        self.max_conc = int(max_concurrency)
+        self.poll = int(poll)
+        self.device = device
+        self.setup_workers = int(setup_workers)
+        self._lock = threading.Condition()
+        self._queue: deque = deque()
+        self._results: List[Result] = []
+        self._in_flight = {}  # context handle -> (request, bytes, arrival, start)
+        self._in_flight_bytes = 0.0
+        self._open = 0  # admitted and not finished (setting up or in the group)
+        self._stop = False
+        self._error: Optional[BaseException] = None
+        self._t0 = time.perf_counter()
+        self._engine = threading.Thread(target=self._run, daemon=True)
+        self._engine.start()
+
+    def now(self) -> float:
+        return time.perf_counter() - self._t0
+
+    def submit(self, req: Request) -> None:
+        nbytes = request_bytes(req)
+        if nbytes > self.budget:
+            raise ValueError(f"request {req.rid} needs {nbytes/1e9:.2f} GB, over the budget")
+        with self._lock:
+            self._queue.append((req, nbytes, self.now()))
+            self._lock.notify_all()
+
+    def _setup(self, req: Request, nbytes: float, t_arr: float):
+        ms = req.micro
+        t_start = self.now()
+        opts = E.options_init(precision=req.precision, batched=1, device=self.device)
+        return E.setup(ms.shape, ms.phase, ms.C, ms.strain, opts), (req, nbytes, t_arr, t_start)
+
+    def _admit(self, pool, pending: set) -> None:
+        while True:
+            with self._lock:
+                if not self._queue or len(self._in_flight) + len(pending) >= self.max_conc:
+                    return
+                req, nbytes, t_arr = self._queue[0]
+                if self._in_flight_bytes + nbytes > self.budget:
+                    return
+                self._queue.popleft()
+                self._in_flight_bytes += nbytes
+                self._open += 1
+            pending.add(pool.submit(self._setup, req, nbytes, t_arr))
+
+    def _join(self, group, pending: set) -> None:
+        for f in [f for f in pending if f.done()]:
+            pending.discard(f)
+            h, meta = f.result()
+            self._in_flight[h] = meta
+            group.add(h, meta[0].tol, 50000)
+
+    def _finish(self, h, status, info, meta) -> None:
+        req, nbytes, t_arr, t_start = meta
+        ms = req.micro
+        avg = np.empty((ms.nrhs, 6))
+        try:
+            for r in range(ms.nrhs):
+                a = np.empty(6)
+                E.stress(h, r, None, a, None, None)
+                avg[r] = a
+        finally:
+            E.destroy(h)
+        res = Result(req.rid, ms.shape, ms.nrhs, status, info["iters"], info["relres_true"], avg, t_arr,
+                     t_start, self.now())
+        with self._lock:
+            self._results.append(res)
+            self._in_flight_bytes -= nbytes
+            self._open -= 1
+            self._lock.notify_all()
+
+    def _run(self) -> None:
+        try:
+            with E.Group(E.options_init(device=self.device)) as group, \
+                    ThreadPoolExecutor(self.setup_workers) as pool:
+                pending: set = set()
+                while True:
+                    self._admit(pool, pending)
+                    self._join(group, pending)
+                    if not self._in_flight:
+                        if pending:
+                            wait(pending, timeout=0.05, return_when=FIRST_COMPLETED)
+                            continue
+                        with self._lock:
+                            if self._stop and not self._queue:
+                                return
+                            if not self._queue:
+                                self._lock.wait(0.05)
+                        continue
+                    done, _ = group.run(self.poll)
+                    for h, st, info in done:  # stress and release off the engine thread
+                        pool.submit(self._finish, h, st, info, self._in_flight.pop(h))
+        except BaseException as e:  # surfaced by drain()
+            with self._lock:
+                self._error = e
+                self._lock.notify_all()
+
+    def drain(self) -> List[Result]:
+        with self._lock:
+            while (self._queue or self._open) and self._error is None:
+                self._lock.wait(0.05)
+            if self._error is not None:
+                raise RuntimeError("group engine failed") from self._error
+            out = sorted(self._results, key=lambda r: r.rid)
+            self._results = []
+            return out
+
+    def close(self):
+        with self._lock:
+            self._stop = True
+            self._lock.notify_all()
+        self._engine.join(timeout=30)
+
+
+def run_stream(requests: List[Request], server) -> List[Result]:
     """Submit requests at their arrival offsets (seconds) and wait for all."""
     start = server.now()
     for req in sorted(requests, key=lambda r: r.arrival):
@@ -202,6 +339,9 @@ def main(argv=None):
     ap.add_argument("--concurrency", type=int, default=8)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--seed", type=int, default=4000)
+    ap.add_argument("--engine", choices=["group", "streams"], default="group",
+                    help="group: one launch per sweep for all requests; streams: one stream per request")
+    ap.add_argument("--poll", type=int, default=8, help="group: iterations between admissions")
     args = ap.parse_args(argv)
 
     import torch
@@ -212,7 +352,8 @@ def main(argv=None):
     pool = make_pool(args.pool, args.seed, prec)
     print(f"# pool of {len(pool)} requests: edges {[r.micro.shape[0] for r in pool]}, "
           f"cases {[r.micro.nrhs for r in pool]}", file=sys.stderr, flush=True)
-    srv = Server(max_concurrency=args.concurrency)
+    srv = (GroupServer(max_concurrency=args.concurrency, poll=args.poll) if args.engine == "group"
+           else Server(max_concurrency=args.concurrency))
     # warm-up and saturation: closed loop, everything queued at t = 0
     run_stream([dataclasses.replace(r, rid=i, arrival=0.0) for i, r in enumerate(pool)], srv)
     nsat = max(len(pool), args.requests // 2)
@@ -221,7 +362,9 @@ def main(argv=None):
                       for i in range(nsat)], srv)
     sat_rate = len(sat) / (time.perf_counter() - t0)
     out = {"metric": "p50/p99 solve latency under Poisson arrivals (continuous batching)",
-           "precision": args.precision, "tol": pool[0].tol, "concurrency": args.concurrency,
+           "engine": args.engine, "poll": args.poll if args.engine == "group" else None,
+           "precision": args.precision, "tol": pool[0].tol,
+           "concurrency": args.concurrency,
            "saturation_solves_per_s": round(sat_rate, 3), "rates": []}
     rng = np.random.default_rng(args.seed)
     for frac in args.rates:

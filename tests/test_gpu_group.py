@@ -1,0 +1,120 @@
+"""Group engine (continuous batching, one launch per sweep for all members):
+every member's result equals, bit for bit, the same problem solved alone
+with elas3d_solve, whatever the mix and the admission times."""
+
+import numpy as np
+import pytest
+
+from paper_2602_07354_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2602_07354_amd import elas3d
+    elas3d.lib()
+    return elas3d
+
+
+def _poly(shape, seed, nrhs=1):
+    strain = synth.unit_load_cases()[:nrhs] if nrhs > 1 else np.array([[2e-4, -1e-4, 1e-3, 3e-4, -2e-4, 1e-4]])
+    return synth.polycrystal(shape, 12, seed, [dict(kind="sphere", fraction=0.02, median=1.5, sigma=0.3)], strain)
+
+
+def _homogeneous():
+    C = np.stack([synth.cubic_stiffness(206, 133, 119)])
+    return synth.Microstructure((12, 10, 8), np.zeros(960, np.int32), C, np.array([[1e-3, 0, 0, 0, 0, 0]]), {})
+
+
+def _cases(E):
+    mixed = dict(precision=E.PREC_MIXED)
+    return [
+        ("eshelby fp64", synth.eshelby_inclusion(20), {}),
+        ("poly fp64 x3", _poly((24, 20, 18), 5, 3), dict(batched=1)),
+        ("poly mixed", _poly((30, 26, 22), 6), mixed),
+        ("poly mixed x2", _poly((17, 19, 23), 7, 2), dict(batched=1, **mixed)),
+        ("zero load", _homogeneous(), {}),
+        ("forced fallback", _poly((20, 18, 16), 8), dict(inner_tol=0.9, **mixed)),
+        ("poly fp64 paper", _poly((22, 16, 19), 9), dict(convergence=E.CONV_PAPER)),
+    ]
+
+
+def _outcome(ctx, info, nrhs):
+    return {
+        "info": {k: info[k] for k in ("status", "iters", "restarts", "relres_true", "relres_recursive",
+                                      "relres_precond", "fp64_fallback")},
+        "w": [ctx.solution(r) for r in range(nrhs)],
+        "avg": [ctx.stress(r, voxel=False)["avg"] for r in range(nrhs)],
+    }
+
+
+def _same(a, b):
+    assert a["info"] == b["info"]
+    for x, y in zip(a["w"], b["w"]):
+        assert np.array_equal(x, y)
+    for x, y in zip(a["avg"], b["avg"]):
+        assert np.array_equal(x, y)
+
+
+def test_group_results_equal_solo_solves(E):
+    tol, maxit = 1e-9, 20000
+    cases = _cases(E)
+    solo = []
+    for name, ms, kw in cases:
+        with E.Context.from_micro(ms, **kw) as ctx:
+            st, info = ctx.solve(tol, maxit)
+            solo.append(_outcome(ctx, info, ms.nrhs))
+        say("  solo", name, info["iters"], info["restarts"], info["fp64_fallback"])
+    assert any(f for f in solo[5]["info"]["fp64_fallback"])  # the fallback path is exercised
+    ctxs = [E.Context.from_micro(ms, **kw) for _, ms, kw in cases]
+    got = {}
+    try:
+        with E.Group() as g:
+            for k in (0, 1, 4):
+                g.add(ctxs[k].handle, tol, maxit)
+            pending = [2, 3, 5, 6]
+            rounds = 0
+            while len(got) < len(cases):
+                done, active = g.run(4 if rounds % 2 else 7)
+                rounds += 1
+                for h, st, info in done:
+                    k = [c.handle for c in ctxs].index(h)
+                    got[k] = _outcome(ctxs[k], info, cases[k][1].nrhs)
+                if pending and rounds % 3 == 1:  # joins while others are mid-solve
+                    g.add(ctxs[pending.pop(0)].handle, tol, maxit)
+                assert rounds < 100000
+        say("  group rounds", rounds)
+    finally:
+        for c in ctxs:
+            c.close()
+    for k, (name, _, _) in enumerate(cases):
+        say("case:", name)
+        _same(got[k], solo[k])
+
+
+def test_group_admission_rules(E):
+    ms2 = _poly((12, 12, 12), 3, 2)
+    ms1 = _poly((12, 12, 12), 4)
+    with E.Group() as g, E.Context.from_micro(ms2) as unbatched, E.Context.from_micro(ms1) as c1:
+        with pytest.raises(E.Elas3dError) as ei:
+            g.add(unbatched.handle, 1e-8)
+        assert ei.value.code == E.EBADARG
+        g.add(c1.handle, 1e-8)
+        with pytest.raises(E.Elas3dError) as ei:
+            g.add(c1.handle, 1e-8)
+        assert ei.value.code == E.EORDER
+        with pytest.raises(E.Elas3dError) as ei:
+            c1.solve(1e-8)
+        assert ei.value.code == E.EORDER
+        while True:
+            done, active = g.run(16)
+            if done:
+                assert done[0][0] == c1.handle and done[0][1] == E.OK
+                break
+        st, info = c1.solve(1e-8)  # back to normal use once returned
+        assert st == E.OK

@@ -294,15 +294,17 @@ def test_homogeneous_effective_stiffness_is_C(E):
     assert np.allclose(avg.T / 1e-3, C, rtol=1e-12)
 
 
-def test_serving_results_same_alone_and_in_the_mix(E):
-    """Continuous batching: requests of uneven size solved concurrently (own
-    streams, admitted by memory budget) give bit-identical results to the
-    same requests solved alone."""
-    say("case: serving mix vs alone")
+@pytest.mark.parametrize("engine", ["group", "streams"])
+def test_serving_results_same_alone_and_in_the_mix(E, engine):
+    """Continuous batching: requests of uneven size admitted by memory budget
+    and solved together (one launch per sweep for the whole mix, or one
+    stream per request) give bit-identical results to the same requests
+    solved alone."""
+    say("case: serving mix vs alone,", engine)
     from paper_2602_07354_amd import serve
     pool = [r for r in serve.make_pool(12, seed0=900) if r.micro.shape[0] <= 96][:5]
     alone = [serve.solve_one(r) for r in pool]
-    srv = serve.Server(max_concurrency=4)
+    srv = serve.GroupServer(max_concurrency=4) if engine == "group" else serve.Server(max_concurrency=4)
     try:
         # all queued at once (concurrent), then a staggered stream
         mixed = serve.run_stream(pool, srv)
