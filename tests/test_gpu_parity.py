@@ -149,8 +149,22 @@ def test_config_poly100_metric_and_sampled_parity(E, orc):
     assert np.all(out["sigma"][:, void] == 0.0)
 
 
-def test_edge_cases(E):
+def test_edge_cases(E, orc):
     say("case: edge cases")
+    # the smallest grids (2 nodes in a dimension: both neighbours are the same
+    # node through the periodic wrap) against the oracle
+    for shape in [(2, 3, 2), (2, 2, 2), (3, 2, 5)]:
+        say("  grid", shape)
+        ms2 = _small_poly(shape, 31 + shape[2], porosity=0.0, grains=3)
+        P2 = orc.Problem.from_micro(ms2)
+        ro = P2.solve(ms2.strain[0], tol=1e-12)
+        with E.Context.from_micro(ms2) as ctx:
+            st, info = ctx.solve(1e-12, 1000)
+            assert st == E.OK and abs(info["iters"][0] - ro["iters"]) <= 2
+            so, _ = P2.stress(ms2.strain[0], ro["w"])
+            assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
+            x = np.random.default_rng(1).standard_normal((3, ms2.n))
+            assert _rel(ctx.apply(x), P2.apply(x)) <= 1e-12
     iso = synth.isotropic_stiffness(200, .3)
     C = np.stack([iso, np.zeros((6, 6))])
     strain = np.array([[1e-3, 0, 0, 0, 0, 0]])
@@ -177,6 +191,11 @@ def test_edge_cases(E):
     with E.Context.from_micro(ms) as ctx:
         st, info = ctx.solve(1e-10, 1)
         assert st == E.NOT_CONVERGED and info["iters"][0] == 1
+        ctx.stress(0)
+    # maxit = 0: no iteration, not converged, outputs valid
+    with E.Context.from_micro(ms) as ctx:
+        st, info = ctx.solve(1e-10, 0)
+        assert st == E.NOT_CONVERGED and info["iters"][0] == 0
         ctx.stress(0)
     # stress before solve is an ordering error
     with E.Context.from_micro(ms) as ctx:
