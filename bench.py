@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
-    ap.add_argument("--autotune", action="store_true", help="autotune the sweep geometry")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default sweep geometry (32x8 workgroups) instead of autotuning it")
     ap.add_argument("--nrhs", type=int, default=1, help="load cases solved per step (of the workload's)")
     ap.add_argument("--batched", action="store_true",
                     help="solve the load cases as one lockstep multi-RHS batch (else one after another)")
@@ -81,9 +82,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str) -> dict:
+def measured_traffic(workload: str, tile) -> dict:
     """HBM bytes per launch of the fused sweep from the committed counter
-    summary, if it was taken on this kernel source and workload."""
+    summary, if it was taken on this kernel source, workload and sweep
+    geometry (lanes in x, y and z-chunk length)."""
     out = {"bytes": None, "source": None}
     if not os.path.exists(COUNTERS):
         return out
@@ -93,8 +95,9 @@ def measured_traffic(workload: str) -> dict:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload:
-        out["source"] = "stale (kernel or workload changed since the counters were taken)"
+    if (kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload
+            or kv.get("op_tile") != " ".join(str(v) for v in tile)):
+        out["source"] = "stale (kernel, workload or sweep geometry differs from the counters' run)"
         return out
     out["bytes"] = float(kv["op_traffic_bytes_per_dispatch"])
     out["source"] = os.path.relpath(COUNTERS, ROOT)
@@ -198,7 +201,7 @@ def main():
 
     def step(record, precision):
         opts = E.options_init(inputs_on_device=1, outputs_on_device=1, timing=1, device=0,
-                              stream=stream.cuda_stream, autotune=1 if args.autotune else 0,
+                              stream=stream.cuda_stream, autotune=0 if args.no_autotune else 1,
                               batched=1 if args.batched else 0,
                               precision=E.PREC_MIXED if precision == "mixed" else E.PREC_FP64)
         h = E.setup(ms.shape, phase, ms.C, ms.strain[:nrhs], opts)
@@ -244,6 +247,8 @@ def main():
                                      max(1, sum(r[1]["n_operator"] for r in mrecs)), 4),
             "update_ms_avg": round(sum(r[1]["t_update_ms"] for r in mrecs) /
                                    max(1, sum(r[1]["n_update"] for r in mrecs)), 4),
+            "op_tile": mrecs[0][1]["op_tile"],
+            "update_blocks": mrecs[0][1]["update_blocks"],
         }
 
     iters = [sum(r[1]["iters"]) for r in recs]  # summed over the load cases
@@ -260,7 +265,7 @@ def main():
     op_bytes = (OPERATOR_BYTES_PER_NODE_FP64 if head == "fp64" else 6 * 12 + 4) * ms.n * rhs_per_launch
     achieved = op_bytes / (op_ms / 1e3) / 1e9
     tile = recs[0][1]["op_tile"]
-    traffic = (measured_traffic(ms.meta.get("workload")) if head == "fp64" and nrhs == 1 and tile[:2] == [32, 8]
+    traffic = (measured_traffic(ms.meta.get("workload"), tile) if head == "fp64" and nrhs == 1
                else {"bytes": None, "source": None})
     out = {
         "metric": "Gdof*iterations/s of the block-Jacobi PCG solve to true rel-res 1e-8 "
@@ -315,6 +320,7 @@ def main():
             "copy_GBs_measured": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
             "op_tile": tile,
+            "update_blocks": recs[0][1]["update_blocks"],
         },
     }
     if not args.no_cpu_baseline:

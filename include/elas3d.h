@@ -97,7 +97,9 @@ typedef struct elas3d_options {
                                   when timing is on); default 1                      */
     int32_t autotune;          /* nonzero: before the first iteration of each
                                   precision, time the candidate workgroup shapes
-                                  and chunkings of the direction+operator sweep and
+                                  (32x8, 16x16, 64x4, 32x16 lanes) and z-chunkings
+                                  (about 2048 to 16384 workgroups) of the
+                                  direction+operator sweep and
                                   the grid of the update sweep on the live problem,
                                   keep the fastest (cached per process by grid,
                                   precision and RHS count).  The reduction order

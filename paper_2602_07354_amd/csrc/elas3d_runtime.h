@@ -15,7 +15,7 @@ namespace e3d::rt {
 constexpr int kSweepBlocks = 4096;  // grid of the node-wise sweeps
 // autotuning candidates: workgroup targets of the operator sweep (every tile
 // shape) and grids of the update sweep
-constexpr int kTuneTargets[3] = {2048, 4096, 8192};
+constexpr int kTuneTargets[4] = {2048, 4096, 8192, 16384};
 constexpr int kTuneUpdate[5] = {1024, 2048, 4096, 8192, 16384};
 constexpr int kPartialValues = 8;   // partial sums per block, upper bound
 constexpr int kDefaultPoll = 16;
