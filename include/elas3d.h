@@ -133,6 +133,10 @@ typedef struct elas3d_info {
                                                   length of the direction+operator
                                                   sweep (of the inner solve in mixed) */
     int32_t update_blocks;                     /* grid of the update sweep           */
+    int64_t precond_rows;                      /* rows of the M^-1 dictionary: one per
+                                                  phase (shared by the nodes whose
+                                                  eight voxels all have it) plus one
+                                                  per phase-boundary node            */
 } elas3d_info;
 
 /* Fill `opt` with the defaults (FP64, residual criterion, block Jacobi,
@@ -301,8 +305,9 @@ int elas3d_group_run(elas3d_group* g, int32_t iters, elas3d_ctx** done, elas3d_i
  * stay valid, unsolved, on their own streams). */
 void elas3d_group_destroy(elas3d_group* g);
 
-/* Device bytes a context with these sizes and options would allocate (0 for
- * sizes that elas3d_setup would reject). */
+/* Device bytes a context with these sizes and options allocates at most (0
+ * for sizes that elas3d_setup would reject); the bound counts one M^-1 row
+ * per node, where setup stores one per phase and per phase-boundary node. */
 double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
                            const elas3d_options* opt);
 

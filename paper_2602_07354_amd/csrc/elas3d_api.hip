@@ -70,12 +70,14 @@ double plan_bytes(int32_t nx, int32_t ny, int32_t nz, int nphase, int nrhs, bool
     const int64_t n = (int64_t)nx * ny * nz;
     const double N = (double)n;
     double bytes = 0.0;
-    if (mixed)  // FP32 work, M^-1, table
-        bytes += 4.0 * (18.0 * (batched ? nrhs : 1) + 6.0) * N + 4.0 * nphase * e3d::kCoefStride;
+    if (mixed)  // FP32 work, table
+        bytes += 4.0 * 18.0 * (batched ? nrhs : 1) * N + 4.0 * nphase * e3d::kCoefStride;
     bytes += 4.0 * N;                          // phase ids
     bytes += 8.0 * 3.0 * N * nrhs * 2.0;       // b and w per case
     bytes += 8.0 * 15.0 * N * (batched ? nrhs : 1);  // g, z, h0, h1, Ah
-    bytes += 8.0 * 6.0 * N;                    // M^-1 (symmetric 3x3)
+    // M^-1 (symmetric 3x3) rows: at most one per phase and one per node, and
+    // the row index of each node
+    bytes += (8.0 * 6.0 * (mixed ? 1.5 : 1.0)) * (N + nphase) + 4.0 * N;
     bytes += (double)nphase * 8.0 * (e3d::kCoefStride + e3d::kDiagStride + 1.0) +
              (double)nphase * nrhs * 8.0 * e3d::kSigStride;
     bytes += 8.0 * kPartialValues * partial_slots(Dims{nx, ny, nz, (int)n}, nrhs);  // partial sums
@@ -209,7 +211,7 @@ void free_ctx(elas3d_ctx* c)
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     for (void* p : {(void*)c->phase, (void*)c->coef, (void*)c->diag, (void*)c->solid, (void*)c->sig,
-                    (void*)c->bundle64, (void*)c->minv, (void*)c->partials,
+                    (void*)c->bundle64, (void*)c->midx, (void*)c->minv, (void*)c->partials,
                     (void*)c->norms, (void*)c->dscratch, (void*)c->dflag, (void*)c->S,
                     (void*)c->bundle32, (void*)c->minv32, (void*)c->coef32})
         if (p) hipFree(p);
@@ -269,7 +271,7 @@ std::map<std::array<int, 6>, std::pair<e3d::OpGeom, int>> g_tune_cache;
 // is, and the update sweep leaves g as it is and rewrites z = M^-1 g; no
 // finalize kernel runs, so the scalars are untouched.
 template <typename T>
-int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* const M[6])
+int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const e3d::MinvRows<T>& M)
 {
     const int pi = sizeof(T) == sizeof(double) ? 0 : 1;
     const std::array<int, 6> key = {c->device, c->d.nx, c->d.ny, c->d.nz, (int)sizeof(T), R};
@@ -345,7 +347,7 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* c
 // batch k while batch k+1 is already queued.  Optional HIP-event timing of
 // every launch that did real work.  Then the step owed to w is applied.
 template <typename T>
-int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* const M[6], int maxit,
+int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const e3d::MinvRows<T>& M, int maxit,
             elas3d_info* info, RunStats* rs_out)
 {
     const Dims& d = c->d;
@@ -496,7 +498,7 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, T* co
 // into its device scalars, then the init sweep (fresh: w = 0, g = b;
 // otherwise g already holds the residual to continue from).
 template <typename T>
-int start_run(elas3d_ctx* c, int r, const FieldsT<T>& f, T* const M[6], double tol, int maxit,
+int start_run(elas3d_ctx* c, int r, const FieldsT<T>& f, const e3d::MinvRows<T>& M, double tol, int maxit,
               int mode, int it0, int fresh, int from_residual, const double* norms2)
 {
     Scalars init{};
@@ -513,9 +515,9 @@ int start_run(elas3d_ctx* c, int r, const FieldsT<T>& f, T* const M[6], double t
     return 0;
 }
 
-template int start_run<double>(elas3d_ctx*, int, const FieldsT<double>&, double* const[6], double, int, int,
+template int start_run<double>(elas3d_ctx*, int, const FieldsT<double>&, const e3d::MinvRows<double>&, double, int, int,
                                int, int, int, const double*);
-template int start_run<float>(elas3d_ctx*, int, const FieldsT<float>&, float* const[6], double, int, int, int,
+template int start_run<float>(elas3d_ctx*, int, const FieldsT<float>&, const e3d::MinvRows<float>&, double, int, int, int,
                               int, int, const double*);
 
 // Mark RHS r of the next batch as finished (its sweeps return at once).
@@ -536,9 +538,7 @@ int park(elas3d_ctx* c, int r, const Scalars& fin)
 int solve_fp64(elas3d_ctx* c, int r0, int R, double tol, int maxit, bool cont, int it0,
                elas3d_info* info, CaseResult* res)
 {
-    const Dims& d = c->d;
-    double* M[6];
-    c->minv_planes(M);
+    const e3d::MinvRows<double> M = c->minv_rows();
     const e3d::Tables t = c->tables();
     std::vector<int> running(R, 1);
     for (int q = 0; q < R; ++q) {
@@ -642,8 +642,7 @@ int solve_mixed(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info
                 CaseResult* res)
 {
     const Dims& d = c->d;
-    float* M32[6];
-    c->minv32_planes(M32);
+    const e3d::MinvRows<float> M32 = c->minv32_rows();
     const e3d::Tables t = c->tables();
     const double inner_tol = c->opt.inner_tol > 0.0 ? c->opt.inner_tol : 1e-4;
     std::vector<double> bnorm2(R), bref2(R), rel(R);
@@ -886,10 +885,9 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     SETUPCHK(hipMalloc(&c->solid, (size_t)nphase));
     SETUPCHK(hipMalloc(&c->sig, 8 * (size_t)nrhs * nphase * e3d::kSigStride));
     SETUPCHK(hipMalloc(&c->bundle64, 8 * N * (opt.batched ? 21 * (size_t)nrhs : 6 * (size_t)nrhs + 15)));
-    SETUPCHK(hipMalloc(&c->minv, 8 * 6 * N));
+    SETUPCHK(hipMalloc(&c->midx, 4 * N));
     if (mixed) {
         SETUPCHK(hipMalloc(&c->bundle32, 4 * 18 * N * (opt.batched ? (size_t)nrhs : 1)));
-        SETUPCHK(hipMalloc(&c->minv32, 4 * 6 * N));
         SETUPCHK(hipMalloc(&c->coef32, 4 * (size_t)nphase * e3d::kCoefStride));
     }
     SETUPCHK(hipMalloc(&c->partials, 8 * (size_t)kPartialValues * c->partial_stride));
@@ -933,12 +931,39 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
                                   c->sig + (size_t)r * nphase * e3d::kSigStride, bp, c->partials,
                                   c->norms + 2 * r, kSweepBlocks));
     }
-    double* M[6];
-    c->minv_planes(M);
-    SETUPCHK(e3d::launch_precond(c->stream, c->d, c->phase, c->tables(),
-                                 opt.preconditioner == ELAS3D_PRECOND_NONE ? 1 : 0, M));
-    // mixed: the blocks are inverted in FP64 and stored rounded to FP32
-    if (mixed) SETUPCHK(e3d::launch_to_float(c->stream, c->minv, c->minv32, 6 * N));
+    // M^-1 as a dictionary: count the phase-boundary nodes of each chunk (in
+    // the partial-sum buffer), lay their rows out after the nphase shared
+    // ones, then fill the rows and every node's row index
+    {
+        const int identity = opt.preconditioner == ELAS3D_PRECOND_NONE ? 1 : 0;
+        const size_t nchunks = (N + e3d::kPrecondChunk - 1) / e3d::kPrecondChunk;
+        if (nchunks > 2 * (size_t)kPartialValues * c->partial_stride) {
+            free_ctx(c);
+            return fail(nullptr, ELAS3D_EDEVICE, "preconditioner chunk table exceeds the partial-sum buffer");
+        }
+        int* chunk = reinterpret_cast<int*>(c->partials);
+        SETUPCHK(e3d::launch_precond_count(c->stream, c->d, c->phase, chunk));
+        std::vector<int> cnt(nchunks);
+        SETUPCHK(hipMemcpyAsync(cnt.data(), chunk, sizeof(int) * nchunks, hipMemcpyDeviceToHost, c->stream));
+        SETUPCHK(hipStreamSynchronize(c->stream));
+        size_t nb = 0;
+        for (size_t q = 0; q < nchunks; ++q) {
+            const int v = cnt[q];
+            cnt[q] = (int)nb;
+            nb += (size_t)v;
+        }
+        c->mrows = (size_t)nphase + nb;
+        SETUPCHK(hipMemcpyAsync(chunk, cnt.data(), sizeof(int) * nchunks, hipMemcpyHostToDevice, c->stream));
+        SETUPCHK(hipMalloc(&c->minv, 8 * 6 * c->mrows));
+        if (mixed) SETUPCHK(hipMalloc(&c->minv32, 4 * 6 * c->mrows));
+        const e3d::MinvRows<double> M = c->minv_rows();
+        SETUPCHK(e3d::launch_precond_table(c->stream, nphase, c->tables(), identity, M.m));
+        SETUPCHK(e3d::launch_precond_fill(c->stream, c->d, c->phase, c->tables(), identity, nphase, chunk,
+                                          c->midx, M.m));
+        // mixed: the blocks are inverted in FP64 and stored rounded to FP32
+        if (mixed) SETUPCHK(e3d::launch_to_float(c->stream, c->minv, c->minv32, 6 * c->mrows));
+        SETUPCHK(hipStreamSynchronize(c->stream));  // (cnt is read by the copy)
+    }
     // (host input arrays must not be read after return)
     SETUPCHK(hipStreamSynchronize(c->stream));
     (void)t0;
@@ -977,14 +1002,18 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
     if (info) {
         info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
         // two fused sweeps: direction+operator (read z, h, w, phase; write h, w, Ah)
-        // and update+precondition (read g, Ah, M^-1; write g, z)
-        // per RHS: fused sweep 6 vectors + phase, update sweep 4 vectors + M^-1
-        // (M^-1 read once per node for a batch)
+        // and update+precondition (read g, Ah, the M^-1 row index and the
+        // rows of phase-boundary nodes; write g, z); per RHS: fused sweep 6
+        // vectors + phase, update sweep 4 vectors; M^-1 once per node for a
+        // batch (the nphase shared rows stay in cache)
         const int rb = ctx->batched() ? nrhs : 1;
+        const double N = (double)ctx->N();
+        const double nbnd = (double)(ctx->mrows - (size_t)ctx->nphase);
+        info->precond_rows = (int64_t)ctx->mrows;
         if (ctx->opt.precision == ELAS3D_PREC_MIXED)
-            info->bytes_per_iter = (double)ctx->N() * rb * ((6 * 12.0 + 4.0) + (4 * 12.0 + 24.0 / rb));
+            info->bytes_per_iter = N * rb * ((6 * 12.0 + 4.0) + 4 * 12.0) + 4.0 * N + 24.0 * nbnd;
         else
-            info->bytes_per_iter = (double)ctx->N() * rb * ((6 * 24.0 + 4.0) + (4 * 24.0 + 48.0 / rb));
+            info->bytes_per_iter = N * rb * ((6 * 24.0 + 4.0) + 4 * 24.0) + 4.0 * N + 48.0 * nbnd;
     }
     return worst;
 }
@@ -1085,7 +1114,13 @@ int elas3d_get_precond(elas3d_ctx* ctx, double* minv)
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
     if (!minv) return fail(ctx, ELAS3D_EBADARG, "NULL output");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    return export_field(ctx, ctx->minv, 6, minv);
+    const size_t N = ctx->N();
+    double* dst = ctx->opt.outputs_on_device ? minv : ctx->work64(0);
+    HIPCHK(ctx, e3d::launch_precond_expand(ctx->stream, ctx->d, ctx->minv_rows(), dst));
+    if (!ctx->opt.outputs_on_device)
+        HIPCHK(ctx, hipMemcpyAsync(minv, dst, 8 * 6 * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return 0;
 }
 
 int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w)

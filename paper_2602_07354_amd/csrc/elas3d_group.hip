@@ -87,8 +87,7 @@ int mfail(Member& m, int rc)
 int start64(Member& m, int q, int it0, bool fresh)
 {
     elas3d_ctx* c = m.c;
-    double* M[6];
-    c->minv_planes(M);
+    const e3d::MinvRows<double> M = c->minv_rows();
     return start_run<double>(c, q, c->fields(q), M, m.tol, m.maxit, c->opt.convergence, it0, fresh ? 1 : 0,
                              fresh ? 0 : 1, c->norms + 2 * q);
 }
@@ -121,8 +120,7 @@ int refine_all(Member& m, const int* want)
 int start_cycle(Member& m, bool* any)
 {
     elas3d_ctx* c = m.c;
-    float* M32[6];
-    c->minv32_planes(M32);
+    const e3d::MinvRows<float> M32 = c->minv32_rows();
     *any = false;
     for (int q = 0; q < m.R; ++q) {
         int rc;
@@ -323,11 +321,11 @@ int build_plan(elas3d_group* g, int lane)
         if constexpr (sizeof(T) == sizeof(double)) {
             gm.f = c->fields(0);
             gm.rs = c->rs64();
-            c->minv_planes(gm.minv);
+            gm.minv = c->minv_rows();
         } else {
             gm.f = c->fields32(0);
             gm.rs = c->rs32();
-            c->minv32_planes(gm.minv);
+            gm.minv = c->minv32_rows();
         }
         mem.push_back(gm);
     }

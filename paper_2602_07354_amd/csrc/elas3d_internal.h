@@ -100,6 +100,17 @@ __host__ __device__ inline FieldsT<T> shifted(const FieldsT<T>& f, size_t off)
     return g;
 }
 
+// The inverse diagonal blocks as a dictionary of rows: node m uses row
+// idx[m], whose six symmetric entries (xx, yy, zz, yz, xz, xy) are
+// m[q][row * kMS].  Rows [0, nphase) belong to the nodes whose eight voxels
+// all have phase p (the same block for all of them); each remaining row to
+// one node at a phase boundary, in node order.
+template <typename T>
+struct MinvRows {
+    const uint32_t* idx;
+    T* m[6];
+};
+
 struct Tables {
     const double* coef;    // nphase * kCoefStride: C/16, packed
     const float* coef32;   // the same rounded to FP32 (mixed precision), or nullptr
@@ -133,13 +144,27 @@ OpGeom op_geometry(const Dims& d, int kz_hint, int tile = 0, int target_blocks =
 hipError_t launch_load(hipStream_t st, const Dims& d, const int32_t* phase, const double* sig,
                        double* const b[3], double* partials, double* out2 /* bnorm2, bref2 */,
                        int max_blocks);
-hipError_t launch_precond(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
-                          int identity, double* const minv[6]);
+// Preconditioner build in three steps.  count: boundary nodes (whose eight
+// voxels do not all share one phase) of each chunk of kPrecondChunk nodes
+// into counts[chunk]; the host takes the exclusive prefix sum.  fill: every
+// node's row (its phase, or nphase + offsets[chunk] + its rank in the chunk)
+// into M.idx, and the inverted block of each boundary node into its row.
+// table: rows [0, nphase).  identity: plain CG (I on nodes with stiffness).
+constexpr int kPrecondChunk = 4096;
+hipError_t launch_precond_count(hipStream_t st, const Dims& d, const int32_t* phase, int* counts);
+hipError_t launch_precond_fill(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
+                               int identity, int nphase, const int* offsets, uint32_t* idx,
+                               double* const rows[6]);
+hipError_t launch_precond_table(hipStream_t st, int nphase, const Tables& t, int identity,
+                                double* const rows[6]);
+// Dense SoA planes (6 x N, FP64) of the dictionary M.
+hipError_t launch_precond_expand(hipStream_t st, const Dims& d, const MinvRows<double>& M,
+                                 double* out);
 // The PCG sweeps exist for T = double (FP64 solve) and T = float (inner
 // solve of the mixed-precision refinement); dot products are FP64 in both.
 // norms2: device {||b||^2, ||b||_ref^2} of the run (zero-load test).
 template <typename T>
-hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, T* const minv[6],
+hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, const MinvRows<T>& M,
                            int fresh, int from_residual, Scalars* S, double* partials,
                            int max_blocks, const double* norms2);
 // The two iteration sweeps run a batch of nrhs right-hand sides in lockstep:
@@ -154,7 +179,7 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
                                      bool finalize = true);
 template <typename T>
 hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f, size_t rs,
-                                 int nrhs, T* const minv[6], Scalars* S, double* partials,
+                                 int nrhs, const MinvRows<T>& M, Scalars* S, double* partials,
                                  int max_blocks, bool finalize = true);
 template <typename T>
 hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& f, Scalars* S);
@@ -196,7 +221,7 @@ struct GroupMember {
     FieldsT<T> f;
     size_t rs;
     int nrhs;
-    T* minv[6];
+    MinvRows<T> minv;
     Scalars* S;
     double* partials;
     int upd_blocks;

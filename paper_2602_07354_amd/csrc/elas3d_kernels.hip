@@ -511,85 +511,188 @@ __global__ void __launch_bounds__(kBlock) load_kernel(Dims d, const int32_t* __r
     block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
 }
 
-// Inverse of the assembled diagonal 3x3 block (Eq. block_precond).  The
-// corner block of a phase is D + sx sy Oxy + sx sz Oxz + sy sz Oyz (four
-// symmetric pieces per phase, ordered xx, yy, zz, yz, xz, xy); nodes whose
-// eight voxels are all void get 0, plain CG gets I on the other nodes.
-__global__ void __launch_bounds__(kBlock) precond_kernel(Dims d, const int32_t* __restrict__ phase,
-                                                         const double* __restrict__ diag,
-                                                         const uint8_t* __restrict__ solid,
-                                                         int identity, double* m0, double* m1,
-                                                         double* m2, double* m3, double* m4,
-                                                         double* m5)
+// Inverse of the assembled diagonal 3x3 block (Eq. block_precond) of a node
+// from the phases of its eight voxels (voxel a = ax + 2 ay + 4 az lies at
+// (i - ax, j - ay, k - az)).  The corner block of a phase is
+// D + sx sy Oxy + sx sz Oxz + sy sz Oyz (four symmetric pieces per phase,
+// ordered xx, yy, zz, yz, xz, xy); nodes whose eight voxels are all void get
+// 0, plain CG gets I on the other nodes.
+__device__ __forceinline__ void block_inverse(const int (&ph)[8], const double* __restrict__ diag,
+                                              const uint8_t* __restrict__ solid, int identity, double (&r)[6])
 {
-    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        int i, j, k;
-        node_ijk(m, d, i, j, k);
-        double A[6] = {0, 0, 0, 0, 0, 0};
-        int nsolid = 0;
+    double A[6] = {0, 0, 0, 0, 0, 0};
+    int nsolid = 0;
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
-            const int ii = i - ax < 0 ? d.nx - 1 : i - ax;
-            const int jj = j - ay < 0 ? d.ny - 1 : j - ay;
-            const int kk = k - az < 0 ? d.nz - 1 : k - az;
-            const int p = phase[ii + d.nx * (jj + d.ny * kk)];
-            nsolid += solid[p];
-            const double* t = diag + (size_t)p * kDiagStride;
-            const double sxy = (ax == ay) ? 1.0 : -1.0;
-            const double sxz = (ax == az) ? 1.0 : -1.0;
-            const double syz = (ay == az) ? 1.0 : -1.0;
+    for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+        const int p = ph[a];
+        nsolid += solid[p];
+        const double* t = diag + (size_t)p * kDiagStride;
+        const double sxy = (ax == ay) ? 1.0 : -1.0;
+        const double sxz = (ax == az) ? 1.0 : -1.0;
+        const double syz = (ay == az) ? 1.0 : -1.0;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) A[q] += t[q] + sxy * t[6 + q] + sxz * t[12 + q] + syz * t[18 + q];
-        }
-        double r[6] = {0, 0, 0, 0, 0, 0};
-        if (nsolid > 0) {
-            if (identity) {
-                r[0] = r[1] = r[2] = 1.0;
-            } else {
-                // symmetric [a b c; b d e; c e f] with a=xx d=yy f=zz e=yz c=xz b=xy
-                const double a_ = A[0], d_ = A[1], f_ = A[2], e_ = A[3], c_ = A[4], b_ = A[5];
-                const double c00 = d_ * f_ - e_ * e_;
-                const double c01 = c_ * e_ - b_ * f_;
-                const double c02 = b_ * e_ - c_ * d_;
-                const double c11 = a_ * f_ - c_ * c_;
-                const double c12 = b_ * c_ - a_ * e_;
-                const double c22 = a_ * d_ - b_ * b_;
-                const double inv = 1.0 / (a_ * c00 + b_ * c01 + c_ * c02);
-                r[0] = c00 * inv;
-                r[1] = c11 * inv;
-                r[2] = c22 * inv;
-                r[3] = c12 * inv;
-                r[4] = c02 * inv;
-                r[5] = c01 * inv;
-            }
-        }
-        const size_t mq = (size_t)m * kMS;
-        m0[mq] = r[0];
-        m1[mq] = r[1];
-        m2[mq] = r[2];
-        m3[mq] = r[3];
-        m4[mq] = r[4];
-        m5[mq] = r[5];
+        for (int q = 0; q < 6; ++q) A[q] += t[q] + sxy * t[6 + q] + sxz * t[12 + q] + syz * t[18 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) r[q] = 0.0;
+    if (nsolid == 0) return;
+    if (identity) {
+        r[0] = r[1] = r[2] = 1.0;
+        return;
+    }
+    // symmetric [a b c; b d e; c e f] with a=xx d=yy f=zz e=yz c=xz b=xy
+    const double a_ = A[0], d_ = A[1], f_ = A[2], e_ = A[3], c_ = A[4], b_ = A[5];
+    const double c00 = d_ * f_ - e_ * e_;
+    const double c01 = c_ * e_ - b_ * f_;
+    const double c02 = b_ * e_ - c_ * d_;
+    const double c11 = a_ * f_ - c_ * c_;
+    const double c12 = b_ * c_ - a_ * e_;
+    const double c22 = a_ * d_ - b_ * b_;
+    const double inv = 1.0 / (a_ * c00 + b_ * c01 + c_ * c02);
+    r[0] = c00 * inv;
+    r[1] = c11 * inv;
+    r[2] = c22 * inv;
+    r[3] = c12 * inv;
+    r[4] = c02 * inv;
+    r[5] = c01 * inv;
+}
+
+// Phases of the eight voxels around node m; true when they are all the same.
+__device__ __forceinline__ bool node_phases(const Dims& d, const int32_t* __restrict__ phase, int m,
+                                            int (&ph)[8])
+{
+    int i, j, k;
+    node_ijk(m, d, i, j, k);
+    const int im = i == 0 ? d.nx - 1 : i - 1;
+    const int jm = j == 0 ? d.ny - 1 : j - 1;
+    const int km = k == 0 ? d.nz - 1 : k - 1;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int ii = (a & 1) ? im : i, jj = ((a >> 1) & 1) ? jm : j, kk = (a >> 2) ? km : k;
+        ph[a] = phase[ii + d.nx * (jj + d.ny * kk)];
+    }
+    bool same = true;
+#pragma unroll
+    for (int a = 1; a < 8; ++a) same = same && ph[a] == ph[0];
+    return same;
+}
+
+// Nodes of chunk blockIdx.x: base + s * kBlock + threadIdx.x, s = 0..15, so
+// that ranks in node order are wave ballots plus a running offset.
+static_assert(kPrecondChunk == 16 * kBlock, "a preconditioner chunk is 16 rows of a workgroup");
+
+__global__ void __launch_bounds__(kBlock) precond_count_kernel(Dims d, const int32_t* __restrict__ phase,
+                                                               int* __restrict__ counts)
+{
+    __shared__ int wc[kBlock / 64];
+    const size_t base = (size_t)blockIdx.x * kPrecondChunk;
+    int cnt = 0;
+    for (int s = 0; s < kPrecondChunk / kBlock; ++s) {
+        const size_t m = base + (size_t)s * kBlock + threadIdx.x;
+        int ph[8];
+        if (m < (size_t)d.n && !node_phases(d, phase, (int)m, ph)) ++cnt;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wc[w];
+        counts[blockIdx.x] = t;
     }
 }
 
-template <typename T>
-struct MinvT {
-    const T* m[6];
-};
+__global__ void __launch_bounds__(kBlock) precond_fill_kernel(Dims d, const int32_t* __restrict__ phase,
+                                                              const double* __restrict__ diag,
+                                                              const uint8_t* __restrict__ solid,
+                                                              int identity, int nphase,
+                                                              const int* __restrict__ offsets,
+                                                              uint32_t* __restrict__ idx,
+                                                              double* m0, double* m1, double* m2,
+                                                              double* m3, double* m4, double* m5)
+{
+    __shared__ int wc[kBlock / 64];
+    const size_t base = (size_t)blockIdx.x * kPrecondChunk;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int run = offsets[blockIdx.x];
+    for (int s = 0; s < kPrecondChunk / kBlock; ++s) {
+        const size_t m = base + (size_t)s * kBlock + threadIdx.x;
+        int ph[8];
+        const bool live = m < (size_t)d.n;
+        const bool bnd = live && !node_phases(d, phase, (int)m, ph);
+        const unsigned long long ball = __ballot(bnd);
+        if (lane == 0) wc[wid] = __popcll(ball);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            before += w < wid ? wc[w] : 0;
+            total += wc[w];
+        }
+        __syncthreads();  // wc is rewritten by the next row
+        if (live) {
+            if (bnd) {
+                const int row = nphase + run + before + __popcll(ball & below);
+                idx[m] = (uint32_t)row;
+                double r[6];
+                block_inverse(ph, diag, solid, identity, r);
+                const size_t mq = (size_t)row * kMS;
+                m0[mq] = r[0];
+                m1[mq] = r[1];
+                m2[mq] = r[2];
+                m3[mq] = r[3];
+                m4[mq] = r[4];
+                m5[mq] = r[5];
+            } else {
+                idx[m] = (uint32_t)ph[0];
+            }
+        }
+        run += total;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) precond_table_kernel(int nphase, const double* __restrict__ diag,
+                                                               const uint8_t* __restrict__ solid,
+                                                               int identity, double* m0, double* m1,
+                                                               double* m2, double* m3, double* m4,
+                                                               double* m5)
+{
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nphase) return;
+    const int ph[8] = {p, p, p, p, p, p, p, p};
+    double r[6];
+    block_inverse(ph, diag, solid, identity, r);
+    const size_t mq = (size_t)p * kMS;
+    m0[mq] = r[0];
+    m1[mq] = r[1];
+    m2[mq] = r[2];
+    m3[mq] = r[3];
+    m4[mq] = r[4];
+    m5[mq] = r[5];
+}
+
+__global__ void __launch_bounds__(kBlock) precond_expand_kernel(Dims d, MinvRows<double> M, double* out)
+{
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
+        const size_t row = (size_t)M.idx[m] * kMS;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out[(size_t)q * d.n + m] = M.m[q][row];
+    }
+}
 
 // Start (or restart) of a PCG run: g = b (or the residual already in g),
 // z = M^-1 g, current direction h = 0, w = 0 on a fresh start.  Dots in FP64.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, MinvT<T> M, int fresh,
+__global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, MinvRows<T> M, int fresh,
                                                           int from_residual, double* partials,
                                                           int stride)
 {
     double acc[2] = {0.0, 0.0};
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
         const int mv = m * kVS;
-        const size_t mq = (size_t)m * kMS;
+        const size_t mq = (size_t)M.idx[m] * kMS;
         T g[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -621,7 +724,7 @@ __global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, 
 // (by value: the fields stay in scalar registers)
 template <typename T>
 __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, const size_t rs, const int nrhs,
-                                            const MinvT<T> M, const Scalars* S, double* partials,
+                                            const MinvRows<T> M, const Scalars* S, double* partials,
                                             const int stride, const int bid, const int nblk)
 {
     unsigned active = 0;
@@ -642,9 +745,10 @@ __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, co
     // strength-reducing every field address into its own 64-bit induction
     // variable, which triples the register count
     for (int m = bid * kBlock + threadIdx.x; m < d.n; m += (unsigned)nblk * kBlock) {
+        const size_t mq = (size_t)M.idx[m] * kMS;
         T mm[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) mm[q] = M.m[q][(size_t)m * kMS];
+        for (int q = 0; q < 6; ++q) mm[q] = M.m[q][mq];
         const T xx = mm[0], yy = mm[1], zz = mm[2], yz = mm[3], xz = mm[4], xy = mm[5];
 #pragma unroll
         for (int r = 0; r < kMaxRhs; ++r) {
@@ -670,7 +774,7 @@ __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, co
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<T> f, size_t rs,
-                                                                int nrhs, MinvT<T> M,
+                                                                int nrhs, MinvRows<T> M,
                                                                 const Scalars* S, double* partials,
                                                                 int stride)
 {
@@ -771,6 +875,9 @@ struct OpArgs {
 #ifndef E3D_OP_MIN_WAVES
 #define E3D_OP_MIN_WAVES 1
 #endif
+#ifndef E3D_W_REDIRECT
+#define E3D_W_REDIRECT 1
+#endif
 
 // Workgroup lbr (logical, of nblocks) of an operator sweep over a.
 template <int TX, int TY, int MODE, typename T>
@@ -837,6 +944,15 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
         hoff = ((i0 - 1 + hx + nx) % nx) + nx * ((j0 - 1 + hy + ny) % ny);
     }
     const int oslot = (ty + 1) * LX + (tx + 1);
+    // w is needed only where the lane writes it: lanes that own no output
+    // node load the w of the nearest owned node of the tile instead (a line
+    // another lane of the workgroup loads anyway), so the overlap rows and
+    // columns of neighbouring tiles cost no w traffic
+    int wown = own;
+    if (E3D_W_REDIRECT && !out_ok) {
+        const int wi = min(gi, min(i0 + TX - 2, nx - 1)), wj = min(gj, min(j0 + TY - 2, ny - 1));
+        wown = wi + nx * wj;
+    }
 
     // Raw values of the next node plane, prefetched one step ahead and only
     // combined (h_new = z + gamma h_old, or x + xd) when the step that needs
@@ -849,11 +965,12 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
         const int base = kw * plane;
         const int io = (base + own) * kVS, ih = (base + hoff) * kVS;
         if constexpr (FUSED) {
+            const int iw = (base + wown) * kVS;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 rh[c] = hold[c][io];
                 rz[c] = a.z[c][io];
-                rw[c] = a.w[c][io];
+                rw[c] = a.w[c][iw];
                 hh[c] = hold[c][ih];
                 hz[c] = a.z[c][ih];
             }
@@ -1075,7 +1192,7 @@ struct UpdArgs {
     FieldsT<T> f;
     size_t rs;
     int nrhs;
-    MinvT<T> M;
+    MinvRows<T> M;
     const Scalars* S;
     double* partials;
 };
@@ -1394,30 +1511,47 @@ hipError_t launch_load(hipStream_t st, const Dims& d, const int32_t* phase, cons
     return hipGetLastError();
 }
 
-hipError_t launch_precond(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
-                          int identity, double* const minv[6])
+hipError_t launch_precond_count(hipStream_t st, const Dims& d, const int32_t* phase, int* counts)
+{
+    const int nb = (int)(((size_t)d.n + kPrecondChunk - 1) / kPrecondChunk);
+    hipLaunchKernelGGL(precond_count_kernel, dim3(nb), dim3(kBlock), 0, st, d, phase, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_fill(hipStream_t st, const Dims& d, const int32_t* phase, const Tables& t,
+                               int identity, int nphase, const int* offsets, uint32_t* idx,
+                               double* const rows[6])
+{
+    const int nb = (int)(((size_t)d.n + kPrecondChunk - 1) / kPrecondChunk);
+    hipLaunchKernelGGL(precond_fill_kernel, dim3(nb), dim3(kBlock), 0, st, d, phase, t.diag, t.solid,
+                       identity, nphase, offsets, idx, rows[0], rows[1], rows[2], rows[3], rows[4],
+                       rows[5]);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_table(hipStream_t st, int nphase, const Tables& t, int identity,
+                                double* const rows[6])
+{
+    const int nb = (nphase + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(precond_table_kernel, dim3(nb), dim3(kBlock), 0, st, nphase, t.diag, t.solid,
+                       identity, rows[0], rows[1], rows[2], rows[3], rows[4], rows[5]);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_expand(hipStream_t st, const Dims& d, const MinvRows<double>& M, double* out)
 {
     const int nb = sweep_blocks(d.n, 8192);
-    hipLaunchKernelGGL(precond_kernel, dim3(nb), dim3(kBlock), 0, st, d, phase, t.diag, t.solid,
-                       identity, minv[0], minv[1], minv[2], minv[3], minv[4], minv[5]);
+    hipLaunchKernelGGL(precond_expand_kernel, dim3(nb), dim3(kBlock), 0, st, d, M, out);
     return hipGetLastError();
 }
 
 template <typename T>
-static MinvT<T> mk_minv(T* const minv[6])
-{
-    MinvT<T> M;
-    for (int q = 0; q < 6; ++q) M.m[q] = minv[q];
-    return M;
-}
-
-template <typename T>
-hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, T* const minv[6],
+hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, const MinvRows<T>& M,
                            int fresh, int from_residual, Scalars* S, double* partials,
                            int max_blocks, const double* norms2)
 {
     const int nb = sweep_blocks(d.n, max_blocks);
-    hipLaunchKernelGGL(pcg_init_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, mk_minv(minv), fresh,
+    hipLaunchKernelGGL(pcg_init_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, M, fresh,
                        from_residual, partials, nb);
     hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_INIT,
                        (const double*)partials, nb, nb, S, (double*)nullptr, norms2, 0);
@@ -1460,12 +1594,12 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
 
 template <typename T>
 hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f, size_t rs,
-                                 int nrhs, T* const minv[6], Scalars* S, double* partials,
+                                 int nrhs, const MinvRows<T>& M, Scalars* S, double* partials,
                                  int max_blocks, bool finalize)
 {
     const int nb = sweep_blocks(d.n, max_blocks);
     hipLaunchKernelGGL(update_precond_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, rs, nrhs,
-                       mk_minv(minv), (const Scalars*)S, partials, nb);
+                       M, (const Scalars*)S, partials, nb);
     if (!finalize) return hipGetLastError();
     hipLaunchKernelGGL(finalize_kernel<2>, dim3(nrhs), dim3(kFinThreads), 0, st, (int)FIN_UPDATE,
                        (const double*)partials, nb, nb, S, (double*)nullptr, (const double*)nullptr,
@@ -1567,7 +1701,7 @@ hipError_t group_prepare(hipStream_t st, const GroupMember<T>* m, int n, char* s
         u.f = g.f;
         u.rs = g.rs;
         u.nrhs = g.nrhs;
-        u.M = mk_minv(g.minv);
+        u.M = g.minv;
         u.S = g.S;
         u.partials = g.partials;
         up[i] = u;
@@ -1610,14 +1744,14 @@ hipError_t launch_group_iteration(hipStream_t st, const GroupPlan& p)
 }
 
 #define E3D_INSTANTIATE(T)                                                                          \
-    template hipError_t launch_pcg_init<T>(hipStream_t, const Dims&, const FieldsT<T>&, T* const[6],  \
+    template hipError_t launch_pcg_init<T>(hipStream_t, const Dims&, const FieldsT<T>&, const MinvRows<T>&, \
                                            int, int, Scalars*, double*, int, const double*);         \
     template hipError_t launch_direction_operator<T>(hipStream_t, const Dims&, const OpGeom&,         \
                                                      const int32_t*, const Tables&,                  \
                                                      const FieldsT<T>&, size_t, int, Scalars*,        \
                                                      double*, bool);                                 \
     template hipError_t launch_update_precond<T>(hipStream_t, const Dims&, const FieldsT<T>&, size_t, \
-                                                 int, T* const[6], Scalars*, double*, int, bool);    \
+                                                 int, const MinvRows<T>&, Scalars*, double*, int, bool);    \
     template hipError_t launch_final_update<T>(hipStream_t, const Dims&, const FieldsT<T>&, Scalars*);     \
     template size_t group_plan_bytes<T>(int, int);                                                   \
     template hipError_t group_prepare<T>(hipStream_t, const GroupMember<T>*, int, char*, char*,       \

@@ -55,9 +55,13 @@ struct elas3d_ctx {
     // so that every field of RHS r lies r*21N after RHS 0's.  Otherwise the
     // RHS keep [w | b] (6N each) and share one 15N work area after them.
     double* bundle64 = nullptr;
-    double* minv = nullptr;  // 6N
+    // M^-1 as a dictionary: row of each node, and mrows rows of six entries
+    // (one per phase, then one per phase-boundary node)
+    uint32_t* midx = nullptr;
+    size_t mrows = 0;
+    double* minv = nullptr;
     // mixed precision: FP32 g, z, h0, h1, Ah, d (18N floats per work slot),
-    // M^-1 (6N), table
+    // M^-1 rows, table
     float* bundle32 = nullptr;
     float* minv32 = nullptr;
     float* coef32 = nullptr;
@@ -113,9 +117,15 @@ struct elas3d_ctx {
         }
         return f;
     }
-    void minv_planes(double* out[6]) const
+    // entry q of the M^-1 rows starting at base
+    template <typename P>
+    P* mcomp(P* base, int q) const { return base + e3d::comp_offset(q, mrows); }
+    e3d::MinvRows<double> minv_rows() const
     {
-        for (int q = 0; q < 6; ++q) out[q] = comp(minv, q);
+        e3d::MinvRows<double> M;
+        M.idx = midx;
+        for (int q = 0; q < 6; ++q) M.m[q] = mcomp(minv, q);
+        return M;
     }
     e3d::FieldsT<float> fields32(int rhs)
     {
@@ -132,9 +142,12 @@ struct elas3d_ctx {
         }
         return f;
     }
-    void minv32_planes(float* out[6]) const
+    e3d::MinvRows<float> minv32_rows() const
     {
-        for (int q = 0; q < 6; ++q) out[q] = comp(minv32, q);
+        e3d::MinvRows<float> M;
+        M.idx = midx;
+        for (int q = 0; q < 6; ++q) M.m[q] = mcomp(minv32, q);
+        return M;
     }
     e3d::Tables tables() const { return e3d::Tables{coef, coef32, diag, solid}; }
 };
@@ -169,7 +182,7 @@ struct CaseResult {
 // Start a PCG run of RHS r (device scalars and the init sweep), enqueued on
 // the context's stream through pinned staging slot r of c->hS.
 template <typename T>
-int start_run(elas3d_ctx* c, int r, const FieldsT<T>& f, T* const M[6], double tol, int maxit, int mode,
+int start_run(elas3d_ctx* c, int r, const FieldsT<T>& f, const e3d::MinvRows<T>& M, double tol, int maxit, int mode,
               int it0, int fresh, int from_residual, const double* norms2);
 // Mark RHS r finished for the sweeps that follow (enqueued, staging slot r).
 int park(elas3d_ctx* c, int r, const Scalars& fin);

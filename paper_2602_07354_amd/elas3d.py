@@ -91,6 +91,7 @@ class Info(ctypes.Structure):
         ("fp64_fallback", ctypes.c_int32 * _R),
         ("op_tile", ctypes.c_int32 * 3),
         ("update_blocks", ctypes.c_int32),
+        ("precond_rows", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -112,6 +113,7 @@ class Info(ctypes.Structure):
             "fp64_fallback": list(self.fp64_fallback[:n]),
             "op_tile": list(self.op_tile),
             "update_blocks": self.update_blocks,
+            "precond_rows": self.precond_rows,
         }
 
 
