@@ -33,9 +33,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 COUNTERS = os.path.join(ROOT, "profiles", "op_kernel_poly500_fp64_counters.txt")
 KERNEL_SOURCES = ("paper_2602_07354_amd/csrc/elas3d_kernels.hip", "paper_2602_07354_amd/csrc/elas3d_internal.h")
-# Algorithmic HBM bytes per node of the fused direction+operator sweep:
-# read z, h_old, w and write h_new, w, Ah (6 x 3 doubles) plus the phase id.
-OPERATOR_BYTES_PER_NODE_FP64 = 6 * 24 + 4
+# Algorithmic HBM bytes per node of the fused direction+operator sweep, the
+# mean of its two alternating forms: read z, h_old and the phase id, write
+# h_new and Ah (4 x 3 values + 4 bytes); every other iteration it also pays
+# the two steps w owes (read w and the older direction, write w: 3 x 3
+# values).  Per launch: 5.5 vectors + phase.
+OPERATOR_BYTES_PER_NODE_FP64 = (4 * 24 + 4 + 7 * 24 + 4) / 2  # 136
+OPERATOR_BYTES_PER_NODE_FP32 = (4 * 12 + 4 + 7 * 12 + 4) / 2  # 70
 
 WORKLOAD_TEXT = {
     "poly500": "500^3 periodic Voronoi polycrystal, 8000 rotated cubic SS316L grains "
@@ -262,7 +266,7 @@ def main():
     op_ms = t_op / max(1, n_op)
     # a batched launch sweeps every RHS still running: RHS-sweeps per launch
     rhs_per_launch = (sum(iters) / max(1, n_op)) if args.batched else 1.0
-    op_bytes = (OPERATOR_BYTES_PER_NODE_FP64 if head == "fp64" else 6 * 12 + 4) * ms.n * rhs_per_launch
+    op_bytes = (OPERATOR_BYTES_PER_NODE_FP64 if head == "fp64" else OPERATOR_BYTES_PER_NODE_FP32) * ms.n * rhs_per_launch
     achieved = op_bytes / (op_ms / 1e3) / 1e9
     tile = recs[0][1]["op_tile"]
     traffic = (measured_traffic(ms.meta.get("workload"), tile) if head == "fp64" and nrhs == 1

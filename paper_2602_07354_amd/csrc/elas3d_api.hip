@@ -266,10 +266,12 @@ std::map<std::array<int, 6>, std::pair<e3d::OpGeom, int>> g_tune_cache;
 
 // Time every candidate geometry of the two iteration sweeps on the live
 // fields and keep the fastest.  Runs right after the start of a run, where
-// lambda = gamma = 0 and h_old = 0: the operator sweep then writes
-// h_new = z (which the first iteration writes again) and Ah, leaves w as it
-// is, and the update sweep leaves g as it is and rewrites z = M^-1 g; no
-// finalize kernel runs, so the scalars are untouched.
+// lambda = gamma = 0, h_old = 0 and w owes nothing: the operator sweep then
+// writes h_new = z (which the first iteration writes again) and Ah and
+// leaves w alone, and the update sweep leaves g as it is and rewrites
+// z = M^-1 g; no finalize kernel runs, so the scalars are untouched.  (The
+// sweeps that also pay w's owed steps, every other iteration, are not
+// timed.)
 template <typename T>
 int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const e3d::MinvRows<T>& M)
 {
@@ -1001,19 +1003,20 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
     auto t1 = std::chrono::steady_clock::now();
     if (info) {
         info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
-        // two fused sweeps: direction+operator (read z, h, w, phase; write h, w, Ah)
-        // and update+precondition (read g, Ah, the M^-1 row index and the
-        // rows of phase-boundary nodes; write g, z); per RHS: fused sweep 6
-        // vectors + phase, update sweep 4 vectors; M^-1 once per node for a
-        // batch (the nphase shared rows stay in cache)
+        // two fused sweeps: direction+operator (read z, h_old, phase; write
+        // h_new, Ah; every other iteration also read w and the older h and
+        // write w) and update+precondition (read g, Ah, the M^-1 row index
+        // and the rows of phase-boundary nodes; write g, z); per RHS: fused
+        // sweep 5.5 vectors + phase on average, update sweep 4 vectors; M^-1
+        // once per node for a batch (the nphase shared rows stay in cache)
         const int rb = ctx->batched() ? nrhs : 1;
         const double N = (double)ctx->N();
         const double nbnd = (double)(ctx->mrows - (size_t)ctx->nphase);
         info->precond_rows = (int64_t)ctx->mrows;
         if (ctx->opt.precision == ELAS3D_PREC_MIXED)
-            info->bytes_per_iter = N * rb * ((6 * 12.0 + 4.0) + 4 * 12.0) + 4.0 * N + 24.0 * nbnd;
+            info->bytes_per_iter = N * rb * ((5.5 * 12.0 + 4.0) + 4 * 12.0) + 4.0 * N + 24.0 * nbnd;
         else
-            info->bytes_per_iter = N * rb * ((6 * 24.0 + 4.0) + 4 * 24.0) + 4.0 * N + 48.0 * nbnd;
+            info->bytes_per_iter = N * rb * ((5.5 * 24.0 + 4.0) + 4 * 24.0) + 4.0 * N + 48.0 * nbnd;
     }
     return worst;
 }

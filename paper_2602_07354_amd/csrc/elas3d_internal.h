@@ -48,20 +48,25 @@ struct Scalars {
     double gg;      // z.g of the current iterate
     double gg0;     // z0.g0 (reference of the paper's criterion)
     double hAh;     // h.Ah of the current direction
-    double lambda;  // step size; applied to w lazily by the next direction sweep
+    double lambda;  // step size; applied to w lazily by a later direction sweep
     double gamma;   // Fletcher-Reeves coefficient for the next direction
     double rr;      // g.g
     double bnorm2;  // ||b||^2 of the case
     double bref2;   // sum_e ||K_e u^E_e||^2 (scale for the zero-load test)
     double tol;
     double rr_true;  // ||A w + b||^2 from the last residual sweep
+    double lambda_prev;  // step size of the older owed step when pending == 2
     int it;          // iterations done
     int maxit;       // iteration cap of this run
     int done;        // nonzero: every later sweep returns at once
     int status;      // 0 converged, 1 not converged, 2 breakdown
     int mode;        // 0 residual criterion, 1 paper criterion
     int cur;         // which of the two direction buffers holds the current h
-    int pending;     // 1 while w still owes -lambda*h of the last iteration
+    // steps w still owes: 0; 1: -lambda h (h in buffer cur); 2: first
+    // -lambda_prev h (h in buffer cur ^ 1), then -lambda h (buffer cur).
+    // Direction sweeps pay both owed steps when there are two and none
+    // otherwise, so w is read and written every other iteration.
+    int pending;
     int pad;
 };
 

@@ -378,6 +378,7 @@ __device__ __forceinline__ void finalize_body(int kind, const double* partials, 
         S->bnorm2 = norms[0];
         S->bref2 = norms[1];
         S->lambda = 0.0;
+        S->lambda_prev = 0.0;
         S->gamma = 0.0;
         S->cur = 0;
         S->pending = 0;
@@ -395,13 +396,23 @@ __device__ __forceinline__ void finalize_body(int kind, const double* partials, 
     if (kind == FIN_DIRECTION) {
         const double hAh = tot[0];
         S->hAh = hAh;
-        S->pending = 0;  // the sweep applied the previous step to w
-        S->cur ^= 1;     // the sweep wrote the new direction to the other buffer
+        // the sweep wrote the new direction to the other buffer; it paid the
+        // owed steps if there were two and left a single one owed
+        const int owed = S->pending;
         if (!(hAh > 0.0) || !isfinite(hAh)) {
             S->status = 2;
             S->done = 1;
-            S->lambda = 0.0;
+            if (owed != 1) {
+                S->pending = 0;
+                S->lambda = 0.0;
+                S->cur ^= 1;
+            }  // else lambda h of buffer cur stays owed, for the final update
         } else {
+            if (owed == 1)
+                S->lambda_prev = S->lambda;  // now in buffer cur ^ 1
+            else
+                S->pending = 0;
+            S->cur ^= 1;
             S->lambda = S->gg / hAh;
         }
         return;
@@ -410,7 +421,7 @@ __device__ __forceinline__ void finalize_body(int kind, const double* partials, 
         const double gg_new = tot[0];
         const double rr = tot[NV > 1 ? 1 : 0];
         S->it += 1;
-        S->pending = 1;
+        S->pending += 1;
         S->rr = rr;
         const double gg_last = S->gg;
         S->gg = gg_new;
@@ -720,7 +731,7 @@ __global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, 
 
 // Algorithm 2, C-D for a batch of RHS sharing M^-1 (loaded once per node):
 // g -= lambda Ah, z = M^-1 g, partials z.g and g.g (FP64) per RHS.
-// (w -= lambda h is deferred to the next direction sweep, which reads h anyway.)
+// (w -= lambda h is deferred to a later direction sweep, which reads h anyway.)
 // (by value: the fields stay in scalar registers)
 template <typename T>
 __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, const size_t rs, const int nrhs,
@@ -781,16 +792,22 @@ __global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<
     update_body<T>(d, f, rs, nrhs, M, S, partials, stride, blockIdx.x, gridDim.x);
 }
 
-// The step size of the last iteration still owed to w.
+// The steps still owed to w at the end of a run, oldest first.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) final_update_kernel(Dims d, FieldsT<T> f, const Scalars* S)
 {
-    if (!S->pending) return;
-    const T lam = (T)S->lambda;
+    const int owed = S->pending;
+    if (!owed) return;
+    const T lam = (T)S->lambda, lamp = (T)S->lambda_prev;
     T* const* h = S->cur ? f.h1 : f.h0;
+    T* const* ho = S->cur ? f.h0 : f.h1;
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) f.w[c][m * kVS] = fma(-lam, h[c][m * kVS], f.w[c][m * kVS]);
+        for (int c = 0; c < 3; ++c) {
+            T w = f.w[c][m * kVS];
+            if (owed == 2) w = fma(-lamp, ho[c][m * kVS], w);
+            f.w[c][m * kVS] = fma(-lam, h[c][m * kVS], w);
+        }
     }
 }
 
@@ -869,25 +886,40 @@ struct OpArgs {
 // OP_APPLY : y = A x (+ add) in FP64, optional ||y||^2 partials.
 // OP_FUSED : Algorithm 2 steps E and A of one iteration in a single sweep, in
 //            T: h_new = z + gamma h_old (written to the other direction
-//            buffer), w -= lambda h_old (the previous step, deferred),
-//            Ah = A h_new and the partial h_new.Ah (FP64).
+//            buffer), Ah = A h_new and the partial h_new.Ah (FP64); when w
+//            owes two steps (WPAY), also w -= lambda_prev h_prev (the
+//            buffer's old content) and w -= lambda h_old, in that order.
 // OP_REFINE: y = A (x + xd) + add in FP64, stored as FP32, ||y||^2.
 #ifndef E3D_OP_MIN_WAVES
 #define E3D_OP_MIN_WAVES 1
 #endif
+
 #ifndef E3D_W_REDIRECT
 #define E3D_W_REDIRECT 1
 #endif
 
+// Arithmetic type of an operator sweep.
+template <int MODE, typename T>
+using OpReal = typename std::conditional<MODE == OP_FUSED, T, double>::type;
+
+// LDS of an operator-sweep workgroup: a node plane with its halo row and
+// column, and the in-plane force exchange.
+template <int TX, int TY, typename R>
+struct OpShared {
+    R sn[3][(TY + 1) * (TX + 1)];
+    R sf[3][3][TX * TY];
+};
+
 // Workgroup lbr (logical, of nblocks) of an operator sweep over a.
-template <int TX, int TY, int MODE, typename T>
-__device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nblocks)
+template <int TX, int TY, int MODE, typename T, bool WPAY>
+__device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nblocks,
+                                        OpShared<TX, TY, OpReal<MODE, T>>& sh)
 {
     constexpr bool FUSED = MODE == OP_FUSED;
-    using R = typename std::conditional<FUSED, T, double>::type;  // arithmetic type
+    using R = OpReal<MODE, T>;
     constexpr int NT = TX * TY, LX = TX + 1, LY = TY + 1;
-    __shared__ R sn[3][LY * LX];
-    __shared__ R sf[3][3][NT];
+    auto& sn = sh.sn;
+    auto& sf = sh.sf;
 
     // logical workgroup -> (RHS, tile block): the tiles of one RHS are a
     // contiguous range in the XCD-local order, laid out as in a single-RHS
@@ -898,7 +930,7 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
     const int ntb = nblocks / nr;  // tile blocks per RHS
     const int rhs = lbr / ntb;
     const int lb = lbr - rhs * ntb;
-    R gam = R(0), lam = R(0);
+    R gam = R(0), lam = R(0), lamp = R(0);
     const T* hold[3] = {nullptr, nullptr, nullptr};
     T* hnew[3] = {nullptr, nullptr, nullptr};
     if constexpr (FUSED) {
@@ -906,6 +938,7 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
         if (S->done) return;
         gam = (R)S->gamma;
         lam = (R)S->lambda;
+        lamp = (R)S->lambda_prev;
         const int cur = S->cur;
         const size_t off = (size_t)rhs * a.rs;
 #pragma unroll
@@ -953,13 +986,21 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
         const int wi = min(gi, min(i0 + TX - 2, nx - 1)), wj = min(gj, min(j0 + TY - 2, ny - 1));
         wown = wi + nx * wj;
     }
+    // h of two iterations back, paid to w: the old content of the buffer
+    // this sweep overwrites, read by its owner lane before the overwrite.
+    // Lanes without an output node read the current direction instead (a
+    // buffer nothing writes during the sweep; the value is not used): the
+    // two buffers lie the same distance apart in every component (checked
+    // at launch), so one offset per lane selects the buffer.
+    int poff = 0;
+    if constexpr (WPAY) poff = out_ok ? 0 : (int)(hold[0] - hnew[0]);
 
     // Raw values of the next node plane, prefetched one step ahead and only
     // combined (h_new = z + gamma h_old, or x + xd) when the step that needs
     // them starts, so the loads stay in flight across a whole element layer.
     // All loads are unconditional: the wait counts of the compiler then never
     // make the contraction wait on a prefetch.
-    R rz[3], rh[3], rw[3], hz[3], hh[3];
+    R rz[3], rh[3], rw[3], rp[3], hz[3], hh[3];
     auto fetch = [&](int kk) {
         const int kw = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
         const int base = kw * plane;
@@ -970,7 +1011,10 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
             for (int c = 0; c < 3; ++c) {
                 rh[c] = hold[c][io];
                 rz[c] = a.z[c][io];
-                rw[c] = a.w[c][iw];
+                if constexpr (WPAY) {
+                    rw[c] = a.w[c][iw];
+                    rp[c] = hnew[c][(ptrdiff_t)iw + poff];
+                }
                 hh[c] = hold[c][ih];
                 hz[c] = a.z[c][ih];
             }
@@ -1047,7 +1091,7 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     hnew[c][idx] = ov[c];
-                    a.w[c][idx] = fma(-lam, rh[c], rw[c]);
+                    if constexpr (WPAY) a.w[c][idx] = fma(-lam, rh[c], fma(-lamp, rp[c], rw[c]));
                 }
             }
         }
@@ -1125,10 +1169,27 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
     }
 }
 
+// One operator-sweep workgroup; a fused sweep pays w's owed steps when its
+// RHS owes two (the same decision for the whole workgroup).
+template <int TX, int TY, int MODE, typename T>
+__device__ __forceinline__ void op_dispatch(const OpArgs<T>& a, const int lbr, const int nblocks)
+{
+    __shared__ OpShared<TX, TY, OpReal<MODE, T>> sh;
+    if constexpr (MODE == OP_FUSED) {
+        const int ntb = nblocks / a.nrhs;
+        if (a.S[lbr / ntb].pending == 2)
+            op_body<TX, TY, MODE, T, true>(a, lbr, nblocks, sh);
+        else
+            op_body<TX, TY, MODE, T, false>(a, lbr, nblocks, sh);
+    } else {
+        op_body<TX, TY, MODE, T, false>(a, lbr, nblocks, sh);
+    }
+}
+
 template <int TX, int TY, int MODE, typename T>
 __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> a)
 {
-    op_body<TX, TY, MODE, T>(a, xcd_local_block(), gridDim.x);
+    op_dispatch<TX, TY, MODE, T>(a, xcd_local_block(), gridDim.x);
 }
 
 // Copy of a work-list entry held in scalar registers: the entry is the same
@@ -1183,7 +1244,7 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_group_kernel(OpPa
 {
     const int b = xcd_local_block();
     const int p = find_entry(pk.first, pk.n, b);
-    op_body<TX, TY, OP_FUSED, T>(pk.m[p], b - pk.first[p], pk.first[p + 1] - pk.first[p]);
+    op_dispatch<TX, TY, OP_FUSED, T>(pk.m[p], b - pk.first[p], pk.first[p + 1] - pk.first[p]);
 }
 
 template <typename T>
@@ -1558,11 +1619,23 @@ hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, c
     return hipGetLastError();
 }
 
+// The fused sweep selects a direction buffer per lane by one element offset:
+// h1 must lie the same distance (under 2^31 elements) from h0 in every
+// component.
+template <typename T>
+static bool direction_buffers_ok(const FieldsT<T>& f)
+{
+    const ptrdiff_t dh = f.h1[0] - f.h0[0];
+    if (dh <= -((ptrdiff_t)1 << 31) || dh >= ((ptrdiff_t)1 << 31)) return false;
+    return f.h1[1] - f.h0[1] == dh && f.h1[2] - f.h0[2] == dh;
+}
+
 template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
                                      const int32_t* phase, const Tables& t, const FieldsT<T>& f,
                                      size_t rs, int nrhs, Scalars* S, double* partials, bool finalize)
 {
+    if (!direction_buffers_ok(f)) return hipErrorInvalidValue;
     OpArgs<T> a = {};
     a.d = d;
     a.tiles_x = g.tiles_x;
@@ -1665,6 +1738,7 @@ hipError_t group_prepare(hipStream_t st, const GroupMember<T>* m, int n, char* s
     for (int i = 0; i < n; ++i) {
         const GroupMember<T>& g = m[i];
         if (g.g.tile != 0) return hipErrorInvalidValue;  // groups run workgroup shape 0
+        if (!direction_buffers_ok(g.f)) return hipErrorInvalidValue;
         OpArgs<T> a = {};
         a.d = g.d;
         a.tiles_x = g.g.tiles_x;
