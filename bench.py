@@ -223,10 +223,12 @@ def main():
         for _ in range(args.warmup):
             step(None, precision)
         torch.cuda.synchronize()
+        print(f"# {precision}: warm-up done", file=sys.stderr, flush=True)
         recs = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step(recs, precision)
+            print(f"# {precision}: step done, {sum(recs[-1][1]['iters'])} iterations", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         return recs, time.perf_counter() - t0
 
@@ -308,6 +310,7 @@ def main():
         "mixed_speedup_time_to_solution": (
             round(float(np.mean([r[1]["t_solve_s"] for r in recs])) /
                   float(np.mean(mixed["time_to_solution_s"])), 3) if mixed else None),
+        "precond_rows": recs[0][1]["precond_rows"],
         "operator_ms_avg": round(op_ms, 4),
         "update_ms_avg": round(t_up / max(1, n_up), 4),
         "roofline": {
