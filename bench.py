@@ -45,6 +45,8 @@ WORKLOAD_TEXT = {
     "poly500": "500^3 periodic Voronoi polycrystal, 8000 rotated cubic SS316L grains "
                "(C11/C12/C44 = 206/133/119 GPa), 2% pores (spheres, oblate 4:4:1, z-prolate "
                "keyholes in thirds), eps_zz = 1e-3",
+    "poly800": "800^3 periodic Voronoi polycrystal, 32768 rotated cubic SS316L grains (the 500^3 grain "
+               "density), 2% pores (spheres, oblate 4:4:1, z-prolate keyholes in thirds), eps_zz = 1e-3",
     "poly300": "300^3 periodic Voronoi polycrystal, 3000 grains, 0.5% spheres + 0.5% oblate pores",
     "poly100": "100^3 periodic Voronoi polycrystal, 500 grains, 1% spherical pores, eps_xx = 1e-3",
     "eshelby20": "20^3 isotropic matrix with a stiff spherical inclusion, eps_xx = 1e-3",
