@@ -97,7 +97,7 @@ typedef struct elas3d_options {
                                   when timing is on); default 1                      */
     int32_t autotune;          /* nonzero: before the first iteration of each
                                   precision, time the candidate workgroup shapes
-                                  (32x8, 16x16, 64x4, 32x16 lanes) and z-chunkings
+                                  (32x8, 16x16, 64x4, 32x16, 64x8 lanes) and z-chunkings
                                   (about 2048 to 16384 workgroups) of the
                                   direction+operator sweep and
                                   the grid of the update sweep on the live problem,
@@ -108,7 +108,7 @@ typedef struct elas3d_options {
                                   Default 0                                          */
     int32_t tile;              /* workgroup shape of the direction+operator sweep
                                   when not autotuned: 0 = 32x8 lanes (default),
-                                  1 = 16x16, 2 = 64x4, 3 = 32x16                     */
+                                  1 = 16x16, 2 = 64x4, 3 = 32x16, 4 = 64x8          */
 } elas3d_options;
 
 typedef struct elas3d_info {

@@ -126,11 +126,11 @@ struct Tables {
 // Workgroup shapes (lanes in x and y) of the tiled operator sweep.  Shape 0
 // is the default of every sweep; the fused direction + operator sweep can be
 // autotuned over all of them.
-constexpr int kNumTiles = 4;
+constexpr int kNumTiles = 5;
 struct TileShape {
     int tx, ty;
 };
-constexpr TileShape kTileShapes[kNumTiles] = {{32, 8}, {16, 16}, {64, 4}, {32, 16}};
+constexpr TileShape kTileShapes[kNumTiles] = {{32, 8}, {16, 16}, {64, 4}, {32, 16}, {64, 8}};
 
 // Kernel launch geometry of the tiled operator sweep.
 struct OpGeom {

@@ -1290,6 +1290,7 @@ hipError_t launch_op_tiled(hipStream_t st, const OpGeom& g, unsigned grid, const
         E3D_OP_CASE(1)
         E3D_OP_CASE(2)
         E3D_OP_CASE(3)
+        E3D_OP_CASE(4)
         default:
             return hipErrorInvalidValue;
     }

@@ -34,7 +34,7 @@ CONV_RESIDUAL, CONV_PAPER = 0, 1
 PRECOND_BLOCK_JACOBI, PRECOND_NONE = 0, 1
 MAX_RHS = 6
 # workgroup shapes (lanes in x, y) of the direction+operator sweep, by options.tile
-TILE_SHAPES = ((32, 8), (16, 16), (64, 4), (32, 16))
+TILE_SHAPES = ((32, 8), (16, 16), (64, 4), (32, 16), (64, 8))
 # doubles per pore of elas3d_carve_pores: centre 3, semi-axes 3, R row-major 9
 PORE_STRIDE = 15
 

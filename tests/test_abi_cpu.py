@@ -94,7 +94,7 @@ def test_setup_rejects_bad_options(E):
     shape, phase, C, strain = _good()
     for kw in ({"precision": 7}, {"convergence": 3}, {"preconditioner": -1},
                {"poll_interval": -2}, {"hbm_budget_bytes": -1.0}, {"inner_tol": 2.0},
-               {"tile": 4}, {"tile": -1}):
+               {"tile": 5}, {"tile": -1}):
         with pytest.raises(E.Elas3dError) as ei:
             E.setup(shape, phase, C, strain, E.options_init(**kw))
         assert ei.value.code == E.EBADARG

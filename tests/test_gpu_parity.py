@@ -350,7 +350,7 @@ def test_graph_replay_matches_eager_launches(E):
     assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 def test_every_sweep_tile_shape_matches_oracle(E, orc, tile):
     """Each workgroup shape of the fused direction+operator sweep (the
     autotuner's candidates) solves to the oracle's solution; ragged sizes so
