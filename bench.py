@@ -70,8 +70,10 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default sweep geometry (32x8 workgroups) instead of autotuning it")
     ap.add_argument("--tile", type=int, default=None,
-                    help="fix the workgroup shape of the fused sweep (index into elas3d.TILE_SHAPES, "
-                         "default z-chunking) instead of autotuning")
+                    help="fix the workgroup shape of the fused sweep (index into elas3d.TILE_SHAPES) "
+                         "instead of autotuning")
+    ap.add_argument("--zchunk", type=int, default=0,
+                    help="with --tile: z planes per workgroup (0 = automatic)")
     ap.add_argument("--nrhs", type=int, default=1, help="load cases solved per step (of the workload's)")
     ap.add_argument("--batched", action="store_true",
                     help="solve the load cases as one lockstep multi-RHS batch (else one after another)")
@@ -212,7 +214,7 @@ def main():
         opts = E.options_init(inputs_on_device=1, outputs_on_device=1, timing=1, device=0,
                               stream=stream.cuda_stream,
                               autotune=0 if (args.no_autotune or args.tile is not None) else 1,
-                              tile=args.tile or 0,
+                              tile=args.tile or 0, zchunk=args.zchunk if args.tile is not None else 0,
                               batched=1 if args.batched else 0,
                               precision=E.PREC_MIXED if precision == "mixed" else E.PREC_FP64)
         h = E.setup(ms.shape, phase, ms.C, ms.strain[:nrhs], opts)

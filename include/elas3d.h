@@ -109,6 +109,9 @@ typedef struct elas3d_options {
     int32_t tile;              /* workgroup shape of the direction+operator sweep
                                   when not autotuned: 0 = 32x8 lanes (default),
                                   1 = 16x16, 2 = 64x4, 3 = 32x16, 4 = 64x8          */
+    int32_t zchunk;            /* z planes per workgroup of that sweep when not
+                                  autotuned; 0 = automatic (about 4096 workgroups);
+                                  values above nz mean nz                            */
 } elas3d_options;
 
 typedef struct elas3d_info {

@@ -55,17 +55,20 @@ void default_options(elas3d_options* o)
 // Device bytes of a context (kept in one place so the budget check and
 // elas3d_device_bytes agree).
 // Partial sums per value slot: one per workgroup (and RHS) of the largest
-// grid any sweep or autotuning candidate can launch.
-int partial_slots(const Dims& d, int nrhs)
+// grid any sweep, autotuning candidate or fixed geometry (tile, zchunk) can
+// launch.
+long long partial_slots(const Dims& d, int nrhs, int tile, int zchunk)
 {
     long long most = 65536;
-    for (int tile = 0; tile < e3d::kNumTiles; ++tile)
+    for (int t = 0; t < e3d::kNumTiles; ++t)
         for (int target : kTuneTargets)
-            most = std::max(most, (long long)e3d::op_geometry(d, 0, tile, target).blocks * nrhs);
-    return (int)most;
+            most = std::max(most, (long long)e3d::op_geometry(d, 0, t, target).blocks * nrhs);
+    most = std::max(most, (long long)e3d::op_geometry(d, zchunk, tile).blocks * nrhs);
+    return most;
 }
 
-double plan_bytes(int32_t nx, int32_t ny, int32_t nz, int nphase, int nrhs, bool mixed, bool batched)
+double plan_bytes(int32_t nx, int32_t ny, int32_t nz, int nphase, int nrhs, bool mixed, bool batched,
+                  int tile, int zchunk)
 {
     const int64_t n = (int64_t)nx * ny * nz;
     const double N = (double)n;
@@ -80,7 +83,7 @@ double plan_bytes(int32_t nx, int32_t ny, int32_t nz, int nphase, int nrhs, bool
     bytes += (8.0 * 6.0 * (mixed ? 1.5 : 1.0)) * (N + nphase) + 4.0 * N;
     bytes += (double)nphase * 8.0 * (e3d::kCoefStride + e3d::kDiagStride + 1.0) +
              (double)nphase * nrhs * 8.0 * e3d::kSigStride;
-    bytes += 8.0 * kPartialValues * partial_slots(Dims{nx, ny, nz, (int)n}, nrhs);  // partial sums
+    bytes += 8.0 * kPartialValues * (double)partial_slots(Dims{nx, ny, nz, (int)n}, nrhs, tile, zchunk);
     bytes += 4096.0;
     return bytes;
 }
@@ -161,7 +164,9 @@ int validate_options(const elas3d_options* o)
     if (!(o->inner_tol >= 0.0) || !(o->inner_tol < 1.0))
         return fail(nullptr, ELAS3D_EBADARG, "options.inner_tol must be in [0, 1)");
     if (o->tile < 0 || o->tile >= e3d::kNumTiles)
-        return fail(nullptr, ELAS3D_EBADARG, "options.tile must be in [0, 3]");
+        return fail(nullptr, ELAS3D_EBADARG,
+                    "options.tile must be in [0, " + std::to_string(e3d::kNumTiles - 1) + "]");
+    if (o->zchunk < 0) return fail(nullptr, ELAS3D_EBADARG, "options.zchunk must be >= 0");
     return 0;
 }
 
@@ -802,8 +807,9 @@ double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, i
 {
     if (nx < 1 || ny < 1 || nz < 1 || 3 * (int64_t)nx * ny * nz >= ((int64_t)1 << 31) || nrhs < 1)
         return 0.0;
+    const bool valid_geom = opt && opt->tile >= 0 && opt->tile < e3d::kNumTiles && opt->zchunk >= 0;
     return plan_bytes(nx, ny, nz, nphase, nrhs, opt && opt->precision == ELAS3D_PREC_MIXED,
-                      opt && opt->batched);
+                      opt && opt->batched, valid_geom ? opt->tile : 0, valid_geom ? opt->zchunk : 0);
 }
 
 int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int32_t* phase,
@@ -832,7 +838,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     }
     const int64_t n = (int64_t)nx * ny * nz;
     const bool mixed = opt.precision == ELAS3D_PREC_MIXED;
-    const double need = plan_bytes(nx, ny, nz, nphase, nrhs, mixed, opt.batched != 0);
+    const double need = plan_bytes(nx, ny, nz, nphase, nrhs, mixed, opt.batched != 0, opt.tile, opt.zchunk);
     double budget = opt.hbm_budget_bytes;
     if (budget <= 0.0) {
         size_t free_b = 0, total_b = 0;
@@ -858,10 +864,17 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->bytes = need;
     c->geom = e3d::op_geometry(c->d, 0);
     for (int q = 0; q < 2; ++q) {
-        c->geom_sweep[q] = e3d::op_geometry(c->d, 0, opt.tile);
+        c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, opt.tile);
         c->upd_blocks[q] = kSweepBlocks;
     }
-    c->partial_stride = partial_slots(c->d, nrhs);
+    {
+        const long long slots = partial_slots(c->d, nrhs, opt.tile, opt.zchunk);
+        if (slots >= (1LL << 31) / kPartialValues) {
+            free_ctx(c);
+            return fail(nullptr, ELAS3D_EBADARG, "options.zchunk gives too many workgroups");
+        }
+        c->partial_stride = (int)slots;
+    }
 
     auto bail = [&](hipError_t e, const char* what) {
         std::string m = std::string(what) + ": " + hipGetErrorString(e);

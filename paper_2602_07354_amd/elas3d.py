@@ -67,6 +67,7 @@ class Options(ctypes.Structure):
         ("graphs", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
         ("tile", ctypes.c_int32),
+        ("zchunk", ctypes.c_int32),
     ]
 
 

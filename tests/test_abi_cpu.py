@@ -43,6 +43,8 @@ def test_struct_layout_matches_c(E, tmp_path):
         'printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(elas3d_info, t_operator_ms), offsetof(elas3d_info, n_update),'
         ' offsetof(elas3d_info, fp64_fallback), offsetof(elas3d_info, op_tile),'
         ' offsetof(elas3d_info, update_blocks), offsetof(elas3d_options, autotune));\n'
+        'printf("%zu %zu %zu\\n", offsetof(elas3d_options, tile), offsetof(elas3d_options, zchunk),'
+        ' offsetof(elas3d_info, precond_rows));\n'
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -51,7 +53,8 @@ def test_struct_layout_matches_c(E, tmp_path):
     py = [ctypes.sizeof(E.Options), E.Options.hbm_budget_bytes.offset, E.Options.stream.offset,
           E.Options.graphs.offset, ctypes.sizeof(E.Info), E.Info.relres_true.offset,
           E.Info.t_operator_ms.offset, E.Info.n_update.offset, E.Info.fp64_fallback.offset,
-          E.Info.op_tile.offset, E.Info.update_blocks.offset, E.Options.autotune.offset]
+          E.Info.op_tile.offset, E.Info.update_blocks.offset, E.Options.autotune.offset,
+          E.Options.tile.offset, E.Options.zchunk.offset, E.Info.precond_rows.offset]
     assert c == py
 
 
@@ -94,7 +97,7 @@ def test_setup_rejects_bad_options(E):
     shape, phase, C, strain = _good()
     for kw in ({"precision": 7}, {"convergence": 3}, {"preconditioner": -1},
                {"poll_interval": -2}, {"hbm_budget_bytes": -1.0}, {"inner_tol": 2.0},
-               {"tile": 5}, {"tile": -1}):
+               {"tile": 5}, {"tile": -1}, {"zchunk": -3}):
         with pytest.raises(E.Elas3dError) as ei:
             E.setup(shape, phase, C, strain, E.options_init(**kw))
         assert ei.value.code == E.EBADARG

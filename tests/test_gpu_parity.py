@@ -208,6 +208,33 @@ def test_edge_cases(E, orc):
     assert ei.value.code == E.ENOMEM
 
 
+def test_runs_cut_after_k_iterations_match_oracle_iterates(E, orc):
+    """w owes the last step or two of a run until a direction sweep or the
+    end of the run pays them; after exactly k iterations (k = 1..5 covers a
+    run ending with one and with two owed steps, after a paying sweep and
+    not) the iterate equals the oracle's k-th PCG iterate, for a single case
+    and for each case of a batched run."""
+    say("case: iterates after k iterations")
+    ms = _small_poly((17, 19, 23), 29)
+    ms2 = synth.polycrystal((17, 19, 23), 12, 29, [dict(kind="sphere", fraction=0.02, median=1.5, sigma=0.3)],
+                            synth.unit_load_cases()[[2, 4]])
+    P = orc.Problem.from_micro(ms)
+    P2 = orc.Problem.from_micro(ms2)
+    for k in range(1, 6):
+        ro = P.solve(ms.strain[0], tol=1e-30, maxit=k)
+        assert ro["iters"] == k
+        with E.Context.from_micro(ms) as ctx:
+            st, info = ctx.solve(1e-30, k)
+            assert st == E.NOT_CONVERGED and info["iters"][0] == k
+            assert _rel(ctx.solution(0), ro["w"]) <= 1e-11, k
+        with E.Context.from_micro(ms2, batched=1) as ctx:
+            st, info = ctx.solve(1e-30, k)
+            for r in range(2):
+                assert info["iters"][r] == k
+                ro2 = P2.solve(ms2.strain[r], tol=1e-30, maxit=k)
+                assert _rel(ctx.solution(r), ro2["w"]) <= 1e-11, (k, r)
+
+
 def test_deterministic_and_device_inputs(E):
     say("case: determinism and device-resident inputs")
     import torch
@@ -369,6 +396,22 @@ def test_every_sweep_tile_shape_matches_oracle(E, orc, tile):
             out = ctx.stress(0)
         so, _ = P.stress(ms.strain[0], ro["w"])
         assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
+
+
+def test_fixed_z_chunking_matches_oracle(E, orc):
+    """options.zchunk fixes the z planes per workgroup of the fused sweep
+    (values above nz mean nz); every choice solves to the oracle's answer."""
+    say("case: fixed z chunking")
+    ms = _small_poly((37, 29, 21), 47, grains=15)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    for zc in (1, 5, 21, 100):
+        with E.Context.from_micro(ms, tile=4, zchunk=zc) as ctx:
+            st, info = ctx.solve(1e-12, 20000)
+            assert st == E.OK and info["op_tile"] == [64, 8, min(zc, 21)]
+            assert abs(info["iters"][0] - ro["iters"]) <= 2
+            assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
 
 
 def test_autotuned_geometry_solves_and_is_cached(E, orc):
