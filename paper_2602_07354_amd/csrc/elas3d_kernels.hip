@@ -839,18 +839,20 @@ __global__ void __launch_bounds__(kBlock) to_float_kernel(const double* __restri
 #endif
 constexpr int kXcds = 8;  // MI355X: 8 accelerator dies, each with its own L2
 
-// Workgroups are handed to the XCDs round-robin (id % 8).  This bijection
-// gives each XCD a contiguous range of logical tiles instead, so that tiles
-// that share halo rows and cache lines run on the same L2 at about the same
-// time.
-__device__ __forceinline__ int xcd_local_block()
+// Workgroups are handed to the XCDs round-robin: of nb consecutive
+// workgroups, the b-th and the (b+8)-th run on the same XCD.  This bijection
+// of b in [0, nb) gives each XCD a contiguous range of logical tiles
+// instead, so that tiles that share halo rows and cache lines run on the
+// same L2 at about the same time.
+__device__ __forceinline__ int xcd_map(const int b, const int nb)
 {
-    const int nb = gridDim.x, b = blockIdx.x;
     if (!E3D_XCD_REMAP || nb < kXcds) return b;
     const int per = nb / kXcds, rem = nb % kXcds;
     const int x = b % kXcds, j = b / kXcds;
     return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
 }
+
+__device__ __forceinline__ int xcd_local_block() { return xcd_map(blockIdx.x, gridDim.x); }
 
 // Operator sweep modes.
 enum OpMode { OP_APPLY = 0, OP_FUSED = 1, OP_REFINE = 2 };
@@ -1242,9 +1244,13 @@ struct OpPack {
 template <int TX, int TY, typename T>
 __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_group_kernel(OpPack<T> pk)
 {
-    const int b = xcd_local_block();
+    // each problem's workgroups are spread over all XCDs (contiguous tile
+    // ranges per XCD within the problem), so problems of different sizes do
+    // not load some XCDs more than others
+    const int b = blockIdx.x;
     const int p = find_entry(pk.first, pk.n, b);
-    op_dispatch<TX, TY, OP_FUSED, T>(pk.m[p], b - pk.first[p], pk.first[p + 1] - pk.first[p]);
+    const int nbp = pk.first[p + 1] - pk.first[p];
+    op_dispatch<TX, TY, OP_FUSED, T>(pk.m[p], xcd_map(b - pk.first[p], nbp), nbp);
 }
 
 template <typename T>
@@ -1553,6 +1559,12 @@ OpGeom op_geometry(const Dims& d, int kz_hint, int tile, int target_blocks)
         int chunks = (target + ntiles - 1) / ntiles;
         if (chunks > d.nz) chunks = d.nz;
         kz = (d.nz + chunks - 1) / chunks;
+        // Short chunks pay their extra lower plane and start-up on few
+        // planes: on small grids lengthen them toward 16 planes while about
+        // target/8 workgroups (one round on the chip at the default) remain.
+        const long long fill = (long long)ntiles * d.nz / (target / 8 > 0 ? target / 8 : 1);
+        const int kz_fill = (int)std::min<long long>(16, fill);
+        if (kz < kz_fill) kz = kz_fill;
         if (kz < 4 && d.nz >= 4) kz = 4;
     }
     if (kz > d.nz) kz = d.nz;
