@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 COUNTERS = os.path.join(ROOT, "profiles", "op_kernel_poly500_fp64_counters.txt")
+VALU_COUNTERS = os.path.join(ROOT, "profiles", "op_kernel_poly500_valu_counters.txt")
+VALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X vector peaks
 KERNEL_SOURCES = ("paper_2602_07354_amd/csrc/elas3d_kernels.hip", "paper_2602_07354_amd/csrc/elas3d_internal.h")
 # Algorithmic HBM bytes per node of the fused direction+operator sweep, the
 # mean of its two alternating forms: read z, h_old and the phase id, write
@@ -93,26 +95,44 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, tile) -> dict:
-    """HBM bytes per launch of the fused sweep from the committed counter
-    summary, if it was taken on this kernel source, workload and sweep
+def _counter_summary(path: str, workload: str, tile):
+    """key: value lines of a committed counter summary, or None (with the
+    reason) unless it was taken on this kernel source, workload and sweep
     geometry (lanes in x, y and z-chunk length)."""
-    out = {"bytes": None, "source": None}
-    if not os.path.exists(COUNTERS):
-        return out
+    if not os.path.exists(path):
+        return None, None
     kv = {}
-    with open(COUNTERS) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if (kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload
             or kv.get("op_tile") != " ".join(str(v) for v in tile)):
-        out["source"] = "stale (kernel, workload or sweep geometry differs from the counters' run)"
-        return out
-    out["bytes"] = float(kv["op_traffic_bytes_per_dispatch"])
-    out["source"] = os.path.relpath(COUNTERS, ROOT)
-    return out
+        return None, "stale (kernel, workload or sweep geometry differs from the counters' run)"
+    return kv, os.path.relpath(path, ROOT)
+
+
+def measured_traffic(workload: str, tile) -> dict:
+    """HBM bytes per launch of the fused sweep from the committed counter
+    summary (see _counter_summary)."""
+    kv, src = _counter_summary(COUNTERS, workload, tile)
+    return {"bytes": float(kv["op_traffic_bytes_per_dispatch"]) if kv else None, "source": src}
+
+
+def measured_valu(workload: str, tile, precision: str, op_ms: float):
+    """Achieved vector-ALU rate of the fused sweep: its counted flops per
+    launch (committed summary, see _counter_summary) over the launch
+    duration measured now, against the vector peak; and its MFMA count."""
+    kv, src = _counter_summary(VALU_COUNTERS, workload, tile)
+    if not kv:
+        return {"achieved": None, "source": src}
+    flops = float(kv[precision + "_flops_per_dispatch"])
+    achieved = flops / (op_ms * 1e-3) / 1e12
+    peak = VALU_PEAK_TFLOPS[precision]
+    return {"achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "flops_per_launch": flops, "mfma_instructions": float(kv[precision + "_mfma_per_dispatch"]),
+            "source": src}
 
 
 def copy_bandwidth(torch, dev, gib: float = 4.0) -> float:
@@ -265,6 +285,7 @@ def main():
             "op_tile": mrecs[0][1]["op_tile"],
             "update_blocks": mrecs[0][1]["update_blocks"],
         }
+        mixed["valu"] = measured_valu(ms.meta.get("workload"), mixed["op_tile"], "fp32", mixed["operator_ms_avg"])
 
     iters = [sum(r[1]["iters"]) for r in recs]  # summed over the load cases
     t_op = sum(r[1]["t_operator_ms"] for r in recs)
@@ -337,6 +358,8 @@ def main():
             "frac_of_copy": round(achieved / copy_gbs, 4),
             "op_tile": tile,
             "update_blocks": recs[0][1]["update_blocks"],
+            "valu": (measured_valu(ms.meta.get("workload"), tile, "fp64" if head == "fp64" else "fp32", op_ms)
+                     if nrhs == 1 else None),
         },
     }
     if not args.no_cpu_baseline:
