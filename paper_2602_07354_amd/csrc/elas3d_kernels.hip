@@ -906,10 +906,18 @@ using OpReal = typename std::conditional<MODE == OP_FUSED, T, double>::type;
 
 // LDS of an operator-sweep workgroup: a node plane with its halo row and
 // column, and the in-plane force exchange.
+// One workgroup barrier per plane step: the node plane and the force
+// exchange are double-buffered by step parity, and the forces of step s are
+// summed and stored after the barrier of step s + 1 (0: one buffer, two
+// barriers per step)
+#ifndef E3D_ONE_BARRIER
+#define E3D_ONE_BARRIER 1
+#endif
 template <int TX, int TY, typename R>
 struct OpShared {
-    R sn[3][(TY + 1) * (TX + 1)];
-    R sf[3][3][TX * TY];
+    static constexpr int NB = E3D_ONE_BARRIER ? 2 : 1;  // buffers, used by step parity
+    R sn[NB][3][(TY + 1) * (TX + 1)];
+    R sf[NB][3][3][TX * TY];
 };
 
 // Workgroup lbr (logical, of nblocks) of an operator sweep over a.
@@ -920,8 +928,9 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
     constexpr bool FUSED = MODE == OP_FUSED;
     using R = OpReal<MODE, T>;
     constexpr int NT = TX * TY, LX = TX + 1, LY = TY + 1;
-    auto& sn = sh.sn;
-    auto& sf = sh.sf;
+    constexpr int NB = OpShared<TX, TY, R>::NB;
+    auto& SN = sh.sn;
+    auto& SF = sh.sf;
 
     // logical workgroup -> (RHS, tile block): the tiles of one RHS are a
     // contiguous range in the XCD-local order, laid out as in a single-RHS
@@ -1056,32 +1065,65 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
     // of the current element layer, carry = upper-face forces of the previous
     // layer (they act on the same node plane as this layer's lower face).
     R lo[3][4], carry[3][4];
-    auto read_face = [&](R (&F)[3][4]) {
+    auto read_face = [&](int b, R (&F)[3][4]) {
+        auto& sn = SN[b];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             face_fwd(sn[c][ty * LX + tx], sn[c][ty * LX + tx + 1], sn[c][(ty + 1) * LX + tx],
                      sn[c][(ty + 1) * LX + tx + 1], F[c]);
     };
+    double dot = 0.0;
+    // y of node plane kl (of the element layers above and below it): the
+    // lane's own part m plus its neighbours' parts from buffer b; the dot
+    // with h (fused) or y (the other modes)
+    auto emit = [&](int b, const R (&m)[3], const R (&hk)[3], int kl) {
+        auto& sf = SF[b];
+        const int idx = ((kl < 0 ? kl + nz : kl) * plane + own) * kVS;
+        R yv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            R v = m[c] + sf[2][c][tid + 1];
+            v += sf[1][c][tid + TX];
+            v += sf[0][c][tid + TX + 1];
+            if constexpr (!FUSED) {
+                if (a.add[0]) v += a.add[c][idx];
+            }
+            yv[c] = v;
+            if constexpr (FUSED) a.y[c][idx] = v;
+            else if constexpr (MODE == OP_REFINE) a.yr[c][idx] = (float)v;
+            else a.yd[c][idx] = v;
+        }
+        if constexpr (FUSED) {
+            dot += (double)hk[0] * yv[0] + (double)hk[1] * yv[1] + (double)hk[2] * yv[2];
+        } else {
+            dot += yv[0] * yv[0] + yv[1] * yv[1] + yv[2] * yv[2];
+        }
+    };
     // prologue: node plane k0-1 gives the lower face of element layer k0-1
+    // (in the last buffer, so that with two buffers step 0 may write the
+    // first one at once)
     fetch(k0 - 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        sn[c][oslot] = own_value(c);
-        if (has_halo) sn[c][hslot] = halo_value(c);
+        SN[NB - 1][c][oslot] = own_value(c);
+        if (has_halo) SN[NB - 1][c][hslot] = halo_value(c);
     }
     __syncthreads();
-    read_face(lo);
+    read_face(NB - 1, lo);
     const int nsteps = kend - k0 + 1;
     // coefficients of the current layer, phase of the next one
     R Cu[21];
     load_coef(coef, layer_phase(k0 - 1), Cu);
     int p_next = layer_phase(min(k0, kend - 1));
     fetch(k0);
-    __syncthreads();
+    if constexpr (NB == 1) __syncthreads();
 
-    double dot = 0.0;
     R hprev[3] = {R(0), R(0), R(0)};  // own node value of the lower plane
+    // two buffers: the forces of step s are summed and stored after the
+    // barrier of step s + 1, from these
+    R mine_d[3] = {R(0), R(0), R(0)}, hout_d[3] = {R(0), R(0), R(0)};
     for (int s = 0; s < nsteps; ++s) {
+        const int b = NB == 2 ? (s & 1) : 0;
         const int ku = k0 + s;
         const int kuw = ku >= nz ? ku - nz : ku;
         R ov[3];
@@ -1099,12 +1141,15 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            sn[c][oslot] = ov[c];
-            if (has_halo) sn[c][hslot] = halo_value(c);
+            SN[b][c][oslot] = ov[c];
+            if (has_halo) SN[b][c][hslot] = halo_value(c);
         }
         __syncthreads();
+        if constexpr (NB == 2) {
+            if (s > 1 && out_ok) emit(b ^ 1, mine_d, hout_d, k0 - 2 + s);
+        }
         R up[3][4];
-        read_face(up);
+        read_face(b, up);
         fetch(min(ku + 1, kend));  // the last step re-reads plane kend (unused)
 
         R FL[3][4], FU[3][4];
@@ -1125,9 +1170,9 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
 #pragma unroll
                 for (int q = 0; q < 4; ++q) F[q] = carry[c][q] + FL[c][q];
                 face_adj(F, v);
-                sf[0][c][tid] = v[0];
-                sf[1][c][tid] = v[1];
-                sf[2][c][tid] = v[2];
+                SF[b][0][c][tid] = v[0];
+                SF[b][1][c][tid] = v[1];
+                SF[b][2][c][tid] = v[2];
                 mine[c] = v[3];
             }
         }
@@ -1138,32 +1183,22 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
                 carry[c][q] = FU[c][q];
                 lo[c][q] = up[c][q];
             }
-        __syncthreads();
-        if (s > 0 && out_ok) {
-            const int kl = k0 - 1 + s;
-            const int idx = ((kl < 0 ? kl + nz : kl) * plane + own) * kVS;
-            R yv[3];
+        if constexpr (NB == 1) {
+            __syncthreads();
+            if (s > 0 && out_ok) emit(0, mine, hprev, k0 - 1 + s);
+        } else {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                R v = mine[c] + sf[2][c][tid + 1];
-                v += sf[1][c][tid + TX];
-                v += sf[0][c][tid + TX + 1];
-                if constexpr (!FUSED) {
-                    if (a.add[0]) v += a.add[c][idx];
-                }
-                yv[c] = v;
-                if constexpr (FUSED) a.y[c][idx] = v;
-                else if constexpr (MODE == OP_REFINE) a.yr[c][idx] = (float)v;
-                else a.yd[c][idx] = v;
-            }
-            if constexpr (FUSED) {
-                dot += (double)hprev[0] * yv[0] + (double)hprev[1] * yv[1] + (double)hprev[2] * yv[2];
-            } else {
-                dot += yv[0] * yv[0] + yv[1] * yv[1] + yv[2] * yv[2];
+                mine_d[c] = mine[c];
+                hout_d[c] = hprev[c];
             }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) hprev[c] = ov[c];
+    }
+    if constexpr (NB == 2) {
+        __syncthreads();
+        if (nsteps > 1 && out_ok) emit((nsteps - 1) & 1, mine_d, hout_d, k0 - 2 + nsteps);
     }
     if (FUSED || a.want_norm) {
         double v[1] = {dot};
