@@ -286,11 +286,13 @@ int elas3d_group_create(elas3d_group** out, const elas3d_options* opt);
 
 /* Admit ctx (all of its load cases) with the stopping data of elas3d_solve.
  * The context must be on the group's device, not in another group, and set
- * up with options.batched when it has more than one load case.  Until it is
- * returned by elas3d_group_run it runs on the group's stream and must not be
- * used or destroyed by the caller.  A member with nothing to solve (zero
- * load) finishes at once.  Returns 0, ELAS3D_EBADARG, ELAS3D_EORDER (already
- * in a group) or ELAS3D_EDEVICE. */
+ * up with options.batched when it has more than one load case.  While the
+ * group runs it, it uses the group's stream and its own entry points
+ * (solve, stress, von_mises, apply, get_*) return ELAS3D_EORDER;
+ * elas3d_destroy withdraws it from the group first.  A member with nothing
+ * to solve (zero load) finishes at once.  Returns 0, ELAS3D_EBADARG,
+ * ELAS3D_EORDER (in a group, or finished in one and not returned yet) or
+ * ELAS3D_EDEVICE. */
 int elas3d_group_add(elas3d_group* g, elas3d_ctx* ctx, double tol, int32_t maxit);
 
 /* Run `iters` lockstep iterations (>= 1) of every member, then settle the
@@ -314,7 +316,9 @@ void elas3d_group_destroy(elas3d_group* g);
 double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
                            const elas3d_options* opt);
 
-/* Release every device resource of the context (NULL is a no-op). */
+/* Release every device resource of the context (NULL is a no-op).  A
+ * context that a group runs, or holds finished and not yet returned, is
+ * withdrawn from the group first (after the group's work in flight). */
 void elas3d_destroy(elas3d_ctx* ctx);
 
 /* Message of the last error of `ctx`, or of the calling thread's last

@@ -785,6 +785,31 @@ int record_results(elas3d_ctx* c, int r0, int R, const CaseResult* res, elas3d_i
     return worst;
 }
 
+// Two fused sweeps per iteration: direction+operator (read z, h_old, phase;
+// write h_new, Ah; every other iteration also read w and the older h and
+// write w) and update+precondition (read g, Ah, the M^-1 row index and the
+// rows of phase-boundary nodes; write g, z).  Per RHS: the fused sweep moves
+// 5.5 vectors + phase on average, the update 4 vectors; M^-1 once per node
+// for a batch (the nphase shared rows stay in cache).
+void iteration_bytes(const elas3d_ctx* c, int nrhs, elas3d_info* info)
+{
+    const int rb = c->batched() ? nrhs : 1;
+    const double N = (double)c->N();
+    const double nbnd = (double)(c->mrows - (size_t)c->nphase);
+    info->precond_rows = (int64_t)c->mrows;
+    if (c->opt.precision == ELAS3D_PREC_MIXED)
+        info->bytes_per_iter = N * rb * ((5.5 * 12.0 + 4.0) + 4 * 12.0) + 4.0 * N + 24.0 * nbnd;
+    else
+        info->bytes_per_iter = N * rb * ((5.5 * 24.0 + 4.0) + 4 * 24.0) + 4.0 * N + 48.0 * nbnd;
+}
+
+// Per-context entry points that use the context's stream or work area
+// refuse it while a group runs it.
+int grouped(elas3d_ctx* c)
+{
+    return c->group ? fail(c, ELAS3D_EORDER, "context is a member of a group") : 0;
+}
+
 }  // namespace e3d::rt
 
 extern "C" {
@@ -994,7 +1019,7 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
     if (maxit < 0) return fail(ctx, ELAS3D_EBADARG, "maxit must be >= 0");
     if (nrhs < 1 || nrhs > ctx->nrhs)
         return fail(ctx, ELAS3D_EBADARG, "nrhs must be in [1, nrhs of setup]");
-    if (ctx->group) return fail(ctx, ELAS3D_EORDER, "context is a member of a group");
+    if (int rc = grouped(ctx)) return rc;
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->nrhs = nrhs;
@@ -1016,20 +1041,7 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
     auto t1 = std::chrono::steady_clock::now();
     if (info) {
         info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
-        // two fused sweeps: direction+operator (read z, h_old, phase; write
-        // h_new, Ah; every other iteration also read w and the older h and
-        // write w) and update+precondition (read g, Ah, the M^-1 row index
-        // and the rows of phase-boundary nodes; write g, z); per RHS: fused
-        // sweep 5.5 vectors + phase on average, update sweep 4 vectors; M^-1
-        // once per node for a batch (the nphase shared rows stay in cache)
-        const int rb = ctx->batched() ? nrhs : 1;
-        const double N = (double)ctx->N();
-        const double nbnd = (double)(ctx->mrows - (size_t)ctx->nphase);
-        info->precond_rows = (int64_t)ctx->mrows;
-        if (ctx->opt.precision == ELAS3D_PREC_MIXED)
-            info->bytes_per_iter = N * rb * ((5.5 * 12.0 + 4.0) + 4 * 12.0) + 4.0 * N + 24.0 * nbnd;
-        else
-            info->bytes_per_iter = N * rb * ((5.5 * 24.0 + 4.0) + 4 * 24.0) + 4.0 * N + 48.0 * nbnd;
+        iteration_bytes(ctx, nrhs, info);
     }
     return worst;
 }
@@ -1038,6 +1050,7 @@ int elas3d_stress(elas3d_ctx* ctx, int32_t rhs, double* sigma_voxel, double* sig
                   double* u_node, double* energy)
 {
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (int rc = grouped(ctx)) return rc;
     if (rhs < 0 || rhs >= ctx->nrhs) return fail(ctx, ELAS3D_EBADARG, "rhs out of range");
     if (!ctx->solved[rhs]) return fail(ctx, ELAS3D_EORDER, "load case not solved yet");
     HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -1072,6 +1085,7 @@ int elas3d_stress(elas3d_ctx* ctx, int32_t rhs, double* sigma_voxel, double* sig
 int elas3d_von_mises(elas3d_ctx* ctx, int32_t rhs, double* vm, double* vm_max, int64_t* argmax)
 {
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (int rc = grouped(ctx)) return rc;
     if (rhs < 0 || rhs >= ctx->nrhs) return fail(ctx, ELAS3D_EBADARG, "rhs out of range");
     if (!ctx->solved[rhs]) return fail(ctx, ELAS3D_EORDER, "load case not solved yet");
     HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -1092,6 +1106,7 @@ int elas3d_von_mises(elas3d_ctx* ctx, int32_t rhs, double* vm, double* vm_max, i
 int elas3d_apply(elas3d_ctx* ctx, const double* x, double* y)
 {
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (int rc = grouped(ctx)) return rc;
     if (!x || !y) return fail(ctx, ELAS3D_EBADARG, "x or y is NULL");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     const size_t N = ctx->N();
@@ -1120,6 +1135,7 @@ int elas3d_apply(elas3d_ctx* ctx, const double* x, double* y)
 int elas3d_get_load(elas3d_ctx* ctx, int32_t rhs, double* b)
 {
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (int rc = grouped(ctx)) return rc;
     if (rhs < 0 || rhs >= ctx->nrhs || !b) return fail(ctx, ELAS3D_EBADARG, "bad rhs or NULL output");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     return export_field(ctx, ctx->bptr(rhs), 3, b);
@@ -1128,6 +1144,7 @@ int elas3d_get_load(elas3d_ctx* ctx, int32_t rhs, double* b)
 int elas3d_get_precond(elas3d_ctx* ctx, double* minv)
 {
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (int rc = grouped(ctx)) return rc;
     if (!minv) return fail(ctx, ELAS3D_EBADARG, "NULL output");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     const size_t N = ctx->N();
@@ -1142,6 +1159,7 @@ int elas3d_get_precond(elas3d_ctx* ctx, double* minv)
 int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w)
 {
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
+    if (int rc = grouped(ctx)) return rc;
     if (rhs < 0 || rhs >= ctx->nrhs || !w) return fail(ctx, ELAS3D_EBADARG, "bad rhs or NULL output");
     if (!ctx->solved[rhs]) return fail(ctx, ELAS3D_EORDER, "load case not solved yet");
     HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -1151,6 +1169,8 @@ int elas3d_get_solution(elas3d_ctx* ctx, int32_t rhs, double* w)
 void elas3d_destroy(elas3d_ctx* ctx)
 {
     if (!ctx) return;
+    if (ctx->group) group_forget(ctx->group, ctx);
+    if (ctx->group_done) group_forget(ctx->group_done, ctx);
     hipSetDevice(ctx->device);
     free_ctx(ctx);
 }

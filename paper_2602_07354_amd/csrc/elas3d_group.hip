@@ -368,19 +368,35 @@ int finish(elas3d_group* g, Member& m)
     int rc = record_results(c, 0, m.R, m.res, &info);
     if (rc < 0) return mfail(m, rc);
     info.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - m.t0).count();
-    const int rb = c->batched() ? m.R : 1;
-    if (m.mixed)
-        info.bytes_per_iter = (double)c->N() * rb * ((6 * 12.0 + 4.0) + (4 * 12.0 + 24.0 / rb));
-    else
-        info.bytes_per_iter = (double)c->N() * rb * ((6 * 24.0 + 4.0) + (4 * 24.0 + 48.0 / rb));
+    iteration_bytes(c, m.R, &info);
     // the work list changed: the stream must be idle before the context leaves it
     GCHK(hipStreamSynchronize(g->stream));
     leave(g, m);
+    c->group_done = g;
     g->done.push_back({c, info});
     return 0;
 }
 
 }  // namespace
+
+void e3d::rt::group_forget(elas3d_group* g, elas3d_ctx* c)
+{
+    hipSetDevice(g->device);
+    hipStreamSynchronize(g->stream);  // no sweep of the group is in flight
+    for (size_t i = 0; i < g->members.size(); ++i)
+        if (g->members[i].c == c) {
+            leave(g, g->members[i]);
+            g->members.erase(g->members.begin() + (long)i);
+            g->dirty = true;
+            break;
+        }
+    for (size_t i = 0; i < g->done.size(); ++i)
+        if (g->done[i].first == c) {
+            g->done.erase(g->done.begin() + (long)i);
+            break;
+        }
+    c->group_done = nullptr;
+}
 
 extern "C" {
 
@@ -420,6 +436,7 @@ int elas3d_group_add(elas3d_group* g, elas3d_ctx* ctx, double tol, int32_t maxit
     if (!(tol >= 0.0) || !std::isfinite(tol)) return gfail(ELAS3D_EBADARG, "tol must be finite and >= 0");
     if (maxit < 0) return gfail(ELAS3D_EBADARG, "maxit must be >= 0");
     if (ctx->group) return gfail(ELAS3D_EORDER, "context is already in a group");
+    if (ctx->group_done) return gfail(ELAS3D_EORDER, "context finished in a group and was not returned yet");
     if (ctx->device != g->device) return gfail(ELAS3D_EBADARG, "context is on another device");
     if (ctx->nrhs > 1 && !ctx->batched())
         return gfail(ELAS3D_EBADARG, "a member with several load cases must be set up with options.batched");
@@ -509,6 +526,7 @@ int elas3d_group_run(elas3d_group* g, int32_t iters, elas3d_ctx** done, elas3d_i
     int k = 0;
     while (k < cap && !g->done.empty()) {
         done[k] = g->done.front().first;
+        done[k]->group_done = nullptr;
         infos[k] = g->done.front().second;
         g->done.erase(g->done.begin());
         ++k;
@@ -524,6 +542,7 @@ void elas3d_group_destroy(elas3d_group* g)
     hipSetDevice(g->device);
     if (g->stream) hipStreamSynchronize(g->stream);
     for (Member& m : g->members) leave(g, m);
+    for (auto& d : g->done) d.first->group_done = nullptr;
     for (int l = 0; l < 2; ++l) {
         if (g->dev[l]) hipFree(g->dev[l]);
         if (g->staging[l]) hipHostFree(g->staging[l]);

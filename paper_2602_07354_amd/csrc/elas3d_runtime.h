@@ -74,7 +74,8 @@ struct elas3d_ctx {
     Scalars* hS = nullptr;        // pinned, 2 slots of kMaxRhs
     double* hscratch = nullptr;   // pinned, 64 doubles
     std::vector<int> solved;
-    elas3d_group* group = nullptr;  // group the context is solved in, if any
+    elas3d_group* group = nullptr;       // group the context is solved in, if any
+    elas3d_group* group_done = nullptr;  // group holding it finished, not yet returned
     double bytes = 0.0;
     std::string err;
 
@@ -203,5 +204,11 @@ int true_residual(elas3d_ctx* c, int r, double* rr);
 // Per-RHS statistics of a finished solve into info (may be NULL); marks the
 // RHS solved; returns the worst status.
 int record_results(elas3d_ctx* c, int r0, int R, const CaseResult* res, elas3d_info* info);
+// Algorithmic HBM bytes of one PCG iteration over nrhs cases and the M^-1
+// dictionary's size, into info.
+void iteration_bytes(const elas3d_ctx* c, int nrhs, elas3d_info* info);
+// Withdraw c from the group that runs it or holds it finished (before c is
+// destroyed): waits until the group's stream is idle.
+void group_forget(elas3d_group* g, elas3d_ctx* c);
 
 }  // namespace e3d::rt

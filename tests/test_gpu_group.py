@@ -118,3 +118,46 @@ def test_group_admission_rules(E):
                 break
         st, info = c1.solve(1e-8)  # back to normal use once returned
         assert st == E.OK
+
+
+def test_grouped_context_is_guarded_and_can_be_withdrawn(E):
+    """While a group runs a context, its own entry points refuse it (EORDER);
+    destroying a member withdraws it, and the remaining members still finish
+    with their solo results bit for bit; a member that finished but was not
+    returned yet can be destroyed as well, and cannot join again before."""
+    tol, maxit = 1e-9, 20000
+    keep_ms = _poly((24, 20, 18), 11)
+    with E.Context.from_micro(keep_ms) as solo:
+        st, info = solo.solve(tol, maxit)
+        want = _outcome(solo, info, 1)
+    keep = E.Context.from_micro(keep_ms)
+    gone = E.Context.from_micro(_poly((30, 26, 22), 12))
+    quick = E.Context.from_micro(_homogeneous())  # zero load: finishes on admission
+    try:
+        with E.Group() as g:
+            g.add(keep.handle, tol, maxit)
+            g.add(gone.handle, tol, maxit)
+            for call in (lambda: keep.stress(0), lambda: keep.apply(np.zeros((3, keep.n))),
+                         lambda: keep.solution(0), lambda: keep.solve(tol, maxit)):
+                with pytest.raises(E.Elas3dError) as ei:
+                    call()
+                assert ei.value.code == E.EORDER
+            g.run(5)
+            gone.close()  # withdrawn mid-run
+            g.add(quick.handle, tol, maxit)
+            with pytest.raises(E.Elas3dError) as ei:
+                g.add(quick.handle, tol, maxit)  # finished, not returned yet
+            assert ei.value.code == E.EORDER
+            quick.close()  # destroyed before it was returned
+            got = []
+            while True:
+                done, active = g.run(16)
+                got += done
+                if active == 0:
+                    break
+            assert [h for h, _, _ in got] == [keep.handle]
+            _same(_outcome(keep, got[0][2], 1), want)
+    finally:
+        keep.close()
+        gone.close()
+        quick.close()
