@@ -121,6 +121,10 @@ def test_device_bytes_plan(E):
     assert flat > 220 * 6000 * 6000 * 2
     # sizes setup would reject
     assert E.device_bytes((1000, 1000, 1000), 2, 1) == 0.0
+    # a fixed one-plane z chunking launches a workgroup per tile and plane:
+    # its partial sums are part of the plan
+    one = E.device_bytes((500, 500, 500), 8001, 1, E.options_init(tile=0, zchunk=1))
+    assert one > b1 + 8.0 * 17 * 72 * 500 * 2
 
 
 def test_generator_rejects_bad_arguments(E):
