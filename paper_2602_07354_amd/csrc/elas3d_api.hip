@@ -352,7 +352,7 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
 // batch of R right-hand sides [r0, r0+R) in batches of `poll`, until the
 // device has raised the stop flag of every RHS; the host looks at the flags of
 // batch k while batch k+1 is already queued.  Optional HIP-event timing of
-// every launch that did real work.  Then the step owed to w is applied.
+// every launch that did real work.  Then the steps still owed to w are applied.
 template <typename T>
 int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const e3d::MinvRows<T>& M, int maxit,
             elas3d_info* info, RunStats* rs_out)

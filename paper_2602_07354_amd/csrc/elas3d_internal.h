@@ -24,16 +24,14 @@ struct Dims {
     int n;
 };
 
-// Layout of node vectors in device memory.  Interleaved (the default): the
-// three components of a node are adjacent, component c of node m at 3m + c
-// of the field, and the six entries of a node's M^-1 block at 6m + q.  Every
-// workgroup of the tiled operator sweep then reads each row of its tile as
-// one contiguous run of 3 x 8 x TX bytes per field instead of three separate
-// runs, which streams markedly better from HBM.  With E3D_INTERLEAVE=0 the
-// fields are SoA planes (component c at c*N + m), the layout of the C-ABI.
-// A field of T is always 3N (M^-1: 6N) contiguous elements; kernels address
-// component c through a pointer to its first element (base + c*kComp) and
-// node m at m*kVS.
+// Layout of node vectors in device memory.  SoA planes (the default, and the
+// layout of the C-ABI): component c of node m at c*N + m.  With
+// E3D_INTERLEAVE=1 the three components of a node are adjacent (3m + c) and
+// the six entries of an M^-1 row r at 6r + q; a memory-only model of the
+// operator sweep streamed 15-18 % faster that way, the real sweep did not,
+// so SoA stays the default.  A vector field of T is 3N contiguous elements
+// (the M^-1 dictionary 6 x its rows); kernels address component c through a
+// pointer to its first element and node m at m*kVS (row r at r*kMS).
 #ifndef E3D_INTERLEAVE
 #define E3D_INTERLEAVE 0
 #endif
