@@ -208,6 +208,37 @@ def test_edge_cases(E, orc):
     assert ei.value.code == E.ENOMEM
 
 
+def _boundary_nodes(ms):
+    """Nodes whose eight voxels (i-a, j-b, k-c), a, b, c in {0, 1}, do not all
+    have one phase (periodic), counted on the host."""
+    nx, ny, nz = ms.shape
+    p = ms.phase.reshape(nz, ny, nx)
+    same = np.ones(p.shape, dtype=bool)
+    for c in (0, 1):
+        for b in (0, 1):
+            for a in (0, 1):
+                same &= np.roll(p, (c, b, a), axis=(0, 1, 2)) == p
+    return int((~same).sum())
+
+
+@pytest.mark.parametrize("shape", [(17, 19, 23), (2, 3, 2), (40, 40, 40)])
+def test_precond_dictionary_rows(E, orc, shape):
+    """M^-1 is stored as one row per phase and one per phase-boundary node;
+    its rows expand to the oracle's per-node blocks (also for plain CG)."""
+    say("case: M^-1 dictionary", shape)
+    ms = _small_poly(shape, 53, grains=9)
+    P = orc.Problem.from_micro(ms)
+    for cg in (False, True):
+        kw = dict(preconditioner=E.PRECOND_NONE) if cg else {}
+        with E.Context.from_micro(ms, **kw) as ctx:
+            st, info = ctx.solve(1e-6, 5)
+            assert info["precond_rows"] == ms.nphase + _boundary_nodes(ms)
+            M = ctx.precond()
+        Mo = P.precond(identity=cg)
+        assert _rel(M, Mo) <= (0.0 if cg else 1e-12)
+        assert np.array_equal(np.all(M == 0, axis=(1, 2)), np.all(Mo == 0, axis=(1, 2)))
+
+
 def test_runs_cut_after_k_iterations_match_oracle_iterates(E, orc):
     """w owes the last step or two of a run until a direction sweep or the
     end of the run pays them; after exactly k iterations (k = 1..5 covers a
