@@ -101,10 +101,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def _counter_summary(path: str, workload: str, tile):
+def _counter_summary(path: str, workload: str, tile, tile_key: str = "op_tile"):
     """key: value lines of a committed counter summary, or None (with the
     reason) unless it was taken on this kernel source, workload and sweep
-    geometry (lanes in x, y and z-chunk length)."""
+    geometry (lanes in x, y and z-chunk length; under tile_key)."""
     if not os.path.exists(path):
         return None, None
     kv = {}
@@ -114,7 +114,7 @@ def _counter_summary(path: str, workload: str, tile):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if (kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload
-            or kv.get("op_tile") != " ".join(str(v) for v in tile)):
+            or kv.get(tile_key) != " ".join(str(v) for v in tile)):
         return None, "stale (kernel, workload or sweep geometry differs from the counters' run)"
     return kv, os.path.relpath(path, ROOT)
 
@@ -130,7 +130,7 @@ def measured_valu(workload: str, tile, precision: str, op_ms: float):
     """Achieved vector-ALU rate of the fused sweep: its counted flops per
     launch (committed summary, see _counter_summary) over the launch
     duration measured now, against the vector peak; and its MFMA count."""
-    kv, src = _counter_summary(VALU_COUNTERS, workload, tile)
+    kv, src = _counter_summary(VALU_COUNTERS, workload, tile, "op_tile" if precision == "fp64" else "fp32_op_tile")
     if not kv:
         return {"achieved": None, "source": src}
     flops = float(kv[precision + "_flops_per_dispatch"])
