@@ -896,9 +896,6 @@ struct OpArgs {
 #define E3D_OP_MIN_WAVES 1
 #endif
 
-#ifndef E3D_W_REDIRECT
-#define E3D_W_REDIRECT 1
-#endif
 
 // Arithmetic type of an operator sweep.
 template <int MODE, typename T>
@@ -908,16 +905,11 @@ using OpReal = typename std::conditional<MODE == OP_FUSED, T, double>::type;
 // column, and the in-plane force exchange.
 // One workgroup barrier per plane step: the node plane and the force
 // exchange are double-buffered by step parity, and the forces of step s are
-// summed and stored after the barrier of step s + 1 (0: one buffer, two
-// barriers per step)
-#ifndef E3D_ONE_BARRIER
-#define E3D_ONE_BARRIER 1
-#endif
+// summed and stored after the barrier of step s + 1.
 template <int TX, int TY, typename R>
 struct OpShared {
-    static constexpr int NB = E3D_ONE_BARRIER ? 2 : 1;  // buffers, used by step parity
-    R sn[NB][3][(TY + 1) * (TX + 1)];
-    R sf[NB][3][3][TX * TY];
+    R sn[2][3][(TY + 1) * (TX + 1)];
+    R sf[2][3][3][TX * TY];
 };
 
 // Workgroup lbr (logical, of nblocks) of an operator sweep over a.
@@ -928,7 +920,6 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
     constexpr bool FUSED = MODE == OP_FUSED;
     using R = OpReal<MODE, T>;
     constexpr int NT = TX * TY, LX = TX + 1, LY = TY + 1;
-    constexpr int NB = OpShared<TX, TY, R>::NB;
     auto& SN = sh.sn;
     auto& SF = sh.sf;
 
@@ -993,7 +984,7 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
     // another lane of the workgroup loads anyway), so the overlap rows and
     // columns of neighbouring tiles cost no w traffic
     int wown = own;
-    if (E3D_W_REDIRECT && !out_ok) {
+    if (!out_ok) {
         const int wi = min(gi, min(i0 + TX - 2, nx - 1)), wj = min(gj, min(j0 + TY - 2, ny - 1));
         wown = wi + nx * wj;
     }
@@ -1100,30 +1091,28 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
         }
     };
     // prologue: node plane k0-1 gives the lower face of element layer k0-1
-    // (in the last buffer, so that with two buffers step 0 may write the
-    // first one at once)
+    // (in buffer 1, so that step 0 may write buffer 0 at once)
     fetch(k0 - 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        SN[NB - 1][c][oslot] = own_value(c);
-        if (has_halo) SN[NB - 1][c][hslot] = halo_value(c);
+        SN[1][c][oslot] = own_value(c);
+        if (has_halo) SN[1][c][hslot] = halo_value(c);
     }
     __syncthreads();
-    read_face(NB - 1, lo);
+    read_face(1, lo);
     const int nsteps = kend - k0 + 1;
     // coefficients of the current layer, phase of the next one
     R Cu[21];
     load_coef(coef, layer_phase(k0 - 1), Cu);
     int p_next = layer_phase(min(k0, kend - 1));
     fetch(k0);
-    if constexpr (NB == 1) __syncthreads();
 
     R hprev[3] = {R(0), R(0), R(0)};  // own node value of the lower plane
-    // two buffers: the forces of step s are summed and stored after the
-    // barrier of step s + 1, from these
+    // the own force part and h of the plane that step s completes, summed
+    // and stored after the barrier of step s + 1
     R mine_d[3] = {R(0), R(0), R(0)}, hout_d[3] = {R(0), R(0), R(0)};
     for (int s = 0; s < nsteps; ++s) {
-        const int b = NB == 2 ? (s & 1) : 0;
+        const int b = s & 1;
         const int ku = k0 + s;
         const int kuw = ku >= nz ? ku - nz : ku;
         R ov[3];
@@ -1145,9 +1134,7 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
             if (has_halo) SN[b][c][hslot] = halo_value(c);
         }
         __syncthreads();
-        if constexpr (NB == 2) {
-            if (s > 1 && out_ok) emit(b ^ 1, mine_d, hout_d, k0 - 2 + s);
-        }
+        if (s > 1 && out_ok) emit(b ^ 1, mine_d, hout_d, k0 - 2 + s);
         R up[3][4];
         read_face(b, up);
         fetch(min(ku + 1, kend));  // the last step re-reads plane kend (unused)
@@ -1183,23 +1170,16 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
                 carry[c][q] = FU[c][q];
                 lo[c][q] = up[c][q];
             }
-        if constexpr (NB == 1) {
-            __syncthreads();
-            if (s > 0 && out_ok) emit(0, mine, hprev, k0 - 1 + s);
-        } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                mine_d[c] = mine[c];
-                hout_d[c] = hprev[c];
-            }
+        for (int c = 0; c < 3; ++c) {
+            mine_d[c] = mine[c];
+            hout_d[c] = hprev[c];
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) hprev[c] = ov[c];
     }
-    if constexpr (NB == 2) {
-        __syncthreads();
-        if (nsteps > 1 && out_ok) emit((nsteps - 1) & 1, mine_d, hout_d, k0 - 2 + nsteps);
-    }
+    __syncthreads();
+    if (nsteps > 1 && out_ok) emit((nsteps - 1) & 1, mine_d, hout_d, k0 - 2 + nsteps);
     if (FUSED || a.want_norm) {
         double v[1] = {dot};
         block_partials<1, NT>(v, a.partials + (size_t)rhs * ntb, ntb, lb);
