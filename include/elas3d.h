@@ -290,7 +290,10 @@ int elas3d_group_create(elas3d_group** out, const elas3d_options* opt);
  * group runs it, it uses the group's stream and its own entry points
  * (solve, stress, von_mises, apply, get_*) return ELAS3D_EORDER;
  * elas3d_destroy withdraws it from the group first.  A member with nothing
- * to solve (zero load) finishes at once.  Returns 0, ELAS3D_EBADARG,
+ * to solve (zero load) finishes at once.  Members sweep with workgroup shape
+ * 0 and the default z-chunking (options.tile, zchunk and autotune apply to
+ * elas3d_solve only), so a member's results equal those of elas3d_solve with
+ * the default geometry, bit for bit.  Returns 0, ELAS3D_EBADARG,
  * ELAS3D_EORDER (in a group, or finished in one and not returned yet) or
  * ELAS3D_EDEVICE. */
 int elas3d_group_add(elas3d_group* g, elas3d_ctx* ctx, double tol, int32_t maxit);
