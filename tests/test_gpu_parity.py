@@ -149,6 +149,75 @@ def test_config_poly100_metric_and_sampled_parity(E, orc):
     assert np.all(out["sigma"][:, void] == 0.0)
 
 
+def test_config_poly500_bench_launch_sampled_parity(E, orc):
+    """The benchmark's own configuration: poly500 generated on the device,
+    phase ids device-resident, autotuned sweep geometry.  Sampled nodes of
+    the operator, load and M^-1 against the oracle; the M^-1 dictionary's
+    size; FP64 and mixed-precision solves to 1e-8 with properties that hold
+    at any size (true residual, Hill-Mandel, zero stress in pores, the two
+    precisions agreeing)."""
+    import torch
+    from paper_2602_07354_amd import generate
+    say("case: poly500 in the benchmark's launch configuration")
+    rec = synth.workload_recipe("poly500")
+    dev = torch.device("cuda:0")
+    phase = torch.empty(int(np.prod(rec["shape"])), dtype=torch.int32, device=dev)
+    ms = generate.workload("poly500", phase=phase)
+    torch.cuda.synchronize()
+    host = synth.Microstructure(ms.shape, phase.cpu().numpy(), ms.C, ms.strain, ms.meta)
+    P = orc.Problem.from_micro(host)
+    rng = np.random.default_rng(500)
+    sel = np.sort(rng.choice(host.n, 300, replace=False))
+    eh = np.r_[ms.strain[0][:3], 2 * ms.strain[0][3:]]
+    void = host.phase == host.nphase - 1
+    avg = {}
+    for prec in (E.PREC_FP64, E.PREC_MIXED):
+        opts = E.options_init(inputs_on_device=1, autotune=1, device=0, precision=prec)
+        h = E.setup(ms.shape, phase, ms.C, ms.strain[:1], opts)
+        try:
+            if prec == E.PREC_FP64:
+                x = rng.standard_normal((3, host.n))
+                y = np.empty_like(x)
+                E.apply(h, x, y)
+                assert _rel(y[:, sel], P.apply_at(x, sel)) <= 1e-12
+                del x, y
+                b = np.empty((3, host.n))
+                E.get_load(h, 0, b)
+                assert _rel(b[:, sel], P.load_at(ms.strain[0], sel)) <= 1e-12
+                M = np.empty((6, host.n))
+                E.get_precond(h, M)
+                Mo = P.precond_at(sel)
+                Ms = np.stack([M[q][sel] for q in (0, 5, 4, 5, 1, 3, 4, 3, 2)], axis=1).reshape(-1, 3, 3)
+                assert _rel(Ms, Mo) <= 1e-12
+                del M
+            st, info = E.solve(h, 1e-8, 50000, 1)
+            say("  ", "fp64" if prec == E.PREC_FP64 else "mixed", "iterations", info.iters[0],
+                "relres", info.relres_true[0], "tile", list(info.op_tile))
+            assert st == E.OK and info.relres_true[0] <= 1e-8
+            assert tuple(info.op_tile[:2]) in E.TILE_SHAPES
+            sig = np.empty((6, host.n))
+            a6, en = np.empty(6), np.empty(1)
+            assert E.lib().elas3d_stress(h, 0, sig.ctypes.data, a6.ctypes.data, None, en.ctypes.data) == 0
+            assert np.all(sig[:, void] == 0.0)
+            del sig
+            avg[prec] = a6
+            if prec == E.PREC_FP64:
+                assert info.precond_rows == host.nphase + _boundary_nodes(host)
+                w = np.empty((3, host.n))
+                E.get_solution(h, 0, w)
+                g = np.empty_like(w)
+                E.apply(h, w, g)
+                g += b
+                assert np.linalg.norm(g) <= 1e-8 * np.linalg.norm(b) * 1.01
+                # Hill-Mandel: 2 Pi = N E_hat.<sigma> + w.g
+                lhs, rhs = 2 * en[0], host.n * eh @ a6 + np.sum(w * g)
+                assert abs(lhs - rhs) <= 1e-9 * abs(lhs)
+                del w, g, b
+        finally:
+            E.destroy(h)
+    assert _rel(avg[E.PREC_MIXED], avg[E.PREC_FP64]) <= 1e-6
+
+
 def test_edge_cases(E, orc):
     say("case: edge cases")
     # the smallest grids (2 nodes in a dimension: both neighbours are the same
