@@ -88,16 +88,21 @@ def parse():
     return ap.parse_args()
 
 
+def source_code(text: str) -> str:
+    """C++ source without comments, trailing blanks and empty lines (the
+    kernel sources hold no string literal with a comment marker)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_hash() -> str:
-    """Hash of the kernel sources without their comments and blank lines, so
-    that only code changes set the committed counter summaries aside."""
+    """Hash of the kernel sources' code, so that only code changes set the
+    committed counter summaries aside."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel)) as f:
-            text = f.read()
-        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
-        h.update("\n".join(line for line in lines if line).encode())
+            h.update(source_code(f.read()).encode())
     return h.hexdigest()
 
 
