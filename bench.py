@@ -119,7 +119,7 @@ def _counter_summary(path: str, workload: str, tile, tile_key: str = "op_tile"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if (kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload
-            or kv.get(tile_key) != " ".join(str(v) for v in tile)):
+            or (tile_key is not None and kv.get(tile_key) != " ".join(str(v) for v in tile))):
         return None, "stale (kernel, workload or sweep geometry differs from the counters' run)"
     return kv, os.path.relpath(path, ROOT)
 
@@ -131,14 +131,30 @@ def measured_traffic(workload: str, tile) -> dict:
     return {"bytes": float(kv["op_traffic_bytes_per_dispatch"]) if kv else None, "source": src}
 
 
-def measured_valu(workload: str, tile, precision: str, op_ms: float):
+def measured_valu(workload: str, tile, precision: str, op_ms: float, nz: int):
     """Achieved vector-ALU rate of the fused sweep: its counted flops per
-    launch (committed summary, see _counter_summary) over the launch
-    duration measured now, against the vector peak; and its MFMA count."""
-    kv, src = _counter_summary(VALU_COUNTERS, workload, tile, "op_tile" if precision == "fp64" else "fp32_op_tile")
+    launch (committed summary) over the launch duration measured now,
+    against the vector peak; and its MFMA count.  The summary must be of
+    this kernel source, workload and workgroup shape; another z-chunk length
+    kz changes only the element layers computed (nz plus one per chunk), and
+    the flops are scaled by that count."""
+    key = "op_tile" if precision == "fp64" else "fp32_op_tile"
+    kv, src = _counter_summary(VALU_COUNTERS, workload, tile, key)
+    scaled = False
+    if not kv and src and os.path.exists(VALU_COUNTERS):
+        kv, src = _counter_summary(VALU_COUNTERS, workload, None, None)
+        if kv:
+            tx, ty, kz0 = (int(v) for v in kv[key].split())
+            if (tx, ty) != (int(tile[0]), int(tile[1])):
+                return {"achieved": None, "source": "stale (workgroup shape differs from the counters' run)"}
+            scaled = True
     if not kv:
         return {"achieved": None, "source": src}
     flops = float(kv[precision + "_flops_per_dispatch"])
+    if scaled:
+        layers = lambda kz: nz + -(-nz // kz)  # noqa: E731
+        flops *= layers(int(tile[2])) / layers(kz0)
+        src += " (scaled to z-chunk %d from %d)" % (int(tile[2]), kz0)
     achieved = flops / (op_ms * 1e-3) / 1e12
     peak = VALU_PEAK_TFLOPS[precision]
     return {"achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
@@ -296,7 +312,8 @@ def main():
             "op_tile": mrecs[0][1]["op_tile"],
             "update_blocks": mrecs[0][1]["update_blocks"],
         }
-        mixed["valu"] = measured_valu(ms.meta.get("workload"), mixed["op_tile"], "fp32", mixed["operator_ms_avg"])
+        mixed["valu"] = measured_valu(ms.meta.get("workload"), mixed["op_tile"], "fp32", mixed["operator_ms_avg"],
+                                      ms.shape[2])
 
     iters = [sum(r[1]["iters"]) for r in recs]  # summed over the load cases
     t_op = sum(r[1]["t_operator_ms"] for r in recs)
@@ -369,8 +386,8 @@ def main():
             "frac_of_copy": round(achieved / copy_gbs, 4),
             "op_tile": tile,
             "update_blocks": recs[0][1]["update_blocks"],
-            "valu": (measured_valu(ms.meta.get("workload"), tile, "fp64" if head == "fp64" else "fp32", op_ms)
-                     if nrhs == 1 else None),
+            "valu": (measured_valu(ms.meta.get("workload"), tile, "fp64" if head == "fp64" else "fp32", op_ms,
+                                   ms.shape[2]) if nrhs == 1 else None),
         },
     }
     if not args.no_cpu_baseline:

@@ -20,3 +20,18 @@ def test_counter_summary_requires_matching_geometry(tmp_path):
     assert kv is None and src.startswith("stale")
     kv, src = bench._counter_summary(str(p), "poly300", [64, 8, 125])
     assert kv is None
+
+
+def test_valu_flops_scale_with_the_z_chunk_only(tmp_path, monkeypatch):
+    p = tmp_path / "v.txt"
+    p.write_text("workload: poly500\nop_tile: 64 8 125\nfp32_op_tile: 64 8 63\n"
+                 "kernel_source_sha256: %s\nfp64_flops_per_dispatch: 6e10\nfp64_mfma_per_dispatch: 0\n"
+                 "fp32_flops_per_dispatch: 5.08e10\nfp32_mfma_per_dispatch: 0\n" % bench.kernel_source_hash())
+    monkeypatch.setattr(bench, "VALU_COUNTERS", str(p))
+    same = bench.measured_valu("poly500", [64, 8, 63], "fp32", 2.0, 500)
+    assert same["flops_per_launch"] == 5.08e10 and "scaled" not in same["source"]
+    # 500 planes in chunks of 63 compute 508 element layers, in chunks of 125 504
+    other = bench.measured_valu("poly500", [64, 8, 125], "fp32", 2.0, 500)
+    assert abs(other["flops_per_launch"] - 5.08e10 * 504 / 508) < 1.0 and "scaled" in other["source"]
+    assert bench.measured_valu("poly500", [64, 4, 63], "fp32", 2.0, 500)["achieved"] is None
+    assert bench.measured_valu("poly500", [64, 8, 125], "fp64", 3.0, 500)["frac"] == round(2e10 / 1e12 / 78.6, 4)
