@@ -218,6 +218,54 @@ def test_config_poly500_bench_launch_sampled_parity(E, orc):
     assert _rel(avg[E.PREC_MIXED], avg[E.PREC_FP64]) <= 1e-6
 
 
+def test_config_poly800_capacity_sampled_parity(E, orc):
+    """The 800^3 capacity point in the benchmark's launch configuration:
+    sampled operator, load and M^-1 nodes against the oracle, the M^-1
+    dictionary size, and after 20 iterations the residual recomputed from
+    the returned w (A w + b) against the recursion's, which ties the
+    deferred w updates to the operator at full size."""
+    import torch
+    from paper_2602_07354_amd import generate
+    say("case: poly800 capacity point")
+    rec = synth.workload_recipe("poly800")
+    dev = torch.device("cuda:0")
+    phase = torch.empty(int(np.prod(rec["shape"])), dtype=torch.int32, device=dev)
+    ms = generate.workload("poly800", phase=phase)
+    torch.cuda.synchronize()
+    host = synth.Microstructure(ms.shape, phase.cpu().numpy(), ms.C, ms.strain, ms.meta)
+    P = orc.Problem.from_micro(host)
+    rng = np.random.default_rng(800)
+    sel = np.sort(rng.choice(host.n, 200, replace=False))
+    opts = E.options_init(inputs_on_device=1, autotune=1, device=0)
+    h = E.setup(ms.shape, phase, ms.C, ms.strain[:1], opts)
+    try:
+        v = np.empty((3, host.n))
+        x = rng.standard_normal((3, host.n))
+        E.apply(h, x, v)
+        assert _rel(v[:, sel], P.apply_at(x, sel)) <= 1e-12
+        del x
+        b = np.empty((3, host.n))
+        E.get_load(h, 0, b)
+        assert _rel(b[:, sel], P.load_at(ms.strain[0], sel)) <= 1e-12
+        M = np.empty((6, host.n))
+        E.get_precond(h, M)
+        Ms = np.stack([M[q][sel] for q in (0, 5, 4, 5, 1, 3, 4, 3, 2)], axis=1).reshape(-1, 3, 3)
+        del M
+        assert _rel(Ms, P.precond_at(sel)) <= 1e-12
+        st, info = E.solve(h, 1e-30, 20, 1)
+        say("   20 iterations, recursive rel-res", info.relres_recursive[0], "tile", list(info.op_tile))
+        assert st == E.NOT_CONVERGED and info.iters[0] == 20
+        assert info.precond_rows == host.nphase + _boundary_nodes(host)
+        E.get_solution(h, 0, v)
+        g = np.empty_like(v)
+        E.apply(h, v, g)
+        g += b
+        rel = np.linalg.norm(g) / np.linalg.norm(b)
+        assert abs(rel - info.relres_recursive[0]) <= 1e-6 * info.relres_recursive[0]
+    finally:
+        E.destroy(h)
+
+
 def test_edge_cases(E, orc):
     say("case: edge cases")
     # the smallest grids (2 nodes in a dimension: both neighbours are the same
