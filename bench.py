@@ -74,7 +74,7 @@ def parse():
                     help="keep the default sweep geometry (32x8 workgroups) instead of autotuning it")
     ap.add_argument("--tile", type=int, default=None,
                     help="fix the workgroup shape of the fused sweep (index into elas3d.TILE_SHAPES) "
-                         "instead of autotuning")
+                         "instead of autotuning it (the update sweep is still autotuned)")
     ap.add_argument("--zchunk", type=int, default=0,
                     help="with --tile: z planes per workgroup (0 = automatic)")
     ap.add_argument("--nrhs", type=int, default=1, help="load cases solved per step (of the workload's)")
@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
                     help="fp64: the paper's FP64 PCG; mixed: FP32 inner PCG in FP64 refinement; "
                          "both: time both (the headline value is FP64)")
+    ap.add_argument("--stream-table", action="store_true",
+                    help="print the stream probe's rates per grid and access kind, then exit")
     return ap.parse_args()
 
 
@@ -162,23 +164,22 @@ def measured_valu(workload: str, tile, precision: str, op_ms: float, nz: int):
             "source": src}
 
 
-def copy_bandwidth(torch, dev, gib: float = 4.0) -> float:
-    """Device-to-device copy rate (read + write bytes / s), GB/s: the
-    practical HBM ceiling beside the datasheet peak."""
-    n = int(gib * (1 << 30)) // 8
-    a = torch.ones(n, dtype=torch.float64, device=dev)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        b.copy_(a)
-    e1.record()
-    e1.synchronize()
-    gbs = 5 * 2 * 8 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, b
-    torch.cuda.empty_cache()
-    return gbs
+def stream_rates(E, dev_index: int, gib: float = 4.0, table: bool = False) -> dict:
+    """Best plain-stream rates on the device (GB/s), the practical HBM ceiling
+    beside the datasheet peak: the library's copy, read-only and write-only
+    probe kernels (16 B per lane), plain and non-temporal, over a few grids
+    (each printed as a JSON line when table is set)."""
+    best = {"copy": 0.0, "read": 0.0, "write": 0.0}
+    opts = E.options_init(device=dev_index)
+    for blocks in (2048, 8192, 32768, 131072):
+        for nt in (False, True):
+            r = E.stream_bandwidth(int(gib * (1 << 30)), blocks=blocks, reps=5, nontemporal=nt, options=opts)
+            if table:
+                print(json.dumps({"buffer_GiB": gib, "workgroups": blocks, "nontemporal": nt,
+                                  **{k: round(v, 1) for k, v in r.items()}}), flush=True)
+            for k in best:
+                best[k] = max(best[k], r[k])
+    return {k: round(v, 1) for k, v in best.items()}
 
 
 def cpu_baseline(workload: str, edge: int, iters: int) -> dict:
@@ -219,6 +220,9 @@ def main():
     E.lib()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.stream_table:
+        print(json.dumps({"best": stream_rates(E, 0, table=True)}), flush=True)
+        return
     t_gen = time.perf_counter()
     if args.workload == "eshelby20" or args.host_generator:
         ms = synth.workload(args.workload, scale=args.scale) if args.workload != "eshelby20" \
@@ -236,7 +240,8 @@ def main():
     print(f"# generated {ms.meta.get('workload')} {ms.shape} in {t_gen:.1f} s "
           f"({'host' if ms.meta.get('generated_on') != 'device' else 'device'}), void {void_fraction:.4f}",
           file=sys.stderr, flush=True)
-    copy_gbs = copy_bandwidth(torch, dev)
+    streams = stream_rates(E, dev.index or 0)
+    copy_gbs = streams["copy"]
     if args.calib_copy_gib > 0:
         # a plain elementwise kernel that reads and writes exactly this many
         # bytes once (HBM-counter calibration under rocprofv3 --pmc)
@@ -260,7 +265,7 @@ def main():
     def step(record, precision):
         opts = E.options_init(inputs_on_device=1, outputs_on_device=1, timing=1, device=0,
                               stream=stream.cuda_stream,
-                              autotune=0 if (args.no_autotune or args.tile is not None) else 1,
+                              autotune=0 if args.no_autotune else (2 if args.tile is not None else 1),
                               tile=args.tile or 0, zchunk=args.zchunk if args.tile is not None else 0,
                               batched=1 if args.batched else 0,
                               precision=E.PREC_MIXED if precision == "mixed" else E.PREC_FP64)
@@ -311,6 +316,7 @@ def main():
                                    max(1, sum(r[1]["n_update"] for r in mrecs)), 4),
             "op_tile": mrecs[0][1]["op_tile"],
             "update_blocks": mrecs[0][1]["update_blocks"],
+            "update_nontemporal": mrecs[0][1]["update_nontemporal"],
         }
         mixed["valu"] = measured_valu(ms.meta.get("workload"), mixed["op_tile"], "fp32", mixed["operator_ms_avg"],
                                       ms.shape[2])
@@ -382,10 +388,11 @@ def main():
             "traffic": traffic["bytes"],
             "traffic_source": traffic["source"],
             "bytes_per_launch": round(op_bytes),
-            "copy_GBs_measured": round(copy_gbs, 1),
+            "stream_GBs_measured": streams,
             "frac_of_copy": round(achieved / copy_gbs, 4),
             "op_tile": tile,
             "update_blocks": recs[0][1]["update_blocks"],
+            "update_nontemporal": recs[0][1]["update_nontemporal"],
             "valu": (measured_valu(ms.meta.get("workload"), tile, "fp64" if head == "fp64" else "fp32", op_ms,
                                    ms.shape[2]) if nrhs == 1 else None),
         },

@@ -100,12 +100,16 @@ typedef struct elas3d_options {
                                   (32x8, 16x16, 64x4, 32x16, 64x8 lanes) and z-chunkings
                                   (about 2048 to 16384 workgroups) of the
                                   direction+operator sweep and
-                                  the grid of the update sweep on the live problem,
+                                  the grid (1024 to 32768 workgroups) and the
+                                  plain or non-temporal form of the update sweep
+                                  on the live problem,
                                   keep the fastest (cached per process by grid,
                                   precision and RHS count).  The reduction order
                                   then follows the chosen geometry, so results match
                                   the default geometry's to rounding, not bitwise.
-                                  Default 0                                          */
+                                  2: time the update sweep's candidates only; the
+                                  direction+operator sweep keeps options.tile and
+                                  zchunk.  Default 0                                 */
     int32_t tile;              /* workgroup shape of the direction+operator sweep
                                   when not autotuned: 0 = 32x8 lanes (default),
                                   1 = 16x16, 2 = 64x4, 3 = 32x16, 4 = 64x8          */
@@ -140,6 +144,8 @@ typedef struct elas3d_info {
                                                   phase (shared by the nodes whose
                                                   eight voxels all have it) plus one
                                                   per phase-boundary node            */
+    int32_t update_nontemporal;                /* 1 if the update sweep streams its
+                                                  node vectors non-temporally        */
 } elas3d_info;
 
 /* Fill `opt` with the defaults (FP64, residual criterion, block Jacobi,
@@ -312,6 +318,27 @@ int elas3d_group_run(elas3d_group* g, int32_t iters, elas3d_ctx** done, elas3d_i
 /* Release the group.  Members still running are abandoned (their contexts
  * stay valid, unsolved, on their own streams). */
 void elas3d_group_destroy(elas3d_group* g);
+
+/*
+ * Streaming-bandwidth probe (not part of a solve): the HBM rates that plain
+ * streams reach on the device, the practical ceiling for the solver's sweeps,
+ * which only stream vectors (the operator is matrix-free, Sec. 2.1.2).  The
+ * call allocates two buffers of `bytes` each (freed before it returns) and
+ * times three kernels on the options' device and stream (opt NULL:
+ * defaults): copy (read one buffer, write the other), read-only and
+ * write-only.  `blocks` workgroups of 256 lanes walk the buffer in a
+ * grid-stride loop, 16 bytes per lane and access; nontemporal = 1 makes
+ * every access non-temporal.  Each kernel runs once untimed, then `reps`
+ * times between two events.
+ *   gbs  (host) 3 doubles written: copy (bytes read + bytes written), read
+ *        and write rates, in 1e9 bytes per second.
+ * Returns 0, ELAS3D_EBADARG (gbs NULL, bytes < 1 MiB or not a multiple of
+ * 16, blocks outside [1, 2^24], reps outside [1, 10000], nontemporal not 0
+ * or 1; checked before any device call), ELAS3D_ENOMEM (the buffers do not
+ * fit) or ELAS3D_EDEVICE; the message is in elas3d_last_error(NULL).
+ */
+int elas3d_stream_bandwidth(int64_t bytes, int32_t blocks, int32_t reps, int32_t nontemporal, double* gbs,
+                            const elas3d_options* opt);
 
 /* Device bytes a context with these sizes and options allocates at most (0
  * for sizes that elas3d_setup would reject); the bound counts one M^-1 row

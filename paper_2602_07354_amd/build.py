@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libelas3d.so")
-SOURCES = ["elas3d_kernels.hip", "elas3d_api.hip", "elas3d_generate.hip", "elas3d_group.hip"]
+SOURCES = ["elas3d_kernels.hip", "elas3d_api.hip", "elas3d_generate.hip", "elas3d_group.hip",
+           "elas3d_stream.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

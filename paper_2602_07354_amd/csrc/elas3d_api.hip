@@ -59,7 +59,7 @@ void default_options(elas3d_options* o)
 // launch.
 long long partial_slots(const Dims& d, int nrhs, int tile, int zchunk)
 {
-    long long most = 65536;
+    long long most = kMinPartialSlots;
     for (int t = 0; t < e3d::kNumTiles; ++t)
         for (int target : kTuneTargets)
             most = std::max(most, (long long)e3d::op_geometry(d, 0, t, target).blocks * nrhs);
@@ -264,10 +264,15 @@ int export_field(elas3d_ctx* c, const double* field, int ncomp, double* out)
     return 0;
 }
 
-// Process-wide autotuning results: (device, nx, ny, nz, element size, RHS)
-// -> (operator sweep geometry, update grid).
+// Process-wide autotuning results: (device, nx, ny, nz, element size, RHS,
+// mode) -> (operator sweep geometry, update grid, update non-temporal);
+// mode 2 tunes the update sweep only (its geometry entry is not used).
+struct TuneChoice {
+    e3d::OpGeom geom;
+    int upd_blocks, upd_nt;
+};
 std::mutex g_tune_mu;
-std::map<std::array<int, 6>, std::pair<e3d::OpGeom, int>> g_tune_cache;
+std::map<std::array<int, 7>, TuneChoice> g_tune_cache;
 
 // Time every candidate geometry of the two iteration sweeps on the live
 // fields and keep the fastest.  Runs right after the start of a run, where
@@ -276,18 +281,21 @@ std::map<std::array<int, 6>, std::pair<e3d::OpGeom, int>> g_tune_cache;
 // leaves w alone, and the update sweep leaves g as it is and rewrites
 // z = M^-1 g; no finalize kernel runs, so the scalars are untouched.  (The
 // sweeps that also pay w's owed steps, every other iteration, are not
-// timed.)
+// timed.)  Option autotune = 2 keeps the operator sweep's geometry from
+// options.tile / zchunk and times the update sweep's candidates only.
 template <typename T>
 int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const e3d::MinvRows<T>& M)
 {
     const int pi = sizeof(T) == sizeof(double) ? 0 : 1;
-    const std::array<int, 6> key = {c->device, c->d.nx, c->d.ny, c->d.nz, (int)sizeof(T), R};
+    const bool op_too = c->opt.autotune != 2;
+    const std::array<int, 7> key = {c->device, c->d.nx, c->d.ny, c->d.nz, (int)sizeof(T), R, op_too ? 1 : 2};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            c->geom_sweep[pi] = it->second.first;
-            c->upd_blocks[pi] = it->second.second;
+            if (op_too) c->geom_sweep[pi] = it->second.geom;
+            c->upd_blocks[pi] = it->second.upd_blocks;
+            c->upd_nt[pi] = it->second.upd_nt;
             c->tuned[pi] = 1;
             return 0;
         }
@@ -310,7 +318,7 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
     int rc = 0;
     float best = 1e30f;
     e3d::OpGeom best_g = c->geom_sweep[pi];
-    for (int tile = 0; tile < e3d::kNumTiles && !rc; ++tile)
+    for (int tile = 0; tile < e3d::kNumTiles && !rc && op_too; ++tile)
         for (int target : kTuneTargets) {
             const e3d::OpGeom g = e3d::op_geometry(d, 0, tile, target);
             float ms = 0.f;
@@ -325,26 +333,30 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
             }
         }
     float best_u = 1e30f;
-    int best_nb = c->upd_blocks[pi];
-    for (int nb : kTuneUpdate) {
-        if (rc) break;
-        float ms = 0.f;
-        rc = time_it([&] {
-            return e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials, nb, false);
-        }, ms);
-        if (!rc && ms < best_u) {
-            best_u = ms;
-            best_nb = nb;
+    int best_nb = c->upd_blocks[pi], best_nt = c->upd_nt[pi];
+    for (int nt = 0; nt < 2; ++nt)
+        for (int nb : kTuneUpdate) {
+            if (rc) break;
+            float ms = 0.f;
+            rc = time_it([&] {
+                return e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials, nb, false,
+                                                     nt != 0);
+            }, ms);
+            if (!rc && ms < best_u) {
+                best_u = ms;
+                best_nb = nb;
+                best_nt = nt;
+            }
         }
-    }
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
     if (rc) return rc;
     c->geom_sweep[pi] = best_g;
     c->upd_blocks[pi] = best_nb;
+    c->upd_nt[pi] = best_nt;
     c->tuned[pi] = 1;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {best_g, best_nb};
+    g_tune_cache[key] = {best_g, best_nb, best_nt};
     return 0;
 }
 
@@ -368,6 +380,7 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const
     }
     const e3d::OpGeom geom = c->geom_sweep[pi];
     const int upd_blocks = c->upd_blocks[pi];
+    const bool upd_nt = c->upd_nt[pi] != 0;
     Scalars* S0 = c->S + r0;
     Scalars* h0 = c->hS;                      // slot 0
     Scalars* h1 = c->hS + e3d::kMaxRhs;       // slot 1
@@ -406,7 +419,7 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const
                                                            S0, c->partials);
                     if (e1 == hipSuccess)
                         e1 = e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials,
-                                                           upd_blocks);
+                                                           upd_blocks, true, upd_nt);
                 }
                 hipError_t e2 = hipStreamEndCapture(c->stream, &ge.graph);
                 if (e1 != hipSuccess || e2 != hipSuccess)
@@ -434,7 +447,7 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const
                     HIPCHK(c, hipEventRecord(c->ev_up[ev_used].a, c->stream));
                 }
                 HIPCHK(c, e3d::launch_update_precond<T>(c->stream, d, f0, rs, R, M, S0, c->partials,
-                                                        upd_blocks));
+                                                        upd_blocks, true, upd_nt));
                 if (timing) {
                     HIPCHK(c, hipEventRecord(c->ev_up[ev_used].b, c->stream));
                     ++ev_used;
@@ -778,6 +791,7 @@ int record_results(elas3d_ctx* c, int r0, int R, const CaseResult* res, elas3d_i
             info->op_tile[1] = e3d::kTileShapes[g.tile].ty;
             info->op_tile[2] = g.kz;
             info->update_blocks = c->upd_blocks[pi];
+            info->update_nontemporal = c->upd_nt[pi];
         }
         c->solved[r] = 1;
         worst = std::max(worst, fin.status);
@@ -891,6 +905,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     for (int q = 0; q < 2; ++q) {
         c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, opt.tile);
         c->upd_blocks[q] = kSweepBlocks;
+        c->upd_nt[q] = 0;
     }
     {
         const long long slots = partial_slots(c->d, nrhs, opt.tile, opt.zchunk);

@@ -174,7 +174,10 @@ hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, c
 // f describes RHS 0, RHS r lies r*rs elements further in every field, and S
 // points to nrhs consecutive scalar sets (a RHS whose flag is done is skipped).
 // finalize = false launches the sweep alone (autotuning at the start of a
-// run, where lambda = gamma = 0 leave the iterate unchanged).
+// run, where lambda = gamma = 0 leave the iterate unchanged).  The update
+// sweep runs on at most max_blocks workgroups (it writes 2 * kMaxRhs partial
+// sums per workgroup into partials); nontemporal streams its node vectors
+// past the caches.
 template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
                                      const int32_t* phase, const Tables& t, const FieldsT<T>& f,
@@ -183,7 +186,7 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
 template <typename T>
 hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f, size_t rs,
                                  int nrhs, const MinvRows<T>& M, Scalars* S, double* partials,
-                                 int max_blocks, bool finalize = true);
+                                 int max_blocks, bool finalize = true, bool nontemporal = false);
 template <typename T>
 hipError_t launch_final_update(hipStream_t st, const Dims& d, const FieldsT<T>& f, Scalars* S);
 // Refinement of the mixed-precision solve: r = A (w + d) + b in FP64, stored

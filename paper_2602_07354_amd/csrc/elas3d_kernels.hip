@@ -729,11 +729,29 @@ __global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, 
     block_partials<2, kBlock>(acc, partials, stride, blockIdx.x);
 }
 
+// A load or store of a streamed vector, optionally non-temporal (passed by
+// the caches: on grids far larger than the caches nothing streamed is
+// re-read from them before it is evicted anyway).
+template <bool NT, typename T>
+__device__ __forceinline__ T stream_load(const T* p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void stream_store(T v, T* p)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Algorithm 2, C-D for a batch of RHS sharing M^-1 (loaded once per node):
 // g -= lambda Ah, z = M^-1 g, partials z.g and g.g (FP64) per RHS.
 // (w -= lambda h is deferred to a later direction sweep, which reads h anyway.)
+// NT: the node vectors and dictionary indices are streamed non-temporally;
+// the M^-1 rows (the per-phase ones are shared by most nodes) are not.
 // (by value: the fields stay in scalar registers)
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, const size_t rs, const int nrhs,
                                             const MinvRows<T> M, const Scalars* S, double* partials,
                                             const int stride, const int bid, const int nblk)
@@ -756,7 +774,7 @@ __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, co
     // strength-reducing every field address into its own 64-bit induction
     // variable, which triples the register count
     for (int m = bid * kBlock + threadIdx.x; m < d.n; m += (unsigned)nblk * kBlock) {
-        const size_t mq = (size_t)M.idx[m] * kMS;
+        const size_t mq = (size_t)stream_load<NT>(M.idx + m) * kMS;
         T mm[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) mm[q] = M.m[q][mq];
@@ -767,15 +785,15 @@ __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, co
             const size_t o = (size_t)r * rs + (size_t)m * kVS;
             T g[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) g[c] = fma(-lam[r], f.Ah[c][o], f.g[c][o]);
+            for (int c = 0; c < 3; ++c) g[c] = fma(-lam[r], stream_load<NT>(f.Ah[c] + o), stream_load<NT>(f.g[c] + o));
             const T z0 = xx * g[0] + xy * g[1] + xz * g[2];
             const T z1 = xy * g[0] + yy * g[1] + yz * g[2];
             const T z2 = xz * g[0] + yz * g[1] + zz * g[2];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) f.g[c][o] = g[c];
-            f.z[0][o] = z0;
-            f.z[1][o] = z1;
-            f.z[2][o] = z2;
+            for (int c = 0; c < 3; ++c) stream_store<NT>(g[c], f.g[c] + o);
+            stream_store<NT>(z0, f.z[0] + o);
+            stream_store<NT>(z1, f.z[1] + o);
+            stream_store<NT>(z2, f.z[2] + o);
             acc[2 * r] += (double)z0 * g[0] + (double)z1 * g[1] + (double)z2 * g[2];
             acc[2 * r + 1] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
         }
@@ -783,13 +801,13 @@ __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, co
     block_partials<2 * kMaxRhs, kBlock>(acc, partials, stride, bid);
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ void __launch_bounds__(kBlock) update_precond_kernel(Dims d, FieldsT<T> f, size_t rs,
                                                                 int nrhs, MinvRows<T> M,
                                                                 const Scalars* S, double* partials,
                                                                 int stride)
 {
-    update_body<T>(d, f, rs, nrhs, M, S, partials, stride, blockIdx.x, gridDim.x);
+    update_body<T, NT>(d, f, rs, nrhs, M, S, partials, stride, blockIdx.x, gridDim.x);
 }
 
 // The steps still owed to w at the end of a run, oldest first.
@@ -1289,7 +1307,7 @@ __global__ void __launch_bounds__(kBlock) update_group_kernel(const UpdArgs<T>* 
     const int p = find_entry(first, n, b);
     const int nb = first[p + 1] - first[p];
     const UpdArgs<T> u = load_uniform(list + p);
-    update_body<T>(u.d, u.f, u.rs, u.nrhs, u.M, u.S, u.partials, nb, b - first[p], nb);
+    update_body<T, false>(u.d, u.f, u.rs, u.nrhs, u.M, u.S, u.partials, nb, b - first[p], nb);
 }
 
 #ifndef E3D_OP_TARGET_BLOCKS
@@ -1696,11 +1714,15 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
 template <typename T>
 hipError_t launch_update_precond(hipStream_t st, const Dims& d, const FieldsT<T>& f, size_t rs,
                                  int nrhs, const MinvRows<T>& M, Scalars* S, double* partials,
-                                 int max_blocks, bool finalize)
+                                 int max_blocks, bool finalize, bool nontemporal)
 {
     const int nb = sweep_blocks(d.n, max_blocks);
-    hipLaunchKernelGGL(update_precond_kernel<T>, dim3(nb), dim3(kBlock), 0, st, d, f, rs, nrhs,
-                       M, (const Scalars*)S, partials, nb);
+    if (nontemporal)
+        hipLaunchKernelGGL((update_precond_kernel<T, true>), dim3(nb), dim3(kBlock), 0, st, d, f, rs, nrhs,
+                           M, (const Scalars*)S, partials, nb);
+    else
+        hipLaunchKernelGGL((update_precond_kernel<T, false>), dim3(nb), dim3(kBlock), 0, st, d, f, rs, nrhs,
+                           M, (const Scalars*)S, partials, nb);
     if (!finalize) return hipGetLastError();
     hipLaunchKernelGGL(finalize_kernel<2>, dim3(nrhs), dim3(kFinThreads), 0, st, (int)FIN_UPDATE,
                        (const double*)partials, nb, nb, S, (double*)nullptr, (const double*)nullptr,
@@ -1853,7 +1875,8 @@ hipError_t launch_group_iteration(hipStream_t st, const GroupPlan& p)
                                                      const FieldsT<T>&, size_t, int, Scalars*,        \
                                                      double*, bool);                                 \
     template hipError_t launch_update_precond<T>(hipStream_t, const Dims&, const FieldsT<T>&, size_t, \
-                                                 int, const MinvRows<T>&, Scalars*, double*, int, bool);    \
+                                                 int, const MinvRows<T>&, Scalars*, double*, int, bool,     \
+                                                 bool);                                                     \
     template hipError_t launch_final_update<T>(hipStream_t, const Dims&, const FieldsT<T>&, Scalars*);     \
     template size_t group_plan_bytes<T>(int, int);                                                   \
     template hipError_t group_prepare<T>(hipStream_t, const GroupMember<T>*, int, char*, char*,       \

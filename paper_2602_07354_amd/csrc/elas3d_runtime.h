@@ -16,8 +16,13 @@ constexpr int kSweepBlocks = 4096;  // grid of the node-wise sweeps
 // autotuning candidates: workgroup targets of the operator sweep (every tile
 // shape) and grids of the update sweep
 constexpr int kTuneTargets[4] = {2048, 4096, 8192, 16384};
-constexpr int kTuneUpdate[5] = {1024, 2048, 4096, 8192, 16384};
+constexpr int kTuneUpdate[6] = {1024, 2048, 4096, 8192, 16384, 32768};
 constexpr int kPartialValues = 8;   // partial sums per block, upper bound
+constexpr int kMinPartialSlots = 65536;  // blocks' worth of partials, at least
+// the update sweep writes 2 * kMaxRhs partials per workgroup at stride
+// (its grid): the largest candidate grid must fit the smallest buffer
+static_assert((long long)kTuneUpdate[5] * 2 * kMaxRhs <= (long long)kPartialValues * kMinPartialSlots,
+              "update grid candidates overrun the partials buffer");
 constexpr int kDefaultPoll = 16;
 
 struct EventPair {
@@ -44,6 +49,7 @@ struct elas3d_ctx {
     // the defaults or the autotuned choice
     e3d::OpGeom geom_sweep[2]{};
     int upd_blocks[2] = {0, 0};
+    int upd_nt[2] = {0, 0};  // update sweep streams non-temporally (autotuned)
     int tuned[2] = {0, 0};
 
     int32_t* phase = nullptr;

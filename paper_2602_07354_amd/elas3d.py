@@ -24,7 +24,7 @@ __all__ = [
     "PRECOND_NONE", "TILE_SHAPES", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
     "setup", "solve", "stress", "apply", "get_load", "get_precond", "get_solution",
     "device_bytes", "destroy", "last_error", "version", "Context", "EXPORTS", "von_mises",
-    "generate_grains", "carve_pores", "PORE_STRIDE", "Group",
+    "generate_grains", "carve_pores", "PORE_STRIDE", "Group", "stream_bandwidth",
 ]
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
@@ -45,7 +45,7 @@ EXPORTS = (
     "elas3d_get_load", "elas3d_get_precond", "elas3d_get_solution", "elas3d_device_bytes",
     "elas3d_destroy", "elas3d_last_error", "elas3d_version", "elas3d_von_mises",
     "elas3d_generate_grains", "elas3d_carve_pores", "elas3d_group_create", "elas3d_group_add",
-    "elas3d_group_run", "elas3d_group_destroy",
+    "elas3d_group_run", "elas3d_group_destroy", "elas3d_stream_bandwidth",
 )
 
 
@@ -93,6 +93,7 @@ class Info(ctypes.Structure):
         ("op_tile", ctypes.c_int32 * 3),
         ("update_blocks", ctypes.c_int32),
         ("precond_rows", ctypes.c_int64),
+        ("update_nontemporal", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -115,6 +116,7 @@ class Info(ctypes.Structure):
             "op_tile": list(self.op_tile),
             "update_blocks": self.update_blocks,
             "precond_rows": self.precond_rows,
+            "update_nontemporal": self.update_nontemporal,
         }
 
 
@@ -186,6 +188,8 @@ def lib():
         L.elas3d_group_run.restype = ctypes.c_int
         L.elas3d_group_destroy.argtypes = [vp]
         L.elas3d_group_destroy.restype = None
+        L.elas3d_stream_bandwidth.argtypes = [ctypes.c_int64, i32, i32, i32, vp, ctypes.POINTER(Options)]
+        L.elas3d_stream_bandwidth.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -316,6 +320,16 @@ def device_bytes(shape, nphase: int, nrhs: int, options: Optional[Options] = Non
     nx, ny, nz = (int(s) for s in shape)
     return lib().elas3d_device_bytes(nx, ny, nz, int(nphase), int(nrhs),
                                      ctypes.byref(options) if options is not None else None)
+
+
+def stream_bandwidth(nbytes: int, blocks: int = 32768, reps: int = 5, nontemporal: bool = False,
+                     options: Optional[Options] = None) -> dict:
+    """elas3d_stream_bandwidth: copy, read and write rates in GB/s (1e9 B/s)."""
+    gbs = np.zeros(3)
+    rc = lib().elas3d_stream_bandwidth(int(nbytes), int(blocks), int(reps), int(bool(nontemporal)),
+                                       _ptr(gbs), ctypes.byref(options) if options is not None else None)
+    _check(rc)
+    return {"copy": float(gbs[0]), "read": float(gbs[1]), "write": float(gbs[2])}
 
 
 def destroy(ctx) -> None:

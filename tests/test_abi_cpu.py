@@ -43,8 +43,8 @@ def test_struct_layout_matches_c(E, tmp_path):
         'printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(elas3d_info, t_operator_ms), offsetof(elas3d_info, n_update),'
         ' offsetof(elas3d_info, fp64_fallback), offsetof(elas3d_info, op_tile),'
         ' offsetof(elas3d_info, update_blocks), offsetof(elas3d_options, autotune));\n'
-        'printf("%zu %zu %zu\\n", offsetof(elas3d_options, tile), offsetof(elas3d_options, zchunk),'
-        ' offsetof(elas3d_info, precond_rows));\n'
+        'printf("%zu %zu %zu %zu\\n", offsetof(elas3d_options, tile), offsetof(elas3d_options, zchunk),'
+        ' offsetof(elas3d_info, precond_rows), offsetof(elas3d_info, update_nontemporal));\n'
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -54,7 +54,8 @@ def test_struct_layout_matches_c(E, tmp_path):
           E.Options.graphs.offset, ctypes.sizeof(E.Info), E.Info.relres_true.offset,
           E.Info.t_operator_ms.offset, E.Info.n_update.offset, E.Info.fp64_fallback.offset,
           E.Info.op_tile.offset, E.Info.update_blocks.offset, E.Options.autotune.offset,
-          E.Options.tile.offset, E.Options.zchunk.offset, E.Info.precond_rows.offset]
+          E.Options.tile.offset, E.Options.zchunk.offset, E.Info.precond_rows.offset,
+          E.Info.update_nontemporal.offset]
     assert c == py
 
 
@@ -152,3 +153,19 @@ def test_generator_rejects_bad_arguments(E):
     with pytest.raises(E.Elas3dError):
         E.carve_pores((4, 4, 4), phase, 1, pore[None], float("nan"))
     assert E.lib().elas3d_von_mises(None, 0, None, None, None) == E.EBADARG
+
+
+def test_stream_probe_rejects_bad_arguments(E):
+    """Every argument is checked before the probe touches a device."""
+    for kw in (dict(nbytes=(1 << 20) - 16), dict(nbytes=(1 << 20) + 8), dict(blocks=0),
+               dict(blocks=(1 << 24) + 1), dict(reps=0), dict(reps=10001)):
+        args = dict(nbytes=1 << 20, blocks=64, reps=1)
+        args.update(kw)
+        with pytest.raises(E.Elas3dError) as ei:
+            E.stream_bandwidth(**args)
+        assert ei.value.code == E.EBADARG
+    L = E.lib()
+    assert L.elas3d_stream_bandwidth(1 << 20, 64, 1, 2, np.zeros(3).ctypes.data, None) == E.EBADARG
+    assert "nontemporal" in E.last_error()
+    assert L.elas3d_stream_bandwidth(1 << 20, 64, 1, 0, None, None) == E.EBADARG
+    assert "gbs is NULL" in E.last_error()

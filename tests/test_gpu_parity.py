@@ -617,12 +617,25 @@ def test_autotuned_geometry_solves_and_is_cached(E, orc):
             st, info = ctx.solve(1e-12, 20000)
             assert st == E.OK and info["relres_true"][0] <= 1e-12
             assert tuple(info["op_tile"][:2]) in E.TILE_SHAPES
-            assert info["update_blocks"] in (1024, 2048, 4096, 8192, 16384)
+            assert info["update_blocks"] in (1024, 2048, 4096, 8192, 16384, 32768)
+            assert info["update_nontemporal"] in (0, 1)
             assert abs(info["iters"][0] - ro["iters"]) <= 2
             assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
             infos.append(info)
-    assert infos[0]["op_tile"] == infos[1]["op_tile"]
-    assert infos[0]["update_blocks"] == infos[1]["update_blocks"]
+    for k in ("op_tile", "update_blocks", "update_nontemporal"):
+        assert infos[0][k] == infos[1][k], k
     with E.Context.from_micro(ms, autotune=1, precision=E.PREC_MIXED) as ctx:
         st, info = ctx.solve(1e-10, 20000)
         assert st == E.OK and info["relres_true"][0] <= 1e-10
+    # autotune = 2: the update sweep is tuned, the operator sweep keeps the
+    # geometry the options fix
+    say("case: autotune of the update sweep only, 64x8 fixed")
+    with E.Context.from_micro(ms, tile=4) as ctx:
+        _, fixed = ctx.solve(1e-12, 20000)
+    with E.Context.from_micro(ms, autotune=2, tile=4) as ctx:
+        st, info = ctx.solve(1e-12, 20000)
+        assert st == E.OK and info["relres_true"][0] <= 1e-12
+        assert info["op_tile"] == fixed["op_tile"] and tuple(info["op_tile"][:2]) == (64, 8)
+        assert info["update_blocks"] in (1024, 2048, 4096, 8192, 16384, 32768)
+        assert abs(info["iters"][0] - ro["iters"]) <= 2
+        assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
