@@ -341,13 +341,29 @@ __device__ __forceinline__ void finalize_body(int kind, const double* partials, 
     // sweeps enqueued after the stop flag was raised did no work: leave the
     // scalars of the finished run untouched
     if ((kind == FIN_DIRECTION || kind == FIN_UPDATE) && S->done) return;
+    // Each lane adds its partials in increasing block order.  The loads of
+    // kFinBatch consecutive strides are issued together, so that their
+    // latencies overlap (one at a time, a grid of 32768 update workgroups
+    // took about 90 us to reduce).
+    constexpr int kFinBatch = 8;
     double v[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kFinThreads) s += partials[(size_t)k * stride + b];
-        v[k] = s;
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    int b = threadIdx.x;
+    for (; b + (kFinBatch - 1) * kFinThreads < nblocks; b += kFinBatch * kFinThreads) {
+        double x[NV][kFinBatch];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int u = 0; u < kFinBatch; ++u) x[k][u] = partials[(size_t)k * stride + b + u * kFinThreads];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int u = 0; u < kFinBatch; ++u) v[k] += x[k][u];
     }
+    for (; b < nblocks; b += kFinThreads)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += partials[(size_t)k * stride + b];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
