@@ -116,6 +116,12 @@ typedef struct elas3d_options {
     int32_t zchunk;            /* z planes per workgroup of that sweep when not
                                   autotuned; 0 = automatic (about 4096 workgroups);
                                   values above nz mean nz                            */
+    int32_t update_blocks;     /* workgroups of the update sweep when not
+                                  autotuned: 0 = 4096 (default), else 1..32768
+                                  (at most one per 256 nodes)                        */
+    int32_t update_nontemporal; /* 1: the update sweep streams its node vectors
+                                  non-temporally when not autotuned; 0 (default)
+                                  plain loads and stores.  Same results bitwise     */
 } elas3d_options;
 
 typedef struct elas3d_info {
@@ -299,7 +305,8 @@ int elas3d_group_create(elas3d_group** out, const elas3d_options* opt);
  * to solve (zero load) finishes at once.  Members sweep with workgroup shape
  * 0 and the default z-chunking (options.tile, zchunk and autotune apply to
  * elas3d_solve only), so a member's results equal those of elas3d_solve with
- * the default geometry, bit for bit.  Returns 0, ELAS3D_EBADARG,
+ * the default geometry, bit for bit (options.update_blocks and
+ * update_nontemporal do not apply to members either).  Returns 0, ELAS3D_EBADARG,
  * ELAS3D_EORDER (in a group, or finished in one and not returned yet) or
  * ELAS3D_EDEVICE. */
 int elas3d_group_add(elas3d_group* g, elas3d_ctx* ctx, double tol, int32_t maxit);

@@ -167,6 +167,11 @@ int validate_options(const elas3d_options* o)
         return fail(nullptr, ELAS3D_EBADARG,
                     "options.tile must be in [0, " + std::to_string(e3d::kNumTiles - 1) + "]");
     if (o->zchunk < 0) return fail(nullptr, ELAS3D_EBADARG, "options.zchunk must be >= 0");
+    if (o->update_blocks < 0 || o->update_blocks > kMaxUpdateBlocks)
+        return fail(nullptr, ELAS3D_EBADARG,
+                    "options.update_blocks must be in [0, " + std::to_string(kMaxUpdateBlocks) + "]");
+    if (o->update_nontemporal != 0 && o->update_nontemporal != 1)
+        return fail(nullptr, ELAS3D_EBADARG, "options.update_nontemporal must be 0 or 1");
     return 0;
 }
 
@@ -904,8 +909,8 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->geom = e3d::op_geometry(c->d, 0);
     for (int q = 0; q < 2; ++q) {
         c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, opt.tile);
-        c->upd_blocks[q] = kSweepBlocks;
-        c->upd_nt[q] = 0;
+        c->upd_blocks[q] = opt.update_blocks > 0 ? opt.update_blocks : kSweepBlocks;
+        c->upd_nt[q] = opt.update_nontemporal;
     }
     {
         const long long slots = partial_slots(c->d, nrhs, opt.tile, opt.zchunk);

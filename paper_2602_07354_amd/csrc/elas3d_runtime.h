@@ -19,10 +19,11 @@ constexpr int kTuneTargets[4] = {2048, 4096, 8192, 16384};
 constexpr int kTuneUpdate[6] = {1024, 2048, 4096, 8192, 16384, 32768};
 constexpr int kPartialValues = 8;   // partial sums per block, upper bound
 constexpr int kMinPartialSlots = 65536;  // blocks' worth of partials, at least
+constexpr int kMaxUpdateBlocks = kTuneUpdate[5];  // largest update grid, tuned or set
 // the update sweep writes 2 * kMaxRhs partials per workgroup at stride
-// (its grid): the largest candidate grid must fit the smallest buffer
-static_assert((long long)kTuneUpdate[5] * 2 * kMaxRhs <= (long long)kPartialValues * kMinPartialSlots,
-              "update grid candidates overrun the partials buffer");
+// (its grid): the largest grid must fit the smallest buffer
+static_assert((long long)kMaxUpdateBlocks * 2 * kMaxRhs <= (long long)kPartialValues * kMinPartialSlots,
+              "update grids overrun the partials buffer");
 constexpr int kDefaultPoll = 16;
 
 struct EventPair {

@@ -68,6 +68,8 @@ class Options(ctypes.Structure):
         ("autotune", ctypes.c_int32),
         ("tile", ctypes.c_int32),
         ("zchunk", ctypes.c_int32),
+        ("update_blocks", ctypes.c_int32),
+        ("update_nontemporal", ctypes.c_int32),
     ]
 
 

@@ -45,6 +45,8 @@ def test_struct_layout_matches_c(E, tmp_path):
         ' offsetof(elas3d_info, update_blocks), offsetof(elas3d_options, autotune));\n'
         'printf("%zu %zu %zu %zu\\n", offsetof(elas3d_options, tile), offsetof(elas3d_options, zchunk),'
         ' offsetof(elas3d_info, precond_rows), offsetof(elas3d_info, update_nontemporal));\n'
+        'printf("%zu %zu\\n", offsetof(elas3d_options, update_blocks),'
+        ' offsetof(elas3d_options, update_nontemporal));\n'
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -55,7 +57,8 @@ def test_struct_layout_matches_c(E, tmp_path):
           E.Info.t_operator_ms.offset, E.Info.n_update.offset, E.Info.fp64_fallback.offset,
           E.Info.op_tile.offset, E.Info.update_blocks.offset, E.Options.autotune.offset,
           E.Options.tile.offset, E.Options.zchunk.offset, E.Info.precond_rows.offset,
-          E.Info.update_nontemporal.offset]
+          E.Info.update_nontemporal.offset, E.Options.update_blocks.offset,
+          E.Options.update_nontemporal.offset]
     assert c == py
 
 
@@ -98,7 +101,8 @@ def test_setup_rejects_bad_options(E):
     shape, phase, C, strain = _good()
     for kw in ({"precision": 7}, {"convergence": 3}, {"preconditioner": -1},
                {"poll_interval": -2}, {"hbm_budget_bytes": -1.0}, {"inner_tol": 2.0},
-               {"tile": 5}, {"tile": -1}, {"zchunk": -3}):
+               {"tile": 5}, {"tile": -1}, {"zchunk": -3}, {"update_blocks": -1},
+               {"update_blocks": 32769}, {"update_nontemporal": 2}):
         with pytest.raises(E.Elas3dError) as ei:
             E.setup(shape, phase, C, strain, E.options_init(**kw))
         assert ei.value.code == E.EBADARG

@@ -602,6 +602,37 @@ def test_fixed_z_chunking_matches_oracle(E, orc):
             assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
 
 
+def test_update_sweep_forms_are_bitwise_equal(E, orc):
+    """The plain and the non-temporal form of the update sweep compute the
+    same arithmetic: on the same grid their solves agree bit for bit (FP64,
+    mixed, three batched cases), and they solve to the oracle."""
+    ms = _small_poly((40, 36, 30), 71, grains=24)
+    ms3 = synth.polycrystal((40, 36, 33), 20, 72, [dict(kind="sphere", fraction=0.02, median=1.5, sigma=0.3)],
+                            synth.unit_load_cases()[:3])
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    cases = [("fp64", ms, dict(), 1e-12), ("mixed", ms, dict(precision=E.PREC_MIXED), 1e-10),
+             ("fp64 x3 batched", ms3, dict(batched=1), 1e-10)]
+    for name, m, kw, tol in cases:
+        for blocks in (32768, 37):
+            say("case: update forms,", name, "update grid", blocks)
+            out = []
+            for nt in (0, 1):
+                with E.Context.from_micro(m, update_blocks=blocks, update_nontemporal=nt, **kw) as ctx:
+                    st, info = ctx.solve(tol, 20000)
+                    assert st == E.OK and max(info["relres_true"]) <= tol
+                    assert info["update_blocks"] == blocks and info["update_nontemporal"] == nt
+                    out.append((info["iters"], [ctx.solution(r) for r in range(m.nrhs)],
+                                [ctx.stress(r)["sigma"] for r in range(m.nrhs)]))
+            assert out[0][0] == out[1][0]
+            for a, b in zip(out[0][1] + out[0][2], out[1][1] + out[1][2]):
+                assert np.array_equal(a, b)
+            if name == "fp64":
+                assert abs(out[0][0][0] - ro["iters"]) <= 2
+                so, _ = P.stress(ms.strain[0], ro["w"])
+                assert _rel(out[0][2][0], so) <= 1e-8
+
+
 def test_autotuned_geometry_solves_and_is_cached(E, orc):
     """Autotuning picks one of the candidate geometries, solves to the same
     answer (to rounding) as the default geometry, and a second context of the
