@@ -117,8 +117,9 @@ typedef struct elas3d_options {
                                   autotuned; 0 = automatic (about 4096 workgroups);
                                   values above nz mean nz                            */
     int32_t update_blocks;     /* workgroups of the update sweep when not
-                                  autotuned: 0 = 4096 (default), else 1..32768
-                                  (at most one per 256 nodes)                        */
+                                  autotuned: 0 = automatic (1024 on grids of at
+                                  most 2^21 nodes, else 4096), else 1..32768 (at
+                                  most one per 256 nodes)                            */
     int32_t update_nontemporal; /* 1: the update sweep streams its node vectors
                                   non-temporally when not autotuned; 0 (default)
                                   plain loads and stores.  Same results bitwise     */

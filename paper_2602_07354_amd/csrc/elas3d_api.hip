@@ -909,7 +909,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->geom = e3d::op_geometry(c->d, 0);
     for (int q = 0; q < 2; ++q) {
         c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, opt.tile);
-        c->upd_blocks[q] = opt.update_blocks > 0 ? opt.update_blocks : kSweepBlocks;
+        c->upd_blocks[q] = opt.update_blocks > 0 ? opt.update_blocks : default_update_blocks(c->d.n);
         c->upd_nt[q] = opt.update_nontemporal;
     }
     {

@@ -317,7 +317,7 @@ int build_plan(elas3d_group* g, int lane)
         gm.nrhs = m.R;
         gm.S = c->S;
         gm.partials = c->partials;
-        gm.upd_blocks = kSweepBlocks;
+        gm.upd_blocks = default_update_blocks(c->d.n);
         if constexpr (sizeof(T) == sizeof(double)) {
             gm.f = c->fields(0);
             gm.rs = c->rs64();

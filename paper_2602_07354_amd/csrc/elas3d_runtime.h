@@ -24,6 +24,12 @@ constexpr int kMaxUpdateBlocks = kTuneUpdate[5];  // largest update grid, tuned 
 // (its grid): the largest grid must fit the smallest buffer
 static_assert((long long)kMaxUpdateBlocks * 2 * kMaxRhs <= (long long)kPartialValues * kMinPartialSlots,
               "update grids overrun the partials buffer");
+
+// Grid of the update sweep when it is not autotuned (and of every group
+// member's): 4096 workgroups, or 1024 on grids of at most 2^21 nodes, where
+// fewer workgroups that each loop over more nodes, and a finalize over fewer
+// partials, measured faster (96^3, mixed precision: 37 -> 25 us per launch).
+inline int default_update_blocks(long long n) { return n <= (1LL << 21) ? 1024 : kSweepBlocks; }
 constexpr int kDefaultPoll = 16;
 
 struct EventPair {
