@@ -53,7 +53,11 @@ WORKLOAD_TEXT = {
     "poly300": "300^3 periodic Voronoi polycrystal, 3000 grains, 0.5% spheres + 0.5% oblate pores",
     "poly100": "100^3 periodic Voronoi polycrystal, 500 grains, 1% spherical pores, eps_xx = 1e-3",
     "eshelby20": "20^3 isotropic matrix with a stiff spherical inclusion, eps_xx = 1e-3",
+    "void500": "the paper's Eshelby timing case: 500^3 isotropic matrix (E = 194 GPa, nu = 0.2934) around "
+               "a centred spherical void of radius 20 voxels, eps_zz = 1e-3",
 }
+# workloads built on the host (the device generator makes polycrystals only)
+HOST_WORKLOADS = ("eshelby20", "void500")
 
 
 def parse():
@@ -85,6 +89,9 @@ def parse():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
                     help="fp64: the paper's FP64 PCG; mixed: FP32 inner PCG in FP64 refinement; "
                          "both: time both (the headline value is FP64)")
+    ap.add_argument("--criterion", default="residual", choices=["residual", "paper"],
+                    help="stop on ||g||/||b|| confirmed by the true residual (default), or on the paper's "
+                         "sqrt(z.g / z0.g0)")
     ap.add_argument("--stream-table", action="store_true",
                     help="print the stream probe's rates per grid and access kind, then exit")
     return ap.parse_args()
@@ -224,7 +231,7 @@ def main():
         print(json.dumps({"best": stream_rates(E, 0, table=True)}), flush=True)
         return
     t_gen = time.perf_counter()
-    if args.workload == "eshelby20" or args.host_generator:
+    if args.workload in HOST_WORKLOADS or args.host_generator:
         ms = synth.workload(args.workload, scale=args.scale) if args.workload != "eshelby20" \
             else synth.workload(args.workload)
         phase = torch.from_numpy(ms.phase).to(dev)
@@ -268,6 +275,7 @@ def main():
                               autotune=0 if args.no_autotune else (2 if args.tile is not None else 1),
                               tile=args.tile or 0, zchunk=args.zchunk if args.tile is not None else 0,
                               batched=1 if args.batched else 0,
+                              convergence=E.CONV_PAPER if args.criterion == "paper" else E.CONV_RESIDUAL,
                               precision=E.PREC_MIXED if precision == "mixed" else E.PREC_FP64)
         h = E.setup(ms.shape, phase, ms.C, ms.strain[:nrhs], opts)
         try:
@@ -338,8 +346,10 @@ def main():
     traffic = (measured_traffic(ms.meta.get("workload"), tile) if head == "fp64" and nrhs == 1
                else {"bytes": None, "source": None})
     out = {
-        "metric": "Gdof*iterations/s of the block-Jacobi PCG solve to true rel-res 1e-8 "
-                  "(whole step: setup + solve + stress); FP64 vs mixed time-to-solution beside it",
+        "metric": ("Gdof*iterations/s of the block-Jacobi PCG solve to true rel-res 1e-8 "
+                   if args.criterion == "residual" else
+                   "Gdof*iterations/s of the block-Jacobi PCG solve to the paper's sqrt(z.g/z0.g0) < tol ")
+                  + "(whole step: setup + solve + stress); FP64 vs mixed time-to-solution beside it",
         "value": round(value, 3),
         "unit": "Gdof*iter/s",
         "n_gpus": 1,
@@ -359,6 +369,7 @@ def main():
             "void_fraction": round(void_fraction, 5),
             "generator": ms.meta.get("generated_on", "host"),
             "tol": args.tol,
+            "criterion": args.criterion,
             "precision": head,
             "nrhs": nrhs,
             "batched": bool(args.batched),

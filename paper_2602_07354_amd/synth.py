@@ -319,6 +319,17 @@ def eshelby_inclusion(n: int = 20, radius: Optional[float] = None,
                            "radius": r})
 
 
+def void_sphere(n: int = 500) -> Microstructure:
+    """The paper's Eshelby benchmark, timed in its Table 4 (Sec. 3.1): an
+    isotropic matrix (E = 194 GPa, nu = 0.2934) around a centred spherical
+    void of radius 0.04 n voxels (2 um in a 50 um cube at 500^3), strained
+    1e-3 along X3.  The void is phase 1 with C = 0."""
+    ms = eshelby_inclusion(n, radius=0.04 * n, E_m=194.0, nu_m=0.2934, E_i=0.0, nu_i=0.0,
+                           strain=(0, 0, 1e-3, 0, 0, 0))
+    ms.meta["workload"] = f"void{n}"
+    return ms
+
+
 def _lognormal_radii(rng, median, sigma, n):
     return median * np.exp(sigma * rng.standard_normal(n))
 
@@ -406,7 +417,7 @@ def _poly_recipe(name: str):
     raise KeyError(name)
 
 
-WORKLOADS = ("eshelby20", "poly100", "poly300", "poly500", "poly800")
+WORKLOADS = ("eshelby20", "poly100", "poly300", "poly500", "poly800", "void500")
 
 
 def workload_recipe(name: str, scale: Optional[int] = None) -> dict:
@@ -426,6 +437,8 @@ def workload(name: str, scale: Optional[int] = None, nrhs: Optional[int] = None)
     voxels keeping its grain density and pore recipe (for bounded samples)."""
     if name == "eshelby20":
         return eshelby_inclusion(20)
+    if name == "void500":
+        return void_sphere(500 if scale is None else scale)
     rec = workload_recipe(name, scale)
     strain = np.array(rec["strain"], dtype=np.float64)
     if nrhs is not None:

@@ -89,3 +89,23 @@ def test_serving_request_recipe(n):
             assert ms.void_fraction() < 0.03
             return
     pytest.skip("no request of that size in the first seeds")
+
+
+def test_void_sphere_is_the_papers_timing_case():
+    """Sec. 3.1: E = 194 GPa, nu = 0.2934 around a zero-stiffness spherical
+    void of radius 2 um in a 50 um cube (0.04 of the edge), eps_33 = 1e-3.
+    The void is every voxel whose centre lies within the radius, counted here
+    by brute force."""
+    n = 50
+    ms = synth.workload("void500", scale=n)
+    assert ms.shape == (n, n, n) and ms.nphase == 2
+    r = 0.04 * n
+    c = (np.arange(n) + 0.5 - n / 2.0) ** 2
+    inside = (c[:, None, None] + c[None, :, None] + c[None, None, :]) <= r * r
+    assert np.array_equal(ms.phase.reshape(n, n, n) == 1, inside)
+    assert np.all(ms.C[1] == 0.0)
+    lam = 194.0 * 0.2934 / ((1 + 0.2934) * (1 - 2 * 0.2934))
+    mu = 194.0 / (2 * (1 + 0.2934))
+    assert np.isclose(ms.C[0][2, 2], lam + 2 * mu) and np.isclose(ms.C[0][3, 3], mu)
+    assert np.isclose(ms.C[0][0, 1], lam)
+    assert np.array_equal(ms.strain, [[0, 0, 1e-3, 0, 0, 0]])
