@@ -117,6 +117,30 @@ def test_paper_criterion_matches_oracle(E, orc):
     assert info["relres_precond"][0] < 1e-6
 
 
+def test_void_timing_case_parity(E, orc):
+    """The paper's timing case (a void of radius 0.04 of the edge in an
+    isotropic matrix, eps_33 = 1e-3) at 50^3: the solve to 1e-12 matches the
+    oracle's stress and iteration count, zero stress in the void, and with the
+    paper's criterion at 1e-8 the iteration count matches the oracle's."""
+    say("case: void timing case at 50^3")
+    ms = synth.workload("void500", scale=50)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    rp = P.solve(ms.strain[0], tol=1e-8, mode=1)
+    with E.Context.from_micro(ms) as ctx:
+        st, info = ctx.solve(1e-12, 20000)
+        assert st == E.OK and info["relres_true"][0] <= 1e-12
+        assert abs(info["iters"][0] - ro["iters"]) <= 2
+        sig = ctx.stress(0)["sigma"]
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    assert _rel(sig, so) <= 1e-8
+    assert np.all(sig[:, ms.phase == 1] == 0.0)
+    with E.Context.from_micro(ms, convergence=E.CONV_PAPER) as ctx:
+        st, info = ctx.solve(1e-8, 20000)
+    assert st == E.OK and abs(info["iters"][0] - rp["iters"]) <= 1
+    assert info["relres_precond"][0] < 1e-8
+
+
 def test_config_poly100_metric_and_sampled_parity(E, orc):
     """100^3 polycrystal with 1 % pores, eps_xx = 1e-3, tol 1e-10: sampled
     node parity at full size plus properties that hold at any size."""
