@@ -146,7 +146,9 @@ typedef struct elas3d_info {
     int32_t op_tile[3];                        /* workgroup lanes in x, y and z-chunk
                                                   length of the direction+operator
                                                   sweep (of the inner solve in mixed) */
-    int32_t update_blocks;                     /* grid of the update sweep           */
+    int32_t update_blocks;                     /* grid of the update sweep (launched
+                                                  with fewer workgroups when the grid
+                                                  has under 256 nodes per workgroup) */
     int64_t precond_rows;                      /* rows of the M^-1 dictionary: one per
                                                   phase (shared by the nodes whose
                                                   eight voxels all have it) plus one
