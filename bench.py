@@ -247,7 +247,11 @@ def main():
     print(f"# generated {ms.meta.get('workload')} {ms.shape} in {t_gen:.1f} s "
           f"({'host' if ms.meta.get('generated_on') != 'device' else 'device'}), void {void_fraction:.4f}",
           file=sys.stderr, flush=True)
-    streams = stream_rates(E, dev.index or 0)
+    try:
+        streams = stream_rates(E, dev.index or 0)
+    except E.Elas3dError as e:  # the benchmark stands without its context figure
+        print(f"# stream probe failed: {e}", file=sys.stderr, flush=True)
+        streams = {"copy": None, "read": None, "write": None}
     copy_gbs = streams["copy"]
     if args.calib_copy_gib > 0:
         # a plain elementwise kernel that reads and writes exactly this many
@@ -400,7 +404,7 @@ def main():
             "traffic_source": traffic["source"],
             "bytes_per_launch": round(op_bytes),
             "stream_GBs_measured": streams,
-            "frac_of_copy": round(achieved / copy_gbs, 4),
+            "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
             "op_tile": tile,
             "update_blocks": recs[0][1]["update_blocks"],
             "update_nontemporal": recs[0][1]["update_nontemporal"],
