@@ -1,6 +1,6 @@
 // Streaming-bandwidth probe: the rates that plain HBM streams reach on this
-// device, the practical ceiling against which the solver's sweeps (which only
-// stream vectors through HBM) are judged.  Not part of a solve.
+// device, the practical ceiling for the solver's sweeps (which only stream
+// vectors through HBM).  Not part of a solve.
 //
 // Three kernels over buffers the call allocates: copy (read a, write b), read
 // (sum a) and write (fill b).  Every lane moves 16 bytes per access in a
