@@ -36,3 +36,18 @@ def test_valu_flops_scale_with_the_z_chunk_only(tmp_path, monkeypatch):
     assert bench.measured_valu("poly500", [64, 4, 63], "fp32", 2.0, 500)["achieved"] is None
     # 6e10 flops in 3 ms: 20 TFLOP/s of the 78.6 peak
     assert bench.measured_valu("poly500", [64, 8, 125], "fp64", 3.0, 500)["frac"] == round(20.0 / 78.6, 4)
+
+
+def test_more_than_one_gpu_is_refused():
+    """The benchmark runs on one GPU: --gpus above 1 prints why and exits 2,
+    before anything touches a device."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
