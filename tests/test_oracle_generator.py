@@ -159,3 +159,53 @@ def test_von_mises_closed_forms_and_invariance():
     # sqrt(3 J2) with J2 from the deviator
     D = S - np.trace(S) / 3 * np.eye(3)
     assert np.isclose(a[0], np.sqrt(1.5 * np.sum(D * D)), rtol=1e-13)
+
+
+def _probe_voxels(shape, rng, count):
+    """Random voxels plus every corner and a voxel on each face of the box
+    (the places where the periodic minimum image wraps)."""
+    nx, ny, nz = shape
+    corners = [i + nx * (j + ny * k) for i in (0, nx - 1) for j in (0, ny - 1) for k in (0, nz - 1)]
+    faces = [0 + nx * (ny // 2 + ny * (nz // 2)), nx - 1 + nx * (ny // 2 + ny * (nz // 2)),
+             nx // 2 + nx * (0 + ny * (nz // 2)), nx // 2 + nx * (ny - 1 + ny * (nz // 2)),
+             nx // 2 + nx * (ny // 2 + ny * 0), nx // 2 + nx * (ny // 2 + ny * (nz - 1))]
+    return np.concatenate([rng.integers(0, nx * ny * nz, count), corners, faces]).astype(np.int64)
+
+
+@pytest.mark.parametrize("shape", [(13, 7, 5), (9, 16, 11), (4, 3, 17)])
+def test_grains_at_samples_the_full_assignment(shape):
+    # the sampled helper is Eq. (ellipsoid_dist) evaluated at chosen voxels:
+    # it must agree with the full brute-force map (pinned above by closed
+    # forms and the periodic k-d tree) wherever it is asked, weighted or not
+    rng = _rng(11 + shape[0])
+    box = np.array(shape, dtype=float)
+    seeds = rng.random((23, 3)) * box
+    semi = np.stack([0.6 + rng.random(23), 0.6 + 2.0 * rng.random(23)], axis=1)
+    idx = _probe_voxels(shape, rng, 200)
+    for s in (None, semi):
+        full = oracle.grains(shape, seeds, s)
+        assert np.array_equal(oracle.grains_at(shape, seeds, s, idx), full[idx])
+
+
+@pytest.mark.parametrize("shape", [(15, 11, 9), (8, 19, 6)])
+def test_covered_at_is_the_void_mask_of_carving_every_pore(shape):
+    # a voxel is covered iff carving all pores (no target) makes it void
+    # (Sec. 2.2.3 pore overwrite; the carving is pinned above by lattice
+    # counts, a quarter-turn symmetry and periodic wrap)
+    rng = _rng(23 + shape[1])
+    box = np.array(shape, dtype=float)
+    pores = []
+    for t in range(9):
+        Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        c = rng.random(3) * box
+        if t == 0:
+            c = np.array([0.05, box[1] - 0.05, box[2] - 0.1])  # straddles a corner of the box
+        pores.append(_pore(c, 0.7 + 2.5 * rng.random(3), Q))
+    pores = np.stack(pores)
+    n = int(np.prod(shape))
+    ph, used, nvoid = oracle.carve(shape, np.zeros(n, np.int32), 7, pores)
+    assert used == len(pores) and 0 < nvoid < n
+    idx = np.concatenate([_probe_voxels(shape, rng, 300), np.flatnonzero(ph == 7)[:50]])
+    got = oracle.covered_at(shape, pores, idx)
+    assert np.array_equal(got, (ph[idx] == 7).astype(np.int32))
+    assert got.sum() > 0 and got.sum() < idx.size
