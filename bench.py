@@ -2,13 +2,26 @@
 
 One step = one pass of the whole path over one synthetic microstructure
 already resident in HBM: elas3d_setup (coefficient tables, load vector,
-block-Jacobi inverse), elas3d_solve to a true relative residual of `tol`,
-elas3d_stress (voxel stress planes, mean stress, energy) and destroy.
+block-Jacobi inverse), elas3d_solve for a fixed block of PCG iterations
+(init, the iteration sweeps, the true residual), elas3d_stress (voxel
+stress planes, mean stress, energy) and destroy.  The solve runs the
+product path: iteration batches replayed as HIP graphs, sweep geometry
+autotuned on the first step.  The value is Gdof*iterations/s over the whole
+step (3N x iterations / step time).
 
-Prints one JSON line with the throughput in Gdof*iterations/s over the
-whole step, the roofline of the dominant kernel (the fused
-direction + operator sweep, timed with HIP events on its own stream) and
-the CPU oracle timed on a bounded sample of the same recipe.
+Beside it, measured once per precision outside the timed steps:
+  - time to solution: the same problem solved to a true relative residual
+    of `tol` (FP64 PCG, and FP32 inner PCG inside FP64 refinement);
+  - kernel durations: one extra step with HIP events recorded on the
+    library's stream around every iteration sweep (eager launches, same
+    geometry), which gives the roofline of the dominant kernel (the fused
+    direction + operator sweep);
+  - the CPU oracle on a bounded sample of the same recipe, serial and, when
+    the OpenMP build of the oracle is present, on all host cores.
+
+Progress goes to stderr; one JSON line goes to stdout at the end.  A
+wall-clock budget skips the optional parts (mixed precision, time to
+solution, CPU baseline) that would not fit, and says so in the line.
 
 The microstructure is generated on the device (same recipe and random
 stream as the host generator) before anything is timed.  The measured HBM
@@ -22,6 +35,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import re
 import sys
 import time
@@ -43,6 +57,7 @@ KERNEL_SOURCES = ("paper_2602_07354_amd/csrc/elas3d_kernels.hip", "paper_2602_07
 # values).  Per launch: 5.5 vectors + phase.
 OPERATOR_BYTES_PER_NODE_FP64 = (4 * 24 + 4 + 7 * 24 + 4) / 2  # 136
 OPERATOR_BYTES_PER_NODE_FP32 = (4 * 12 + 4 + 7 * 12 + 4) / 2  # 70
+HOST_THREAD_CAP = 16  # host cores a one-GPU job may use
 
 WORKLOAD_TEXT = {
     "poly500": "500^3 periodic Voronoi polycrystal, 8000 rotated cubic SS316L grains "
@@ -60,18 +75,24 @@ WORKLOAD_TEXT = {
 HOST_WORKLOADS = ("eshelby20", "void500")
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="poly500", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--scale", type=int, default=None, help="re-size the workload to scale^3")
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--maxit", type=int, default=50000)
+    ap.add_argument("--tol", type=float, default=1e-8, help="tolerance of the time-to-solution solves")
+    ap.add_argument("--block-iters", type=int, default=256,
+                    help="PCG iterations of the solve in one timed step")
+    ap.add_argument("--maxit", type=int, default=50000, help="iteration cap of the time-to-solution solves")
+    ap.add_argument("--no-tts", action="store_true", help="skip the time-to-solution solves")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock seconds after which optional parts are skipped")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=100, help="edge of the oracle sample grid")
-    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--cpu-sample", type=int, default=160, help="edge of the oracle's sample grid")
+    ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations timed (0 = automatic)")
+    ap.add_argument("--no-stream-probe", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -88,13 +109,13 @@ def parse():
                     help="generate the microstructure on the host instead of the device")
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
                     help="fp64: the paper's FP64 PCG; mixed: FP32 inner PCG in FP64 refinement; "
-                         "both: time both (the headline value is FP64)")
+                         "both: the FP64 steps are the headline, mixed precision is timed beside them")
     ap.add_argument("--criterion", default="residual", choices=["residual", "paper"],
                     help="stop on ||g||/||b|| confirmed by the true residual (default), or on the paper's "
                          "sqrt(z.g / z0.g0)")
     ap.add_argument("--stream-table", action="store_true",
                     help="print the stream probe's rates per grid and access kind, then exit")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def source_code(text: str) -> str:
@@ -189,35 +210,114 @@ def stream_rates(E, dev_index: int, gib: float = 4.0, table: bool = False) -> di
     return {k: round(v, 1) for k, v in best.items()}
 
 
-def cpu_baseline(workload: str, edge: int, iters: int) -> dict:
-    """The oracle (serial FP64 C) on a bounded sample: the same recipe at edge^3."""
-    import oracle
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(HOST_THREAD_CAP, n))
+
+
+def _oracle_sample(workload: str, edge: int):
+    """The workload's recipe at edge^3 (host arrays), and its name."""
     from paper_2602_07354_amd import synth
+    if workload == "eshelby20":
+        return synth.workload(workload)
+    if workload in HOST_WORKLOADS:
+        return synth.workload(workload, scale=edge)
+    from paper_2602_07354_amd import generate
+    return generate.workload(workload, scale=edge)
 
-    ms = synth.workload(workload, scale=edge) if workload != "eshelby20" else synth.workload(workload)
-    P = oracle.Problem.from_micro(ms)
-    b, r2 = P.load(ms.strain[0])
-    minv = P.precond()
+
+def _oracle_rate(P, strain, b, minv, iters: int, target_s: float):
+    """Seconds per PCG iteration of the oracle: after one untimed run (cold
+    caches), the time of a run of 1 + k iterations minus that of a run of 1
+    (both pay the same start-up preconditioner apply, closing true residual
+    and allocations), over k."""
     t0 = time.perf_counter()
-    r = P.solve(ms.strain[0], tol=0.0, maxit=iters, b=b, minv=minv)
-    dt = time.perf_counter() - t0
-    n_it = max(1, r["iters"])
-    return {
-        "value": 3.0 * ms.n * n_it / dt / 1e9,
-        "unit": "Gdof*iter/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"serial FP64 oracle PCG, {n_it} iterations on the {ms.meta['workload']} grid "
-                  f"({ms.n} voxels, same grain density and pore recipe), {dt:.1f} s",
-    }
+    P.solve(strain, tol=0.0, maxit=0, b=b, minv=minv)
+    t_warm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P.solve(strain, tol=0.0, maxit=1, b=b, minv=minv)
+    t_one = time.perf_counter() - t0
+    if iters <= 0:  # about target_s of iterations
+        iters = int(min(50, max(2, round(target_s / max(1e-3, t_one - 0.5 * t_warm)))))
+    t0 = time.perf_counter()
+    r = P.solve(strain, tol=0.0, maxit=1 + iters, b=b, minv=minv)
+    t_k = time.perf_counter() - t0
+    k = max(1, r["iters"] - 1)
+    return max(1e-9, (t_k - t_one) / k), k, t_warm + t_one + t_k
 
 
-def main():
-    args = parse()
+def cpu_baseline(workload: str, edge: int, iters: int, n_full: int, gpu_iters, time_left: float) -> dict:
+    """The oracle (plain FP64 C, the same algorithm) on a bounded sample: the
+    workload's recipe at edge^3, per-iteration time by difference of two
+    runs, serial on one core and (OpenMP build) on the host's cores.  The
+    time to solution of the full grid is extrapolated as seconds per
+    iteration x (N_full / N_sample) x the GPU's FP64 iteration count."""
+    import oracle
+
+    ms = _oracle_sample(workload, edge)
+    phase = np.asarray(ms.phase)
+    strain = ms.strain[0]
+    out = {"unit": "Gdof*iter/s", "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "sample": f"the {workload} recipe at {ms.shape[0]}x{ms.shape[1]}x{ms.shape[2]} ({ms.n} voxels, "
+                     f"same grain density and pores, generated with the same seeds), FP64 oracle PCG; "
+                     f"seconds per iteration from a run of 1 + k iterations minus a run of 1"}
+    legs = []
+    threads = host_threads()
+    if threads > 1 and oracle.threaded_available():
+        legs.append(("threaded", threads))
+    legs.append(("serial", 1))
+    # seconds of timed iterations per leg, less when little time is left
+    scale = max(0.25, min(1.0, time_left / 120.0))
+    for name, nt in legs:
+        t0 = time.perf_counter()
+        P = oracle.Problem(ms.shape, phase, ms.C, threads=nt if name == "threaded" else 0)
+        b, _ = P.load(strain)
+        minv = P.precond()
+        t_setup = time.perf_counter() - t0
+        s_it, k, spent = _oracle_rate(P, strain, b, minv, iters, scale * (4.0 if name == "threaded" else 8.0))
+        leg = {"value": round(3.0 * ms.n / s_it / 1e9, 5), "threads": nt, "iters": k,
+               "s_per_iter": round(s_it, 4), "setup_s": round(t_setup, 2), "timed_s": round(spent, 2)}
+        if gpu_iters:
+            leg["extrapolated_time_to_solution_s"] = round(s_it * (n_full / ms.n) * gpu_iters, 1)
+        out[name] = leg
+        del P, b, minv
+    head = out.get("threaded") or out["serial"]
+    out["value"] = head["value"]
+    out["cores"] = head["threads"]
+    if gpu_iters:
+        out["extrapolation"] = (f"time to solution of the full grid ({n_full} voxels) extrapolated from the "
+                                f"sample: s/iteration x {n_full / ms.n:.3g} (voxel ratio) x {gpu_iters} (the "
+                                f"GPU's FP64 iterations to the tolerance); not a measured solve")
+    return out
+
+
+def main(argv=None):
+    args = parse(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; sharding the solve over "
                                    "several GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
+    t_start = time.perf_counter()
+
+    def elapsed():
+        return time.perf_counter() - t_start
+
+    def note(msg):
+        print(f"# [{elapsed():6.1f} s] {msg}", file=sys.stderr, flush=True)
 
     import torch
 
@@ -244,14 +344,15 @@ def main():
         void_fraction = ms.meta["void_fraction"]
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
-    print(f"# generated {ms.meta.get('workload')} {ms.shape} in {t_gen:.1f} s "
-          f"({'host' if ms.meta.get('generated_on') != 'device' else 'device'}), void {void_fraction:.4f}",
-          file=sys.stderr, flush=True)
-    try:
-        streams = stream_rates(E, dev.index or 0)
-    except E.Elas3dError as e:  # the benchmark stands without its context figure
-        print(f"# stream probe failed: {e}", file=sys.stderr, flush=True)
-        streams = {"copy": None, "read": None, "write": None}
+    note(f"generated {ms.meta.get('workload')} {ms.shape} in {t_gen:.1f} s "
+         f"({'host' if ms.meta.get('generated_on') != 'device' else 'device'}), void {void_fraction:.4f}")
+    streams = {"copy": None, "read": None, "write": None}
+    if not args.no_stream_probe:
+        try:
+            streams = stream_rates(E, dev.index or 0)
+            note(f"stream probe {streams}")
+        except E.Elas3dError as e:  # the benchmark stands without its context figure
+            note(f"stream probe failed: {e}")
     copy_gbs = streams["copy"]
     if args.calib_copy_gib > 0:
         # a plain elementwise kernel that reads and writes exactly this many
@@ -273,93 +374,126 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.synchronize()
 
-    def step(record, precision):
-        opts = E.options_init(inputs_on_device=1, outputs_on_device=1, timing=1, device=0,
+    def step(precision, maxit, timing=False):
+        """setup + solve (at most maxit iterations per case) + stress + destroy;
+        returns (status, info dict, {setup, solve, stress} in ms)."""
+        opts = E.options_init(inputs_on_device=1, outputs_on_device=1, timing=1 if timing else 0, device=0,
                               stream=stream.cuda_stream,
                               autotune=0 if args.no_autotune else (2 if args.tile is not None else 1),
                               tile=args.tile or 0, zchunk=args.zchunk if args.tile is not None else 0,
                               batched=1 if args.batched else 0,
                               convergence=E.CONV_PAPER if args.criterion == "paper" else E.CONV_RESIDUAL,
                               precision=E.PREC_MIXED if precision == "mixed" else E.PREC_FP64)
+        t0 = time.perf_counter()
         h = E.setup(ms.shape, phase, ms.C, ms.strain[:nrhs], opts)
+        t1 = time.perf_counter()
         try:
-            st, info = E.solve(h, args.tol, args.maxit, nrhs)
+            st, info = E.solve(h, args.tol, maxit, nrhs)
+            t2 = time.perf_counter()
             # voxel stress planes go to a device buffer; mean stress and energy to the host
             for r in range(nrhs):
-                E.lib().elas3d_stress(h, r, sigma.data_ptr(), avg.ctypes.data, None, energy.ctypes.data)
+                E.stress(h, r, sigma, avg, None, energy)
+            t3 = time.perf_counter()
         finally:
             E.destroy(h)
-        if record is not None:
-            record.append((st, info.as_dict()))
+        return st, info.as_dict(), {"setup": 1e3 * (t1 - t0), "solve": 1e3 * (t2 - t1), "stress": 1e3 * (t3 - t2)}
 
-    def timed(precision):
+    def timed_steps(precision):
         for _ in range(args.warmup):
-            step(None, precision)
+            step(precision, args.block_iters)
         torch.cuda.synchronize()
-        print(f"# {precision}: warm-up done", file=sys.stderr, flush=True)
+        note(f"{precision}: {args.warmup} warm-up steps done")
         recs = []
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(recs, precision)
-            print(f"# {precision}: step done, {sum(recs[-1][1]['iters'])} iterations", file=sys.stderr, flush=True)
+            recs.append(step(precision, args.block_iters))
         torch.cuda.synchronize()
-        return recs, time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        note(f"{precision}: {args.steps} timed steps in {dt:.2f} s, "
+             f"{sum(recs[-1][1]['iters'])} iterations per step")
+        return recs, dt
 
+    def kernel_times(precision):
+        """Mean duration of the fused sweep and of the update sweep (each with
+        its finalize), HIP events on the library's stream, over one step."""
+        st, info, _ = step(precision, args.block_iters, timing=True)
+        op_ms = info["t_operator_ms"] / max(1, info["n_operator"])
+        up_ms = info["t_update_ms"] / max(1, info["n_update"])
+        note(f"{precision}: kernel timing step, fused sweep {op_ms:.4f} ms, update {up_ms:.4f} ms "
+             f"({info['n_operator']} launches)")
+        return op_ms, up_ms, info
+
+    def tts(precision):
+        """Time to solution: one solve to tol from w = 0 (setup and stress apart)."""
+        st, info, ms_ = step(precision, args.maxit)
+        note(f"{precision}: solved to {args.tol:g} in {info['t_solve_s']:.3f} s, {sum(info['iters'])} iterations, "
+             f"true rel-res {max(info['relres_true']):.2e}, status {st}")
+        out = {"status": st, "time_to_solution_s": round(info["t_solve_s"], 4), "iters": info["iters"],
+               "restarts": info["restarts"], "relres_true": info["relres_true"],
+               "setup_ms": round(ms_["setup"], 2), "stress_ms": round(ms_["stress"], 2),
+               "gdof_iter_per_s": round(3.0 * ms.n * sum(info["iters"]) / max(1e-9, info["t_solve_s"]) / 1e9, 3)}
+        if precision == "mixed":
+            out["fp64_fallback"] = info["fp64_fallback"]
+        return out
+
+    def leg_summary(recs, dt):
+        iters = [sum(r[1]["iters"]) for r in recs]
+        ms_step = 1e3 * dt / len(recs)
+        parts = {k: round(float(np.median([r[2][k] for r in recs])), 3) for k in ("setup", "solve", "stress")}
+        return {
+            "ms_per_step": round(ms_step, 3),
+            "iters_per_step": iters[0] if len(set(iters)) == 1 else iters,
+            "gdof_iter_per_s": round(3.0 * ms.n * float(np.mean(iters)) / (ms_step / 1e3) / 1e9, 3),
+            "median_ms": parts,
+            "gdof_iter_per_s_solve_only": round(3.0 * ms.n * float(np.mean(iters)) / (parts["solve"] / 1e3) / 1e9, 3),
+            "op_tile": recs[0][1]["op_tile"],
+            "update_blocks": recs[0][1]["update_blocks"],
+            "update_nontemporal": recs[0][1]["update_nontemporal"],
+        }
+
+    skipped = []
     head = "mixed" if args.precision == "mixed" else "fp64"
-    recs, dt = timed(head)
+    recs, dt = timed_steps(head)
+    main_leg = leg_summary(recs, dt)
+    op_ms, up_ms, kinfo = kernel_times(head)
     mixed = None
     if args.precision == "both":
-        mrecs, mdt = timed("mixed")
-        m_iters = [sum(r[1]["iters"]) for r in mrecs]
-        m_ms = 1e3 * mdt / args.steps
-        m_tts = [r[1]["t_solve_s"] for r in mrecs]
-        mixed = {
-            "precision": "FP32 inner PCG + FP64 refinement (FP64 residual, update, dots, 3x3 inversions)",
-            "ms_per_step": round(m_ms, 3),
-            "time_to_solution_s": [round(t, 4) for t in m_tts],
-            "inner_iters": [r[1]["iters"] for r in mrecs],
-            "refinement_cycles": [r[1]["restarts"] for r in mrecs],
-            "relres_true": [max(r[1]["relres_true"]) for r in mrecs],
-            "fp64_fallback": [r[1]["fp64_fallback"] for r in mrecs],
-            "gdof_iter_per_s": round(3.0 * ms.n * float(np.mean(m_iters)) / (m_ms / 1e3) / 1e9, 3),
-            "operator_ms_avg": round(sum(r[1]["t_operator_ms"] for r in mrecs) /
-                                     max(1, sum(r[1]["n_operator"] for r in mrecs)), 4),
-            "update_ms_avg": round(sum(r[1]["t_update_ms"] for r in mrecs) /
-                                   max(1, sum(r[1]["n_update"] for r in mrecs)), 4),
-            "op_tile": mrecs[0][1]["op_tile"],
-            "update_blocks": mrecs[0][1]["update_blocks"],
-            "update_nontemporal": mrecs[0][1]["update_nontemporal"],
-        }
-        mixed["valu"] = measured_valu(ms.meta.get("workload"), mixed["op_tile"], "fp32", mixed["operator_ms_avg"],
-                                      ms.shape[2])
+        if elapsed() < args.budget_s:
+            mrecs, mdt = timed_steps("mixed")
+            mixed = leg_summary(mrecs, mdt)
+            m_op, m_up, _ = kernel_times("mixed")
+            mixed["precision"] = "FP32 inner PCG + FP64 refinement (FP64 residual, update, dots, 3x3 inversions)"
+            mixed["operator_ms_avg"] = round(m_op, 4)
+            mixed["update_ms_avg"] = round(m_up, 4)
+            mixed["valu"] = measured_valu(ms.meta.get("workload"), mixed["op_tile"], "fp32", m_op, ms.shape[2])
+        else:
+            skipped.append("mixed steps")
+    tts_out = {}
+    if not args.no_tts:
+        for prec in ([head, "mixed"] if args.precision == "both" else [head]):
+            if elapsed() < args.budget_s:
+                tts_out[prec] = tts(prec)
+            else:
+                skipped.append(f"{prec} time to solution")
 
-    iters = [sum(r[1]["iters"]) for r in recs]  # summed over the load cases
-    t_op = sum(r[1]["t_operator_ms"] for r in recs)
-    n_op = sum(r[1]["n_operator"] for r in recs)
-    t_up = sum(r[1]["t_update_ms"] for r in recs)
-    n_up = sum(r[1]["n_update"] for r in recs)
-    ms_step = 1e3 * dt / args.steps
-    dof_iters = 3.0 * ms.n * float(np.mean(iters))
-    value = dof_iters / (ms_step / 1e3) / 1e9
-    op_ms = t_op / max(1, n_op)
-    # a batched launch sweeps every RHS still running: RHS-sweeps per launch
-    rhs_per_launch = (sum(iters) / max(1, n_op)) if args.batched else 1.0
+    value = main_leg["gdof_iter_per_s"]
+    rhs_per_launch = (sum(kinfo["iters"]) / max(1, kinfo["n_operator"])) if args.batched else 1.0
     op_bytes = (OPERATOR_BYTES_PER_NODE_FP64 if head == "fp64" else OPERATOR_BYTES_PER_NODE_FP32) * ms.n * rhs_per_launch
     achieved = op_bytes / (op_ms / 1e3) / 1e9
-    tile = recs[0][1]["op_tile"]
+    tile = main_leg["op_tile"]
     traffic = (measured_traffic(ms.meta.get("workload"), tile) if head == "fp64" and nrhs == 1
                else {"bytes": None, "source": None})
     out = {
-        "metric": ("Gdof*iterations/s of the block-Jacobi PCG solve to true rel-res 1e-8 "
-                   if args.criterion == "residual" else
-                   "Gdof*iterations/s of the block-Jacobi PCG solve to the paper's sqrt(z.g/z0.g0) < tol ")
-                  + "(whole step: setup + solve + stress); FP64 vs mixed time-to-solution beside it",
-        "value": round(value, 3),
+        "metric": ("Gdof*iterations/s of the block-Jacobi PCG over whole steps (setup + "
+                   f"{args.block_iters} PCG iterations + true residual + stress); time to true rel-res "
+                   f"{args.tol:g}, FP64 vs mixed precision, beside it"),
+        "value": value,
         "unit": "Gdof*iter/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -373,25 +507,24 @@ def main():
             "void_fraction": round(void_fraction, 5),
             "generator": ms.meta.get("generated_on", "host"),
             "tol": args.tol,
+            "block_iters": args.block_iters,
             "criterion": args.criterion,
             "precision": head,
             "nrhs": nrhs,
             "batched": bool(args.batched),
+            "graphs": True,
             "parallelism": "single GPU",
         },
-        "iters": [r[1]["iters"] for r in recs] if nrhs > 1 else iters,
+        "step": main_leg,
         "status": [r[0] for r in recs],
-        "relres_true": [max(r[1]["relres_true"]) for r in recs],
-        "refinement_cycles": [r[1]["restarts"] for r in recs] if head == "mixed" else None,
-        "fp64_fallback": [r[1]["fp64_fallback"] for r in recs] if head == "mixed" else None,
-        "time_to_solution_s": [round(r[1]["t_solve_s"], 4) for r in recs],
+        "time_to_solution": tts_out or None,
         "mixed": mixed,
         "mixed_speedup_time_to_solution": (
-            round(float(np.mean([r[1]["t_solve_s"] for r in recs])) /
-                  float(np.mean(mixed["time_to_solution_s"])), 3) if mixed else None),
+            round(tts_out[head]["time_to_solution_s"] / tts_out["mixed"]["time_to_solution_s"], 3)
+            if head in tts_out and "mixed" in tts_out and head != "mixed" else None),
         "precond_rows": recs[0][1]["precond_rows"],
         "operator_ms_avg": round(op_ms, 4),
-        "update_ms_avg": round(t_up / max(1, n_up), 4),
+        "update_ms_avg": round(up_ms, 4),
         "roofline": {
             "kernel": "op_kernel<%d,%d,OP_FUSED,%s> (fused direction update + matrix-free operator + h.Ah)"
                       % (tile[0], tile[1], "double" if head == "fp64" else "float"),
@@ -403,20 +536,32 @@ def main():
             "traffic": traffic["bytes"],
             "traffic_source": traffic["source"],
             "bytes_per_launch": round(op_bytes),
+            "duration_source": "HIP events on the library stream around each fused-sweep launch (with its "
+                               "finalize), over one extra step of the same geometry",
             "stream_GBs_measured": streams,
             "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
             "op_tile": tile,
-            "update_blocks": recs[0][1]["update_blocks"],
-            "update_nontemporal": recs[0][1]["update_nontemporal"],
+            "update_blocks": main_leg["update_blocks"],
+            "update_nontemporal": main_leg["update_nontemporal"],
             "valu": (measured_valu(ms.meta.get("workload"), tile, "fp64" if head == "fp64" else "fp32", op_ms,
                                    ms.shape[2]) if nrhs == 1 else None),
         },
+        "skipped": skipped or None,
+        "wall_s": None,
     }
     if not args.no_cpu_baseline:
-        try:
-            out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_iters)
-        except Exception as e:  # the GPU number stands without it
-            out["cpu_baseline"] = {"error": repr(e)}
+        if elapsed() < args.budget_s:
+            try:
+                gpu_iters = sum(tts_out[head]["iters"]) if head in tts_out else None
+                out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_iters, ms.n,
+                                                   gpu_iters, args.budget_s + 120 - elapsed())
+                note("cpu baseline done")
+            except Exception as e:  # the GPU number stands without it
+                out["cpu_baseline"] = {"error": repr(e)}
+        else:
+            skipped.append("cpu baseline")
+            out["skipped"] = skipped
+    out["wall_s"] = round(elapsed(), 1)
     print(json.dumps(out), flush=True)
 
 

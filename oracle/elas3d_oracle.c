@@ -33,11 +33,21 @@
  *     returns converged after 0 iterations.
  *
  * Vector fields are SoA: component c of node m at [c*N + m].
+ *
+ * The same file also builds with OpenMP (-fopenmp) into a separate library
+ * used only to time a threaded CPU baseline (the paper's OpenMP column of
+ * Table 4): the node loops then run in parallel and the element scatter of
+ * the operator runs layer by layer in two (three for odd nz) colours, so
+ * sums are formed in another order.  The serial build, which every pin and
+ * parity test uses, ignores the pragmas and keeps the plain loop order.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NDOF 24
 
@@ -158,24 +168,43 @@ static void affine_element_field(const double* strain, double ue[NDOF])
 
 /* ------------------------------------------------------------------ operator */
 
+/* y += scatter_e(K_e gather_e(x)) for voxel e. */
+static void apply_element(const orc_grid* g, const int32_t* phase, const double* ke, const double* x,
+                          double* y, long e)
+{
+    long nodes[8];
+    double xe[NDOF];
+    const double* K = ke + (size_t)phase[e] * 576;
+    orc_element_nodes(g, e, nodes);
+    gather(g, x, nodes, xe);
+    for (int p = 0; p < NDOF; ++p) {
+        double s = 0.0;
+        for (int q = 0; q < NDOF; ++q) s += K[p * NDOF + q] * xe[q];
+        y[(p % 3) * g->n + nodes[p / 3]] += s;
+    }
+}
+
 /* y = A x, A = sum_e scatter K_e gather (matrix-free, Algorithm 2 step A). */
 void orc_apply(int nx, int ny, int nz, const int32_t* phase, const double* ke,
                const double* x, double* y)
 {
     orc_grid g = mkgrid(nx, ny, nz);
     memset(y, 0, sizeof(double) * 3 * g.n);
-    long nodes[8];
-    double xe[NDOF];
-    for (long e = 0; e < g.n; ++e) {
-        const double* K = ke + (size_t)phase[e] * 576;
-        orc_element_nodes(&g, e, nodes);
-        gather(&g, x, nodes, xe);
-        for (int p = 0; p < NDOF; ++p) {
-            double s = 0.0;
-            for (int q = 0; q < NDOF; ++q) s += K[p * NDOF + q] * xe[q];
-            y[(p % 3) * g.n + nodes[p / 3]] += s;
-        }
+#ifdef _OPENMP
+    /* element layer k writes node planes k and (k+1) % nz only: layers of
+       one colour never write the same plane */
+    const long plane = (long)nx * ny;
+    const int ncol = (nz % 2) ? 3 : 2;
+    for (int col = 0; col < ncol; ++col) {
+        const int kfirst = col < 2 ? col : nz - 1;
+        const int klast = (col == 0 && ncol == 3) ? nz - 2 : nz - 1;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int k = kfirst; k <= klast; k += 2)
+            for (long e = k * plane; e < (k + 1) * plane; ++e) apply_element(&g, phase, ke, x, y, e);
     }
+#else
+    for (long e = 0; e < g.n; ++e) apply_element(&g, phase, ke, x, y, e);
+#endif
 }
 
 /* (A x) at selected nodes only, from the 8 voxels around each node. */
@@ -299,8 +328,9 @@ void orc_precond(int nx, int ny, int nz, const int32_t* phase, const double* ke,
 {
     orc_grid g = mkgrid(nx, ny, nz);
     unsigned char* voidp = void_flags(nphase, C);
-    double D[9];
+#pragma omp parallel for schedule(static)
     for (long m = 0; m < g.n; ++m) {
+        double D[9];
         double* X = minv + 9 * m;
         int solid = orc_diag_block(&g, phase, ke, voidp, m, D);
         if (!solid) {
@@ -333,6 +363,7 @@ void orc_precond_at(int nx, int ny, int nz, const int32_t* phase, const double* 
 
 static void apply_minv(long n, const double* minv, const double* g, double* z)
 {
+#pragma omp parallel for schedule(static)
     for (long m = 0; m < n; ++m) {
         const double* X = minv + 9 * m;
         double g0 = g[m], g1 = g[n + m], g2 = g[2 * n + m];
@@ -345,6 +376,7 @@ static void apply_minv(long n, const double* minv, const double* g, double* z)
 static double dot(long len, const double* a, const double* b)
 {
     double s = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : s)
     for (long t = 0; t < len; ++t) s += a[t] * b[t];
     return s;
 }
@@ -394,6 +426,7 @@ int orc_pcg(int nx, int ny, int nz, const int32_t* phase, const double* ke,
             double hAh = dot(len, h, Ah);                      /* B. step size */
             if (!(hAh > 0.0) || !isfinite(hAh)) { status = ORC_BREAKDOWN; stop = 1; break; }
             double lambda = gg / hAh;
+#pragma omp parallel for schedule(static)
             for (long t = 0; t < len; ++t) {                   /* C. update */
                 w[t] -= lambda * h[t];
                 g[t] -= lambda * Ah[t];
@@ -407,6 +440,7 @@ int orc_pcg(int nx, int ny, int nz, const int32_t* phase, const double* ke,
             int conv = (mode == 1) ? (relpre < tol) : (relres <= tol);
             if (conv) { status = ORC_CONVERGED; break; }
             double gamma = gg / gg_last;                       /* E. Fletcher-Reeves */
+#pragma omp parallel for schedule(static)
             for (long t = 0; t < len; ++t) h[t] = z[t] + gamma * h[t];
         }
         if (stop || status != ORC_CONVERGED || mode == 1) break;
@@ -495,4 +529,14 @@ double orc_energy(int nx, int ny, int nz, const int32_t* phase, const double* ke
         sum += 0.5 * s;
     }
     return sum;
+}
+
+/* Threads of the OpenMP build (timing only); nothing in the serial build. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

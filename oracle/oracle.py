@@ -12,6 +12,7 @@ import numpy as np
 __all__ = [
     "build", "lib", "Problem", "element_stiffness", "stiffness_table",
     "CONVERGED", "NOT_CONVERGED", "BREAKDOWN", "grains", "grains_at", "carve", "covered_at", "von_mises",
+    "threaded_available",
 ]
 
 CONVERGED, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
@@ -20,28 +21,88 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "elas3d_oracle.c")
 _SRC_GEN = os.path.join(_HERE, "microstructure_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same sources built with OpenMP: only for timing a threaded CPU baseline
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_lib_omp = None
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I32 = ctypes.POINTER(ctypes.c_int32)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 
 
-def _stale() -> bool:
-    if not os.path.exists(_LIB):
+def _stale(path: str = _LIB) -> bool:
+    if not os.path.exists(path):
         return True
-    t = os.path.getmtime(_LIB)
+    t = os.path.getmtime(path)
     return any(t < os.path.getmtime(src) for src in (_SRC, _SRC_GEN))
 
 
+def _compile(path: str, extra) -> None:
+    tmp = path + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", *extra, "-o", tmp,
+                           _SRC, _SRC_GEN, "-lm"])
+    os.replace(tmp, path)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction),
+    and the OpenMP build of the same sources used to time the threaded CPU
+    baseline (skipped quietly when the compiler has no OpenMP)."""
     if force or _stale():
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp,
-                               _SRC, _SRC_GEN, "-lm"])
-        os.replace(tmp, _LIB)
+        _compile(_LIB, [])
+    if force or _stale(_LIB_OMP):
+        try:
+            _compile(_LIB_OMP, ["-fopenmp"])
+        except (subprocess.CalledProcessError, OSError):
+            pass
     return _LIB
+
+
+def threaded_available() -> bool:
+    """True when the OpenMP build of the oracle is present (or can be built)."""
+    if _stale(_LIB_OMP):
+        try:
+            _compile(_LIB_OMP, ["-fopenmp"])
+        except (subprocess.CalledProcessError, OSError):
+            return False
+    return os.path.exists(_LIB_OMP)
+
+
+def _declare(L):
+    i, l, d = ctypes.c_int, ctypes.c_long, ctypes.c_double
+    L.orc_element_stiffness.argtypes = [_D, _D]
+    L.orc_stiffness_table.argtypes = [i, _D, _D]
+    L.orc_apply.argtypes = [i, i, i, _I32, _D, _D, _D]
+    L.orc_apply_at.argtypes = [i, i, i, _I32, _D, _D, _I64, l, _D]
+    L.orc_load.argtypes = [i, i, i, _I32, _D, _D, _D, _D]
+    L.orc_load_at.argtypes = [i, i, i, _I32, _D, _D, _I64, l, _D]
+    L.orc_precond.argtypes = [i, i, i, _I32, _D, i, _D, i, _D]
+    L.orc_precond_at.argtypes = [i, i, i, _I32, _D, i, _D, _I64, l, _D]
+    L.orc_pcg.argtypes = [i, i, i, _I32, _D, _D, _D, d, d, i, i, _D, _D, _D]
+    L.orc_pcg.restype = ctypes.c_int
+    L.orc_stress.argtypes = [i, i, i, _I32, i, _D, _D, _D, _D, _D]
+    L.orc_energy.argtypes = [i, i, i, _I32, _D, _D, _D]
+    L.orc_energy.restype = d
+    L.orc_grains.argtypes = [i, i, i, i, _D, _D, _I32]
+    L.orc_carve.argtypes = [i, i, i, _I32, ctypes.c_int32, i, _D, d, _I64]
+    L.orc_carve.restype = ctypes.c_int
+    L.orc_von_mises.argtypes = [l, _D, _D]
+    L.orc_grains_at.argtypes = [i, i, i, i, _D, _D, _I64, l, _I32]
+    L.orc_covered_at.argtypes = [i, i, i, i, _D, _I64, l, _I32]
+    L.orc_set_threads.argtypes = [i]
+    return L
+
+
+def threaded_lib(threads: int):
+    """The OpenMP build, set to `threads` threads (timing only)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not threaded_available():
+            raise RuntimeError("the OpenMP build of the oracle is not available")
+        _lib_omp = _declare(ctypes.CDLL(_LIB_OMP))
+    _lib_omp.orc_set_threads(int(threads))
+    return _lib_omp
 
 
 def lib():
@@ -49,28 +110,7 @@ def lib():
     if _lib is None:
         if _stale():
             build(force=True)
-        L = ctypes.CDLL(_LIB)
-        i, l, d = ctypes.c_int, ctypes.c_long, ctypes.c_double
-        L.orc_element_stiffness.argtypes = [_D, _D]
-        L.orc_stiffness_table.argtypes = [i, _D, _D]
-        L.orc_apply.argtypes = [i, i, i, _I32, _D, _D, _D]
-        L.orc_apply_at.argtypes = [i, i, i, _I32, _D, _D, _I64, l, _D]
-        L.orc_load.argtypes = [i, i, i, _I32, _D, _D, _D, _D]
-        L.orc_load_at.argtypes = [i, i, i, _I32, _D, _D, _I64, l, _D]
-        L.orc_precond.argtypes = [i, i, i, _I32, _D, i, _D, i, _D]
-        L.orc_precond_at.argtypes = [i, i, i, _I32, _D, i, _D, _I64, l, _D]
-        L.orc_pcg.argtypes = [i, i, i, _I32, _D, _D, _D, d, d, i, i, _D, _D, _D]
-        L.orc_pcg.restype = ctypes.c_int
-        L.orc_stress.argtypes = [i, i, i, _I32, i, _D, _D, _D, _D, _D]
-        L.orc_energy.argtypes = [i, i, i, _I32, _D, _D, _D]
-        L.orc_energy.restype = d
-        L.orc_grains.argtypes = [i, i, i, i, _D, _D, _I32]
-        L.orc_carve.argtypes = [i, i, i, _I32, ctypes.c_int32, i, _D, d, _I64]
-        L.orc_carve.restype = ctypes.c_int
-        L.orc_von_mises.argtypes = [l, _D, _D]
-        L.orc_grains_at.argtypes = [i, i, i, i, _D, _D, _I64, l, _I32]
-        L.orc_covered_at.argtypes = [i, i, i, i, _D, _I64, l, _I32]
-        _lib = L
+        _lib = _declare(ctypes.CDLL(_LIB))
     return _lib
 
 
@@ -100,7 +140,10 @@ def stiffness_table(C: np.ndarray) -> np.ndarray:
 class Problem:
     """One microstructure: grid, phase map and per-phase stiffness."""
 
-    def __init__(self, shape, phase, C):
+    def __init__(self, shape, phase, C, threads: int = 0):
+        """threads > 0 runs the OpenMP build on that many threads (timing
+        only; its sums are formed in another order)."""
+        self._L = lib() if threads <= 0 else threaded_lib(threads)
         self.nx, self.ny, self.nz = (int(s) for s in shape)
         self.n = self.nx * self.ny * self.nz
         self.phase = np.ascontiguousarray(phase, dtype=np.int32).reshape(self.n)
@@ -118,14 +161,14 @@ class Problem:
     def apply(self, x: np.ndarray) -> np.ndarray:
         x = _f64(x).reshape(3, self.n)
         y = np.empty_like(x)
-        lib().orc_apply(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(x), _p(y))
+        self._L.orc_apply(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(x), _p(y))
         return y
 
     def apply_at(self, x: np.ndarray, nodes: np.ndarray) -> np.ndarray:
         x = _f64(x).reshape(3, self.n)
         sel = np.ascontiguousarray(nodes, dtype=np.int64)
         y = np.empty((3, sel.size))
-        lib().orc_apply_at(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(x),
+        self._L.orc_apply_at(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(x),
                            _p(sel, _I64), sel.size, _p(y))
         return y
 
@@ -134,28 +177,28 @@ class Problem:
         e = _f64(strain).reshape(6)
         b = np.empty((3, self.n))
         r2 = np.zeros(1)
-        lib().orc_load(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e), _p(b), _p(r2))
+        self._L.orc_load(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e), _p(b), _p(r2))
         return b, float(r2[0])
 
     def load_at(self, strain, nodes) -> np.ndarray:
         e = _f64(strain).reshape(6)
         sel = np.ascontiguousarray(nodes, dtype=np.int64)
         b = np.empty((3, sel.size))
-        lib().orc_load_at(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e),
+        self._L.orc_load_at(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e),
                           _p(sel, _I64), sel.size, _p(b))
         return b
 
     def precond(self, identity: bool = False) -> np.ndarray:
         """N x 3 x 3 inverse diagonal blocks (0 on void-only nodes)."""
         minv = np.empty((self.n, 9))
-        lib().orc_precond(*self._g(), _p(self.phase, _I32), _p(self.ke), self.nphase,
+        self._L.orc_precond(*self._g(), _p(self.phase, _I32), _p(self.ke), self.nphase,
                           _p(self.C), int(identity), _p(minv))
         return minv.reshape(self.n, 3, 3)
 
     def precond_at(self, nodes) -> np.ndarray:
         sel = np.ascontiguousarray(nodes, dtype=np.int64)
         minv = np.empty((sel.size, 9))
-        lib().orc_precond_at(*self._g(), _p(self.phase, _I32), _p(self.ke), self.nphase,
+        self._L.orc_precond_at(*self._g(), _p(self.phase, _I32), _p(self.ke), self.nphase,
                              _p(self.C), _p(sel, _I64), sel.size, _p(minv))
         return minv.reshape(sel.size, 3, 3)
 
@@ -174,7 +217,7 @@ class Problem:
         w = np.empty((3, self.n))
         info = np.zeros(5)
         tr = np.zeros(max(1, maxit)) if trace else None
-        st = lib().orc_pcg(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(minv), _p(b),
+        st = self._L.orc_pcg(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(minv), _p(b),
                            r2, float(tol), int(maxit), int(mode), _p(w), _p(info),
                            _p(tr) if trace else None)
         out = {"w": w, "status": int(st), "iters": int(info[0]), "relres": info[1],
@@ -190,14 +233,14 @@ class Problem:
         w = _f64(w).reshape(3, self.n)
         sig = np.empty((6, self.n))
         avg = np.empty(6)
-        lib().orc_stress(*self._g(), _p(self.phase, _I32), self.nphase, _p(self.C), _p(e),
+        self._L.orc_stress(*self._g(), _p(self.phase, _I32), self.nphase, _p(self.C), _p(e),
                          _p(w), _p(sig), _p(avg))
         return sig, avg
 
     def energy(self, strain, w) -> float:
         e = _f64(strain).reshape(6)
         w = _f64(w).reshape(3, self.n)
-        return float(lib().orc_energy(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e), _p(w)))
+        return float(self._L.orc_energy(*self._g(), _p(self.phase, _I32), _p(self.ke), _p(e), _p(w)))
 
 
 # ------------------------------------------------------------ generator

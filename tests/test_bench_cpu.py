@@ -51,3 +51,15 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_cpu_baseline_reports_both_legs_and_the_extrapolation():
+    out = bench.cpu_baseline("eshelby20", 20, 2, 8000 * 8, 123, 60.0)
+    assert out["kind"] == "oracle" and out["unit"] == "Gdof*iter/s"
+    assert out["serial"]["threads"] == 1 and out["serial"]["value"] > 0 and out["serial"]["iters"] == 2
+    assert out["cores"] >= 1 and out["value"] > 0 and out["cpu_model"]
+    # 8x the sample's voxels, 123 GPU iterations
+    s = out["serial"]
+    assert abs(s["extrapolated_time_to_solution_s"] - s["s_per_iter"] * 8 * 123) <= 0.1 + 1e-3 * s["s_per_iter"] * 984
+    if "threaded" in out:
+        assert out["threaded"]["threads"] > 1 and out["cores"] == out["threaded"]["threads"]
