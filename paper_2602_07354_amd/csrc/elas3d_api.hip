@@ -254,17 +254,14 @@ int ensure_events(elas3d_ctx* c, std::vector<EventPair>& pool, size_t count)
     return 0;
 }
 
-// Copy a device field of ncomp entries per node out as SoA planes (ncomp*N
-// doubles) to the caller's buffer: device memory when outputs_on_device,
-// else host memory, staged through the work area.  The work area of RHS 0
-// is scratch outside a solve.
+// Copy a device field of ncomp planes (ncomp*N doubles) to the caller's
+// buffer: device memory when outputs_on_device, else host memory.
 int export_field(elas3d_ctx* c, const double* field, int ncomp, double* out)
 {
-    const size_t N = c->N();
-    double* dst = c->opt.outputs_on_device ? out : c->work64(0);
-    HIPCHK(c, e3d::launch_relayout(c->stream, field, dst, ncomp, N, 1));
-    if (!c->opt.outputs_on_device)
-        HIPCHK(c, hipMemcpyAsync(out, dst, 8 * (size_t)ncomp * N, hipMemcpyDeviceToHost, c->stream));
+    const size_t bytes = 8 * (size_t)ncomp * c->N();
+    HIPCHK(c, hipMemcpyAsync(out, field, bytes,
+                             c->opt.outputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return 0;
 }
@@ -501,7 +498,7 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const
     int real = 0;  // launches before the last RHS of the batch stopped
     for (int r = 0; r < R; ++r) {
         rs_out[r].fin = h0[r];
-        real = std::max(real, h0[r].it - rs_out[r].it_start + (h0[r].status == 2 ? 1 : 0));
+        real = std::max(real, h0[r].it - rs_out[r].it_start);
     }
     if (timing && info) {
         for (int q = 0; q < real && q < (int)ev_used; ++q) {
@@ -1128,26 +1125,26 @@ int elas3d_apply(elas3d_ctx* ctx, const double* x, double* y)
     if (!ctx) return fail(nullptr, ELAS3D_EBADARG, "ctx is NULL");
     if (int rc = grouped(ctx)) return rc;
     if (!x || !y) return fail(ctx, ELAS3D_EBADARG, "x or y is NULL");
-    HIPCHK(ctx, hipSetDevice(ctx->device));
     const size_t N = ctx->N();
-    // work area (15N): [x planes | x device layout | y device layout | y planes]
-    double* xs = ctx->work64(0);
-    double* xd = xs + 3 * N;
-    double* yd = xs + 6 * N;
-    double* ys = ctx->opt.outputs_on_device ? y : xs + 9 * N;
-    if (ctx->opt.outputs_on_device)
-        HIPCHK(ctx, e3d::launch_relayout(ctx->stream, x, xd, 3, N, 0));
-    else {
+    // the sweep reads x at neighbouring nodes while it writes y
+    if (x < y + 3 * N && y < x + 3 * N) return fail(ctx, ELAS3D_EBADARG, "x and y overlap");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    // caller's device buffers directly, or host data staged through the work
+    // area (15N): [x | y]
+    const double* xd = x;
+    double* yd = y;
+    if (!ctx->opt.outputs_on_device) {
+        double* xs = ctx->work64(0);
         HIPCHK(ctx, hipMemcpyAsync(xs, x, 8 * 3 * N, hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(ctx, e3d::launch_relayout(ctx->stream, xs, xd, 3, N, 0));
+        xd = xs;
+        yd = xs + 3 * N;
     }
     const double* xp[3] = {ctx->comp(xd, 0), ctx->comp(xd, 1), ctx->comp(xd, 2)};
     double* yp[3] = {ctx->comp(yd, 0), ctx->comp(yd, 1), ctx->comp(yd, 2)};
     HIPCHK(ctx, e3d::launch_apply(ctx->stream, ctx->d, ctx->geom, ctx->phase, ctx->tables(), xp, yp,
                                   nullptr, ctx->partials, nullptr));
-    HIPCHK(ctx, e3d::launch_relayout(ctx->stream, yd, ys, 3, N, 1));
     if (!ctx->opt.outputs_on_device)
-        HIPCHK(ctx, hipMemcpyAsync(y, ys, 8 * 3 * N, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(y, yd, 8 * 3 * N, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return 0;
 }

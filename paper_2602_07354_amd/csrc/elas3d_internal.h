@@ -24,21 +24,10 @@ struct Dims {
     int n;
 };
 
-// Layout of node vectors in device memory.  SoA planes (the default, and the
-// layout of the C-ABI): component c of node m at c*N + m.  With
-// E3D_INTERLEAVE=1 the three components of a node are adjacent (3m + c) and
-// the six entries of an M^-1 row r at 6r + q; a memory-only model of the
-// operator sweep streamed 15-18 % faster that way, the real sweep did not,
-// so SoA stays the default.  A vector field of T is 3N contiguous elements
-// (the M^-1 dictionary 6 x its rows); kernels address component c through a
-// pointer to its first element and node m at m*kVS (row r at r*kMS).
-#ifndef E3D_INTERLEAVE
-#define E3D_INTERLEAVE 0
-#endif
-constexpr int kVS = E3D_INTERLEAVE ? 3 : 1;  // vector element stride of a node
-constexpr int kMS = E3D_INTERLEAVE ? 6 : 1;  // M^-1 element stride of a node
-// offset of component c (or M^-1 entry q) from the start of its field
-__host__ __device__ inline size_t comp_offset(int c, size_t n) { return E3D_INTERLEAVE ? (size_t)c : (size_t)c * n; }
+// Layout of node vectors in device memory: SoA planes, the layout of the
+// C-ABI.  A vector field of T is three planes of N elements, component c of
+// node m at c*N + m; kernels address component c through a pointer to its
+// plane and node m at m.  The M^-1 dictionary is six planes of its rows.
 
 // Device-resident scalars of one PCG run (Algorithm 2).  Written only by
 // the single-block finalize kernels; read by the sweep kernels.
@@ -69,7 +58,7 @@ struct Scalars {
 };
 
 // Field pointers of one PCG run (component pointers of T, addressed at
-// m*kVS: double for the FP64 solve, float for the inner solve of the
+// m: double for the FP64 solve, float for the inner solve of the
 // mixed-precision refinement, where w is the correction d and g starts as
 // the rounded residual).
 template <typename T>
@@ -105,7 +94,7 @@ __host__ __device__ inline FieldsT<T> shifted(const FieldsT<T>& f, size_t off)
 
 // The inverse diagonal blocks as a dictionary of rows: node m uses row
 // idx[m], whose six symmetric entries (xx, yy, zz, yz, xz, xy) are
-// m[q][row * kMS].  Rows [0, nphase) belong to the nodes whose eight voxels
+// m[q][row].  Rows [0, nphase) belong to the nodes whose eight voxels
 // all have phase p (the same block for all of them); each remaining row to
 // one node at a phase boundary, in node order.
 template <typename T>
@@ -261,11 +250,5 @@ hipError_t launch_group_iteration(hipStream_t st, const GroupPlan& plan);
 // Message returned by elas3d_last_error(NULL) on this thread (context-free
 // entry points).
 void set_last_error(const std::string& msg);
-
-// Layout conversion between the ABI's SoA planes and the device layout of a
-// field with ncomp components (3: vector, 6: M^-1) of n nodes, FP64,
-// device to device.  to_abi: device layout -> planes; otherwise the reverse.
-hipError_t launch_relayout(hipStream_t st, const double* src, double* dst, int ncomp, size_t n,
-                           int to_abi);
 
 }  // namespace e3d

@@ -416,6 +416,9 @@ __device__ __forceinline__ void finalize_body(int kind, const double* partials, 
         // owed steps if there were two and left a single one owed
         const int owed = S->pending;
         if (!(hAh > 0.0) || !isfinite(hAh)) {
+            // the iteration that found the breakdown counts (its operator
+            // sweep ran), as in Algorithm 2
+            S->it += 1;
             S->status = 2;
             S->done = 1;
             if (owed != 1) {
@@ -525,7 +528,7 @@ __global__ void __launch_bounds__(kBlock) load_kernel(Dims d, const int32_t* __r
         f0 *= 0.25;
         f1 *= 0.25;
         f2 *= 0.25;
-        const size_t mv = (size_t)m * kVS;
+        const size_t mv = (size_t)m;
         bx[mv] = f0;
         by[mv] = f1;
         bz[mv] = f2;
@@ -665,7 +668,7 @@ __global__ void __launch_bounds__(kBlock) precond_fill_kernel(Dims d, const int3
                 idx[m] = (uint32_t)row;
                 double r[6];
                 block_inverse(ph, diag, solid, identity, r);
-                const size_t mq = (size_t)row * kMS;
+                const size_t mq = (size_t)row;
                 m0[mq] = r[0];
                 m1[mq] = r[1];
                 m2[mq] = r[2];
@@ -691,7 +694,7 @@ __global__ void __launch_bounds__(kBlock) precond_table_kernel(int nphase, const
     const int ph[8] = {p, p, p, p, p, p, p, p};
     double r[6];
     block_inverse(ph, diag, solid, identity, r);
-    const size_t mq = (size_t)p * kMS;
+    const size_t mq = (size_t)p;
     m0[mq] = r[0];
     m1[mq] = r[1];
     m2[mq] = r[2];
@@ -703,7 +706,7 @@ __global__ void __launch_bounds__(kBlock) precond_table_kernel(int nphase, const
 __global__ void __launch_bounds__(kBlock) precond_expand_kernel(Dims d, MinvRows<double> M, double* out)
 {
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        const size_t row = (size_t)M.idx[m] * kMS;
+        const size_t row = (size_t)M.idx[m];
 #pragma unroll
         for (int q = 0; q < 6; ++q) out[(size_t)q * d.n + m] = M.m[q][row];
     }
@@ -718,8 +721,8 @@ __global__ void __launch_bounds__(kBlock) pcg_init_kernel(Dims d, FieldsT<T> f, 
 {
     double acc[2] = {0.0, 0.0};
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        const int mv = m * kVS;
-        const size_t mq = (size_t)M.idx[m] * kMS;
+        const int mv = m;
+        const size_t mq = (size_t)M.idx[m];
         T g[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -790,7 +793,7 @@ __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, co
     // strength-reducing every field address into its own 64-bit induction
     // variable, which triples the register count
     for (int m = bid * kBlock + threadIdx.x; m < d.n; m += (unsigned)nblk * kBlock) {
-        const size_t mq = (size_t)stream_load<NT>(M.idx + m) * kMS;
+        const size_t mq = (size_t)stream_load<NT>(M.idx + m);
         T mm[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) mm[q] = M.m[q][mq];
@@ -798,7 +801,7 @@ __device__ __forceinline__ void update_body(const Dims d, const FieldsT<T> f, co
 #pragma unroll
         for (int r = 0; r < kMaxRhs; ++r) {
             if (!(active & (1u << r))) continue;
-            const size_t o = (size_t)r * rs + (size_t)m * kVS;
+            const size_t o = (size_t)r * rs + (size_t)m;
             T g[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) g[c] = fma(-lam[r], stream_load<NT>(f.Ah[c] + o), stream_load<NT>(f.g[c] + o));
@@ -838,9 +841,9 @@ __global__ void __launch_bounds__(kBlock) final_update_kernel(Dims d, FieldsT<T>
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            T w = f.w[c][m * kVS];
-            if (owed == 2) w = fma(-lamp, ho[c][m * kVS], w);
-            f.w[c][m * kVS] = fma(-lam, h[c][m * kVS], w);
+            T w = f.w[c][m];
+            if (owed == 2) w = fma(-lamp, ho[c][m], w);
+            f.w[c][m] = fma(-lam, h[c][m], w);
         }
     }
 }
@@ -851,7 +854,7 @@ __global__ void __launch_bounds__(kBlock) add_correction_kernel(Dims d, double* 
                                                                 const float* d1, const float* d2)
 {
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < d.n; m += gridDim.x * kBlock) {
-        const int mv = m * kVS;
+        const int mv = m;
         w0[mv] += (double)d0[mv];
         w1[mv] += (double)d1[mv];
         w2[mv] += (double)d2[mv];
@@ -1040,9 +1043,9 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
     auto fetch = [&](int kk) {
         const int kw = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
         const int base = kw * plane;
-        const int io = (base + own) * kVS, ih = (base + hoff) * kVS;
+        const int io = (base + own), ih = (base + hoff);
         if constexpr (FUSED) {
-            const int iw = (base + wown) * kVS;
+            const int iw = (base + wown);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 rh[c] = hold[c][io];
@@ -1103,7 +1106,7 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
     // with h (fused) or y (the other modes)
     auto emit = [&](int b, const R (&m)[3], const R (&hk)[3], int kl) {
         auto& sf = SF[b];
-        const int idx = ((kl < 0 ? kl + nz : kl) * plane + own) * kVS;
+        const int idx = ((kl < 0 ? kl + nz : kl) * plane + own);
         R yv[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -1153,7 +1156,7 @@ __device__ __forceinline__ void op_body(OpArgs<T> a, const int lbr, const int nb
 #pragma unroll
         for (int c = 0; c < 3; ++c) ov[c] = own_value(c);
         if (out_ok && ku < kend) {
-            const int idx = (kuw * plane + own) * kVS;
+            const int idx = (kuw * plane + own);
             if constexpr (FUSED) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -1387,7 +1390,7 @@ __device__ __forceinline__ void voxel_stress(const Dims& d, const int32_t* __res
             const double xi[3] = {(double)(a & 1), (double)((a >> 1) & 1), (double)(a >> 2)};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double wv = f.w[c][m * kVS];
+                const double wv = f.w[c][m];
                 u[c][a] = wv;
                 ut_[c][a] = wv + Et[c][0] * xi[0] + Et[c][1] * xi[1] + Et[c][2] * xi[2];
             }
@@ -1541,31 +1544,10 @@ __global__ void __launch_bounds__(kBlock) total_displacement_kernel(Dims d, Stra
         int i, j, k;
         node_ijk(m, d, i, j, k);
         const double X = i, Y = j, Z = k;
-        const int mv = m * kVS;
+        const int mv = m;
         u0[m] = f.w[0][mv] + E.e[0] * X + E.e[5] * Y + E.e[4] * Z;
         u1[m] = f.w[1][mv] + E.e[5] * X + E.e[1] * Y + E.e[3] * Z;
         u2[m] = f.w[2][mv] + E.e[4] * X + E.e[3] * Y + E.e[2] * Z;
-    }
-}
-
-// Between SoA planes (entry q of node m at q*n + m) and the device layout
-// (q*kComp + m*kStride), for a field of ncomp entries per node.
-__global__ void __launch_bounds__(kBlock) relayout_kernel(const double* __restrict__ src,
-                                                          double* __restrict__ dst, int ncomp, size_t n,
-                                                          int to_abi)
-{
-    const size_t total = (size_t)ncomp * n;
-    const size_t node_stride = E3D_INTERLEAVE ? (size_t)ncomp : 1;
-    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < total; t += (size_t)gridDim.x * kBlock) {
-        // t enumerates the device layout; its ABI position is q*n + m
-        const size_t m = E3D_INTERLEAVE ? t / ncomp : t % n;
-        const size_t q = E3D_INTERLEAVE ? t - m * ncomp : t / n;
-        const size_t dev = comp_offset((int)q, n) + m * node_stride;
-        const size_t abi = q * n + m;
-        if (to_abi)
-            dst[abi] = src[dev];
-        else
-            dst[dev] = src[abi];
     }
 }
 
@@ -2006,17 +1988,6 @@ hipError_t launch_phase_check(hipStream_t st, const int32_t* phase, int n, int n
 {
     const int nb = sweep_blocks(n, 2048);
     hipLaunchKernelGGL(phase_check_kernel, dim3(nb), dim3(kBlock), 0, st, phase, n, nphase, bad);
-    return hipGetLastError();
-}
-
-hipError_t launch_relayout(hipStream_t st, const double* src, double* dst, int ncomp, size_t n,
-                           int to_abi)
-{
-    size_t nb = ((size_t)ncomp * n + kBlock - 1) / kBlock;
-    if (nb > 8192) nb = 8192;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(relayout_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, src, dst, ncomp, n,
-                       to_abi);
     return hipGetLastError();
 }
 

@@ -104,7 +104,7 @@ struct elas3d_ctx {
     size_t N() const { return (size_t)d.n; }
     // component c (or M^-1 entry q) of a field starting at base
     template <typename P>
-    P* comp(P* base, int c) const { return base + e3d::comp_offset(c, N()); }
+    P* comp(P* base, int c) const { return base + (size_t)c * N(); }
 
     bool batched() const { return opt.batched != 0; }
     size_t rs64() const { return (batched() ? 21 : 6) * N(); }  // RHS stride of the bundles
@@ -133,7 +133,7 @@ struct elas3d_ctx {
     }
     // entry q of the M^-1 rows starting at base
     template <typename P>
-    P* mcomp(P* base, int q) const { return base + e3d::comp_offset(q, mrows); }
+    P* mcomp(P* base, int q) const { return base + (size_t)q * mrows; }
     e3d::MinvRows<double> minv_rows() const
     {
         e3d::MinvRows<double> M;

@@ -86,3 +86,12 @@ def workload(name: str, scale: Optional[int] = None, nrhs: Optional[int] = None,
     ms = polycrystal(rec["shape"], rec["n_grains"], rec["seed"], rec["pores"], strain, phase=phase)
     ms.meta["workload"] = name if scale is None else f"{name}@{scale}^3"
     return ms
+
+
+def serving_request(seed: int) -> synth.Microstructure:
+    """One request of the serving stream (``synth.serving_recipe``) generated
+    on the device (host phase array)."""
+    rec = synth.serving_recipe(seed)
+    ms = polycrystal(rec["shape"], rec["n_grains"], rec["seed"], rec["pores"], rec["strain"])
+    ms.meta["workload"] = rec["workload"]
+    return ms

@@ -63,6 +63,10 @@ class Result:
     t_start: float
     t_end: float
     error: Optional[str] = None
+    # with keep_fields: per load case the fluctuation displacement w (3 x N)
+    # and the voxel stress (6 x N), host copies
+    w: Optional[list] = None
+    sigma: Optional[list] = None
 
     @property
     def latency(self) -> float:
@@ -74,7 +78,37 @@ def request_bytes(req: Request) -> float:
     return E.device_bytes(req.micro.shape, req.micro.nphase, req.micro.nrhs, o)
 
 
-def solve_one(req: Request, t_arrival: float = 0.0, t0: float = 0.0, device: int = 0) -> Result:
+def _collect(h, ms, keep_fields: bool):
+    """Mean stress of every load case of a solved context (and, with
+    keep_fields, its w and voxel stress planes)."""
+    avg = np.empty((ms.nrhs, 6))
+    ws, sigs = ([], []) if keep_fields else (None, None)
+    for r in range(ms.nrhs):
+        a = np.empty(6)
+        sig = np.empty((6, ms.n)) if keep_fields else None
+        E.stress(h, r, sig, a, None, None)
+        avg[r] = a
+        if keep_fields:
+            w = np.empty((3, ms.n))
+            E.get_solution(h, r, w)
+            ws.append(w)
+            sigs.append(sig)
+    return avg, ws, sigs
+
+
+def _code(e: BaseException) -> int:
+    """Status of a failed request: the library's error code, else EDEVICE."""
+    return int(getattr(e, "code", E.EDEVICE))
+
+
+def _failed(req: Request, code: int, msg: str, t_arrival: float, t_start: float, t_end: float) -> Result:
+    ms = req.micro
+    return Result(req.rid, ms.shape, ms.nrhs, code, [], [], np.zeros((ms.nrhs, 6)), t_arrival, t_start, t_end,
+                  msg)
+
+
+def solve_one(req: Request, t_arrival: float = 0.0, t0: float = 0.0, device: int = 0,
+              keep_fields: bool = False) -> Result:
     """Run one request to completion on the calling thread (own HIP stream)."""
     ms = req.micro
     t_start = time.perf_counter() - t0
@@ -83,26 +117,21 @@ def solve_one(req: Request, t_arrival: float = 0.0, t0: float = 0.0, device: int
         h = E.setup(ms.shape, ms.phase, ms.C, ms.strain, opts)
         try:
             st, info = E.solve(h, req.tol, 50000, ms.nrhs)
-            avg = np.empty((ms.nrhs, 6))
-            for r in range(ms.nrhs):
-                a = np.empty(6)
-                E.stress(h, r, None, a, None, None)
-                avg[r] = a
+            avg, ws, sigs = _collect(h, ms, keep_fields)
         finally:
             E.destroy(h)
         d = info.as_dict()
         return Result(req.rid, ms.shape, ms.nrhs, st, d["iters"], d["relres_true"], avg, t_arrival,
-                      t_start, time.perf_counter() - t0)
-    except E.Elas3dError as e:
-        return Result(req.rid, ms.shape, ms.nrhs, e.code, [], [], np.zeros((ms.nrhs, 6)), t_arrival,
-                      t_start, time.perf_counter() - t0, str(e))
+                      t_start, time.perf_counter() - t0, None, ws, sigs)
+    except Exception as e:  # noqa: BLE001 - a failed request is a result, not a crash
+        return _failed(req, _code(e), str(e), t_arrival, t_start, time.perf_counter() - t0)
 
 
 class Server:
     """Admission by memory budget and concurrency; workers overlap on the GPU."""
 
     def __init__(self, budget_bytes: Optional[float] = None, max_concurrency: int = 8,
-                 device: int = 0):
+                 device: int = 0, keep_fields: bool = False):
         if budget_bytes is None:
             import torch
 
@@ -111,6 +140,7 @@ class Server:
         self.budget = float(budget_bytes)
         self.max_conc = int(max_concurrency)
         self.device = device
+        self.keep_fields = bool(keep_fields)
         self._lock = threading.Condition()
         self._queue: deque = deque()
         self._in_flight_bytes = 0.0
@@ -153,7 +183,7 @@ class Server:
         return self._in_flight_bytes + nbytes <= self.budget
 
     def _work(self, req: Request, nbytes: float, t_arr: float):
-        res = solve_one(req, t_arr, self._t0, self.device)
+        res = solve_one(req, t_arr, self._t0, self.device, self.keep_fields)
         with self._lock:
             self._results.append(res)
             self._in_flight_bytes -= nbytes
@@ -181,7 +211,7 @@ class GroupServer:
     context's own stream) run on worker threads meanwhile."""
 
     def __init__(self, budget_bytes: Optional[float] = None, max_concurrency: int = 64,
-                 poll: int = 8, device: int = 0, setup_workers: int = 4):
+                 poll: int = 8, device: int = 0, setup_workers: int = 4, keep_fields: bool = False):
         if budget_bytes is None:
             import torch
 
@@ -192,6 +222,7 @@ class GroupServer:
         self.poll = int(poll)
         self.device = device
         self.setup_workers = int(setup_workers)
+        self.keep_fields = bool(keep_fields)
         self._lock = threading.Condition()
         self._queue: deque = deque()
         self._results: List[Result] = []
@@ -216,10 +247,15 @@ class GroupServer:
             self._lock.notify_all()
 
     def _setup(self, req: Request, nbytes: float, t_arr: float):
+        """Set up a request's context; a request the library refuses comes
+        back with h = None and the error instead of raising."""
         ms = req.micro
         t_start = self.now()
-        opts = E.options_init(precision=req.precision, batched=1, device=self.device)
-        return E.setup(ms.shape, ms.phase, ms.C, ms.strain, opts), (req, nbytes, t_arr, t_start)
+        try:
+            opts = E.options_init(precision=req.precision, batched=1, device=self.device)
+            return E.setup(ms.shape, ms.phase, ms.C, ms.strain, opts), (req, nbytes, t_arr, t_start), None
+        except Exception as e:  # noqa: BLE001 - becomes the request's error result
+            return None, (req, nbytes, t_arr, t_start), e
 
     def _admit(self, pool, pending: set) -> None:
         while True:
@@ -234,31 +270,41 @@ class GroupServer:
                 self._open += 1
             pending.add(pool.submit(self._setup, req, nbytes, t_arr))
 
-    def _join(self, group, pending: set) -> None:
-        for f in [f for f in pending if f.done()]:
-            pending.discard(f)
-            h, meta = f.result()
-            self._in_flight[h] = meta
-            group.add(h, meta[0].tol, 50000)
-
-    def _finish(self, h, status, info, meta) -> None:
-        req, nbytes, t_arr, t_start = meta
-        ms = req.micro
-        avg = np.empty((ms.nrhs, 6))
-        try:
-            for r in range(ms.nrhs):
-                a = np.empty(6)
-                E.stress(h, r, None, a, None, None)
-                avg[r] = a
-        finally:
-            E.destroy(h)
-        res = Result(req.rid, ms.shape, ms.nrhs, status, info["iters"], info["relres_true"], avg, t_arr,
-                     t_start, self.now())
+    def _release(self, res: Result, nbytes: float) -> None:
         with self._lock:
             self._results.append(res)
             self._in_flight_bytes -= nbytes
             self._open -= 1
             self._lock.notify_all()
+
+    def _join(self, group, pending: set) -> None:
+        for f in [f for f in pending if f.done()]:
+            pending.discard(f)
+            h, meta, err = f.result()
+            req, nbytes, t_arr, t_start = meta
+            if h is not None:
+                try:
+                    group.add(h, req.tol, 50000)
+                    self._in_flight[h] = meta
+                    continue
+                except Exception as e:  # noqa: BLE001
+                    err = e
+                    E.destroy(h)
+            self._release(_failed(req, _code(err), str(err), t_arr, t_start, self.now()), nbytes)
+
+    def _finish(self, h, status, info, meta) -> None:
+        req, nbytes, t_arr, t_start = meta
+        ms = req.micro
+        try:
+            try:
+                avg, ws, sigs = _collect(h, ms, self.keep_fields)
+            finally:
+                E.destroy(h)
+            res = Result(req.rid, ms.shape, ms.nrhs, status, info["iters"], info["relres_true"], avg, t_arr,
+                         t_start, self.now(), None, ws, sigs)
+        except Exception as e:  # noqa: BLE001 - the slot is released whatever happened
+            res = _failed(req, _code(e), str(e), t_arr, t_start, self.now())
+        self._release(res, nbytes)
 
     def _run(self) -> None:
         try:
@@ -303,14 +349,18 @@ class GroupServer:
         self._engine.join(timeout=30)
 
 
-def run_stream(requests: List[Request], server) -> List[Result]:
-    """Submit requests at their arrival offsets (seconds) and wait for all."""
+def run_stream(requests: List[Request], server, progress: int = 0) -> List[Result]:
+    """Submit requests at their arrival offsets (seconds) and wait for all;
+    with progress > 0, a line on stderr every `progress` submissions."""
     start = server.now()
-    for req in sorted(requests, key=lambda r: r.arrival):
+    for k, req in enumerate(sorted(requests, key=lambda r: r.arrival)):
         delay = start + req.arrival - server.now()
         if delay > 0:
             time.sleep(delay)
         server.submit(req)
+        if progress and (k + 1) % progress == 0:
+            print(f"# submitted {k + 1}/{len(requests)} at {server.now() - start:.1f} s",
+                  file=sys.stderr, flush=True)
     return server.drain()
 
 
@@ -326,15 +376,24 @@ def latency_stats(results: List[Result], wall: float) -> dict:
     }
 
 
-def make_pool(n: int, seed0: int = 0, precision: int = E.PREC_MIXED, tol: float = 1e-8):
-    """A pool of distinct seeded serving requests (grid 32^3..128^3, 1-6 cases)."""
-    return [Request(i, synth.serving_request(seed0 + i), tol, precision) for i in range(n)]
+def make_pool(n: int, seed0: int = 0, precision: int = E.PREC_MIXED, tol: float = 1e-8,
+              device_generator: bool = False):
+    """n distinct seeded serving requests (seeds seed0 .. seed0 + n - 1; grid
+    32^3..128^3, 1-6 cases), built on the host or with the device generator
+    (same recipe and random stream)."""
+    if device_generator:
+        from . import generate
+        make = generate.serving_request
+    else:
+        make = synth.serving_request
+    return [Request(i, make(seed0 + i), tol, precision) for i in range(n)]
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--pool", type=int, default=16, help="distinct requests, cycled")
-    ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate")
+    ap.add_argument("--requests", type=int, default=500, help="distinct requests per arrival rate")
+    ap.add_argument("--saturation-requests", type=int, default=200,
+                    help="distinct requests of the closed-loop saturation run")
     ap.add_argument("--rates", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.1])
     ap.add_argument("--concurrency", type=int, default=8)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
@@ -349,37 +408,48 @@ def main(argv=None):
     torch.cuda.set_device(0)
     E.lib()
     prec = E.PREC_MIXED if args.precision == "mixed" else E.PREC_FP64
-    pool = make_pool(args.pool, args.seed, prec)
-    print(f"# pool of {len(pool)} requests: edges {[r.micro.shape[0] for r in pool]}, "
-          f"cases {[r.micro.nrhs for r in pool]}", file=sys.stderr, flush=True)
+
+    def pool(n, seed0):
+        t0 = time.perf_counter()
+        p = make_pool(n, seed0, prec, device_generator=True)
+        print(f"# {n} requests (seeds {seed0}..{seed0 + n - 1}) generated in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        return p
+
     srv = (GroupServer(max_concurrency=args.concurrency, poll=args.poll) if args.engine == "group"
            else Server(max_concurrency=args.concurrency))
-    # warm-up and saturation: closed loop, everything queued at t = 0
-    run_stream([dataclasses.replace(r, rid=i, arrival=0.0) for i, r in enumerate(pool)], srv)
-    nsat = max(len(pool), args.requests // 2)
+    # warm-up, then saturation: closed loop, everything queued at t = 0
+    run_stream(pool(16, args.seed + 900_000), srv)
+    sat_pool = pool(args.saturation_requests, args.seed + 800_000)
     t0 = time.perf_counter()
-    sat = run_stream([dataclasses.replace(pool[i % len(pool)], rid=i, arrival=0.0)
-                      for i in range(nsat)], srv)
+    sat = run_stream(sat_pool, srv, progress=100)
     sat_rate = len(sat) / (time.perf_counter() - t0)
+    print(f"# saturation {sat_rate:.2f} solves/s", file=sys.stderr, flush=True)
+    edges = [r.micro.shape[0] for r in sat_pool]
     out = {"metric": "p50/p99 solve latency under Poisson arrivals (continuous batching)",
            "engine": args.engine, "poll": args.poll if args.engine == "group" else None,
-           "precision": args.precision, "tol": pool[0].tol,
-           "concurrency": args.concurrency,
+           "precision": args.precision, "tol": sat_pool[0].tol,
+           "concurrency": args.concurrency, "requests_per_rate": args.requests,
+           "requests": "distinct seeded requests per rate (none reused): edge uniform over "
+                       "{32, 64, 96, 128}, voxels/2000 grains, U[0, 2 %] spherical pores, 1-6 load cases",
+           "saturation_requests": len(sat), "saturation_edges": {str(e): edges.count(e) for e in sorted(set(edges))},
            "saturation_solves_per_s": round(sat_rate, 3), "rates": []}
+    del sat_pool, sat
     rng = np.random.default_rng(args.seed)
-    for frac in args.rates:
+    for k, frac in enumerate(args.rates):
+        reqs = pool(args.requests, args.seed + 1_000_000 * (k + 1))
         lam = frac * sat_rate
-        gaps = rng.exponential(1.0 / lam, args.requests)
+        gaps = rng.exponential(1.0 / lam, len(reqs))
         arr = np.cumsum(gaps) - gaps[0]
-        reqs = [dataclasses.replace(pool[i % len(pool)], rid=i, arrival=float(arr[i]))
-                for i in range(args.requests)]
+        reqs = [dataclasses.replace(r, rid=i, arrival=float(arr[i])) for i, r in enumerate(reqs)]
         t0 = time.perf_counter()
-        res = run_stream(reqs, srv)
+        res = run_stream(reqs, srv, progress=100)
         st = latency_stats(res, time.perf_counter() - t0)
         st["arrival_rate_frac"] = frac
         st["arrival_rate_per_s"] = round(lam, 3)
-        out["rates"].append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})
+        out["rates"].append({k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in st.items()})
         print(json.dumps(out["rates"][-1]), file=sys.stderr, flush=True)
+        del reqs, res
     srv.close()
     print(json.dumps(out), flush=True)
 

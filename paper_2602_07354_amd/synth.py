@@ -58,6 +58,8 @@ __all__ = [
     "WORKLOADS",
     "unit_load_cases",
     "rng_for",
+    "indefinite_grid",
+    "serving_recipe",
 ]
 
 SS316L_CUBIC = (206.0, 133.0, 119.0)  # C11, C12, C44 in GPa (Table 5)
@@ -330,6 +332,23 @@ def void_sphere(n: int = 500) -> Microstructure:
     return ms
 
 
+def indefinite_grid(shape: Sequence[int], seed: int, neg_fraction: float, e_neg: float) -> Microstructure:
+    """Two isotropic phases (E = 200 and 120 GPa) mixed voxel by voxel, with a
+    fraction of voxels of a third phase whose stiffness is the negative of an
+    isotropic one (-C(e_neg, 0.3)).  Such a C is symmetric and finite, so setup
+    accepts it, but the operator is indefinite: a test input for the step-size
+    breakdown of Algorithm 2 (h.Ah <= 0)."""
+    rng = rng_for(seed)
+    n = int(np.prod(shape))
+    C = np.stack([isotropic_stiffness(200.0, 0.3), isotropic_stiffness(120.0, 0.25),
+                  -isotropic_stiffness(float(e_neg), 0.3)])
+    phase = (rng.random(n) < 0.5).astype(np.int32)
+    phase[rng.random(n) < neg_fraction] = 2
+    return Microstructure(tuple(int(v) for v in shape), phase, C,
+                          np.array([[1e-3, 0, 0, 0, 0, 0]], dtype=np.float64),
+                          {"workload": f"indefinite_{seed}", "neg_voxels": int((phase == 2).sum())})
+
+
 def _lognormal_radii(rng, median, sigma, n):
     return median * np.exp(sigma * rng.standard_normal(n))
 
@@ -448,16 +467,23 @@ def workload(name: str, scale: Optional[int] = None, nrhs: Optional[int] = None)
     return ms
 
 
-def serving_request(seed: int) -> Microstructure:
-    """One request of the serving stream: grid edge uniform over {32, 64, 96, 128},
-    grain count voxels/2000, porosity U[0, 2%] spheres, 1-6 load cases."""
+def serving_recipe(seed: int) -> dict:
+    """Draws of one request of the serving stream: grid edge uniform over
+    {32, 64, 96, 128}, grain count voxels/2000, porosity U[0, 2%] spheres,
+    1-6 load cases (the arguments of ``polycrystal``)."""
     rng = rng_for(seed)
     n = int(rng.choice([32, 64, 96, 128]))
     grains = max(1, (n ** 3) // 2000)
     por = float(rng.uniform(0.0, 0.02))
     nrhs = int(rng.integers(1, 7))
-    ms = polycrystal((n, n, n), grains, seed * 7919 + 1,
-                     [dict(kind="sphere", fraction=por, median=2.0, sigma=0.4)],
-                     unit_load_cases()[:nrhs])
-    ms.meta["workload"] = f"serving_{n}"
+    return {"shape": (n, n, n), "n_grains": grains, "seed": seed * 7919 + 1,
+            "pores": [dict(kind="sphere", fraction=por, median=2.0, sigma=0.4)],
+            "strain": unit_load_cases()[:nrhs], "workload": f"serving_{n}"}
+
+
+def serving_request(seed: int) -> Microstructure:
+    """One request of the serving stream (``serving_recipe``), built on the host."""
+    rec = serving_recipe(seed)
+    ms = polycrystal(rec["shape"], rec["n_grains"], rec["seed"], rec["pores"], rec["strain"])
+    ms.meta["workload"] = rec["workload"]
     return ms

@@ -161,3 +161,51 @@ def test_grouped_context_is_guarded_and_can_be_withdrawn(E):
         keep.close()
         gone.close()
         quick.close()
+
+
+def _rel(a, b):
+    d = a - b
+    return max(np.linalg.norm(d) / max(np.linalg.norm(b), 1e-300), np.abs(d).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_group_members_match_oracle(E, orc):
+    """Members of one group (an FP64 member, a mixed-precision member and a
+    batched FP64 member with three load cases), solved together to a true
+    relative residual of 1e-12, against the oracle's FP64 PCG (Algorithm 2)
+    solved to 1e-12: voxel stress and displacement with its mean over active
+    nodes removed within 1e-8 (element-wise and normwise), iterations of the
+    FP64 members within 2 of the oracle's."""
+    tol = 1e-12
+    cases = [("eshelby fp64", synth.eshelby_inclusion(20), {}),
+             ("poly mixed", _poly((30, 26, 22), 6), dict(precision=E.PREC_MIXED)),
+             ("poly fp64 x3", _poly((24, 20, 18), 5, 3), dict(batched=1))]
+    ctxs = [E.Context.from_micro(ms, **kw) for _, ms, kw in cases]
+    got = {}
+    try:
+        with E.Group() as g:
+            for c in ctxs:
+                g.add(c.handle, tol, 20000)
+            while len(got) < len(ctxs):
+                done, _ = g.run(8)
+                for h, st, info in done:
+                    k = [c.handle for c in ctxs].index(h)
+                    ms = cases[k][1]
+                    got[k] = (st, info, [ctxs[k].solution(r) for r in range(ms.nrhs)],
+                              [ctxs[k].stress(r)["sigma"] for r in range(ms.nrhs)])
+        for k, (name, ms, kw) in enumerate(cases):
+            st, info, ws, sigs = got[k]
+            say("case: group member vs oracle", name, info["iters"])
+            assert st == E.OK and max(info["relres_true"]) <= tol
+            P = orc.Problem.from_micro(ms)
+            active = np.any(np.abs(P.precond()).reshape(ms.n, 9) > 0, axis=1)
+            for r in range(ms.nrhs):
+                ro = P.solve(ms.strain[r], tol=tol)
+                so, _ = P.stress(ms.strain[r], ro["w"])
+                assert _rel(sigs[r], so) <= 1e-8
+                w, wo = ws[r][:, active], ro["w"][:, active]
+                assert _rel(w - w.mean(axis=1, keepdims=True), wo - wo.mean(axis=1, keepdims=True)) <= 1e-8
+                if kw.get("precision", E.PREC_FP64) == E.PREC_FP64:
+                    assert abs(info["iters"][r] - ro["iters"]) <= 2
+    finally:
+        for c in ctxs:
+            c.close()

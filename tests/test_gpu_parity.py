@@ -32,8 +32,14 @@ def E():
 
 
 def _rel(a, b):
-    den = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+    """The larger of the normwise relative error and the largest element
+    error relative to the largest reference element, so that a localised
+    error cannot hide in the norm of a large field."""
+    a, b = np.asarray(a), np.asarray(b)
+    nb, mb = np.linalg.norm(b), np.abs(b).max() if b.size else 0.0
+    d = a - b
+    return max(np.linalg.norm(d) / (nb if nb > 0 else 1.0),
+               (np.abs(d).max() if d.size else 0.0) / (mb if mb > 0 else 1.0))
 
 
 def _small_poly(shape, seed, porosity=0.02, grains=12):
@@ -694,3 +700,33 @@ def test_autotuned_geometry_solves_and_is_cached(E, orc):
         assert info["update_blocks"] in (1024, 2048, 4096, 8192, 16384, 32768)
         assert abs(info["iters"][0] - ro["iters"]) <= 2
         assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
+
+
+from test_oracle_pins import BREAKDOWN_CASES  # noqa: E402
+
+
+@pytest.mark.parametrize("poll", [0, 1])
+@pytest.mark.parametrize("case", BREAKDOWN_CASES, ids=lambda c: "k%d" % c[-1])
+def test_breakdown_matches_oracle(E, orc, case, poll):
+    """Indefinite grid (a phase with -C): the step size of Algorithm 2 meets
+    h.Ah <= 0 at iteration k (pinned on the oracle by the Krylov projection).
+    The GPU stops with BREAKDOWN at the same iteration, and the iterate it
+    returns (every step owed to w paid, none of the breaking iteration) is the
+    oracle's.  k = 1, 2, 3, 8, 13 covers a breakdown with no step owed, with
+    one owed and with two just paid by the sweep; poll 1 looks at the flags
+    after every iteration, 0 after batches of 16 replayed as graphs."""
+    shape, seed, frac, eneg, k = case
+    say("case: breakdown", case, "poll", poll)
+    ms = synth.indefinite_grid(shape, seed, frac, eneg)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12, maxit=500)
+    assert ro["status"] == orc.BREAKDOWN and ro["iters"] == k
+    with E.Context.from_micro(ms, poll_interval=poll) as ctx:
+        st, info = ctx.solve(1e-12, 500)
+        w = ctx.solution(0)
+    assert st == E.BREAKDOWN and info["status"][0] == E.BREAKDOWN
+    assert info["iters"][0] == k
+    if k == 1:
+        assert np.all(w == 0.0)
+    else:
+        assert _rel(w, ro["w"]) <= 1e-10

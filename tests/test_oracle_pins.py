@@ -13,7 +13,9 @@ at least one of them:
 * b, A: homogeneous grid gives b = 0 and exact uniform stress; A is symmetric
   and annihilates translations; the sum of b vanishes.
 * PCG: brute-force dense assembled solve on tiny grids (numpy lstsq),
-  energy decrease, PCG and CG reach the same field.
+  energy decrease, PCG and CG reach the same field; on indefinite grids the
+  step-size breakdown (Algorithm 2, B) at the iteration where the Krylov
+  projection of A stops being positive definite, with the Galerkin iterate.
 * stress + energy: the discrete Hill-Mandel identity
   2 Pi(w) = N E_hat . <sigma>(w) + w . (A w + b) for any w.
 * physics: Eshelby inclusion mean strain against the Mori-Tanaka closed form.
@@ -395,3 +397,57 @@ def test_table3_relations_and_rotation_invariants():
         assert np.isclose(K0, Kr, rtol=1e-12) and np.isclose(G0, Gr, rtol=1e-12)
         if case == 3:
             assert abs(G0 - g["baseline_G_GPa"]) < 0.01
+
+
+# Indefinite grids (a phase with -C) on which the step size of Algorithm 2
+# meets h.Ah <= 0 at iteration k: (shape, seed, fraction of -C voxels, its E, k).
+BREAKDOWN_CASES = [((8, 8, 4), 1, 0.078, 166.3, 1), ((4, 4, 4), 2, 0.2, 262.7, 2),
+                   ((7, 8, 4), 0, 0.104, 117.9, 3), ((5, 4, 4), 209, 0.104, 150.6, 8),
+                   ((4, 4, 4), 488, 0.162, 65.7, 13)]
+
+
+def _dense_minv(minv):
+    n = minv.shape[0]
+    M = np.zeros((3 * n, 3 * n))
+    m = np.arange(n)
+    for c in range(3):
+        for d in range(3):
+            M[c * n + m, d * n + m] = minv[:, c, d]
+    return M
+
+
+@pytest.mark.parametrize("case", BREAKDOWN_CASES, ids=lambda c: "k%d" % c[-1])
+def test_breakdown_iteration_and_iterate_from_the_krylov_space(orc, case):
+    """PCG builds w_j in the Krylov space K_j = span{M^-1 b, (M^-1 A) M^-1 b, ...}
+    with A w_j + b orthogonal to K_j, and its directions are A-conjugate, so
+    the projection V_j^T A V_j of A on K_j has the signs of h_i.Ah_i, i <= j
+    (Sylvester's law of inertia).  Hence the step size breaks down at the
+    first k whose projection is not positive definite, and the iterate left
+    is the Galerkin solution on K_{k-1}: both computed here by dense linear
+    algebra, independently of the recursion."""
+    from paper_2602_07354_amd import synth
+    shape, seed, frac, eneg, k = case
+    ms = synth.indefinite_grid(shape, seed, frac, eneg)
+    P = orc.Problem(ms.shape, ms.phase, ms.C)
+    e6 = ms.strain[0]
+    b, _ = P.load(e6)
+    A = _dense_operator(P)
+    Mi = _dense_minv(P.precond())
+    V = np.zeros((3 * P.n, 0))
+    v = Mi @ b.ravel()
+    eigs = []
+    for j in range(1, k + 1):
+        for _ in range(2):  # Gram-Schmidt, twice
+            v = v - V @ (V.T @ v)
+        V = np.column_stack([V, v / np.linalg.norm(v)])
+        eigs.append(np.linalg.eigvalsh(V.T @ A @ V) / np.abs(A).max())
+        v = Mi @ (A @ V[:, -1])
+    for j, ev in enumerate(eigs[:-1], start=1):
+        assert ev.min() > 1e-6, (j, ev.min())          # K_j, j < k: positive definite
+    assert np.count_nonzero(eigs[-1] < -1e-6) == 1       # K_k: one negative direction
+    res = P.solve(e6, tol=1e-12, maxit=500)
+    assert res["status"] == orc.BREAKDOWN and res["iters"] == k
+    Vk = V[:, : k - 1]
+    w_gal = Vk @ np.linalg.solve(Vk.T @ A @ Vk, -Vk.T @ b.ravel()) if k > 1 else np.zeros(3 * P.n)
+    err = np.linalg.norm(res["w"].ravel() - w_gal)
+    assert err <= 1e-9 * max(np.linalg.norm(w_gal), 1e-30) if k > 1 else err == 0.0
