@@ -262,6 +262,30 @@ int elas3d_generate_grains(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, c
                            const double* semi, int32_t* phase, const elas3d_options* opt);
 
 /*
+ * Allocation-free grain assignment, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and the same result, bit for bit, as
+ * elas3d_generate_grains, but it calls no hipMalloc, hipFree or stream
+ * creation: the seeds sorted by search cell go to a static device work area
+ * of about 3.4 MB (one copy per GPU, held until the process ends) and the
+ * host staging to static host arrays.  Limits and differences:
+ *   - opt must be given with outputs_on_device set: `phase` is device
+ *     memory (N int32);
+ *   - ngrain <= 65536, and at most 131072 search cells (about one per seed;
+ *     more only on very flat grids);
+ *   - runs on opt->stream, or the default stream when it is NULL, and
+ *     returns after the grain map is written (the stream is synchronised);
+ *   - calls are serialised within the process (one lock): every call on a
+ *     GPU shares that GPU's work area, whose contents the next call
+ *     overwrites.
+ * Errors: ELAS3D_EBADARG (as elas3d_generate_grains, plus the limits above;
+ * checked before any device call), ELAS3D_EDEVICE; the message is in
+ * elas3d_last_error(NULL).
+ */
+int elas3d_generate_grains_static(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, const double* seeds,
+                                  const double* semi, int32_t* phase, const elas3d_options* opt);
+
+/*
  * Pore overwrite (Sec. 2.2.3): pores p = 0, 1, ... are carved in order,
  * setting to void_id every voxel whose centre they cover, until the number of
  * void voxels reaches `target` (target < 0: carve all; none is carved when

@@ -27,6 +27,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -263,17 +264,23 @@ int check_grid(int32_t nx, int32_t ny, int32_t nz)
     return 0;
 }
 
-}  // namespace
+// Validated inputs of a grain assignment and its search cells: about one
+// seed per cell, each at least one voxel wide.
+struct GrainPlan {
+    int nx, ny, nz;
+    int nc[3];
+    double h[3];
+    long ncell;
+    double rmax;
+};
 
-extern "C" {
-
-int elas3d_generate_grains(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, const double* seeds,
-                           const double* semi, int32_t* phase, const elas3d_options* opt)
+int grain_plan(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, const double* seeds, const double* semi,
+               GrainPlan& P)
 {
     int rc = check_grid(nx, ny, nz);
     if (rc) return rc;
     if (ngrain < 1) return gen_fail(ELAS3D_EBADARG, "ngrain must be >= 1");
-    if (!seeds || !phase) return gen_fail(ELAS3D_EBADARG, "seeds or phase is NULL");
+    if (!seeds) return gen_fail(ELAS3D_EBADARG, "seeds is NULL");
     const int dims[3] = {nx, ny, nz};
     double rmax = 0.0;
     for (int g = 0; g < ngrain; ++g) {
@@ -287,67 +294,74 @@ int elas3d_generate_grains(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, c
             return gen_fail(ELAS3D_EBADARG, "semi-axes of grain " + std::to_string(g) + " must be > 0");
         rmax = std::max(rmax, std::max(rt, rl));
     }
-    // cells of about one seed each, at least one voxel wide
     const double spacing = std::cbrt((double)nx * ny * nz / ngrain);
-    int nc[3];
-    double h[3];
+    P.nx = nx;
+    P.ny = ny;
+    P.nz = nz;
     for (int d = 0; d < 3; ++d) {
-        nc[d] = (int)std::max(1.0, std::min((double)dims[d], std::floor(dims[d] / spacing)));
-        h[d] = (double)dims[d] / nc[d];
+        P.nc[d] = (int)std::max(1.0, std::min((double)dims[d], std::floor(dims[d] / spacing)));
+        P.h[d] = (double)dims[d] / P.nc[d];
     }
-    const long ncell = (long)nc[0] * nc[1] * nc[2];
-    // counting sort of the seeds by cell (host: a few thousand seeds)
+    P.ncell = (long)P.nc[0] * P.nc[1] * P.nc[2];
+    P.rmax = rmax;
+    return 0;
+}
+
+// Counting sort of the seeds by cell (ascending grain id within a cell):
+// start[ncell + 1] offsets, gid[ngrain] grain of each sorted slot, cols the
+// five SoA columns x, y, z, rt^2, rl^2 (ngrain each); owner and fillp are
+// work arrays (ngrain and ncell).
+void grain_sort(const double* seeds, const double* semi, int ngrain, const GrainPlan& P, int* start, int* owner,
+                int* fillp, int* gid, double* cols)
+{
     auto cell = [&](int d, double x) {
-        int c = (int)std::floor(x / h[d]);
-        return c < 0 ? 0 : (c >= nc[d] ? nc[d] - 1 : c);
+        int c = (int)std::floor(x / P.h[d]);
+        return c < 0 ? 0 : (c >= P.nc[d] ? P.nc[d] - 1 : c);
     };
-    std::vector<int> start(ncell + 1, 0), owner(ngrain);
+    std::fill(start, start + P.ncell + 1, 0);
     for (int g = 0; g < ngrain; ++g) {
         const long c = cell(0, seeds[3 * (size_t)g]) +
-                       (long)nc[0] * (cell(1, seeds[3 * (size_t)g + 1]) + (long)nc[1] * cell(2, seeds[3 * (size_t)g + 2]));
+                       (long)P.nc[0] * (cell(1, seeds[3 * (size_t)g + 1]) +
+                                        (long)P.nc[1] * cell(2, seeds[3 * (size_t)g + 2]));
         owner[g] = (int)c;
         ++start[c + 1];
     }
-    for (long c = 0; c < ncell; ++c) start[c + 1] += start[c];
-    std::vector<int> fillp(start.begin(), start.end() - 1), gid(ngrain);
-    std::vector<double> sx(ngrain), sy(ngrain), sz(ngrain), rt2(ngrain), rl2(ngrain);
-    for (int g = 0; g < ngrain; ++g) {  // ascending g within a cell
+    for (long c = 0; c < P.ncell; ++c) start[c + 1] += start[c];
+    std::copy(start, start + P.ncell, fillp);
+    for (int g = 0; g < ngrain; ++g) {
         const int q = fillp[owner[g]]++;
         gid[q] = g;
-        sx[q] = seeds[3 * (size_t)g];
-        sy[q] = seeds[3 * (size_t)g + 1];
-        sz[q] = seeds[3 * (size_t)g + 2];
+        cols[q] = seeds[3 * (size_t)g];
+        cols[(size_t)ngrain + q] = seeds[3 * (size_t)g + 1];
+        cols[2 * (size_t)ngrain + q] = seeds[3 * (size_t)g + 2];
         const double rt = semi ? semi[2 * (size_t)g] : 1.0, rl = semi ? semi[2 * (size_t)g + 1] : 1.0;
-        rt2[q] = rt * rt;
-        rl2[q] = rl * rl;
+        cols[3 * (size_t)ngrain + q] = rt * rt;
+        cols[4 * (size_t)ngrain + q] = rl * rl;
     }
-    GenCall call;
-    rc = gen_begin(opt, call);
-    if (rc) return rc;
+}
+
+// Copies the sorted seeds to the device buffers and launches the grain
+// kernel on st (asynchronous: the host arrays must stay valid until the
+// stream passes the copies, which pageable host memory guarantees on return).
+int grain_launch(hipStream_t st, const GrainPlan& P, int ngrain, const int* start, const int* gid,
+                 const double* cols, int* dstart, int* dgid, double* dseed, int32_t* out)
+{
+    GENCHK(hipMemcpyAsync(dstart, start, sizeof(int) * (size_t)(P.ncell + 1), hipMemcpyHostToDevice, st));
+    GENCHK(hipMemcpyAsync(dgid, gid, sizeof(int) * (size_t)ngrain, hipMemcpyHostToDevice, st));
+    GENCHK(hipMemcpyAsync(dseed, cols, sizeof(double) * 5 * (size_t)ngrain, hipMemcpyHostToDevice, st));
     GrainGrid G{};
-    G.nx = nx;
-    G.ny = ny;
-    G.nz = nz;
-    G.cx = nc[0];
-    G.cy = nc[1];
-    G.cz = nc[2];
-    G.hx = h[0];
-    G.hy = h[1];
-    G.hz = h[2];
-    const double hmin = std::min(h[0], std::min(h[1], h[2])) * (1.0 - 1e-9);
-    G.bound_scale = hmin * hmin / (rmax * rmax);
-    G.kfull = std::max({nc[0] / 2, nc[1] / 2, nc[2] / 2});
-    int *dstart = nullptr, *dgid = nullptr;
-    double* dseed = nullptr;
-    GENCHK(call.alloc(&dstart, sizeof(int) * start.size()));
-    GENCHK(call.alloc(&dgid, sizeof(int) * (size_t)ngrain));
-    GENCHK(call.alloc(&dseed, sizeof(double) * 5 * (size_t)ngrain));
-    GENCHK(hipMemcpyAsync(dstart, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, call.stream));
-    GENCHK(hipMemcpyAsync(dgid, gid.data(), sizeof(int) * (size_t)ngrain, hipMemcpyHostToDevice, call.stream));
-    const std::vector<double>* cols[5] = {&sx, &sy, &sz, &rt2, &rl2};
-    for (int q = 0; q < 5; ++q)
-        GENCHK(hipMemcpyAsync(dseed + (size_t)q * ngrain, cols[q]->data(), sizeof(double) * (size_t)ngrain,
-                              hipMemcpyHostToDevice, call.stream));
+    G.nx = P.nx;
+    G.ny = P.ny;
+    G.nz = P.nz;
+    G.cx = P.nc[0];
+    G.cy = P.nc[1];
+    G.cz = P.nc[2];
+    G.hx = P.h[0];
+    G.hy = P.h[1];
+    G.hz = P.h[2];
+    const double hmin = std::min(P.h[0], std::min(P.h[1], P.h[2])) * (1.0 - 1e-9);
+    G.bound_scale = hmin * hmin / (P.rmax * P.rmax);
+    G.kfull = std::max({P.nc[0] / 2, P.nc[1] / 2, P.nc[2] / 2});
     G.start = dstart;
     G.gid = dgid;
     G.sx = dseed;
@@ -355,15 +369,121 @@ int elas3d_generate_grains(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, c
     G.sz = dseed + 2 * (size_t)ngrain;
     G.rt2 = dseed + 3 * (size_t)ngrain;
     G.rl2 = dseed + 4 * (size_t)ngrain;
+    const long n = (long)P.nx * P.ny * P.nz;
+    hipLaunchKernelGGL(grains_kernel, dim3(grid_for(n)), dim3(kGenBlock), 0, st, G, out);
+    GENCHK(hipGetLastError());
+    return 0;
+}
+
+// ---- the allocation-free grain assignment ------------------------------
+// Its sorted seeds live in a static device array (one copy per GPU, held
+// until the process ends) and its host staging in static host arrays.
+constexpr int kStaticMaxGrains = 1 << 16;
+constexpr long kStaticMaxCells = 1L << 17;
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kOffStart = 0;
+constexpr size_t kOffGid = align256(kOffStart + sizeof(int) * (kStaticMaxCells + 1));
+constexpr size_t kOffSeed = align256(kOffGid + sizeof(int) * kStaticMaxGrains);
+constexpr size_t kStaticBytes = align256(kOffSeed + sizeof(double) * 5 * kStaticMaxGrains);
+
+__device__ __align__(256) char scratch[kStaticBytes];
+
+struct StaticHost {
+    int start[kStaticMaxCells + 1];
+    int owner[kStaticMaxGrains];
+    int fillp[kStaticMaxCells];
+    int gid[kStaticMaxGrains];
+    double cols[5 * kStaticMaxGrains];
+};
+StaticHost g_static_host;
+std::mutex g_static_mu;
+constexpr int kMaxDevices = 64;
+char* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this GPU's copy of the work area (the array's name is
+// a host-side stand-in, not a device address), looked up once per device
+// with that device current.
+int static_scratch(int dev, char** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return gen_fail(ELAS3D_EBADARG, "device ordinal out of range");
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        GENCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return gen_fail(ELAS3D_EDEVICE, "no device address for the static work area");
+        g_scratch_dev[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int elas3d_generate_grains(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, const double* seeds,
+                           const double* semi, int32_t* phase, const elas3d_options* opt)
+{
+    if (!phase) return gen_fail(ELAS3D_EBADARG, "phase is NULL");
+    GrainPlan P;
+    int rc = grain_plan(nx, ny, nz, ngrain, seeds, semi, P);
+    if (rc) return rc;
+    std::vector<int> start(P.ncell + 1), owner(ngrain), fillp(P.ncell), gid(ngrain);
+    std::vector<double> cols(5 * (size_t)ngrain);
+    grain_sort(seeds, semi, ngrain, P, start.data(), owner.data(), fillp.data(), gid.data(), cols.data());
+    GenCall call;
+    rc = gen_begin(opt, call);
+    if (rc) return rc;
+    int *dstart = nullptr, *dgid = nullptr;
+    double* dseed = nullptr;
+    GENCHK(call.alloc(&dstart, sizeof(int) * start.size()));
+    GENCHK(call.alloc(&dgid, sizeof(int) * (size_t)ngrain));
+    GENCHK(call.alloc(&dseed, sizeof(double) * 5 * (size_t)ngrain));
     const long n = (long)nx * ny * nz;
     const bool dev_out = opt && opt->outputs_on_device;
     int32_t* out = phase;
     if (!dev_out) GENCHK(call.alloc(&out, sizeof(int32_t) * (size_t)n));
-    hipLaunchKernelGGL(grains_kernel, dim3(grid_for(n)), dim3(kGenBlock), 0, call.stream, G, out);
-    GENCHK(hipGetLastError());
+    rc = grain_launch(call.stream, P, ngrain, start.data(), gid.data(), cols.data(), dstart, dgid, dseed, out);
+    if (rc) return rc;
     if (!dev_out)
         GENCHK(hipMemcpyAsync(phase, out, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, call.stream));
     GENCHK(hipStreamSynchronize(call.stream));
+    return 0;
+}
+
+int elas3d_generate_grains_static(int32_t nx, int32_t ny, int32_t nz, int32_t ngrain, const double* seeds,
+                                  const double* semi, int32_t* phase, const elas3d_options* opt)
+{
+    if (!phase) return gen_fail(ELAS3D_EBADARG, "phase is NULL");
+    if (!opt || !opt->outputs_on_device)
+        return gen_fail(ELAS3D_EBADARG, "the allocation-free grain assignment writes device memory only: "
+                                        "set options.outputs_on_device and pass a device phase buffer");
+    if (ngrain > kStaticMaxGrains)
+        return gen_fail(ELAS3D_EBADARG, "ngrain above " + std::to_string(kStaticMaxGrains) +
+                                            " (the static work area's limit)");
+    GrainPlan P;
+    int rc = grain_plan(nx, ny, nz, ngrain, seeds, semi, P);
+    if (rc) return rc;
+    if (P.ncell > kStaticMaxCells)
+        return gen_fail(ELAS3D_EBADARG, std::to_string(P.ncell) + " search cells, above " +
+                                            std::to_string(kStaticMaxCells) + " (the static work area's limit)");
+    // one call at a time in the process: the host staging below and each
+    // device's work area are shared by every call
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (opt->device >= 0) GENCHK(hipSetDevice(opt->device));
+    int dev = 0;
+    GENCHK(hipGetDevice(&dev));
+    char* base = nullptr;
+    rc = static_scratch(dev, &base);
+    if (rc) return rc;
+    StaticHost& H = g_static_host;
+    grain_sort(seeds, semi, ngrain, P, H.start, H.owner, H.fillp, H.gid, H.cols);
+    int* dstart = reinterpret_cast<int*>(base + kOffStart);
+    int* dgid = reinterpret_cast<int*>(base + kOffGid);
+    double* dseed = reinterpret_cast<double*>(base + kOffSeed);
+    hipStream_t st = (hipStream_t)opt->stream;  // NULL: the default stream
+    rc = grain_launch(st, P, ngrain, H.start, H.gid, H.cols, dstart, dgid, dseed, phase);
+    if (rc) return rc;
+    GENCHK(hipStreamSynchronize(st));
     return 0;
 }
 

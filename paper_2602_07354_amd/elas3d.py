@@ -24,7 +24,7 @@ __all__ = [
     "PRECOND_NONE", "TILE_SHAPES", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
     "setup", "solve", "stress", "apply", "get_load", "get_precond", "get_solution",
     "device_bytes", "destroy", "last_error", "version", "Context", "EXPORTS", "von_mises",
-    "generate_grains", "carve_pores", "PORE_STRIDE", "Group", "stream_bandwidth",
+    "generate_grains", "generate_grains_static", "carve_pores", "PORE_STRIDE", "Group", "stream_bandwidth",
 ]
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
@@ -45,7 +45,7 @@ EXPORTS = (
     "elas3d_get_load", "elas3d_get_precond", "elas3d_get_solution", "elas3d_device_bytes",
     "elas3d_destroy", "elas3d_last_error", "elas3d_version", "elas3d_von_mises",
     "elas3d_generate_grains", "elas3d_carve_pores", "elas3d_group_create", "elas3d_group_add",
-    "elas3d_group_run", "elas3d_group_destroy", "elas3d_stream_bandwidth",
+    "elas3d_group_run", "elas3d_group_destroy", "elas3d_stream_bandwidth", "elas3d_generate_grains_static",
 )
 
 
@@ -178,6 +178,8 @@ def lib():
         L.elas3d_von_mises.restype = ctypes.c_int
         L.elas3d_generate_grains.argtypes = [i32, i32, i32, i32, vp, vp, vp, ctypes.POINTER(Options)]
         L.elas3d_generate_grains.restype = ctypes.c_int
+        L.elas3d_generate_grains_static.argtypes = [i32, i32, i32, i32, vp, vp, vp, ctypes.POINTER(Options)]
+        L.elas3d_generate_grains_static.restype = ctypes.c_int
         L.elas3d_carve_pores.argtypes = [i32, i32, i32, vp, i32, i32, vp, d, vp, vp,
                                          ctypes.POINTER(Options)]
         L.elas3d_carve_pores.restype = ctypes.c_int
@@ -300,6 +302,21 @@ def generate_grains(shape, seeds, semi=None, phase=None, options: Optional[Optio
         phase = np.empty(nx * ny * nz, dtype=np.int32)
     rc = lib().elas3d_generate_grains(nx, ny, nz, seeds.shape[0], _ptr(seeds), _ptr(semi), _ptr(phase),
                                       ctypes.byref(options) if options is not None else None)
+    _check(rc)
+    return phase
+
+
+def generate_grains_static(shape, seeds, semi, phase, options: Options):
+    """elas3d_generate_grains_static: the allocation-free grain assignment into
+    the device buffer `phase` (options.outputs_on_device must be set)."""
+    nx, ny, nz = (int(s) for s in shape)
+    seeds = np.ascontiguousarray(seeds, dtype=np.float64).reshape(-1, 3)
+    if semi is not None:
+        semi = np.ascontiguousarray(semi, dtype=np.float64).reshape(-1, 2)
+        if semi.shape[0] != seeds.shape[0]:
+            raise ValueError("semi must have one row per seed")
+    rc = lib().elas3d_generate_grains_static(nx, ny, nz, seeds.shape[0], _ptr(seeds), _ptr(semi), _ptr(phase),
+                                             ctypes.byref(options) if options is not None else None)
     _check(rc)
     return phase
 
