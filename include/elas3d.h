@@ -155,6 +155,9 @@ typedef struct elas3d_info {
                                                   per phase-boundary node            */
     int32_t update_nontemporal;                /* 1 if the update sweep streams its
                                                   node vectors non-temporally        */
+    int32_t apply_tile[3];                     /* workgroup lanes in x, y and z-chunk
+                                                  length of the true-residual and
+                                                  refinement sweeps                   */
 } elas3d_info;
 
 /* Fill `opt` with the defaults (FP64, residual criterion, block Jacobi,

@@ -362,6 +362,76 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
     return 0;
 }
 
+// Geometry of the residual and refinement sweeps (one operator application
+// each, FP64): with options.autotune = 1, the fastest of the candidate
+// workgroup shapes and z-chunkings on the live grid (cached per process by
+// device and grid), timed as y = A w into the FP64 operator-output field of
+// case 0 (no finalize, so no scalar changes; y is rewritten by the first
+// direction sweep); with 2, the forced geometry of options.tile / zchunk.
+// The reduction order of ||y||^2 follows the geometry; y itself does not
+// depend on it.
+std::map<std::array<int, 4>, e3d::OpGeom> g_apply_cache;
+
+int autotune_apply(elas3d_ctx* c)
+{
+    const Dims& d = c->d;
+    if (c->opt.autotune == 2) {
+        c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, c->opt.tile);
+        c->apply_tuned = 1;
+        return 0;
+    }
+    const std::array<int, 4> key = {c->device, d.nx, d.ny, d.nz};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_apply_cache.find(key);
+        if (it != g_apply_cache.end()) {
+            c->geom_apply = it->second;
+            c->apply_tuned = 1;
+            return 0;
+        }
+    }
+    Fields f = c->fields(0);
+    const double* x[3] = {f.w[0], f.w[1], f.w[2]};
+    double* y[3] = {f.Ah[0], f.Ah[1], f.Ah[2]};
+    const e3d::Tables t = c->tables();
+    hipEvent_t ev[2];
+    HIPCHK(c, hipEventCreate(&ev[0]));
+    HIPCHK(c, hipEventCreate(&ev[1]));
+    float best = 1e30f;
+    e3d::OpGeom best_g = c->geom_apply;
+    int rc = 0;
+    for (int tile = 0; tile < e3d::kNumTiles && !rc; ++tile)
+        for (int target : kTuneTargets) {
+            const e3d::OpGeom g = e3d::op_geometry(d, 0, tile, target);
+            auto launch = [&] { return e3d::launch_apply(c->stream, d, g, c->phase, t, x, y, nullptr, c->partials, nullptr); };
+            hipError_t e = launch();  // warm-up
+            for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+                if (k == 0) e = hipEventRecord(ev[0], c->stream);
+                if (e == hipSuccess) e = launch();
+            }
+            if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess) {
+                rc = fail(c, ELAS3D_EDEVICE, std::string("apply autotuning: ") + hipGetErrorString(e));
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_g = g;
+            }
+        }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (rc) return rc;
+    c->geom_apply = best_g;
+    c->apply_tuned = 1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_apply_cache[key] = best_g;
+    return 0;
+}
+
 // Enqueue PCG iterations (direction+operator sweep, update sweep) for the
 // batch of R right-hand sides [r0, r0+R) in batches of `poll`, until the
 // device has raised the stop flag of every RHS; the host looks at the flags of
@@ -613,7 +683,7 @@ int refine_launch(elas3d_ctx* c, int r, int q)
     double* w[3] = {f64.w[0], f64.w[1], f64.w[2]};
     const float* dc[3] = {f32.w[0], f32.w[1], f32.w[2]};
     float* r32[3] = {f32.g[0], f32.g[1], f32.g[2]};
-    HIPCHK(c, e3d::launch_refine(c->stream, c->d, c->geom, c->phase, c->tables(), w, dc, f64.b, r32,
+    HIPCHK(c, e3d::launch_refine(c->stream, c->d, c->geom_apply, c->phase, c->tables(), w, dc, f64.b, r32,
                                  c->partials, c->dscratch + 4 + 2 * q));
     // {||r||^2, ||r||^2}: the norms of the next inner run
     HIPCHK(c, hipMemcpyAsync(c->dscratch + 5 + 2 * q, c->dscratch + 4 + 2 * q, sizeof(double),
@@ -626,7 +696,7 @@ int residual_launch(elas3d_ctx* c, int r, double* norm2)
     Fields f = c->fields(r);
     const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
     double* gy[3] = {f.g[0], f.g[1], f.g[2]};
-    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom, c->phase, c->tables(), wx, gy, f.b, c->partials,
+    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom_apply, c->phase, c->tables(), wx, gy, f.b, c->partials,
                                 norm2));
     return 0;
 }
@@ -647,7 +717,7 @@ int true_residual(elas3d_ctx* c, int r, double* rr)
     Fields f = c->fields(r);
     const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
     double* gy[3] = {f.g[0], f.g[1], f.g[2]};
-    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom, c->phase, c->tables(), wx, gy, f.b, c->partials,
+    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom_apply, c->phase, c->tables(), wx, gy, f.b, c->partials,
                                 c->dscratch));
     HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -744,7 +814,7 @@ int solve_mixed(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info
         Fields f = c->fields(r);
         const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
         double* gy[3] = {f.g[0], f.g[1], f.g[2]};
-        HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom, c->phase, t, wx, gy, f.b, c->partials,
+        HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom_apply, c->phase, t, wx, gy, f.b, c->partials,
                                     c->dscratch));
         CaseResult fr;
         int rc = solve_fp64(c, r, 1, tol, maxit, true, iters[q], info, &fr);
@@ -794,6 +864,9 @@ int record_results(elas3d_ctx* c, int r0, int R, const CaseResult* res, elas3d_i
             info->op_tile[2] = g.kz;
             info->update_blocks = c->upd_blocks[pi];
             info->update_nontemporal = c->upd_nt[pi];
+            info->apply_tile[0] = e3d::kTileShapes[c->geom_apply.tile].tx;
+            info->apply_tile[1] = e3d::kTileShapes[c->geom_apply.tile].ty;
+            info->apply_tile[2] = c->geom_apply.kz;
         }
         c->solved[r] = 1;
         worst = std::max(worst, fin.status);
@@ -904,6 +977,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->solved.assign(nrhs, 0);
     c->bytes = need;
     c->geom = e3d::op_geometry(c->d, 0);
+    c->geom_apply = c->geom;
     for (int q = 0; q < 2; ++q) {
         c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, opt.tile);
         c->upd_blocks[q] = opt.update_blocks > 0 ? opt.update_blocks : default_update_blocks(c->d.n);
@@ -1043,6 +1117,10 @@ int elas3d_solve(elas3d_ctx* ctx, double tol, int32_t maxit, int32_t nrhs, elas3
     }
     HIPCHK(ctx, hipSetDevice(ctx->device));
     auto t0 = std::chrono::steady_clock::now();
+    if (ctx->opt.autotune && !ctx->apply_tuned) {
+        int rc = autotune_apply(ctx);
+        if (rc) return rc;
+    }
     int worst = 0;
     if (ctx->batched()) {
         int rc = solve_batch(ctx, 0, nrhs, tol, maxit, info);

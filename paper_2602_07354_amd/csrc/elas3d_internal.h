@@ -186,7 +186,7 @@ hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const i
                          double* norm2);
 hipError_t launch_to_float(hipStream_t st, const double* src, float* dst, size_t n);
 // y = A x (+ add when add[0] != nullptr); ||y||^2 into *norm2 when norm2 != nullptr.
-// APPLY and REFINE run with tile shape 0 only.
+// APPLY and REFINE run with any workgroup shape (the geometry g).
 hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
                         const Tables& t, const double* const x[3], double* const y[3],
                         const double* const add[3], double* partials, double* norm2);

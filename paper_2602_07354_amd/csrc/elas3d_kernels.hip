@@ -1902,9 +1902,8 @@ hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const in
     }
     a.partials = partials;
     a.want_norm = norm2 != nullptr;
-    if (g.tile != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_APPLY, double>), dim3(g.blocks), dim3(kTX * kTY), 0, st,
-                       a);
+    hipError_t e = launch_op_tiled<OP_APPLY, double>(st, g, (unsigned)g.blocks, a);
+    if (e != hipSuccess) return e;
     if (norm2)
         hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
                            (const double*)partials, g.blocks, g.blocks, (Scalars*)nullptr, norm2,
@@ -1932,9 +1931,8 @@ hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const i
     }
     a.partials = partials;
     a.want_norm = 1;
-    if (g.tile != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((op_kernel<kTX, kTY, OP_REFINE, double>), dim3(g.blocks), dim3(kTX * kTY), 0, st,
-                       a);
+    hipError_t e = launch_op_tiled<OP_REFINE, double>(st, g, (unsigned)g.blocks, a);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
                        (const double*)partials, g.blocks, g.blocks, (Scalars*)nullptr, norm2,
                        (const double*)nullptr, 0);

@@ -51,7 +51,11 @@ struct elas3d_ctx {
     int nphase = 0, nrhs = 0;
     elas3d_options opt{};
     std::vector<double> strain;  // nrhs * 6
-    e3d::OpGeom geom{};  // APPLY / REFINE sweeps (tile shape 0)
+    e3d::OpGeom geom{};  // default geometry (tile shape 0): group members
+    // geometry of the residual and refinement sweeps of elas3d_solve (the
+    // default, or the autotuned choice)
+    e3d::OpGeom geom_apply{};
+    int apply_tuned = 0;
     // direction+operator sweep and update grid per precision (0 FP64, 1 FP32),
     // the defaults or the autotuned choice
     e3d::OpGeom geom_sweep[2]{};

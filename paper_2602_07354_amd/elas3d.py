@@ -96,6 +96,7 @@ class Info(ctypes.Structure):
         ("update_blocks", ctypes.c_int32),
         ("precond_rows", ctypes.c_int64),
         ("update_nontemporal", ctypes.c_int32),
+        ("apply_tile", ctypes.c_int32 * 3),
     ]
 
     def as_dict(self) -> dict:
@@ -119,6 +120,7 @@ class Info(ctypes.Structure):
             "update_blocks": self.update_blocks,
             "precond_rows": self.precond_rows,
             "update_nontemporal": self.update_nontemporal,
+            "apply_tile": list(self.apply_tile),
         }
 
 
