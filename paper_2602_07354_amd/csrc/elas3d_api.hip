@@ -919,7 +919,9 @@ const char* elas3d_last_error(const elas3d_ctx* ctx)
 double elas3d_device_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t nphase, int32_t nrhs,
                            const elas3d_options* opt)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || 3 * (int64_t)nx * ny * nz >= ((int64_t)1 << 31) || nrhs < 1)
+    // the size checks of elas3d_setup
+    if (nx < 2 || ny < 2 || nz < 2 || 3 * (int64_t)nx * ny * nz >= ((int64_t)1 << 31) || nphase < 1 ||
+        nrhs < 1 || nrhs > ELAS3D_MAX_RHS)
         return 0.0;
     const bool valid_geom = opt && opt->tile >= 0 && opt->tile < e3d::kNumTiles && opt->zchunk >= 0;
     return plan_bytes(nx, ny, nz, nphase, nrhs, opt && opt->precision == ELAS3D_PREC_MIXED,
