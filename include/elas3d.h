@@ -97,7 +97,8 @@ typedef struct elas3d_options {
                                   when timing is on); default 1                      */
     int32_t autotune;          /* nonzero: before the first iteration of each
                                   precision, time the candidate workgroup shapes
-                                  (32x8, 16x16, 64x4, 32x16, 64x8 lanes) and z-chunkings
+                                  (options.tile's list; 5 and 6 where nx allows)
+                                  and z-chunkings
                                   (about 2048 to 16384 workgroups) of the
                                   direction+operator sweep and
                                   the grid (1024 to 32768 workgroups) and the
@@ -112,7 +113,11 @@ typedef struct elas3d_options {
                                   zchunk.  Default 0                                 */
     int32_t tile;              /* workgroup shape of the direction+operator sweep
                                   when not autotuned: 0 = 32x8 lanes (default),
-                                  1 = 16x16, 2 = 64x4, 3 = 32x16, 4 = 64x8          */
+                                  1 = 16x16, 2 = 64x4, 3 = 32x16, 4 = 64x8;
+                                  5 = 64x6 + two loader wavefronts (the node
+                                  planes stream into an LDS ring by direct-to-
+                                  LDS loads; nx must be a multiple of 4, else
+                                  EBADARG)                                   */
     int32_t zchunk;            /* z planes per workgroup of that sweep when not
                                   autotuned; 0 = automatic (about 4096 workgroups);
                                   values above nz mean nz                            */

@@ -191,6 +191,16 @@ int validate_setup(int32_t nx, int32_t ny, int32_t nz, const int32_t* phase, int
         return fail(nullptr, ELAS3D_EBADARG, "nrhs must be in [1, 6]");
     int rc = validate_options(o);
     if (rc) return rc;
+    {
+        // a forced wave-specialised shape streams node rows in whole 16-byte
+        // chunks in every precision the context sweeps in
+        const Dims d{nx, ny, nz, (int)n};
+        const int elem = o->precision == ELAS3D_PREC_MIXED ? 4 : 8;
+        if (o->autotune != 1 && !e3d::ws_supported(d, o->tile, elem))
+            return fail(nullptr, ELAS3D_EBADARG,
+                        "options.tile " + std::to_string(o->tile) + " needs nx to be a multiple of " +
+                            std::to_string(16 / elem) + " and nx*ny < 2^27");
+    }
     for (int p = 0; p < nphase; ++p) {
         const double* Cp = C + 36 * (size_t)p;
         double amax = 0.0;
@@ -227,6 +237,10 @@ void free_ctx(elas3d_ctx* c)
         if (p) hipFree(p);
     if (c->hS) hipHostFree(c->hS);
     if (c->hscratch) hipHostFree(c->hscratch);
+    for (auto& e : c->wsd) {
+        if (e.dict) hipFree(e.dict);
+        if (e.map) hipFree(e.map);
+    }
     for (auto& g : c->graphs) {
         hipGraphExecDestroy(g.exec);
         hipGraphDestroy(g.graph);
@@ -266,6 +280,63 @@ int export_field(elas3d_ctx* c, const double* field, int ncomp, double* out)
     return 0;
 }
 
+// Builds (once per geometry) the phase dictionaries of the wave-specialised
+// geometry g; fits is false when some workgroup box of g holds more than
+// kWsDict distinct phases (nothing is kept then).  Other geometries: fits.
+int ws_prepare(elas3d_ctx* c, const e3d::OpGeom& g, bool& fits)
+{
+    fits = true;
+    if (e3d::kTileShapes[g.tile].nl == 0) return 0;
+    for (const auto& e : c->wsd)
+        if (e.g.tile == g.tile && e.g.tiles_x == g.tiles_x && e.g.tiles_y == g.tiles_y && e.g.kz == g.kz) {
+            fits = e.maxcount <= e3d::kWsDict;
+            return 0;
+        }
+    elas3d_ctx::WsDictEntry e{g, nullptr, nullptr, 0};
+    auto drop = [&](hipError_t err) {
+        if (e.dict) hipFree(e.dict);
+        if (e.map) hipFree(e.map);
+        return fail(c, ELAS3D_EDEVICE, std::string("phase dictionaries: ") + hipGetErrorString(err));
+    };
+    hipError_t err = hipMalloc(&e.dict, sizeof(int32_t) * (size_t)g.blocks * e3d::kWsDict);
+    if (err == hipSuccess) err = hipMalloc(&e.map, e3d::ws_map_bytes(g));
+    if (err == hipSuccess) err = hipMemsetAsync(c->dflag + 1, 0, sizeof(int), c->stream);
+    if (err == hipSuccess) err = e3d::launch_ws_dictionary(c->stream, c->d, g, c->phase, e.dict, e.map, c->dflag + 1);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(c->hscratch, c->dflag + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+    if (err != hipSuccess) return drop(err);
+    std::memcpy(&e.maxcount, c->hscratch, sizeof(int));
+    if (e.maxcount > e3d::kWsDict) {
+        hipFree(e.dict);
+        hipFree(e.map);
+        e.dict = nullptr;
+        e.map = nullptr;
+        fits = false;
+    }
+    c->wsd.push_back(e);
+    return 0;
+}
+
+// Frees the dictionaries of geometries neither precision's sweep uses.
+void ws_release_unused(elas3d_ctx* c)
+{
+    std::vector<elas3d_ctx::WsDictEntry> keep;
+    for (auto& e : c->wsd) {
+        bool used = false;
+        for (const auto& g : c->geom_sweep)
+            used = used || (e.g.tile == g.tile && e.g.tiles_x == g.tiles_x && e.g.tiles_y == g.tiles_y &&
+                            e.g.kz == g.kz);
+        if (used) {
+            keep.push_back(e);
+        } else {
+            if (e.dict) hipFree(e.dict);
+            if (e.map) hipFree(e.map);
+        }
+    }
+    c->wsd.swap(keep);
+}
+
 // Process-wide autotuning results: (device, nx, ny, nz, element size, RHS,
 // mode) -> (operator sweep geometry, update grid, update non-temporal);
 // mode 2 tunes the update sweep only (its geometry entry is not used).
@@ -291,14 +362,31 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
     const int pi = sizeof(T) == sizeof(double) ? 0 : 1;
     const bool op_too = c->opt.autotune != 2;
     const std::array<int, 7> key = {c->device, c->d.nx, c->d.ny, c->d.nz, (int)sizeof(T), R, op_too ? 1 : 2};
+    bool cached = false;
+    TuneChoice choice{};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            if (op_too) c->geom_sweep[pi] = it->second.geom;
-            c->upd_blocks[pi] = it->second.upd_blocks;
-            c->upd_nt[pi] = it->second.upd_nt;
+            cached = true;
+            choice = it->second;
+        }
+    }
+    if (cached) {
+        // the cache is keyed by the grid, not the phases: a wave-specialised
+        // choice is kept only when this microstructure's boxes fit its
+        // dictionaries, else this context is tuned afresh (and not cached)
+        bool fits = true;
+        if (op_too) {
+            int rc = ws_prepare(c, choice.geom, fits);
+            if (rc) return rc;
+        }
+        if (fits) {
+            if (op_too) c->geom_sweep[pi] = choice.geom;
+            c->upd_blocks[pi] = choice.upd_blocks;
+            c->upd_nt[pi] = choice.upd_nt;
             c->tuned[pi] = 1;
+            ws_release_unused(c);
             return 0;
         }
     }
@@ -322,10 +410,16 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
     e3d::OpGeom best_g = c->geom_sweep[pi];
     for (int tile = 0; tile < e3d::kNumTiles && !rc && op_too; ++tile)
         for (int target : kTuneTargets) {
+            if (!e3d::ws_supported(d, tile, (int)sizeof(T))) break;  // shape not possible on this grid
             const e3d::OpGeom g = e3d::op_geometry(d, 0, tile, target);
+            bool fits = true;
+            rc = ws_prepare(c, g, fits);
+            if (rc) break;
+            if (!fits) continue;  // a box with more phases than a dictionary holds
+            const e3d::Tables tg = c->tables_for(g);
             float ms = 0.f;
             rc = time_it([&] {
-                return e3d::launch_direction_operator<T>(c->stream, d, g, c->phase, t, f0, rs, R, S0,
+                return e3d::launch_direction_operator<T>(c->stream, d, g, c->phase, tg, f0, rs, R, S0,
                                                          c->partials, false);
             }, ms);
             if (rc) break;
@@ -357,8 +451,11 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
     c->upd_blocks[pi] = best_nb;
     c->upd_nt[pi] = best_nt;
     c->tuned[pi] = 1;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {best_g, best_nb, best_nt};
+    ws_release_unused(c);
+    if (!cached) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {best_g, best_nb, best_nt};
+    }
     return 0;
 }
 
@@ -367,7 +464,8 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
 // workgroup shapes and z-chunkings on the live grid (cached per process by
 // device and grid), timed as y = A w into the FP64 operator-output field of
 // case 0 (no finalize, so no scalar changes; y is rewritten by the first
-// direction sweep); with 2, the forced geometry of options.tile / zchunk.
+// direction sweep); with 2, the forced geometry of options.tile / zchunk
+// (64x8 lanes when that shape exists for the fused sweep only).
 // The reduction order of ||y||^2 follows the geometry; y itself does not
 // depend on it.
 std::map<std::array<int, 4>, e3d::OpGeom> g_apply_cache;
@@ -376,7 +474,9 @@ int autotune_apply(elas3d_ctx* c)
 {
     const Dims& d = c->d;
     if (c->opt.autotune == 2) {
-        c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, c->opt.tile);
+        // the forced shape, or 64x8 in place of a fused-sweep-only one
+        const int tile = e3d::kTileShapes[c->opt.tile].nl > 0 ? 4 : c->opt.tile;
+        c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, tile);
         c->apply_tuned = 1;
         return 0;
     }
@@ -402,6 +502,7 @@ int autotune_apply(elas3d_ctx* c)
     int rc = 0;
     for (int tile = 0; tile < e3d::kNumTiles && !rc; ++tile)
         for (int target : kTuneTargets) {
+            if (e3d::kTileShapes[tile].nl > 0) break;  // fused-sweep-only shapes
             const e3d::OpGeom g = e3d::op_geometry(d, 0, tile, target);
             auto launch = [&] { return e3d::launch_apply(c->stream, d, g, c->phase, t, x, y, nullptr, c->partials, nullptr); };
             hipError_t e = launch();  // warm-up
@@ -442,7 +543,6 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const
             elas3d_info* info, RunStats* rs_out)
 {
     const Dims& d = c->d;
-    const e3d::Tables t = c->tables();
     const int poll = c->opt.poll_interval > 0 ? c->opt.poll_interval : kDefaultPoll;
     const bool timing = c->opt.timing != 0;
     const int pi = sizeof(T) == sizeof(double) ? 0 : 1;
@@ -451,6 +551,7 @@ int iterate(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, const
         if (rc) return rc;
     }
     const e3d::OpGeom geom = c->geom_sweep[pi];
+    const e3d::Tables t = c->tables_for(geom);
     const int upd_blocks = c->upd_blocks[pi];
     const bool upd_nt = c->upd_nt[pi] != 0;
     Scalars* S0 = c->S + r0;
@@ -1099,6 +1200,23 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     }
     // (host input arrays must not be read after return)
     SETUPCHK(hipStreamSynchronize(c->stream));
+    if (opt.autotune != 1 && e3d::kTileShapes[opt.tile].nl > 0) {
+        // the forced wave-specialised shape: its phase dictionaries
+        bool fits = true;
+        int rc2 = ws_prepare(c, c->geom_sweep[0], fits);
+        if (!rc2 && !fits) {
+            free_ctx(c);
+            return fail(nullptr, ELAS3D_EBADARG,
+                        "options.tile " + std::to_string(opt.tile) + ": a workgroup box holds more than " +
+                            std::to_string(e3d::kWsDict) +
+                            " distinct phases; a shorter options.zchunk or another tile");
+        }
+        if (rc2) {
+            std::string m = c->err;
+            free_ctx(c);
+            return fail(nullptr, rc2, m);
+        }
+    }
     (void)t0;
 #undef SETUPCHK
     *out = c;

@@ -103,21 +103,59 @@ struct MinvRows {
     T* m[6];
 };
 
+// Phase dictionaries of the wave-specialised sweep, for one launch geometry
+// (tiles_x, tiles_y, kz): per workgroup box (the element columns and rows
+// its tile reads, element layers k0 - 1 .. kend, periodic), the distinct
+// phase ids in ascending order (kWsDict entries, the unused ones repeating
+// the first), and per element of the box the rank of its phase in that list
+// (one byte; layer u of block b at b * ws_map_block(kz) + u * tx * ty, rows
+// of tx bytes).
+constexpr int kWsDict = 96;
+struct WsTables {
+    const int32_t* dict = nullptr;
+    const uint8_t* map = nullptr;
+    int tile = -1, tiles_x = 0, tiles_y = 0, kz = 0;
+};
+
 struct Tables {
     const double* coef;    // nphase * kCoefStride: C/16, packed
     const float* coef32;   // the same rounded to FP32 (mixed precision), or nullptr
     const double* diag;    // nphase * kDiagStride
     const uint8_t* solid;  // nphase: 1 if the phase has stiffness
+    WsTables ws{};         // the wave-specialised sweep's dictionaries, when built
 };
 
-// Workgroup shapes (lanes in x and y) of the tiled operator sweep.  Shape 0
-// is the default of every sweep; the fused direction + operator sweep can be
-// autotuned over all of them.
-constexpr int kNumTiles = 5;
+// Workgroup shapes of the tiled operator sweep: tx x ty lanes evaluate the
+// element columns of a tile.  Shape 0 is the default of every sweep; the
+// fused direction + operator sweep can be autotuned over all of them, the
+// residual and refinement sweeps over those with nl = 0.
+//
+// nl > 0 marks the wave-specialised form of the fused sweep: the workgroup
+// has nl more wavefronts that only stream the next node planes of z and the
+// current direction into a ring of d planes in LDS (16-byte direct-to-LDS
+// loads), so that several planes are in flight per CU without holding them
+// in registers; the tx x ty lanes compute from the ring.  The phases come
+// from a dictionary per workgroup built at setup (WsTables): its stiffness
+// rows sit in LDS for the whole workgroup, and the ring carries one byte per
+// element, the phase's rank in it.  It needs rows of whole 16-byte chunks of
+// nodes, 16-byte aligned fields and at most kWsDict distinct phases in every
+// workgroup box (ws_supported, launch_ws_dictionary).
+constexpr int kNumTiles = 6;
 struct TileShape {
     int tx, ty;
+    int nl, d;
 };
-constexpr TileShape kTileShapes[kNumTiles] = {{32, 8}, {16, 16}, {64, 4}, {32, 16}, {64, 8}};
+constexpr TileShape kTileShapes[kNumTiles] = {{32, 8, 0, 0}, {16, 16, 0, 0}, {64, 4, 0, 0},
+                                              {32, 16, 0, 0}, {64, 8, 0, 0}, {64, 6, 2, 4}};
+// Lanes of a workgroup of shape t.
+constexpr int tile_lanes(int t) { return kTileShapes[t].tx * kTileShapes[t].ty + 64 * kTileShapes[t].nl; }
+// True when the wave-specialised shape t can run on grid d with elements of
+// elem_bytes: rows of whole 16-byte chunks and planes under 2^27 voxels (its
+// stores address a plane by a 32-bit byte offset).
+inline bool ws_supported(const Dims& d, int t, int elem_bytes)
+{
+    return kTileShapes[t].nl == 0 || (d.nx % (16 / elem_bytes) == 0 && (long long)d.nx * d.ny < (1ll << 27));
+}
 
 // Kernel launch geometry of the tiled operator sweep.
 struct OpGeom {
@@ -129,6 +167,14 @@ struct OpGeom {
 // kz_hint > 0 fixes the z chunk; otherwise the chunks are cut so that about
 // target_blocks workgroups (0: the default, 4096) cover the grid.
 OpGeom op_geometry(const Dims& d, int kz_hint, int tile = 0, int target_blocks = 0);
+
+// Bytes of one workgroup's rank map (kz + 2 layers of tx * ty bytes) and of
+// all of them, for a wave-specialised geometry g (tiles per RHS).
+inline size_t ws_map_block(const OpGeom& g)
+{
+    return (size_t)(g.kz + 2) * kTileShapes[g.tile].tx * kTileShapes[g.tile].ty;
+}
+inline size_t ws_map_bytes(const OpGeom& g) { return (size_t)g.blocks * ws_map_block(g); }
 
 // ---- launchers (elas3d_kernels.hip) -------------------------------------
 // Every launcher enqueues on `st` and returns the hipError_t of the launch.
@@ -167,6 +213,13 @@ hipError_t launch_pcg_init(hipStream_t st, const Dims& d, const FieldsT<T>& f, c
 // sweep runs on at most max_blocks workgroups (it writes 2 * kMaxRhs partial
 // sums per workgroup into partials); nontemporal streams its node vectors
 // past the caches.
+// Phase dictionaries of the wave-specialised geometry g (WsTables): dict
+// (g.blocks * kWsDict int32) and map (ws_map_bytes(g)); *maxcount (device,
+// zeroed by the caller) becomes the largest number of distinct phases of a
+// box, or a number above kWsDict when some box holds more (then dict and map
+// are incomplete and must not be used).
+hipError_t launch_ws_dictionary(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
+                                int32_t* dict, uint8_t* map, int* maxcount);
 template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
                                      const int32_t* phase, const Tables& t, const FieldsT<T>& f,

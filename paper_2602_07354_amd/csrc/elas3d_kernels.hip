@@ -920,6 +920,9 @@ struct OpArgs {
     int want_norm;
     size_t rs;  // FUSED: elements between consecutive RHS of the batch
     int nrhs;   // FUSED: RHS in the batch (workgroup -> (tile, rhs))
+    // wave-specialised FUSED: phase dictionaries of the launch geometry
+    const int32_t* wsdict;
+    const uint8_t* wsmap;
 };
 
 // OP_APPLY : y = A x (+ add) in FP64, optional ||y||^2 partials.
@@ -1246,6 +1249,390 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
     op_dispatch<TX, TY, MODE, T>(a, xcd_local_block(), gridDim.x);
 }
 
+// ----------------------------------------- wave-specialised fused sweep
+
+// The fused sweep above issues every load and store of a plane step from
+// the lanes that also compute, and a wavefront's vector-memory counter
+// retires in issue order: the coefficients a step needs wait behind the
+// stores and loads issued before them, so each step pays a memory latency.
+// Here the workgroup is split:
+//   - NL loader wavefronts copy the coming node planes of z and h_old, and
+//     the phase ranks of the element layers, from HBM into a ring of D
+//     planes in LDS with 16-byte direct-to-LDS loads, D - 1 planes ahead (no
+//     register holds the data in flight); before the first plane they copy
+//     the stiffness rows of the workgroup's phase dictionary (WsTables) into
+//     LDS, where they stay for the whole workgroup;
+//   - the TX x TY compute lanes read a plane's corner values and their
+//     element's phase rank from the ring and its coefficients from the
+//     dictionary rows, form h_new = z + gamma h_old there, and only store:
+//     they issue no global load inside the z march, so no step waits for
+//     memory.
+// The paying form (w owes two steps) and the light form are separate
+// kernels, each with its own register allocation; the launch starts both and
+// the one that does not match the run's state returns at once.
+//
+// Ring layout of one plane slot: fields f = z0 z1 z2 h0 h1 h2, patch rows
+// y = 0 .. TY (node row j0 - 1 + y), each row NCH 16-byte chunks from the
+// chunk-aligned node xa <= i0 - 1 (chunks never straddle the periodic wrap,
+// as nx is a multiple of the chunk): chunk q = (f * LY + y) * NCH + c; then,
+// from a fresh 64-chunk block, the phase ranks of element layer k0 - 1 + u
+// (TY rows of TX bytes, element i0 - 1 + x at byte x); in the paying form,
+// from the next fresh block, w and the older direction on the owned node
+// rows.  A loader instruction moves chunks [64 j, 64 j + 64).
+//
+// In-plane force exchange: a wavefront is one row of TX = 64 lanes, so the
+// part a lane owes its x neighbour is passed by a lane shuffle; the part for
+// the row below (v1 of this lane plus v0 of its x neighbour, summed) goes
+// through LDS.
+template <int TX, int TY, int NL, int D, typename T, bool WPAY>
+struct WsCfg {
+    static constexpr int CH = 16 / (int)sizeof(T);  // elements per chunk
+    static constexpr int NCH = TX / CH + 1;         // chunks per patch row
+    static constexpr int LY = TY + 1;               // patch rows
+    static constexpr int NF = 6;                    // z (3 components), h_old (3)
+    static constexpr int QN = NF * LY * NCH;        // node chunks per plane
+    static constexpr int NIN = (QN + 63) / 64;      // loader instructions of node chunks
+    static constexpr int LAYER = TX * TY;           // bytes of a layer of phase ranks
+    static constexpr int QP = LAYER / 16;           // its chunks
+    static constexpr int NIP = 1;
+    // paying form: w and the older direction (3 components each) on the
+    // owned node rows j0 .. j0 + TY - 2, from the chunk-aligned node <= i0
+    static constexpr int QW = WPAY ? NF * (TY - 1) * NCH : 0;
+    static constexpr int NIW = (QW + 63) / 64;
+    static constexpr int NI = ((NIN + NIP + NIW) + NL - 1) / NL * NL;  // loader instructions per plane
+    static constexpr int PER_W = NI / NL;           // per loader wavefront
+    static constexpr int SLOT = NI * 64 * 16;       // ring bytes per plane
+    static constexpr int PH_OFF = NIN * 64 * 16;    // byte offset of the phase ranks in a slot
+    static constexpr int W_OFF = (NIN + NIP) * 64 * 16;  // byte offset of w / the older direction
+    static constexpr int NT = TX * TY;              // compute lanes
+    static constexpr int NTOT = NT + 64 * NL;
+    // dictionary rows: kCoefStride elements each, in 16-byte chunks
+    static constexpr int CHR = kCoefStride * (int)sizeof(T) / 16;
+    static constexpr int NCI = kWsDict * CHR / 64;  // loader instructions of the rows
+    static_assert(TX == 64, "one wavefront per row of the tile");
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    static_assert(LAYER % 16 == 0 && QP <= 64, "a layer of ranks in one instruction");
+    static_assert(kCoefStride * sizeof(T) % 16 == 0 && kWsDict * CHR % 64 == 0, "whole dictionary instructions");
+    static_assert(kWsDict <= 256, "ranks are bytes");
+    // vmcnt that lets D - 2 planes of a loader wavefront stay in flight
+    static constexpr int WAIT = (D - 2) * PER_W > 63 ? 63 : (D - 2) * PER_W;
+    static constexpr int WAIT0 = (D - 1) * PER_W > 63 ? 63 : (D - 1) * PER_W;
+};
+
+template <int TX, int TY, int NL, int D, typename T, bool WPAY>
+struct OpSharedWS {
+    using C = WsCfg<TX, TY, NL, D, T, WPAY>;
+    alignas(16) char ring[D][C::SLOT];
+    T sf[2][3][C::NT];
+    alignas(16) T cc[kWsDict][kCoefStride];  // the dictionary's stiffness rows
+};
+
+// s_waitcnt on the vector-memory counter only (gfx9 encoding: vmcnt in bits
+// 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N <= 63, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Stores of the compute wavefronts go through buffer descriptors of one
+// plane of a field: a lane with nothing to store passes an offset past the
+// descriptor's range, and the hardware drops its write.  Every step then
+// issues the same stores on every path, so the memory counter a later wait
+// names is exact instead of the smallest count over the paths.
+constexpr int kDropOffset = 0x40000000;  // beyond every plane (under 2^27 voxels)
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(T* field, size_t first, int count)
+{
+    const unsigned long long p = reinterpret_cast<unsigned long long>(field + first);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)p);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(p >> 32));
+    T* q = reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, 0, count * (int)sizeof(T), 0x00020000);
+}
+typedef unsigned int e3d_u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void plane_store(double v, __amdgpu_buffer_rsrc_t r, int byte_off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(e3d_u2, v), r, byte_off, 0, 0);
+}
+__device__ __forceinline__ void plane_store(float v, __amdgpu_buffer_rsrc_t r, int byte_off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
+}
+
+template <int TX, int TY, int NL, int D, typename T, bool WPAY>
+__device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int nblocks,
+                                           OpSharedWS<TX, TY, NL, D, T, WPAY>& sh)
+{
+    using C = WsCfg<TX, TY, NL, D, T, WPAY>;
+    using R = T;
+    constexpr int NT = C::NT, LY = C::LY, NCH = C::NCH, CH = C::CH;
+
+    const int nr = a.nrhs;
+    const int ntb = nblocks / nr;  // tile blocks per RHS
+    const int rhs = lbr / ntb;
+    const int lb = lbr - rhs * ntb;
+    const Scalars* S = a.S + rhs;
+    // the other form's kernel serves this sweep, or the run is over
+    if (S->done || ((S->pending == 2) != WPAY)) return;
+    const R gam = (R)S->gamma;
+    const int cur = S->cur;
+    const size_t roff = (size_t)rhs * a.rs;
+    const T* hold[3];
+    T* hnew[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        hold[c] = (cur ? a.h1[c] : a.h0[c]) + roff;
+        hnew[c] = (cur ? a.h0[c] : a.h1[c]) + roff;
+        a.z[c] += roff;
+        a.w[c] += roff;
+        a.y[c] += roff;
+    }
+
+    const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
+    const int plane = nx * ny;
+    const int ntiles = a.tiles_x * a.tiles_y;
+    const int bz = lb / ntiles, t = lb - bz * ntiles;
+    const int by = t / a.tiles_x, bx = t - by * a.tiles_x;
+    const int i0 = bx * (TX - 1), j0 = by * (TY - 1);
+    const int k0 = bz * a.kz;
+    const int kend = min(k0 + a.kz, nz);
+    const int nsteps = kend - k0 + 1;
+    // chunk-aligned start of the patch rows (xs = i0 - 1 may be -1)
+    const int xs = i0 - 1;
+    const int xa = (xs >= 0 ? xs / CH : -((-xs + CH - 1) / CH)) * CH;
+    const int xw = (i0 / CH) * CH;  // owned nodes (paying form's w block)
+    const uint8_t* rmap = a.wsmap + (size_t)lb * ((size_t)(a.kz + 2) * C::LAYER);
+    auto wrapk = [&](int kk) { return kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk); };
+    const int tid = threadIdx.x;
+    double dot = 0.0;
+
+    if (tid >= NT) {
+        // ---------------------------------------------------------- loader
+        const int lw = (tid - NT) >> 6, lane = tid & 63;
+        const char* src[C::PER_W];
+#pragma unroll
+        for (int i = 0; i < C::PER_W; ++i) {
+            const int j = lw + NL * i;  // instruction index in the slot
+            if (j < C::NIN) {
+                const int q = 64 * j + lane;
+                const int qq = q < C::QN ? q : 0;  // padding lanes copy chunk 0 into the block's tail
+                const int f = qq / (LY * NCH), rem = qq - f * (LY * NCH);
+                const int y = rem / NCH, c = rem - y * NCH;
+                const int gx = ((xa + c * CH) % nx + nx) % nx;
+                const int gy = ((j0 - 1 + y) % ny + ny) % ny;
+                // field base by selects (a lane-varying index into the
+                // argument arrays would move them to scratch memory)
+                const int f3 = f < 3 ? f : f - 3;
+                const T* bz_ = f3 == 0 ? a.z[0] : (f3 == 1 ? a.z[1] : a.z[2]);
+                const T* bh_ = f3 == 0 ? hold[0] : (f3 == 1 ? hold[1] : hold[2]);
+                src[i] = reinterpret_cast<const char*>((f < 3 ? bz_ : bh_) + (gx + (size_t)nx * gy));
+            } else if (j < C::NIN + C::NIP) {
+                src[i] = reinterpret_cast<const char*>(rmap + 16 * (lane < C::QP ? lane : 0));
+            } else if (j < C::NIN + C::NIP + C::NIW) {
+                // w and the older direction (the buffer this sweep
+                // overwrites: read here before the owner lane writes it)
+                const int q = 64 * (j - C::NIN - C::NIP) + lane;
+                const int qq = q < C::QW ? q : 0;
+                const int f = qq / ((TY - 1) * NCH), rem = qq - f * ((TY - 1) * NCH);
+                const int y = rem / NCH, c = rem - y * NCH;
+                const int gx = ((xw + c * CH) % nx + nx) % nx;
+                const int gy = (j0 + y) % ny;
+                const int f3 = f < 3 ? f : f - 3;
+                const T* bw_ = f3 == 0 ? a.w[0] : (f3 == 1 ? a.w[1] : a.w[2]);
+                const T* bp_ = f3 == 0 ? hnew[0] : (f3 == 1 ? hnew[1] : hnew[2]);
+                src[i] = reinterpret_cast<const char*>((f < 3 ? bw_ : bp_) + (gx + (size_t)nx * gy));
+            } else {
+                // padding instruction: the first chunk of z's plane (it takes
+                // the node-plane offset, in bounds of a T field only)
+                src[i] = reinterpret_cast<const char*>(a.z[0]);
+            }
+        }
+        auto issue = [&](int u) {  // node plane and element layer k0 - 1 + u into ring slot u % D
+            const int uc = min(u, nsteps);
+            const size_t pn = (size_t)wrapk(k0 - 1 + uc) * plane * sizeof(T), pp = (size_t)uc * C::LAYER;
+            char* dst = sh.ring[u % D];
+#pragma unroll
+            for (int i = 0; i < C::PER_W; ++i) {
+                const int j = lw + NL * i;
+                __builtin_amdgcn_global_load_lds((const void*)(src[i] + (j < C::NIN || j >= C::NIN + C::NIP ? pn : pp)),
+                                                 (void*)(dst + (size_t)j * 1024), 16, 0, 0);
+            }
+        };
+        // the dictionary's stiffness rows (landed with plane 0, issued before it)
+        {
+            const int32_t* dl = a.wsdict + (size_t)lb * kWsDict;
+            char* ccb = reinterpret_cast<char*>(&sh.cc[0][0]);
+#pragma unroll
+            for (int m = 0; m < (C::NCI + NL - 1) / NL; ++m) {
+                const int i = lw + NL * m;
+                if (i < C::NCI) {
+                    const int g = 64 * i + lane;
+                    const int r = g / C::CHR, q = g - r * C::CHR;
+                    const T* row = a.coef + (size_t)dl[r] * kCoefStride + q * CH;
+                    __builtin_amdgcn_global_load_lds((const void*)row, (void*)(ccb + (size_t)i * 1024), 16, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < D; ++u) issue(u);
+        wait_vmcnt<C::WAIT0>();  // plane 0 landed
+        __builtin_amdgcn_s_barrier();
+        for (int s = 0; s < nsteps; ++s) {
+            // slot (s - 1) % D was read before the last barrier: refill it
+            if (s >= 1) issue(s - 1 + D);
+            wait_vmcnt<C::WAIT>();  // plane s + 1 landed
+            __builtin_amdgcn_s_barrier();
+        }
+        wait_vmcnt<0>();  // no copy into LDS may outlive the workgroup
+        __builtin_amdgcn_s_barrier();
+    } else {
+        // --------------------------------------------------------- compute
+        const R lam = (R)S->lambda, lamp = (R)S->lambda_prev;
+        const int tx = tid % TX, ty = tid / TX;
+        const int gi = i0 + tx, gj = j0 + ty;
+        const int own = (gi % nx) + nx * (gj % ny);
+        const bool out_ok = (tx < TX - 1) && (ty < TY - 1) && (gi < nx) && (gj < ny);
+        // element offsets of the lane's four corners in a ring slot (field 0)
+        // and of its element's phase id
+        const int off0 = xs - xa;
+        const int e00 = (ty * NCH) * CH + tx + off0, e10 = e00 + 1;
+        const int e01 = ((ty + 1) * NCH) * CH + tx + off0, e11 = e01 + 1;
+        const int eph = ty * TX + tx;
+        // own node in the w block (rows of owned nodes only; lanes that own
+        // none read a clamped slot and do not use it)
+        const int ew = min(ty, TY - 2) * NCH * CH + min(tx, TX - 2) + (i0 - xw);
+        constexpr int FSTRIDE = LY * NCH * CH;       // elements between fields
+        constexpr int WSTRIDE = (TY - 1) * NCH * CH;  // between w-block fields
+        // corner values h_new (z + gamma h_old) of the plane in a ring slot as
+        // face spectra, the own node's value and h_old
+        auto read_plane = [&](int slot, R (&F)[3][4], R (&ownv)[3], R (&ownh)[3]) {
+            const R* rg = reinterpret_cast<const R*>(sh.ring[slot]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R* zf = rg + c * FSTRIDE;
+                const R* hf = rg + (c + 3) * FSTRIDE;
+                const R v00 = fma(gam, hf[e00], zf[e00]);
+                const R v10 = fma(gam, hf[e10], zf[e10]);
+                const R v01 = fma(gam, hf[e01], zf[e01]);
+                const R h11 = hf[e11];
+                const R v11 = fma(gam, h11, zf[e11]);
+                face_fwd(v00, v10, v01, v11, F[c]);
+                ownv[c] = v11;
+                ownh[c] = h11;
+            }
+        };
+        // phase rank of the lane's element in the layer of a ring slot, and
+        // its coefficients from the dictionary rows
+        auto slot_rank = [&](int slot) {
+            return (int)reinterpret_cast<const uint8_t*>(sh.ring[slot] + C::PH_OFF)[eph];
+        };
+        auto read_coef = [&](int rank, R (&Cx)[21]) {
+            const R* row = sh.cc[rank];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) Cx[q] = row[q];
+        };
+        auto& SF = sh.sf;
+        R lo[3][4], carry[3][4];
+        __syncthreads();  // plane and layer k0 - 1 in slot 0, the dictionary rows in LDS
+        // rank of the layer the next contraction computes (read a step ahead:
+        // the loaders refill a slot during the step after the one that reads it)
+        int rank = slot_rank(0);
+        {
+            R ov[3], oh[3];
+            read_plane(0, lo, ov, oh);
+        }
+        R hprev[3] = {R(0), R(0), R(0)};
+        R mine_d[3] = {R(0), R(0), R(0)}, hout_d[3] = {R(0), R(0), R(0)};
+        for (int s = 0; s < nsteps; ++s) {
+            const int b = s & 1;
+            const int ku = k0 + s;
+            __syncthreads();  // plane ku in slot (s + 1) % D; forces of step s - 1 in SF[b ^ 1]
+            // Ah of plane ku - 2 (stored at the end of the step)
+            const bool emit = s > 1 && out_ok;
+            R yv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yv[c] = mine_d[c] + SF[b ^ 1][c][tid + TX];
+            if (emit) dot += (double)hout_d[0] * yv[0] + (double)hout_d[1] * yv[1] + (double)hout_d[2] * yv[2];
+            {
+                const size_t pk = (size_t)wrapk(ku - 2) * plane;
+                const int off = emit ? own * (int)sizeof(T) : kDropOffset;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) plane_store(yv[c], plane_rsrc(a.y[c], pk, plane), off);
+            }
+            const int slot = (s + 1) % D;
+            R Cu[21];
+            read_coef(rank, Cu);
+            rank = slot_rank(slot);
+            R up[3][4], ov[3], oh[3];
+            read_plane(slot, up, ov, oh);
+            R FL[3][4], FU[3][4];
+            element_force_faces(Cu, lo, up, FL, FU);
+            R mine[3] = {R(0), R(0), R(0)};
+            if (s > 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    R F[4], v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) F[q] = carry[c][q] + FL[c][q];
+                    face_adj(F, v);
+                    // own node: v3 + the x neighbour's v2; row below: v1 + the x neighbour's v0
+                    mine[c] = v[3] + __shfl_down(v[2], 1);
+                    SF[b][c][tid] = v[1] + __shfl_down(v[0], 1);
+                }
+            }
+            // h_new (and w) of plane ku
+            {
+                const size_t pk = (size_t)min(ku, nz - 1) * plane;
+                const int off = (out_ok && ku < kend) ? own * (int)sizeof(T) : kDropOffset;
+                const R* wb = reinterpret_cast<const R*>(sh.ring[slot] + C::W_OFF);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    plane_store(ov[c], plane_rsrc(hnew[c], pk, plane), off);
+                    if constexpr (WPAY)
+                        plane_store(fma(-lam, oh[c], fma(-lamp, wb[(c + 3) * WSTRIDE + ew], wb[c * WSTRIDE + ew])),
+                                    plane_rsrc(a.w[c], pk, plane), off);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    carry[c][q] = FU[c][q];
+                    lo[c][q] = up[c][q];
+                }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                mine_d[c] = mine[c];
+                hout_d[c] = hprev[c];
+                hprev[c] = ov[c];
+            }
+        }
+        __syncthreads();
+        if (nsteps > 1 && out_ok) {
+            const int b = (nsteps - 1) & 1;
+            const int idx = wrapk(k0 - 2 + nsteps) * plane + own;
+            R yv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                yv[c] = mine_d[c] + SF[b][c][tid + TX];
+                a.y[c][idx] = yv[c];
+            }
+            dot += (double)hout_d[0] * yv[0] + (double)hout_d[1] * yv[1] + (double)hout_d[2] * yv[2];
+        }
+    }
+    double v[1] = {dot};
+    block_partials<1, C::NTOT>(v, a.partials + (size_t)rhs * ntb, ntb, lb);
+}
+
+template <int TX, int TY, int NL, int D, typename T, bool WPAY>
+__global__ void __launch_bounds__(TX* TY + 64 * NL, 1) op_kernel_ws(OpArgs<T> a)
+{
+    __shared__ OpSharedWS<TX, TY, NL, D, T, WPAY> sh;
+    op_body_ws<TX, TY, NL, D, T, WPAY>(a, xcd_local_block(), gridDim.x, sh);
+}
+
 // Copy of a work-list entry held in scalar registers: the entry is the same
 // for the whole workgroup, and reading it word by word through readfirstlane
 // keeps its pointers out of the vector registers of the sweep.
@@ -1334,7 +1721,17 @@ __global__ void __launch_bounds__(kBlock) update_group_kernel(const UpdArgs<T>* 
 #endif
 constexpr int kTX = kTileShapes[0].tx, kTY = kTileShapes[0].ty;
 
-// Launch of the operator sweep with the workgroup shape of g.tile.
+// Ring depth of the wave-specialised sweep: the shape's d planes in FP64,
+// two more for the FP32 sweep (half the bytes per plane); one less for the
+// paying form, whose planes also carry w and the older direction.
+template <typename T, bool WPAY>
+constexpr int ws_depth(int t)
+{
+    return kTileShapes[t].d + (sizeof(T) == 4 ? 2 : 0) - (WPAY ? 1 : 0);
+}
+
+// Launch of the operator sweep with the workgroup shape of g.tile (the
+// wave-specialised shapes exist for the fused sweep only).
 template <int MODE, typename T>
 hipError_t launch_op_tiled(hipStream_t st, const OpGeom& g, unsigned grid, const OpArgs<T>& a)
 {
@@ -1343,16 +1740,32 @@ hipError_t launch_op_tiled(hipStream_t st, const OpGeom& g, unsigned grid, const
         hipLaunchKernelGGL((op_kernel<kTileShapes[I].tx, kTileShapes[I].ty, MODE, T>), dim3(grid), \
                            dim3(kTileShapes[I].tx * kTileShapes[I].ty), 0, st, a);             \
         break;
+#define E3D_WS_CASE(I)                                                                        \
+    case I:                                                                                   \
+        if constexpr (MODE == OP_FUSED) {                                                     \
+            hipLaunchKernelGGL((op_kernel_ws<kTileShapes[I].tx, kTileShapes[I].ty, kTileShapes[I].nl, \
+                                             ws_depth<T, false>(I), T, false>),                \
+                               dim3(grid), dim3(tile_lanes(I)), 0, st, a);                    \
+            hipLaunchKernelGGL((op_kernel_ws<kTileShapes[I].tx, kTileShapes[I].ty, kTileShapes[I].nl, \
+                                             ws_depth<T, true>(I), T, true>),                  \
+                               dim3(grid), dim3(tile_lanes(I)), 0, st, a);                    \
+        } else {                                                                              \
+            return hipErrorInvalidValue;                                                      \
+        }                                                                                     \
+        break;
+    static_assert(kNumTiles == 6, "a launch case per shape");
     switch (g.tile) {
         E3D_OP_CASE(0)
         E3D_OP_CASE(1)
         E3D_OP_CASE(2)
         E3D_OP_CASE(3)
         E3D_OP_CASE(4)
+        E3D_WS_CASE(5)
         default:
             return hipErrorInvalidValue;
     }
 #undef E3D_OP_CASE
+#undef E3D_WS_CASE
     return hipGetLastError();
 }
 
@@ -1573,6 +1986,102 @@ int sweep_blocks(int n, int max_blocks)
 
 }  // namespace
 
+// ------------------------------------------------ phase dictionaries
+// One workgroup per box of the wave-specialised geometry (the element
+// columns i0 - 1 .. i0 + TX - 2 and rows j0 - 1 .. j0 + TY - 2 of its tile,
+// element layers k0 - 1 .. kend, all periodic): the distinct phase ids go
+// into an LDS hash set, their ranks in ascending order become the box's
+// dictionary, and each element of the box gets its rank as a byte.
+constexpr int kWsHash = 1024;  // hash slots (well above kWsDict + one insertion per lane)
+template <int TX, int TY>
+__global__ void __launch_bounds__(256) ws_dict_kernel(Dims d, int tiles_x, int tiles_y, int kz,
+                                                     const int32_t* __restrict__ phase, int32_t* __restrict__ dict,
+                                                     uint8_t* __restrict__ map, int* maxcount)
+{
+    __shared__ int key[kWsHash];
+    __shared__ int rank_of[kWsHash];
+    __shared__ int count;
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int lb = blockIdx.x;
+    const int ntiles = tiles_x * tiles_y;
+    const int bz = lb / ntiles, t = lb - bz * ntiles;
+    const int by = t / tiles_x, bx = t - by * tiles_x;
+    const int i0 = bx * (TX - 1), j0 = by * (TY - 1), k0 = bz * kz;
+    const int kend = min(k0 + kz, nz);
+    const int layers = kend - k0 + 2;  // u = 0 .. nsteps
+    const int nel = layers * TY * TX;
+    const int tid = threadIdx.x;
+    for (int h = tid; h < kWsHash; h += 256) key[h] = -1;
+    if (tid == 0) count = 0;
+    __syncthreads();
+    auto element_phase = [&](int e) {
+        const int u = e / (TY * TX), r = e - u * (TY * TX);
+        const int y = r / TX, x = r - y * TX;
+        const int gx = ((i0 - 1 + x) % nx + nx) % nx;
+        const int gy = ((j0 - 1 + y) % ny + ny) % ny;
+        int gz = k0 - 1 + u;
+        gz = gz < 0 ? gz + nz : (gz >= nz ? gz - nz : gz);
+        return phase[(size_t)gx + (size_t)nx * ((size_t)gy + (size_t)ny * gz)];
+    };
+    auto slot_of = [](int p) { return (int)(((unsigned)p * 2654435761u) >> 22); };  // 10 bits
+    for (int e = tid; e < nel; e += 256) {
+        if (*(volatile int*)&count > kWsDict) break;  // too many: stop early (the table never fills)
+        const int p = element_phase(e);
+        int h = slot_of(p);
+        while (true) {
+            const int old = atomicCAS(&key[h], -1, p);
+            if (old == -1) {
+                atomicAdd(&count, 1);
+                break;
+            }
+            if (old == p) break;
+            h = (h + 1) & (kWsHash - 1);
+        }
+    }
+    __syncthreads();
+    const int c = count;
+    if (tid == 0) atomicMax(maxcount, c);
+    if (c > kWsDict) return;
+    // rank = number of smaller ids in the set
+    int first = -1;
+    for (int h = tid; h < kWsHash; h += 256) {
+        const int k = key[h];
+        if (k < 0) continue;
+        int r = 0;
+        for (int h2 = 0; h2 < kWsHash; ++h2) {
+            const int k2 = key[h2];
+            r += (k2 >= 0 && k2 < k);
+        }
+        rank_of[h] = r;
+        dict[(size_t)lb * kWsDict + r] = k;
+        if (r == 0) first = k;
+    }
+    // unused entries repeat rank 0 (a valid row to copy)
+    __shared__ int first_id;
+    if (first >= 0) first_id = first;
+    __syncthreads();
+    for (int r = c + tid; r < kWsDict; r += 256) dict[(size_t)lb * kWsDict + r] = first_id;
+    uint8_t* out = map + (size_t)lb * ((size_t)(kz + 2) * TX * TY);
+    for (int e = tid; e < nel; e += 256) {
+        const int p = element_phase(e);
+        int h = slot_of(p);
+        while (key[h] != p) h = (h + 1) & (kWsHash - 1);
+        out[e] = (uint8_t)rank_of[h];
+    }
+}
+
+hipError_t launch_ws_dictionary(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
+                                int32_t* dict, uint8_t* map, int* maxcount)
+{
+    if (g.tile < 0 || g.tile >= kNumTiles || kTileShapes[g.tile].nl == 0 || g.blocks <= 0)
+        return hipErrorInvalidValue;
+    static_assert(kTileShapes[5].nl > 0 && kTileShapes[5].tx == 64 && kTileShapes[5].ty == 6,
+                  "the one wave-specialised shape");
+    hipLaunchKernelGGL((ws_dict_kernel<64, 6>), dim3(g.blocks), dim3(256), 0, st, d, g.tiles_x, g.tiles_y,
+                       g.kz, phase, dict, map, maxcount);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- launchers
 
 OpGeom op_geometry(const Dims& d, int kz_hint, int tile, int target_blocks)
@@ -1674,13 +2183,33 @@ static bool direction_buffers_ok(const FieldsT<T>& f)
     return f.h1[1] - f.h0[1] == dh && f.h1[2] - f.h0[2] == dh;
 }
 
+// The wave-specialised sweep copies 16-byte chunks of z and the direction
+// buffers: rows a whole number of chunks, every field and RHS offset
+// 16-byte aligned.
+template <typename T>
+static bool ws_fields_ok(const Dims& d, int tile, const FieldsT<T>& f, size_t rs)
+{
+    if (kTileShapes[tile].nl == 0) return true;
+    if (!ws_supported(d, tile, (int)sizeof(T)) || (rs * sizeof(T)) % 16 != 0) return false;
+    for (int c = 0; c < 3; ++c)
+        if (((uintptr_t)f.z[c] | (uintptr_t)f.h0[c] | (uintptr_t)f.h1[c]) % 16 != 0) return false;
+    return true;
+}
+
 template <typename T>
 hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom& g,
                                      const int32_t* phase, const Tables& t, const FieldsT<T>& f,
                                      size_t rs, int nrhs, Scalars* S, double* partials, bool finalize)
 {
     if (!direction_buffers_ok(f)) return hipErrorInvalidValue;
+    if (g.tile < 0 || g.tile >= kNumTiles || !ws_fields_ok(d, g.tile, f, rs)) return hipErrorInvalidValue;
+    if (kTileShapes[g.tile].nl > 0 &&
+        (!t.ws.dict || !t.ws.map || t.ws.tile != g.tile || t.ws.tiles_x != g.tiles_x ||
+         t.ws.tiles_y != g.tiles_y || t.ws.kz != g.kz))
+        return hipErrorInvalidValue;  // no dictionaries built for this geometry
     OpArgs<T> a = {};
+    a.wsdict = t.ws.dict;
+    a.wsmap = t.ws.map;
     a.d = d;
     a.tiles_x = g.tiles_x;
     a.tiles_y = g.tiles_y;

@@ -96,6 +96,16 @@ struct elas3d_ctx {
     double bytes = 0.0;
     std::string err;
 
+    // phase dictionaries of the wave-specialised sweep, one entry per
+    // geometry built (maxcount > kWsDict: too many phases, nothing kept)
+    struct WsDictEntry {
+        e3d::OpGeom g;
+        int32_t* dict;
+        uint8_t* map;
+        int maxcount;
+    };
+    std::vector<WsDictEntry> wsd;
+
     std::vector<e3d::rt::EventPair> ev_op, ev_up;
     // captured iteration batches, keyed by (element size, first RHS, RHS count)
     struct GraphEntry {
@@ -168,6 +178,16 @@ struct elas3d_ctx {
         return M;
     }
     e3d::Tables tables() const { return e3d::Tables{coef, coef32, diag, solid}; }
+    // the tables plus the dictionaries of geometry g, when built
+    e3d::Tables tables_for(const e3d::OpGeom& g) const
+    {
+        e3d::Tables t = tables();
+        for (const auto& e : wsd)
+            if (e.dict && e.g.tile == g.tile && e.g.tiles_x == g.tiles_x && e.g.tiles_y == g.tiles_y &&
+                e.g.kz == g.kz)
+                t.ws = e3d::WsTables{e.dict, e.map, g.tile, g.tiles_x, g.tiles_y, g.kz};
+        return t;
+    }
 };
 
 

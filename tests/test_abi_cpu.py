@@ -101,11 +101,25 @@ def test_setup_rejects_bad_options(E):
     shape, phase, C, strain = _good()
     for kw in ({"precision": 7}, {"convergence": 3}, {"preconditioner": -1},
                {"poll_interval": -2}, {"hbm_budget_bytes": -1.0}, {"inner_tol": 2.0},
-               {"tile": 5}, {"tile": -1}, {"zchunk": -3}, {"update_blocks": -1},
+               {"tile": 6}, {"tile": -1}, {"zchunk": -3}, {"update_blocks": -1},
                {"update_blocks": 32769}, {"update_nontemporal": 2}):
         with pytest.raises(E.Elas3dError) as ei:
             E.setup(shape, phase, C, strain, E.options_init(**kw))
         assert ei.value.code == E.EBADARG
+
+
+def test_setup_rejects_a_forced_shape_the_grid_cannot_run(E):
+    """The wave-specialised shapes need rows of whole 16-byte chunks: an odd
+    nx (FP64) or one not a multiple of 4 (mixed precision) is refused before
+    any device call."""
+    from paper_2602_07354_amd import synth
+    C = synth.isotropic_stiffness(200, .3)[None]
+    strain = np.array([[1e-3, 0, 0, 0, 0, 0]])
+    for shape, kw in (((5, 4, 4), {"tile": 5}), ((6, 4, 4), {"tile": 5, "precision": 1})):
+        phase = np.zeros(int(np.prod(shape)), np.int32)
+        with pytest.raises(E.Elas3dError) as ei:
+            E.setup(shape, phase, C, strain, E.options_init(**kw))
+        assert ei.value.code == E.EBADARG and "multiple" in str(ei.value)
 
 
 def test_null_context_calls_are_rejected(E):

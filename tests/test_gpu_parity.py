@@ -595,7 +595,7 @@ def test_graph_replay_matches_eager_launches(E):
     assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])  # 5: test_wave_specialised_sweep_matches_oracle
 def test_every_sweep_tile_shape_matches_oracle(E, orc, tile):
     """Each workgroup shape of the fused direction+operator sweep (the
     autotuner's candidates) solves to the oracle's solution; ragged sizes so
@@ -730,3 +730,146 @@ def test_breakdown_matches_oracle(E, orc, case, poll):
         assert np.all(w == 0.0)
     else:
         assert _rel(w, ro["w"]) <= 1e-10
+
+
+@pytest.mark.parametrize("tile", [5])
+def test_wave_specialised_sweep_matches_oracle(E, orc, tile):
+    """The wave-specialised fused sweep (loader wavefronts streaming node
+    planes into an LDS ring): solves to the oracle's solution in FP64 and
+    mixed precision on a grid with partial tiles in x (68 = 63 + 5) and y,
+    and on one narrower than a tile (nx = 8: the patch rows wrap around the
+    periodic box several times); the iterates after k = 1..5 iterations
+    equal the oracle's, single case and batched."""
+    for shape, grains in (((68, 29, 21), 20), ((8, 6, 5), 4)):
+        say("case: wave-specialised sweep, tile", tile, shape)
+        ms = _small_poly(shape, 61 + shape[0], grains=grains)
+        P = orc.Problem.from_micro(ms)
+        ro = P.solve(ms.strain[0], tol=1e-12)
+        so, _ = P.stress(ms.strain[0], ro["w"])
+        for precision in (E.PREC_FP64, E.PREC_MIXED):
+            with E.Context.from_micro(ms, tile=tile, precision=precision) as ctx:
+                st, info = ctx.solve(1e-12 if precision == E.PREC_FP64 else 1e-10, 20000)
+                assert st == E.OK
+                assert info["op_tile"][:2] == list(E.TILE_SHAPES[tile])
+                if precision == E.PREC_FP64:
+                    assert abs(info["iters"][0] - ro["iters"]) <= 2
+                out = ctx.stress(0)
+            assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
+    say("case: wave-specialised sweep iterates, tile", tile)
+    shape = (20, 19, 23)
+    ms = _small_poly(shape, 29)
+    ms2 = synth.polycrystal(shape, 12, 29, [dict(kind="sphere", fraction=0.02, median=1.5, sigma=0.3)],
+                            synth.unit_load_cases()[[2, 4]])
+    P = orc.Problem.from_micro(ms)
+    P2 = orc.Problem.from_micro(ms2)
+    for k in range(1, 6):
+        ro = P.solve(ms.strain[0], tol=1e-30, maxit=k)
+        with E.Context.from_micro(ms, tile=tile) as ctx:
+            st, info = ctx.solve(1e-30, k)
+            assert st == E.NOT_CONVERGED and info["iters"][0] == k
+            assert _rel(ctx.solution(0), ro["w"]) <= 1e-11, k
+        with E.Context.from_micro(ms2, batched=1, tile=tile) as ctx:
+            st, info = ctx.solve(1e-30, k)
+            for r in range(2):
+                ro2 = P2.solve(ms2.strain[r], tol=1e-30, maxit=k)
+                assert _rel(ctx.solution(r), ro2["w"]) <= 1e-11, (k, r)
+
+
+def _many_phase_grid(shape, nphase, seed):
+    """Every voxel its own random draw among nphase rotated 316L crystals: a
+    64-voxel row meets far more distinct phases than a grain structure does."""
+    rng = synth.rng_for(seed)
+    C = synth.rotate_stiffness(synth.cubic_stiffness(*synth.SS316L_CUBIC), synth.random_rotations(rng, nphase))
+    phase = rng.integers(0, nphase, int(np.prod(shape))).astype(np.int32)
+    return synth.Microstructure(tuple(shape), phase, C,
+                                np.array([[2e-4, -1e-4, 1e-3, 3e-4, -2e-4, 1e-4]]), {"workload": "many_phase"})
+
+
+def test_sweep_with_many_phases_per_box(E, orc):
+    """A grid whose rows hold dozens of distinct phases, so that a
+    wave-specialised workgroup box holds more than its phase dictionary: the
+    forced wave-specialised shape is refused at setup, and with autotuning
+    another shape is chosen and solves to the oracle's solution.  (Parity of
+    the classic sweep on it: test_sweep_with_many_phases_per_row_matches_oracle.)"""
+    ms = _many_phase_grid((72, 13, 11), 300, 7)
+    for prec in (E.PREC_FP64, E.PREC_MIXED):
+        with pytest.raises(E.Elas3dError) as ei:
+            E.Context.from_micro(ms, tile=5, precision=prec)
+        assert ei.value.code == E.EBADARG and "distinct phases" in str(ei.value)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    with E.Context.from_micro(ms, autotune=1) as ctx:
+        st, info = ctx.solve(1e-12, 20000)
+        assert st == E.OK and abs(info["iters"][0] - ro["iters"]) <= 2
+        assert info["op_tile"][:2] != list(E.TILE_SHAPES[5])
+        assert _rel(ctx.solution(0), ro["w"]) <= 1e-9
+
+
+def test_wave_specialised_sweep_with_a_full_dictionary(E, orc):
+    """Every voxel draws one of exactly 96 phases (a workgroup box holds all
+    of them: the phase dictionary is full, ranks 0..95 in use): the
+    wave-specialised sweep's iterates after k = 1..3 iterations equal the
+    oracle's, and the FP64 and mixed-precision solves reach its stress."""
+    ms = _many_phase_grid((72, 13, 11), 96, 11)
+    assert len(np.unique(ms.phase)) == 96
+    P = orc.Problem.from_micro(ms)
+    for k in range(1, 4):
+        say("case: full dictionary, iterations", k)
+        ro = P.solve(ms.strain[0], tol=1e-30, maxit=k)
+        with E.Context.from_micro(ms, tile=5) as ctx:
+            st, info = ctx.solve(1e-30, k)
+            assert st == E.NOT_CONVERGED and info["iters"][0] == k
+            assert _rel(ctx.solution(0), ro["w"]) <= 1e-11, k
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    for precision in (E.PREC_FP64, E.PREC_MIXED):
+        say("case: full dictionary, converged, precision", precision)
+        with E.Context.from_micro(ms, tile=5, precision=precision) as ctx:
+            st, info = ctx.solve(1e-12 if precision == E.PREC_FP64 else 1e-10, 20000)
+            assert st == E.OK and info["op_tile"][:2] == list(E.TILE_SHAPES[5])
+            out = ctx.stress(0)
+        assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
+
+
+@pytest.mark.parametrize("tile", [4])
+def test_sweep_with_many_phases_per_row_matches_oracle(E, orc, tile):
+    """A grid whose rows hold dozens of distinct phases (every voxel its own
+    draw): the iterates after k = 1..4 iterations and the converged stress
+    equal the oracle's in FP64, and the mixed-precision solve reaches the
+    oracle's solution."""
+    ms = _many_phase_grid((72, 13, 11), 300, 7)
+    rows = ms.phase.reshape(11, 13, 72)
+    assert min(len(np.unique(rows[k, j, :64])) for k in range(11) for j in range(13)) > 32
+    P = orc.Problem.from_micro(ms)
+    for k in range(1, 5):
+        say("case: many phases per row, tile", tile, "iterations", k)
+        ro = P.solve(ms.strain[0], tol=1e-30, maxit=k)
+        with E.Context.from_micro(ms, tile=tile) as ctx:
+            st, info = ctx.solve(1e-30, k)
+            assert st == E.NOT_CONVERGED and info["iters"][0] == k
+            assert _rel(ctx.solution(0), ro["w"]) <= 1e-11, k
+    say("case: many phases per row, converged, tile", tile)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    for precision in (E.PREC_FP64, E.PREC_MIXED):
+        with E.Context.from_micro(ms, tile=tile, precision=precision) as ctx:
+            st, info = ctx.solve(1e-12 if precision == E.PREC_FP64 else 1e-10, 20000)
+            assert st == E.OK
+            if precision == E.PREC_FP64:
+                assert abs(info["iters"][0] - ro["iters"]) <= 2
+            out = ctx.stress(0)
+        assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
+
+
+def test_wave_specialised_shape_needs_whole_chunks(E):
+    """Forcing a wave-specialised shape on a grid whose rows are not a whole
+    number of 16-byte chunks is refused at setup (before any device work)."""
+    ms = _small_poly((37, 29, 21), 41, grains=15)
+    for prec in (E.PREC_FP64, E.PREC_MIXED):
+        with pytest.raises(E.Elas3dError) as ei:
+            E.Context.from_micro(ms, tile=5, precision=prec)
+        assert ei.value.code == E.EBADARG and "multiple" in str(ei.value)
+    ms2 = _small_poly((38, 29, 21), 41, grains=15)  # even: FP64 fine, mixed needs 4
+    E.Context.from_micro(ms2, tile=5).close()
+    with pytest.raises(E.Elas3dError):
+        E.Context.from_micro(ms2, tile=5, precision=E.PREC_MIXED)
