@@ -51,12 +51,19 @@ VALU_COUNTERS = os.path.join(ROOT, "profiles", "op_kernel_poly500_valu_counters.
 VALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X vector peaks
 KERNEL_SOURCES = ("paper_2602_07354_amd/csrc/elas3d_kernels.hip", "paper_2602_07354_amd/csrc/elas3d_internal.h")
 # Algorithmic HBM bytes per node of the fused direction+operator sweep, the
-# mean of its two alternating forms: read z, h_old and the phase id, write
-# h_new and Ah (4 x 3 values + 4 bytes); every other iteration it also pays
-# the two steps w owes (read w and the older direction, write w: 3 x 3
-# values).  Per launch: 5.5 vectors + phase.
-OPERATOR_BYTES_PER_NODE_FP64 = (4 * 24 + 4 + 7 * 24 + 4) / 2  # 136
-OPERATOR_BYTES_PER_NODE_FP32 = (4 * 12 + 4 + 7 * 12 + 4) / 2  # 70
+# mean of its two alternating forms: read z, h_old and the element's phase,
+# write h_new and Ah (4 x 3 values + the phase); every other iteration it
+# also pays the two steps w owes (read w and the older direction, write w:
+# 3 x 3 values).  Per launch: 5.5 vectors + the phase, which the classic
+# shapes read as a 4-byte id and the wave-specialised one as a 1-byte rank
+# in its workgroup's phase dictionary.
+WS_SHAPE = (64, 6)  # lanes of the wave-specialised shape (options.tile 5)
+
+
+def operator_bytes_per_node(precision: str, tile) -> float:
+    v = 24 if precision == "fp64" else 12
+    ph = 1 if tuple(int(t) for t in tile[:2]) == WS_SHAPE else 4
+    return (4 * v + ph + 7 * v + ph) / 2
 HOST_THREAD_CAP = 16  # host cores a one-GPU job may use
 
 WORKLOAD_TEXT = {
@@ -479,7 +486,8 @@ def main(argv=None):
 
     value = main_leg["gdof_iter_per_s"]
     rhs_per_launch = (sum(kinfo["iters"]) / max(1, kinfo["n_operator"])) if args.batched else 1.0
-    op_bytes = (OPERATOR_BYTES_PER_NODE_FP64 if head == "fp64" else OPERATOR_BYTES_PER_NODE_FP32) * ms.n * rhs_per_launch
+    op_bytes = (operator_bytes_per_node("fp64" if head == "fp64" else "fp32", main_leg["op_tile"]) * ms.n
+                * rhs_per_launch)
     achieved = op_bytes / (op_ms / 1e3) / 1e9
     tile = main_leg["op_tile"]
     traffic = (measured_traffic(ms.meta.get("workload"), tile) if head == "fp64" and nrhs == 1
@@ -526,8 +534,12 @@ def main(argv=None):
         "operator_ms_avg": round(op_ms, 4),
         "update_ms_avg": round(up_ms, 4),
         "roofline": {
-            "kernel": "op_kernel<%d,%d,OP_FUSED,%s> (fused direction update + matrix-free operator + h.Ah)"
-                      % (tile[0], tile[1], "double" if head == "fp64" else "float"),
+            "kernel": (("op_kernel_ws<64,6,2 loader wavefronts,%s> (wave-specialised fused direction update + "
+                        "matrix-free operator + h.Ah; its light and paying forms)"
+                        % ("double" if head == "fp64" else "float"))
+                       if tuple(int(t) for t in tile[:2]) == WS_SHAPE else
+                       "op_kernel<%d,%d,OP_FUSED,%s> (fused direction update + matrix-free operator + h.Ah)"
+                       % (tile[0], tile[1], "double" if head == "fp64" else "float")),
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,

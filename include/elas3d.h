@@ -97,7 +97,8 @@ typedef struct elas3d_options {
                                   when timing is on); default 1                      */
     int32_t autotune;          /* nonzero: before the first iteration of each
                                   precision, time the candidate workgroup shapes
-                                  (options.tile's list; 5 and 6 where nx allows)
+                                  (options.tile's list; 5 where the grid and
+                                  its phases allow)
                                   and z-chunkings
                                   (about 2048 to 16384 workgroups) of the
                                   direction+operator sweep and
@@ -116,8 +117,12 @@ typedef struct elas3d_options {
                                   1 = 16x16, 2 = 64x4, 3 = 32x16, 4 = 64x8;
                                   5 = 64x6 + two loader wavefronts (the node
                                   planes stream into an LDS ring by direct-to-
-                                  LDS loads; nx must be a multiple of 4, else
-                                  EBADARG)                                   */
+                                  LDS loads; nx must be a multiple of 2, of 4
+                                  in mixed precision, nx*ny < 2^27, and no
+                                  workgroup box may hold more than 96
+                                  distinct phases, else EBADARG; setup builds
+                                  a phase dictionary per workgroup, about
+                                  1.3 bytes per voxel)                        */
     int32_t zchunk;            /* z planes per workgroup of that sweep when not
                                   autotuned; 0 = automatic (about 4096 workgroups);
                                   values above nz mean nz                            */

@@ -84,6 +84,11 @@ double plan_bytes(int32_t nx, int32_t ny, int32_t nz, int nphase, int nrhs, bool
     bytes += (double)nphase * 8.0 * (e3d::kCoefStride + e3d::kDiagStride + 1.0) +
              (double)nphase * nrhs * 8.0 * e3d::kSigStride;
     bytes += 8.0 * kPartialValues * (double)partial_slots(Dims{nx, ny, nz, (int)n}, nrhs, tile, zchunk);
+    if (tile >= 0 && tile < e3d::kNumTiles && e3d::kTileShapes[tile].nl > 0) {
+        // the forced wave-specialised shape's phase dictionaries
+        const e3d::OpGeom g = e3d::op_geometry(Dims{nx, ny, nz, (int)n}, zchunk, tile);
+        bytes += (double)e3d::ws_map_bytes(g) + 4.0 * e3d::kWsDict * g.blocks;
+    }
     bytes += 4096.0;
     return bytes;
 }
@@ -318,15 +323,17 @@ int ws_prepare(elas3d_ctx* c, const e3d::OpGeom& g, bool& fits)
     return 0;
 }
 
-// Frees the dictionaries of geometries neither precision's sweep uses.
-void ws_release_unused(elas3d_ctx* c)
+// Frees the dictionaries of geometries neither precision's sweep uses (nor
+// `also`, when given).
+void ws_release_unused(elas3d_ctx* c, const e3d::OpGeom* also = nullptr)
 {
+    auto same = [](const e3d::OpGeom& a, const e3d::OpGeom& b) {
+        return a.tile == b.tile && a.tiles_x == b.tiles_x && a.tiles_y == b.tiles_y && a.kz == b.kz;
+    };
     std::vector<elas3d_ctx::WsDictEntry> keep;
     for (auto& e : c->wsd) {
-        bool used = false;
-        for (const auto& g : c->geom_sweep)
-            used = used || (e.g.tile == g.tile && e.g.tiles_x == g.tiles_x && e.g.tiles_y == g.tiles_y &&
-                            e.g.kz == g.kz);
+        bool used = also && same(e.g, *also);
+        for (const auto& g : c->geom_sweep) used = used || same(e.g, g);
         if (used) {
             keep.push_back(e);
         } else {
@@ -427,6 +434,7 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
                 best = ms;
                 best_g = g;
             }
+            ws_release_unused(c, &best_g);  // at most the best candidate's dictionaries stay
         }
     float best_u = 1e30f;
     int best_nb = c->upd_blocks[pi], best_nt = c->upd_nt[pi];

@@ -34,7 +34,8 @@ CONV_RESIDUAL, CONV_PAPER = 0, 1
 PRECOND_BLOCK_JACOBI, PRECOND_NONE = 0, 1
 MAX_RHS = 6
 # workgroup shapes (compute lanes in x, y) of the direction+operator sweep, by
-# options.tile; 5 adds two loader wavefronts (nx a multiple of 4)
+# options.tile; 5 adds two loader wavefronts (nx a multiple of 2, of 4 in mixed
+# precision; at most 96 distinct phases per workgroup box)
 TILE_SHAPES = ((32, 8), (16, 16), (64, 4), (32, 16), (64, 8), (64, 6))
 WS_TILES = (5,)
 # doubles per pore of elas3d_carve_pores: centre 3, semi-axes 3, R row-major 9
