@@ -401,6 +401,8 @@ def main(argv=None):
     ap.add_argument("--engine", choices=["group", "streams"], default="group",
                     help="group: one launch per sweep for all requests; streams: one stream per request")
     ap.add_argument("--poll", type=int, default=8, help="group: iterations between admissions")
+    ap.add_argument("--saturation-only", action="store_true",
+                    help="run the warm-up and the closed-loop saturation run only (for a kernel trace)")
     args = ap.parse_args(argv)
 
     import torch
@@ -425,6 +427,11 @@ def main(argv=None):
     sat = run_stream(sat_pool, srv, progress=100)
     sat_rate = len(sat) / (time.perf_counter() - t0)
     print(f"# saturation {sat_rate:.2f} solves/s", file=sys.stderr, flush=True)
+    if args.saturation_only:
+        srv.close()
+        print(json.dumps({"engine": args.engine, "precision": args.precision, "saturation_requests": len(sat),
+                          "saturation_solves_per_s": round(sat_rate, 3)}), flush=True)
+        return
     edges = [r.micro.shape[0] for r in sat_pool]
     out = {"metric": "p50/p99 solve latency under Poisson arrivals (continuous batching)",
            "engine": args.engine, "poll": args.poll if args.engine == "group" else None,
