@@ -57,12 +57,12 @@ KERNEL_SOURCES = ("paper_2602_07354_amd/csrc/elas3d_kernels.hip", "paper_2602_07
 # 3 x 3 values).  Per launch: 5.5 vectors + the phase, which the classic
 # shapes read as a 4-byte id and the wave-specialised one as a 1-byte rank
 # in its workgroup's phase dictionary.
-WS_SHAPE = (64, 6)  # lanes of the wave-specialised shape (options.tile 5)
+WS_SHAPES = (5,)  # options.tile of the wave-specialised shape
 
 
-def operator_bytes_per_node(precision: str, tile) -> float:
+def operator_bytes_per_node(precision: str, shape: int) -> float:
     v = 24 if precision == "fp64" else 12
-    ph = 1 if tuple(int(t) for t in tile[:2]) == WS_SHAPE else 4
+    ph = 1 if shape in WS_SHAPES else 4
     return (4 * v + ph + 7 * v + ph) / 2
 HOST_THREAD_CAP = 16  # host cores a one-GPU job may use
 
@@ -143,10 +143,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def _counter_summary(path: str, workload: str, tile, tile_key: str = "op_tile"):
+def _counter_summary(path: str, workload: str, tile, tile_key: str = "op_tile", shape=None):
     """key: value lines of a committed counter summary, or None (with the
     reason) unless it was taken on this kernel source, workload and sweep
-    geometry (lanes in x, y and z-chunk length; under tile_key)."""
+    geometry (lanes in x, y and z-chunk length under tile_key; the shape
+    index under the matching *_shape key, when the file gives one)."""
     if not os.path.exists(path):
         return None, None
     kv = {}
@@ -155,20 +156,22 @@ def _counter_summary(path: str, workload: str, tile, tile_key: str = "op_tile"):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
+    shape_key = tile_key.replace("tile", "shape") if tile_key else None
     if (kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload
-            or (tile_key is not None and kv.get(tile_key) != " ".join(str(v) for v in tile))):
+            or (tile_key is not None and kv.get(tile_key) != " ".join(str(v) for v in tile))
+            or (shape is not None and shape_key in kv and kv[shape_key] != str(shape))):
         return None, "stale (kernel, workload or sweep geometry differs from the counters' run)"
     return kv, os.path.relpath(path, ROOT)
 
 
-def measured_traffic(workload: str, tile) -> dict:
+def measured_traffic(workload: str, tile, shape=None) -> dict:
     """HBM bytes per launch of the fused sweep from the committed counter
     summary (see _counter_summary)."""
-    kv, src = _counter_summary(COUNTERS, workload, tile)
+    kv, src = _counter_summary(COUNTERS, workload, tile, shape=shape)
     return {"bytes": float(kv["op_traffic_bytes_per_dispatch"]) if kv else None, "source": src}
 
 
-def measured_valu(workload: str, tile, precision: str, op_ms: float, nz: int):
+def measured_valu(workload: str, tile, precision: str, op_ms: float, nz: int, shape=None):
     """Achieved vector-ALU rate of the fused sweep: its counted flops per
     launch (committed summary) over the launch duration measured now,
     against the vector peak; and its MFMA count.  The summary must be of
@@ -176,7 +179,7 @@ def measured_valu(workload: str, tile, precision: str, op_ms: float, nz: int):
     kz changes only the element layers computed (nz plus one per chunk), and
     the flops are scaled by that count."""
     key = "op_tile" if precision == "fp64" else "fp32_op_tile"
-    kv, src = _counter_summary(VALU_COUNTERS, workload, tile, key)
+    kv, src = _counter_summary(VALU_COUNTERS, workload, tile, key, shape=shape)
     scaled = False
     if not kv and src and os.path.exists(VALU_COUNTERS):
         kv, src = _counter_summary(VALU_COUNTERS, workload, None, None)
@@ -455,6 +458,7 @@ def main(argv=None):
             "median_ms": parts,
             "gdof_iter_per_s_solve_only": round(3.0 * ms.n * float(np.mean(iters)) / (parts["solve"] / 1e3) / 1e9, 3),
             "op_tile": recs[0][1]["op_tile"],
+            "op_shape": recs[0][1]["op_shape"],
             "update_blocks": recs[0][1]["update_blocks"],
             "update_nontemporal": recs[0][1]["update_nontemporal"],
         }
@@ -473,7 +477,8 @@ def main(argv=None):
             mixed["precision"] = "FP32 inner PCG + FP64 refinement (FP64 residual, update, dots, 3x3 inversions)"
             mixed["operator_ms_avg"] = round(m_op, 4)
             mixed["update_ms_avg"] = round(m_up, 4)
-            mixed["valu"] = measured_valu(ms.meta.get("workload"), mixed["op_tile"], "fp32", m_op, ms.shape[2])
+            mixed["valu"] = measured_valu(ms.meta.get("workload"), mixed["op_tile"], "fp32", m_op, ms.shape[2],
+                                          shape=mixed["op_shape"])
         else:
             skipped.append("mixed steps")
     tts_out = {}
@@ -486,11 +491,11 @@ def main(argv=None):
 
     value = main_leg["gdof_iter_per_s"]
     rhs_per_launch = (sum(kinfo["iters"]) / max(1, kinfo["n_operator"])) if args.batched else 1.0
-    op_bytes = (operator_bytes_per_node("fp64" if head == "fp64" else "fp32", main_leg["op_tile"]) * ms.n
+    op_bytes = (operator_bytes_per_node("fp64" if head == "fp64" else "fp32", main_leg["op_shape"]) * ms.n
                 * rhs_per_launch)
     achieved = op_bytes / (op_ms / 1e3) / 1e9
     tile = main_leg["op_tile"]
-    traffic = (measured_traffic(ms.meta.get("workload"), tile) if head == "fp64" and nrhs == 1
+    traffic = (measured_traffic(ms.meta.get("workload"), tile, main_leg["op_shape"]) if head == "fp64" and nrhs == 1
                else {"bytes": None, "source": None})
     out = {
         "metric": ("Gdof*iterations/s of the block-Jacobi PCG over whole steps (setup + "
@@ -534,10 +539,10 @@ def main(argv=None):
         "operator_ms_avg": round(op_ms, 4),
         "update_ms_avg": round(up_ms, 4),
         "roofline": {
-            "kernel": (("op_kernel_ws<64,6,2 loader wavefronts,%s> (wave-specialised fused direction update + "
+            "kernel": (("op_kernel_ws<%d,%d,2 loader wavefronts,%s> (wave-specialised fused direction update + "
                         "matrix-free operator + h.Ah; its light and paying forms)"
-                        % ("double" if head == "fp64" else "float"))
-                       if tuple(int(t) for t in tile[:2]) == WS_SHAPE else
+                        % (tile[0], tile[1], "double" if head == "fp64" else "float"))
+                       if main_leg["op_shape"] in WS_SHAPES else
                        "op_kernel<%d,%d,OP_FUSED,%s> (fused direction update + matrix-free operator + h.Ah)"
                        % (tile[0], tile[1], "double" if head == "fp64" else "float")),
             "bound": "hbm",
@@ -553,10 +558,11 @@ def main(argv=None):
             "stream_GBs_measured": streams,
             "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
             "op_tile": tile,
+            "op_shape": main_leg["op_shape"],
             "update_blocks": main_leg["update_blocks"],
             "update_nontemporal": main_leg["update_nontemporal"],
             "valu": (measured_valu(ms.meta.get("workload"), tile, "fp64" if head == "fp64" else "fp32", op_ms,
-                                   ms.shape[2]) if nrhs == 1 else None),
+                                   ms.shape[2], shape=main_leg["op_shape"]) if nrhs == 1 else None),
         },
         "skipped": skipped or None,
         "wall_s": None,

@@ -168,6 +168,10 @@ typedef struct elas3d_info {
     int32_t apply_tile[3];                     /* workgroup lanes in x, y and z-chunk
                                                   length of the true-residual and
                                                   refinement sweeps                   */
+    int32_t op_shape;                          /* the options.tile index of the
+                                                  direction+operator sweep's shape
+                                                  (op_tile's lanes do not tell 4
+                                                  from 6)                            */
 } elas3d_info;
 
 /* Fill `opt` with the defaults (FP64, residual criterion, block Jacobi,

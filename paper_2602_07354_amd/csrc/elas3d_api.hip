@@ -84,7 +84,7 @@ double plan_bytes(int32_t nx, int32_t ny, int32_t nz, int nphase, int nrhs, bool
     bytes += (double)nphase * 8.0 * (e3d::kCoefStride + e3d::kDiagStride + 1.0) +
              (double)nphase * nrhs * 8.0 * e3d::kSigStride;
     bytes += 8.0 * kPartialValues * (double)partial_slots(Dims{nx, ny, nz, (int)n}, nrhs, tile, zchunk);
-    if (tile >= 0 && tile < e3d::kNumTiles && e3d::kTileShapes[tile].nl > 0) {
+    if (tile >= 0 && tile < e3d::kNumTiles && e3d::is_ws(tile)) {
         // the forced wave-specialised shape's phase dictionaries
         const e3d::OpGeom g = e3d::op_geometry(Dims{nx, ny, nz, (int)n}, zchunk, tile);
         bytes += (double)e3d::ws_map_bytes(g) + 4.0 * e3d::kWsDict * g.blocks;
@@ -291,7 +291,7 @@ int export_field(elas3d_ctx* c, const double* field, int ncomp, double* out)
 int ws_prepare(elas3d_ctx* c, const e3d::OpGeom& g, bool& fits)
 {
     fits = true;
-    if (e3d::kTileShapes[g.tile].nl == 0) return 0;
+    if (!e3d::is_ws(g.tile)) return 0;
     for (const auto& e : c->wsd)
         if (e.g.tile == g.tile && e.g.tiles_x == g.tiles_x && e.g.tiles_y == g.tiles_y && e.g.kz == g.kz) {
             fits = e.maxcount <= e3d::kWsDict;
@@ -483,7 +483,7 @@ int autotune_apply(elas3d_ctx* c)
     const Dims& d = c->d;
     if (c->opt.autotune == 2) {
         // the forced shape, or 64x8 in place of a fused-sweep-only one
-        const int tile = e3d::kTileShapes[c->opt.tile].nl > 0 ? 4 : c->opt.tile;
+        const int tile = e3d::is_ws(c->opt.tile) ? 4 : c->opt.tile;
         c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, tile);
         c->apply_tuned = 1;
         return 0;
@@ -510,7 +510,7 @@ int autotune_apply(elas3d_ctx* c)
     int rc = 0;
     for (int tile = 0; tile < e3d::kNumTiles && !rc; ++tile)
         for (int target : kTuneTargets) {
-            if (e3d::kTileShapes[tile].nl > 0) break;  // fused-sweep-only shapes
+            if (e3d::is_ws(tile)) break;  // fused-sweep-only shapes
             const e3d::OpGeom g = e3d::op_geometry(d, 0, tile, target);
             auto launch = [&] { return e3d::launch_apply(c->stream, d, g, c->phase, t, x, y, nullptr, c->partials, nullptr); };
             hipError_t e = launch();  // warm-up
@@ -976,6 +976,7 @@ int record_results(elas3d_ctx* c, int r0, int R, const CaseResult* res, elas3d_i
             info->apply_tile[0] = e3d::kTileShapes[c->geom_apply.tile].tx;
             info->apply_tile[1] = e3d::kTileShapes[c->geom_apply.tile].ty;
             info->apply_tile[2] = c->geom_apply.kz;
+            info->op_shape = g.tile;
         }
         c->solved[r] = 1;
         worst = std::max(worst, fin.status);
@@ -1208,7 +1209,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     }
     // (host input arrays must not be read after return)
     SETUPCHK(hipStreamSynchronize(c->stream));
-    if (opt.autotune != 1 && e3d::kTileShapes[opt.tile].nl > 0) {
+    if (opt.autotune != 1 && e3d::is_ws(opt.tile)) {
         // the forced wave-specialised shape: its phase dictionaries
         bool fits = true;
         int rc2 = ws_prepare(c, c->geom_sweep[0], fits);

@@ -143,10 +143,12 @@ struct Tables {
 constexpr int kNumTiles = 6;
 struct TileShape {
     int tx, ty;
-    int nl, d;
+    int nl, d;  // d > 0: wave-specialised, with nl loader wavefronts and a ring of d planes
 };
 constexpr TileShape kTileShapes[kNumTiles] = {{32, 8, 0, 0}, {16, 16, 0, 0}, {64, 4, 0, 0},
                                               {32, 16, 0, 0}, {64, 8, 0, 0}, {64, 6, 2, 4}};
+// True for the wave-specialised shapes (fused sweep only).
+constexpr bool is_ws(int t) { return kTileShapes[t].d > 0; }
 // Lanes of a workgroup of shape t.
 constexpr int tile_lanes(int t) { return kTileShapes[t].tx * kTileShapes[t].ty + 64 * kTileShapes[t].nl; }
 // True when the wave-specialised shape t can run on grid d with elements of
@@ -154,7 +156,7 @@ constexpr int tile_lanes(int t) { return kTileShapes[t].tx * kTileShapes[t].ty +
 // stores address a plane by a 32-bit byte offset).
 inline bool ws_supported(const Dims& d, int t, int elem_bytes)
 {
-    return kTileShapes[t].nl == 0 || (d.nx % (16 / elem_bytes) == 0 && (long long)d.nx * d.ny < (1ll << 27));
+    return !is_ws(t) || (d.nx % (16 / elem_bytes) == 0 && (long long)d.nx * d.ny < (1ll << 27));
 }
 
 // Kernel launch geometry of the tiled operator sweep.

@@ -1299,13 +1299,14 @@ struct WsCfg {
     // owned node rows j0 .. j0 + TY - 2, from the chunk-aligned node <= i0
     static constexpr int QW = WPAY ? NF * (TY - 1) * NCH : 0;
     static constexpr int NIW = (QW + 63) / 64;
+    static constexpr int NT = TX * TY;              // compute lanes
+    static constexpr int NTOT = NT + 64 * NL;
+    static constexpr int NLOAD = NL;                // loader wavefronts
     static constexpr int NI = ((NIN + NIP + NIW) + NL - 1) / NL * NL;  // loader instructions per plane
     static constexpr int PER_W = NI / NL;           // per loader wavefront
     static constexpr int SLOT = NI * 64 * 16;       // ring bytes per plane
     static constexpr int PH_OFF = NIN * 64 * 16;    // byte offset of the phase ranks in a slot
     static constexpr int W_OFF = (NIN + NIP) * 64 * 16;  // byte offset of w / the older direction
-    static constexpr int NT = TX * TY;              // compute lanes
-    static constexpr int NTOT = NT + 64 * NL;
     // dictionary rows: kCoefStride elements each, in 16-byte chunks
     static constexpr int CHR = kCoefStride * (int)sizeof(T) / 16;
     static constexpr int NCI = kWsDict * CHR / 64;  // loader instructions of the rows
@@ -1314,6 +1315,7 @@ struct WsCfg {
     static_assert(LAYER % 16 == 0 && QP <= 64, "a layer of ranks in one instruction");
     static_assert(kCoefStride * sizeof(T) % 16 == 0 && kWsDict * CHR % 64 == 0, "whole dictionary instructions");
     static_assert(kWsDict <= 256, "ranks are bytes");
+    static_assert(NL >= 1 && D >= 3, "loader wavefronts and a ring of at least three planes");
     // vmcnt that lets D - 2 planes of a loader wavefront stay in flight
     static constexpr int WAIT = (D - 2) * PER_W > 63 ? 63 : (D - 2) * PER_W;
     static constexpr int WAIT0 = (D - 1) * PER_W > 63 ? 63 : (D - 1) * PER_W;
@@ -1361,6 +1363,105 @@ __device__ __forceinline__ void plane_store(float v, __amdgpu_buffer_rsrc_t r, i
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
 }
 
+// Copy duties of one loader wavefront in the wave-specialised sweep: the
+// source of each of its PER_W direct-to-LDS instructions of a ring slot
+// (instruction j = cw + NL i of the slot layout above), the plane and layer
+// offsets of slot u, and the dictionary rows.  Field bases are held as plain values: a
+// select among the argument struct's members would take its address and
+// move it to scratch memory.
+template <class C, typename T>
+struct WsCopier {
+    const char* src[C::PER_W];
+    const int32_t* dict;
+    const T* coef;
+    const uint8_t* rmap;
+    int cw, lane, k0, nsteps, nz;
+    size_t plane;
+
+    __device__ __forceinline__ void init(const OpArgs<T>& a, const T* const (&hold)[3], T* const (&hnew)[3],
+                                         int lb, int cw_, int lane_, int xa, int xw, int j0, int k0_, int nsteps_)
+    {
+        constexpr int LY = C::LY, NCH = C::NCH, CH = C::CH, TY = C::NT / 64;
+        const int nx = a.d.nx, ny = a.d.ny;
+        const T *z0 = a.z[0], *z1 = a.z[1], *z2 = a.z[2];
+        const T *o0 = hold[0], *o1 = hold[1], *o2 = hold[2];
+        const T *w0 = a.w[0], *w1 = a.w[1], *w2 = a.w[2];
+        const T *n0 = hnew[0], *n1 = hnew[1], *n2 = hnew[2];
+        cw = cw_;
+        lane = lane_;
+        k0 = k0_;
+        nsteps = nsteps_;
+        nz = a.d.nz;
+        plane = (size_t)nx * ny;
+        dict = a.wsdict + (size_t)lb * kWsDict;
+        coef = a.coef;
+        rmap = a.wsmap + (size_t)lb * ((size_t)(a.kz + 2) * C::LAYER);
+#pragma unroll
+        for (int i = 0; i < C::PER_W; ++i) {
+            const int j = cw + C::NLOAD * i;
+            if (j < C::NIN) {
+                const int q = 64 * j + lane;
+                const int qq = q < C::QN ? q : 0;  // padding lanes copy chunk 0 into the block's tail
+                const int f = qq / (LY * NCH), rem = qq - f * (LY * NCH);
+                const int y = rem / NCH, c = rem - y * NCH;
+                const int gx = ((xa + c * CH) % nx + nx) % nx;
+                const int gy = ((j0 - 1 + y) % ny + ny) % ny;
+                const int f3 = f < 3 ? f : f - 3;
+                const T* bz_ = f3 == 0 ? z0 : (f3 == 1 ? z1 : z2);
+                const T* bh_ = f3 == 0 ? o0 : (f3 == 1 ? o1 : o2);
+                src[i] = reinterpret_cast<const char*>((f < 3 ? bz_ : bh_) + (gx + (size_t)nx * gy));
+            } else if (j < C::NIN + C::NIP) {
+                src[i] = reinterpret_cast<const char*>(rmap + 16 * (lane < C::QP ? lane : 0));
+            } else if (j < C::NIN + C::NIP + C::NIW) {
+                // w and the older direction (the buffer this sweep
+                // overwrites: read here before the owner lane writes it)
+                const int q = 64 * (j - C::NIN - C::NIP) + lane;
+                const int qq = q < C::QW ? q : 0;
+                const int f = qq / ((TY - 1) * NCH), rem = qq - f * ((TY - 1) * NCH);
+                const int y = rem / NCH, c = rem - y * NCH;
+                const int gx = ((xw + c * CH) % nx + nx) % nx;
+                const int gy = (j0 + y) % ny;
+                const int f3 = f < 3 ? f : f - 3;
+                const T* bw_ = f3 == 0 ? w0 : (f3 == 1 ? w1 : w2);
+                const T* bp_ = f3 == 0 ? n0 : (f3 == 1 ? n1 : n2);
+                src[i] = reinterpret_cast<const char*>((f < 3 ? bw_ : bp_) + (gx + (size_t)nx * gy));
+            } else {
+                // padding instruction: the first chunk of z's plane (it takes
+                // the node-plane offset, in bounds of a T field only)
+                src[i] = reinterpret_cast<const char*>(z0);
+            }
+        }
+    }
+    // node plane and element layer k0 - 1 + u into the ring slot at dst
+    __device__ __forceinline__ void issue(char* dst, int u) const
+    {
+        const int uc = min(u, nsteps);
+        int kw = k0 - 1 + uc;
+        kw = kw < 0 ? kw + nz : (kw >= nz ? kw - nz : kw);
+        const size_t pn = (size_t)kw * plane * sizeof(T), pp = (size_t)uc * C::LAYER;
+#pragma unroll
+        for (int i = 0; i < C::PER_W; ++i) {
+            const int j = cw + C::NLOAD * i;
+            __builtin_amdgcn_global_load_lds((const void*)(src[i] + (j < C::NIN || j >= C::NIN + C::NIP ? pn : pp)),
+                                             (void*)(dst + (size_t)j * 1024), 16, 0, 0);
+        }
+    }
+    // this wavefront's share of the dictionary's stiffness rows
+    __device__ __forceinline__ void issue_dict(char* ccb) const
+    {
+#pragma unroll
+        for (int m = 0; m < (C::NCI + C::NLOAD - 1) / C::NLOAD; ++m) {
+            const int i = cw + C::NLOAD * m;
+            if (i < C::NCI) {
+                const int g = 64 * i + lane;
+                const int r = g / C::CHR, q = g - r * C::CHR;
+                const T* row = coef + (size_t)dict[r] * kCoefStride + q * C::CH;
+                __builtin_amdgcn_global_load_lds((const void*)row, (void*)(ccb + (size_t)i * 1024), 16, 0, 0);
+            }
+        }
+    }
+};
+
 template <int TX, int TY, int NL, int D, typename T, bool WPAY>
 __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int nblocks,
                                            OpSharedWS<TX, TY, NL, D, T, WPAY>& sh)
@@ -1403,85 +1504,23 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
     const int xs = i0 - 1;
     const int xa = (xs >= 0 ? xs / CH : -((-xs + CH - 1) / CH)) * CH;
     const int xw = (i0 / CH) * CH;  // owned nodes (paying form's w block)
-    const uint8_t* rmap = a.wsmap + (size_t)lb * ((size_t)(a.kz + 2) * C::LAYER);
     auto wrapk = [&](int kk) { return kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk); };
     const int tid = threadIdx.x;
     double dot = 0.0;
 
+    const int lane = tid & 63;
     if (tid >= NT) {
         // ---------------------------------------------------------- loader
-        const int lw = (tid - NT) >> 6, lane = tid & 63;
-        const char* src[C::PER_W];
+        WsCopier<C, T> cp;
+        cp.init(a, hold, hnew, lb, (tid - NT) >> 6, lane, xa, xw, j0, k0, nsteps);
+        cp.issue_dict(reinterpret_cast<char*>(&sh.cc[0][0]));
 #pragma unroll
-        for (int i = 0; i < C::PER_W; ++i) {
-            const int j = lw + NL * i;  // instruction index in the slot
-            if (j < C::NIN) {
-                const int q = 64 * j + lane;
-                const int qq = q < C::QN ? q : 0;  // padding lanes copy chunk 0 into the block's tail
-                const int f = qq / (LY * NCH), rem = qq - f * (LY * NCH);
-                const int y = rem / NCH, c = rem - y * NCH;
-                const int gx = ((xa + c * CH) % nx + nx) % nx;
-                const int gy = ((j0 - 1 + y) % ny + ny) % ny;
-                // field base by selects (a lane-varying index into the
-                // argument arrays would move them to scratch memory)
-                const int f3 = f < 3 ? f : f - 3;
-                const T* bz_ = f3 == 0 ? a.z[0] : (f3 == 1 ? a.z[1] : a.z[2]);
-                const T* bh_ = f3 == 0 ? hold[0] : (f3 == 1 ? hold[1] : hold[2]);
-                src[i] = reinterpret_cast<const char*>((f < 3 ? bz_ : bh_) + (gx + (size_t)nx * gy));
-            } else if (j < C::NIN + C::NIP) {
-                src[i] = reinterpret_cast<const char*>(rmap + 16 * (lane < C::QP ? lane : 0));
-            } else if (j < C::NIN + C::NIP + C::NIW) {
-                // w and the older direction (the buffer this sweep
-                // overwrites: read here before the owner lane writes it)
-                const int q = 64 * (j - C::NIN - C::NIP) + lane;
-                const int qq = q < C::QW ? q : 0;
-                const int f = qq / ((TY - 1) * NCH), rem = qq - f * ((TY - 1) * NCH);
-                const int y = rem / NCH, c = rem - y * NCH;
-                const int gx = ((xw + c * CH) % nx + nx) % nx;
-                const int gy = (j0 + y) % ny;
-                const int f3 = f < 3 ? f : f - 3;
-                const T* bw_ = f3 == 0 ? a.w[0] : (f3 == 1 ? a.w[1] : a.w[2]);
-                const T* bp_ = f3 == 0 ? hnew[0] : (f3 == 1 ? hnew[1] : hnew[2]);
-                src[i] = reinterpret_cast<const char*>((f < 3 ? bw_ : bp_) + (gx + (size_t)nx * gy));
-            } else {
-                // padding instruction: the first chunk of z's plane (it takes
-                // the node-plane offset, in bounds of a T field only)
-                src[i] = reinterpret_cast<const char*>(a.z[0]);
-            }
-        }
-        auto issue = [&](int u) {  // node plane and element layer k0 - 1 + u into ring slot u % D
-            const int uc = min(u, nsteps);
-            const size_t pn = (size_t)wrapk(k0 - 1 + uc) * plane * sizeof(T), pp = (size_t)uc * C::LAYER;
-            char* dst = sh.ring[u % D];
-#pragma unroll
-            for (int i = 0; i < C::PER_W; ++i) {
-                const int j = lw + NL * i;
-                __builtin_amdgcn_global_load_lds((const void*)(src[i] + (j < C::NIN || j >= C::NIN + C::NIP ? pn : pp)),
-                                                 (void*)(dst + (size_t)j * 1024), 16, 0, 0);
-            }
-        };
-        // the dictionary's stiffness rows (landed with plane 0, issued before it)
-        {
-            const int32_t* dl = a.wsdict + (size_t)lb * kWsDict;
-            char* ccb = reinterpret_cast<char*>(&sh.cc[0][0]);
-#pragma unroll
-            for (int m = 0; m < (C::NCI + NL - 1) / NL; ++m) {
-                const int i = lw + NL * m;
-                if (i < C::NCI) {
-                    const int g = 64 * i + lane;
-                    const int r = g / C::CHR, q = g - r * C::CHR;
-                    const T* row = a.coef + (size_t)dl[r] * kCoefStride + q * CH;
-                    __builtin_amdgcn_global_load_lds((const void*)row, (void*)(ccb + (size_t)i * 1024), 16, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < D; ++u) issue(u);
+        for (int u = 0; u < D; ++u) cp.issue(sh.ring[u % D], u);
         wait_vmcnt<C::WAIT0>();  // plane 0 landed
         __builtin_amdgcn_s_barrier();
         for (int s = 0; s < nsteps; ++s) {
             // slot (s - 1) % D was read before the last barrier: refill it
-            if (s >= 1) issue(s - 1 + D);
+            if (s >= 1) cp.issue(sh.ring[(s - 1 + D) % D], s - 1 + D);
             wait_vmcnt<C::WAIT>();  // plane s + 1 landed
             __builtin_amdgcn_s_barrier();
         }
@@ -2073,9 +2112,8 @@ __global__ void __launch_bounds__(256) ws_dict_kernel(Dims d, int tiles_x, int t
 hipError_t launch_ws_dictionary(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,
                                 int32_t* dict, uint8_t* map, int* maxcount)
 {
-    if (g.tile < 0 || g.tile >= kNumTiles || kTileShapes[g.tile].nl == 0 || g.blocks <= 0)
-        return hipErrorInvalidValue;
-    static_assert(kTileShapes[5].nl > 0 && kTileShapes[5].tx == 64 && kTileShapes[5].ty == 6,
+    if (g.tile < 0 || g.tile >= kNumTiles || !is_ws(g.tile) || g.blocks <= 0) return hipErrorInvalidValue;
+    static_assert(kNumTiles == 6 && is_ws(5) && kTileShapes[5].tx == 64 && kTileShapes[5].ty == 6,
                   "the one wave-specialised shape");
     hipLaunchKernelGGL((ws_dict_kernel<64, 6>), dim3(g.blocks), dim3(256), 0, st, d, g.tiles_x, g.tiles_y,
                        g.kz, phase, dict, map, maxcount);
@@ -2189,7 +2227,7 @@ static bool direction_buffers_ok(const FieldsT<T>& f)
 template <typename T>
 static bool ws_fields_ok(const Dims& d, int tile, const FieldsT<T>& f, size_t rs)
 {
-    if (kTileShapes[tile].nl == 0) return true;
+    if (!is_ws(tile)) return true;
     if (!ws_supported(d, tile, (int)sizeof(T)) || (rs * sizeof(T)) % 16 != 0) return false;
     for (int c = 0; c < 3; ++c)
         if (((uintptr_t)f.z[c] | (uintptr_t)f.h0[c] | (uintptr_t)f.h1[c]) % 16 != 0) return false;
@@ -2203,7 +2241,7 @@ hipError_t launch_direction_operator(hipStream_t st, const Dims& d, const OpGeom
 {
     if (!direction_buffers_ok(f)) return hipErrorInvalidValue;
     if (g.tile < 0 || g.tile >= kNumTiles || !ws_fields_ok(d, g.tile, f, rs)) return hipErrorInvalidValue;
-    if (kTileShapes[g.tile].nl > 0 &&
+    if (is_ws(g.tile) &&
         (!t.ws.dict || !t.ws.map || t.ws.tile != g.tile || t.ws.tiles_x != g.tiles_x ||
          t.ws.tiles_y != g.tiles_y || t.ws.kz != g.kz))
         return hipErrorInvalidValue;  // no dictionaries built for this geometry

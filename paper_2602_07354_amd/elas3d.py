@@ -100,6 +100,7 @@ class Info(ctypes.Structure):
         ("precond_rows", ctypes.c_int64),
         ("update_nontemporal", ctypes.c_int32),
         ("apply_tile", ctypes.c_int32 * 3),
+        ("op_shape", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -124,6 +125,7 @@ class Info(ctypes.Structure):
             "precond_rows": self.precond_rows,
             "update_nontemporal": self.update_nontemporal,
             "apply_tile": list(self.apply_tile),
+            "op_shape": self.op_shape,
         }
 
 

@@ -45,8 +45,9 @@ def test_struct_layout_matches_c(E, tmp_path):
         ' offsetof(elas3d_info, update_blocks), offsetof(elas3d_options, autotune));\n'
         'printf("%zu %zu %zu %zu\\n", offsetof(elas3d_options, tile), offsetof(elas3d_options, zchunk),'
         ' offsetof(elas3d_info, precond_rows), offsetof(elas3d_info, update_nontemporal));\n'
-        'printf("%zu %zu %zu\\n", offsetof(elas3d_options, update_blocks),'
-        ' offsetof(elas3d_options, update_nontemporal), offsetof(elas3d_info, apply_tile));\n'
+        'printf("%zu %zu %zu %zu\\n", offsetof(elas3d_options, update_blocks),'
+        ' offsetof(elas3d_options, update_nontemporal), offsetof(elas3d_info, apply_tile),'
+        ' offsetof(elas3d_info, op_shape));\n'
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -58,7 +59,7 @@ def test_struct_layout_matches_c(E, tmp_path):
           E.Info.op_tile.offset, E.Info.update_blocks.offset, E.Options.autotune.offset,
           E.Options.tile.offset, E.Options.zchunk.offset, E.Info.precond_rows.offset,
           E.Info.update_nontemporal.offset, E.Options.update_blocks.offset,
-          E.Options.update_nontemporal.offset, E.Info.apply_tile.offset]
+          E.Options.update_nontemporal.offset, E.Info.apply_tile.offset, E.Info.op_shape.offset]
     assert c == py
 
 

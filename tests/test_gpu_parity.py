@@ -750,7 +750,7 @@ def test_wave_specialised_sweep_matches_oracle(E, orc, tile):
             with E.Context.from_micro(ms, tile=tile, precision=precision) as ctx:
                 st, info = ctx.solve(1e-12 if precision == E.PREC_FP64 else 1e-10, 20000)
                 assert st == E.OK
-                assert info["op_tile"][:2] == list(E.TILE_SHAPES[tile])
+                assert info["op_tile"][:2] == list(E.TILE_SHAPES[tile]) and info["op_shape"] == tile
                 if precision == E.PREC_FP64:
                     assert abs(info["iters"][0] - ro["iters"]) <= 2
                 out = ctx.stress(0)
@@ -792,20 +792,22 @@ def test_sweep_with_many_phases_per_box(E, orc):
     another shape is chosen and solves to the oracle's solution.  (Parity of
     the classic sweep on it: test_sweep_with_many_phases_per_row_matches_oracle.)"""
     ms = _many_phase_grid((72, 13, 11), 300, 7)
-    for prec in (E.PREC_FP64, E.PREC_MIXED):
-        with pytest.raises(E.Elas3dError) as ei:
-            E.Context.from_micro(ms, tile=5, precision=prec)
-        assert ei.value.code == E.EBADARG and "distinct phases" in str(ei.value)
+    for tile in E.WS_TILES:
+        for prec in (E.PREC_FP64, E.PREC_MIXED):
+            with pytest.raises(E.Elas3dError) as ei:
+                E.Context.from_micro(ms, tile=tile, precision=prec)
+            assert ei.value.code == E.EBADARG and "distinct phases" in str(ei.value)
     P = orc.Problem.from_micro(ms)
     ro = P.solve(ms.strain[0], tol=1e-12)
     with E.Context.from_micro(ms, autotune=1) as ctx:
         st, info = ctx.solve(1e-12, 20000)
         assert st == E.OK and abs(info["iters"][0] - ro["iters"]) <= 2
-        assert info["op_tile"][:2] != list(E.TILE_SHAPES[5])
+        assert info["op_shape"] not in E.WS_TILES
         assert _rel(ctx.solution(0), ro["w"]) <= 1e-9
 
 
-def test_wave_specialised_sweep_with_a_full_dictionary(E, orc):
+@pytest.mark.parametrize("tile", [5])
+def test_wave_specialised_sweep_with_a_full_dictionary(E, orc, tile):
     """Every voxel draws one of exactly 96 phases (a workgroup box holds all
     of them: the phase dictionary is full, ranks 0..95 in use): the
     wave-specialised sweep's iterates after k = 1..3 iterations equal the
@@ -816,7 +818,7 @@ def test_wave_specialised_sweep_with_a_full_dictionary(E, orc):
     for k in range(1, 4):
         say("case: full dictionary, iterations", k)
         ro = P.solve(ms.strain[0], tol=1e-30, maxit=k)
-        with E.Context.from_micro(ms, tile=5) as ctx:
+        with E.Context.from_micro(ms, tile=tile) as ctx:
             st, info = ctx.solve(1e-30, k)
             assert st == E.NOT_CONVERGED and info["iters"][0] == k
             assert _rel(ctx.solution(0), ro["w"]) <= 1e-11, k
@@ -824,9 +826,9 @@ def test_wave_specialised_sweep_with_a_full_dictionary(E, orc):
     so, _ = P.stress(ms.strain[0], ro["w"])
     for precision in (E.PREC_FP64, E.PREC_MIXED):
         say("case: full dictionary, converged, precision", precision)
-        with E.Context.from_micro(ms, tile=5, precision=precision) as ctx:
+        with E.Context.from_micro(ms, tile=tile, precision=precision) as ctx:
             st, info = ctx.solve(1e-12 if precision == E.PREC_FP64 else 1e-10, 20000)
-            assert st == E.OK and info["op_tile"][:2] == list(E.TILE_SHAPES[5])
+            assert st == E.OK and info["op_shape"] == tile
             out = ctx.stress(0)
         assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
 
