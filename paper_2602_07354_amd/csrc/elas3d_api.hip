@@ -323,8 +323,8 @@ int ws_prepare(elas3d_ctx* c, const e3d::OpGeom& g, bool& fits)
     return 0;
 }
 
-// Frees the dictionaries of geometries neither precision's sweep uses (nor
-// `also`, when given).
+// Frees the dictionaries of geometries that neither precision's fused sweep
+// nor the residual sweep uses (nor `also`, when given).
 void ws_release_unused(elas3d_ctx* c, const e3d::OpGeom* also = nullptr)
 {
     auto same = [](const e3d::OpGeom& a, const e3d::OpGeom& b) {
@@ -332,7 +332,7 @@ void ws_release_unused(elas3d_ctx* c, const e3d::OpGeom* also = nullptr)
     };
     std::vector<elas3d_ctx::WsDictEntry> keep;
     for (auto& e : c->wsd) {
-        bool used = also && same(e.g, *also);
+        bool used = (also && same(e.g, *also)) || same(e.g, c->geom_apply);
         for (const auto& g : c->geom_sweep) used = used || same(e.g, g);
         if (used) {
             keep.push_back(e);
@@ -476,24 +476,44 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
 // (64x8 lanes when that shape exists for the fused sweep only).
 // The reduction order of ||y||^2 follows the geometry; y itself does not
 // depend on it.
-std::map<std::array<int, 4>, e3d::OpGeom> g_apply_cache;
+std::map<std::array<int, 4>, std::pair<e3d::OpGeom, e3d::OpGeom>> g_apply_cache;  // (apply, refine)
 
 int autotune_apply(elas3d_ctx* c)
 {
     const Dims& d = c->d;
     if (c->opt.autotune == 2) {
-        // the forced shape, or 64x8 in place of a fused-sweep-only one
-        const int tile = e3d::is_ws(c->opt.tile) ? 4 : c->opt.tile;
-        c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, tile);
+        // the forced shape (its phase dictionaries were built at setup); the
+        // refinement sweep takes 64x8 in place of the wave-specialised shape
+        c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, c->opt.tile);
+        c->geom_refine = e3d::is_ws(c->opt.tile) ? e3d::op_geometry(d, c->opt.zchunk, 4) : c->geom_apply;
+        if (e3d::is_ws(c->opt.tile)) {
+            bool fits = true;
+            int rc = ws_prepare(c, c->geom_apply, fits);
+            if (rc) return rc;
+            if (!fits) c->geom_apply = c->geom_refine;
+        }
         c->apply_tuned = 1;
         return 0;
     }
     const std::array<int, 4> key = {c->device, d.nx, d.ny, d.nz};
     {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_apply_cache.find(key);
-        if (it != g_apply_cache.end()) {
-            c->geom_apply = it->second;
+        std::pair<e3d::OpGeom, e3d::OpGeom> hit;
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_apply_cache.find(key);
+            if (it != g_apply_cache.end()) {
+                hit = it->second;
+                found = true;
+            }
+        }
+        if (found) {
+            // a wave-specialised choice needs this microstructure's dictionaries
+            bool fits = true;
+            int rc = ws_prepare(c, hit.first, fits);
+            if (rc) return rc;
+            c->geom_apply = fits ? hit.first : hit.second;
+            c->geom_refine = hit.second;
             c->apply_tuned = 1;
             return 0;
         }
@@ -501,17 +521,21 @@ int autotune_apply(elas3d_ctx* c)
     Fields f = c->fields(0);
     const double* x[3] = {f.w[0], f.w[1], f.w[2]};
     double* y[3] = {f.Ah[0], f.Ah[1], f.Ah[2]};
-    const e3d::Tables t = c->tables();
     hipEvent_t ev[2];
     HIPCHK(c, hipEventCreate(&ev[0]));
     HIPCHK(c, hipEventCreate(&ev[1]));
-    float best = 1e30f;
-    e3d::OpGeom best_g = c->geom_apply;
+    float best = 1e30f, best_classic = 1e30f;
+    e3d::OpGeom best_g = c->geom_apply, best_cg = c->geom_apply;
     int rc = 0;
     for (int tile = 0; tile < e3d::kNumTiles && !rc; ++tile)
         for (int target : kTuneTargets) {
-            if (e3d::is_ws(tile)) break;  // fused-sweep-only shapes
+            if (!e3d::ws_supported(d, tile, 8)) break;  // shape not possible on this grid
             const e3d::OpGeom g = e3d::op_geometry(d, 0, tile, target);
+            bool fits = true;
+            rc = ws_prepare(c, g, fits);
+            if (rc) break;
+            if (!fits) continue;  // a box with more phases than a dictionary holds
+            const e3d::Tables t = c->tables_for(g);
             auto launch = [&] { return e3d::launch_apply(c->stream, d, g, c->phase, t, x, y, nullptr, c->partials, nullptr); };
             hipError_t e = launch();  // warm-up
             for (int k = 0; k < 3 && e == hipSuccess; ++k) {
@@ -530,14 +554,20 @@ int autotune_apply(elas3d_ctx* c)
                 best = ms;
                 best_g = g;
             }
+            if (!e3d::is_ws(tile) && ms < best_classic) {  // the refinement sweep has no wave-specialised form
+                best_classic = ms;
+                best_cg = g;
+            }
+            ws_release_unused(c, &best_g);  // at most the best candidate's dictionaries stay
         }
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
     if (rc) return rc;
     c->geom_apply = best_g;
+    c->geom_refine = best_cg;
     c->apply_tuned = 1;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_apply_cache[key] = best_g;
+    g_apply_cache[key] = {best_g, best_cg};
     return 0;
 }
 
@@ -792,7 +822,7 @@ int refine_launch(elas3d_ctx* c, int r, int q)
     double* w[3] = {f64.w[0], f64.w[1], f64.w[2]};
     const float* dc[3] = {f32.w[0], f32.w[1], f32.w[2]};
     float* r32[3] = {f32.g[0], f32.g[1], f32.g[2]};
-    HIPCHK(c, e3d::launch_refine(c->stream, c->d, c->geom_apply, c->phase, c->tables(), w, dc, f64.b, r32,
+    HIPCHK(c, e3d::launch_refine(c->stream, c->d, c->geom_refine, c->phase, c->tables(), w, dc, f64.b, r32,
                                  c->partials, c->dscratch + 4 + 2 * q));
     // {||r||^2, ||r||^2}: the norms of the next inner run
     HIPCHK(c, hipMemcpyAsync(c->dscratch + 5 + 2 * q, c->dscratch + 4 + 2 * q, sizeof(double),
@@ -805,7 +835,7 @@ int residual_launch(elas3d_ctx* c, int r, double* norm2)
     Fields f = c->fields(r);
     const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
     double* gy[3] = {f.g[0], f.g[1], f.g[2]};
-    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom_apply, c->phase, c->tables(), wx, gy, f.b, c->partials,
+    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom_apply, c->phase, c->tables_for(c->geom_apply), wx, gy, f.b, c->partials,
                                 norm2));
     return 0;
 }
@@ -826,7 +856,7 @@ int true_residual(elas3d_ctx* c, int r, double* rr)
     Fields f = c->fields(r);
     const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
     double* gy[3] = {f.g[0], f.g[1], f.g[2]};
-    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom_apply, c->phase, c->tables(), wx, gy, f.b, c->partials,
+    HIPCHK(c, e3d::launch_apply(c->stream, c->d, c->geom_apply, c->phase, c->tables_for(c->geom_apply), wx, gy, f.b, c->partials,
                                 c->dscratch));
     HIPCHK(c, hipMemcpyAsync(c->hscratch, c->dscratch, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -923,8 +953,8 @@ int solve_mixed(elas3d_ctx* c, int r0, int R, double tol, int maxit, elas3d_info
         Fields f = c->fields(r);
         const double* wx[3] = {f.w[0], f.w[1], f.w[2]};
         double* gy[3] = {f.g[0], f.g[1], f.g[2]};
-        HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom_apply, c->phase, t, wx, gy, f.b, c->partials,
-                                    c->dscratch));
+        HIPCHK(c, e3d::launch_apply(c->stream, d, c->geom_apply, c->phase, c->tables_for(c->geom_apply), wx, gy,
+                                    f.b, c->partials, c->dscratch));
         CaseResult fr;
         int rc = solve_fp64(c, r, 1, tol, maxit, true, iters[q], info, &fr);
         if (rc) return rc;
@@ -1090,6 +1120,7 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->bytes = need;
     c->geom = e3d::op_geometry(c->d, 0);
     c->geom_apply = c->geom;
+    c->geom_refine = c->geom;
     for (int q = 0; q < 2; ++q) {
         c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, opt.tile);
         c->upd_blocks[q] = opt.update_blocks > 0 ? opt.update_blocks : default_update_blocks(c->d.n);

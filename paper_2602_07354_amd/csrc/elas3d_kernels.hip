@@ -1284,19 +1284,22 @@ __global__ void __launch_bounds__(TX* TY, E3D_OP_MIN_WAVES) op_kernel(OpArgs<T> 
 // part a lane owes its x neighbour is passed by a lane shuffle; the part for
 // the row below (v1 of this lane plus v0 of its x neighbour, summed) goes
 // through LDS.
-template <int TX, int TY, int NL, int D, typename T, bool WPAY>
+template <int TX, int TY, int NL, int D, typename T, bool WPAY, int MODE>
 struct WsCfg {
     static constexpr int CH = 16 / (int)sizeof(T);  // elements per chunk
     static constexpr int NCH = TX / CH + 1;         // chunks per patch row
     static constexpr int LY = TY + 1;               // patch rows
-    static constexpr int NF = 6;                    // z (3 components), h_old (3)
+    // OP_FUSED: z (3 components) and h_old (3); OP_APPLY: x (3)
+    static constexpr bool APPLY = MODE == OP_APPLY;
+    static constexpr int NF = APPLY ? 3 : 6;
     static constexpr int QN = NF * LY * NCH;        // node chunks per plane
     static constexpr int NIN = (QN + 63) / 64;      // loader instructions of node chunks
     static constexpr int LAYER = TX * TY;           // bytes of a layer of phase ranks
     static constexpr int QP = LAYER / 16;           // its chunks
     static constexpr int NIP = 1;
-    // paying form: w and the older direction (3 components each) on the
-    // owned node rows j0 .. j0 + TY - 2, from the chunk-aligned node <= i0
+    // paying form: w and the older direction (3 components each), or the
+    // added vector in APPLY, on the owned node rows j0 .. j0 + TY - 2, from
+    // the chunk-aligned node <= i0
     static constexpr int QW = WPAY ? NF * (TY - 1) * NCH : 0;
     static constexpr int NIW = (QW + 63) / 64;
     static constexpr int NT = TX * TY;              // compute lanes
@@ -1321,9 +1324,9 @@ struct WsCfg {
     static constexpr int WAIT0 = (D - 1) * PER_W > 63 ? 63 : (D - 1) * PER_W;
 };
 
-template <int TX, int TY, int NL, int D, typename T, bool WPAY>
+template <int TX, int TY, int NL, int D, typename T, bool WPAY, int MODE>
 struct OpSharedWS {
-    using C = WsCfg<TX, TY, NL, D, T, WPAY>;
+    using C = WsCfg<TX, TY, NL, D, T, WPAY, MODE>;
     alignas(16) char ring[D][C::SLOT];
     T sf[2][3][C::NT];
     alignas(16) T cc[kWsDict][kCoefStride];  // the dictionary's stiffness rows
@@ -1378,15 +1381,18 @@ struct WsCopier {
     int cw, lane, k0, nsteps, nz;
     size_t plane;
 
-    __device__ __forceinline__ void init(const OpArgs<T>& a, const T* const (&hold)[3], T* const (&hnew)[3],
+    // nf: the node-plane fields (slot fields 0 .. NF - 1), of: the owned-row
+    // fields of the paying form / the added vector (0 .. NF - 1)
+    __device__ __forceinline__ void init(const OpArgs<T>& a, const T* const (&nf)[6], const T* const (&of)[6],
                                          int lb, int cw_, int lane_, int xa, int xw, int j0, int k0_, int nsteps_)
     {
         constexpr int LY = C::LY, NCH = C::NCH, CH = C::CH, TY = C::NT / 64;
         const int nx = a.d.nx, ny = a.d.ny;
-        const T *z0 = a.z[0], *z1 = a.z[1], *z2 = a.z[2];
-        const T *o0 = hold[0], *o1 = hold[1], *o2 = hold[2];
-        const T *w0 = a.w[0], *w1 = a.w[1], *w2 = a.w[2];
-        const T *n0 = hnew[0], *n1 = hnew[1], *n2 = hnew[2];
+        const T *n0 = nf[0], *n1 = nf[1], *n2 = nf[2], *n3 = nf[3], *n4 = nf[4], *n5 = nf[5];
+        const T *o0 = of[0], *o1 = of[1], *o2 = of[2], *o3 = of[3], *o4 = of[4], *o5 = of[5];
+        auto pick = [](int f, const T* p0, const T* p1, const T* p2, const T* p3, const T* p4, const T* p5) {
+            return f == 0 ? p0 : f == 1 ? p1 : f == 2 ? p2 : f == 3 ? p3 : f == 4 ? p4 : p5;
+        };
         cw = cw_;
         lane = lane_;
         k0 = k0_;
@@ -1406,29 +1412,24 @@ struct WsCopier {
                 const int y = rem / NCH, c = rem - y * NCH;
                 const int gx = ((xa + c * CH) % nx + nx) % nx;
                 const int gy = ((j0 - 1 + y) % ny + ny) % ny;
-                const int f3 = f < 3 ? f : f - 3;
-                const T* bz_ = f3 == 0 ? z0 : (f3 == 1 ? z1 : z2);
-                const T* bh_ = f3 == 0 ? o0 : (f3 == 1 ? o1 : o2);
-                src[i] = reinterpret_cast<const char*>((f < 3 ? bz_ : bh_) + (gx + (size_t)nx * gy));
+                src[i] = reinterpret_cast<const char*>(pick(f, n0, n1, n2, n3, n4, n5) + (gx + (size_t)nx * gy));
             } else if (j < C::NIN + C::NIP) {
                 src[i] = reinterpret_cast<const char*>(rmap + 16 * (lane < C::QP ? lane : 0));
             } else if (j < C::NIN + C::NIP + C::NIW) {
-                // w and the older direction (the buffer this sweep
-                // overwrites: read here before the owner lane writes it)
+                // owned-row fields (in the fused sweep w and the older
+                // direction, the buffer it overwrites: read here before the
+                // owner lane writes it)
                 const int q = 64 * (j - C::NIN - C::NIP) + lane;
                 const int qq = q < C::QW ? q : 0;
                 const int f = qq / ((TY - 1) * NCH), rem = qq - f * ((TY - 1) * NCH);
                 const int y = rem / NCH, c = rem - y * NCH;
                 const int gx = ((xw + c * CH) % nx + nx) % nx;
                 const int gy = (j0 + y) % ny;
-                const int f3 = f < 3 ? f : f - 3;
-                const T* bw_ = f3 == 0 ? w0 : (f3 == 1 ? w1 : w2);
-                const T* bp_ = f3 == 0 ? n0 : (f3 == 1 ? n1 : n2);
-                src[i] = reinterpret_cast<const char*>((f < 3 ? bw_ : bp_) + (gx + (size_t)nx * gy));
+                src[i] = reinterpret_cast<const char*>(pick(f, o0, o1, o2, o3, o4, o5) + (gx + (size_t)nx * gy));
             } else {
-                // padding instruction: the first chunk of z's plane (it takes
-                // the node-plane offset, in bounds of a T field only)
-                src[i] = reinterpret_cast<const char*>(z0);
+                // padding instruction: the first chunk of field 0's plane (it
+                // takes the node-plane offset, in bounds of a T field only)
+                src[i] = reinterpret_cast<const char*>(n0);
             }
         }
     }
@@ -1462,33 +1463,54 @@ struct WsCopier {
     }
 };
 
-template <int TX, int TY, int NL, int D, typename T, bool WPAY>
+// MODE OP_FUSED: the direction + operator sweep (WPAY: the form that pays
+// w's two owed steps).  MODE OP_APPLY (FP64): y = A x, plus the added vector
+// when WPAY, with the optional ||y||^2 partials; one right-hand side.
+template <int TX, int TY, int NL, int D, typename T, bool WPAY, int MODE>
 __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int nblocks,
-                                           OpSharedWS<TX, TY, NL, D, T, WPAY>& sh)
+                                           OpSharedWS<TX, TY, NL, D, T, WPAY, MODE>& sh)
 {
-    using C = WsCfg<TX, TY, NL, D, T, WPAY>;
+    using C = WsCfg<TX, TY, NL, D, T, WPAY, MODE>;
     using R = T;
     constexpr int NT = C::NT, LY = C::LY, NCH = C::NCH, CH = C::CH;
+    constexpr bool FUSED = MODE == OP_FUSED;
+    static_assert(FUSED || (MODE == OP_APPLY && sizeof(T) == 8), "the fused sweep, or the FP64 operator");
 
-    const int nr = a.nrhs;
-    const int ntb = nblocks / nr;  // tile blocks per RHS
-    const int rhs = lbr / ntb;
-    const int lb = lbr - rhs * ntb;
-    const Scalars* S = a.S + rhs;
-    // the other form's kernel serves this sweep, or the run is over
-    if (S->done || ((S->pending == 2) != WPAY)) return;
-    const R gam = (R)S->gamma;
-    const int cur = S->cur;
-    const size_t roff = (size_t)rhs * a.rs;
-    const T* hold[3];
-    T* hnew[3];
+    int ntb = nblocks, rhs = 0, lb = lbr;
+    R gam = R(0);
+    const Scalars* S = nullptr;
+    const T* nf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const T* of[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    T* hnew[3] = {nullptr, nullptr, nullptr};
+    T* wdst[3] = {nullptr, nullptr, nullptr};
+    T* ydst[3];
+    if constexpr (FUSED) {
+        ntb = nblocks / a.nrhs;  // tile blocks per RHS
+        rhs = lbr / ntb;
+        lb = lbr - rhs * ntb;
+        S = a.S + rhs;
+        // the other form's kernel serves this sweep, or the run is over
+        if (S->done || ((S->pending == 2) != WPAY)) return;
+        gam = (R)S->gamma;
+        const int cur = S->cur;
+        const size_t roff = (size_t)rhs * a.rs;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        hold[c] = (cur ? a.h1[c] : a.h0[c]) + roff;
-        hnew[c] = (cur ? a.h0[c] : a.h1[c]) + roff;
-        a.z[c] += roff;
-        a.w[c] += roff;
-        a.y[c] += roff;
+        for (int c = 0; c < 3; ++c) {
+            hnew[c] = (cur ? a.h0[c] : a.h1[c]) + roff;
+            nf[c] = a.z[c] + roff;
+            nf[c + 3] = (cur ? a.h1[c] : a.h0[c]) + roff;
+            wdst[c] = a.w[c] + roff;
+            of[c] = wdst[c];
+            of[c + 3] = hnew[c];
+            ydst[c] = a.y[c] + roff;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            nf[c] = reinterpret_cast<const T*>(a.x[c]);
+            of[c] = reinterpret_cast<const T*>(a.add[c]);
+            ydst[c] = reinterpret_cast<T*>(a.yd[c]);
+        }
     }
 
     const int nx = a.d.nx, ny = a.d.ny, nz = a.d.nz;
@@ -1512,7 +1534,7 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
     if (tid >= NT) {
         // ---------------------------------------------------------- loader
         WsCopier<C, T> cp;
-        cp.init(a, hold, hnew, lb, (tid - NT) >> 6, lane, xa, xw, j0, k0, nsteps);
+        cp.init(a, nf, of, lb, (tid - NT) >> 6, lane, xa, xw, j0, k0, nsteps);
         cp.issue_dict(reinterpret_cast<char*>(&sh.cc[0][0]));
 #pragma unroll
         for (int u = 0; u < D; ++u) cp.issue(sh.ring[u % D], u);
@@ -1528,7 +1550,11 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
         __builtin_amdgcn_s_barrier();
     } else {
         // --------------------------------------------------------- compute
-        const R lam = (R)S->lambda, lamp = (R)S->lambda_prev;
+        R lam = R(0), lamp = R(0);
+        if constexpr (FUSED) {
+            lam = (R)S->lambda;
+            lamp = (R)S->lambda_prev;
+        }
         const int tx = tid % TX, ty = tid / TX;
         const int gi = i0 + tx, gj = j0 + ty;
         const int own = (gi % nx) + nx * (gj % ny);
@@ -1544,22 +1570,30 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
         const int ew = min(ty, TY - 2) * NCH * CH + min(tx, TX - 2) + (i0 - xw);
         constexpr int FSTRIDE = LY * NCH * CH;       // elements between fields
         constexpr int WSTRIDE = (TY - 1) * NCH * CH;  // between w-block fields
-        // corner values h_new (z + gamma h_old) of the plane in a ring slot as
-        // face spectra, the own node's value and h_old
+        // corner values of the plane in a ring slot as face spectra (fused:
+        // h_new = z + gamma h_old; apply: x), the own node's value and, fused,
+        // its h_old
         auto read_plane = [&](int slot, R (&F)[3][4], R (&ownv)[3], R (&ownh)[3]) {
             const R* rg = reinterpret_cast<const R*>(sh.ring[slot]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const R* zf = rg + c * FSTRIDE;
-                const R* hf = rg + (c + 3) * FSTRIDE;
-                const R v00 = fma(gam, hf[e00], zf[e00]);
-                const R v10 = fma(gam, hf[e10], zf[e10]);
-                const R v01 = fma(gam, hf[e01], zf[e01]);
-                const R h11 = hf[e11];
-                const R v11 = fma(gam, h11, zf[e11]);
-                face_fwd(v00, v10, v01, v11, F[c]);
-                ownv[c] = v11;
-                ownh[c] = h11;
+                if constexpr (FUSED) {
+                    const R* hf = rg + (c + 3) * FSTRIDE;
+                    const R v00 = fma(gam, hf[e00], zf[e00]);
+                    const R v10 = fma(gam, hf[e10], zf[e10]);
+                    const R v01 = fma(gam, hf[e01], zf[e01]);
+                    const R h11 = hf[e11];
+                    const R v11 = fma(gam, h11, zf[e11]);
+                    face_fwd(v00, v10, v01, v11, F[c]);
+                    ownv[c] = v11;
+                    ownh[c] = h11;
+                } else {
+                    const R v11 = zf[e11];
+                    face_fwd(zf[e00], zf[e10], zf[e01], v11, F[c]);
+                    ownv[c] = v11;
+                    ownh[c] = R(0);
+                }
             }
         };
         // phase rank of the lane's element in the layer of a ring slot, and
@@ -1588,17 +1622,25 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
             const int b = s & 1;
             const int ku = k0 + s;
             __syncthreads();  // plane ku in slot (s + 1) % D; forces of step s - 1 in SF[b ^ 1]
-            // Ah of plane ku - 2 (stored at the end of the step)
+            // Ah (A x, plus the added vector) of plane ku - 2
             const bool emit = s > 1 && out_ok;
             R yv[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) yv[c] = mine_d[c] + SF[b ^ 1][c][tid + TX];
-            if (emit) dot += (double)hout_d[0] * yv[0] + (double)hout_d[1] * yv[1] + (double)hout_d[2] * yv[2];
+            for (int c = 0; c < 3; ++c) {
+                yv[c] = mine_d[c] + SF[b ^ 1][c][tid + TX];
+                if constexpr (!FUSED) yv[c] += hout_d[c];  // the added vector
+            }
+            if (emit) {
+                if constexpr (FUSED)
+                    dot += (double)hout_d[0] * yv[0] + (double)hout_d[1] * yv[1] + (double)hout_d[2] * yv[2];
+                else
+                    dot += (double)yv[0] * yv[0] + (double)yv[1] * yv[1] + (double)yv[2] * yv[2];
+            }
             {
                 const size_t pk = (size_t)wrapk(ku - 2) * plane;
                 const int off = emit ? own * (int)sizeof(T) : kDropOffset;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) plane_store(yv[c], plane_rsrc(a.y[c], pk, plane), off);
+                for (int c = 0; c < 3; ++c) plane_store(yv[c], plane_rsrc(ydst[c], pk, plane), off);
             }
             const int slot = (s + 1) % D;
             R Cu[21];
@@ -1621,18 +1663,22 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
                     SF[b][c][tid] = v[1] + __shfl_down(v[0], 1);
                 }
             }
-            // h_new (and w) of plane ku
-            {
+            const R* wb = reinterpret_cast<const R*>(sh.ring[slot] + C::W_OFF);
+            if constexpr (FUSED) {
+                // h_new (and w) of plane ku
                 const size_t pk = (size_t)min(ku, nz - 1) * plane;
                 const int off = (out_ok && ku < kend) ? own * (int)sizeof(T) : kDropOffset;
-                const R* wb = reinterpret_cast<const R*>(sh.ring[slot] + C::W_OFF);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     plane_store(ov[c], plane_rsrc(hnew[c], pk, plane), off);
                     if constexpr (WPAY)
                         plane_store(fma(-lam, oh[c], fma(-lamp, wb[(c + 3) * WSTRIDE + ew], wb[c * WSTRIDE + ew])),
-                                    plane_rsrc(a.w[c], pk, plane), off);
+                                    plane_rsrc(wdst[c], pk, plane), off);
                 }
+            } else {
+                // the added vector at the own node of plane ku, carried to its emit
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ov[c] = WPAY ? wb[c * WSTRIDE + ew] : R(0);
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -1656,20 +1702,24 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 yv[c] = mine_d[c] + SF[b][c][tid + TX];
-                a.y[c][idx] = yv[c];
+                if constexpr (!FUSED) yv[c] += hout_d[c];
+                ydst[c][idx] = yv[c];
             }
-            dot += (double)hout_d[0] * yv[0] + (double)hout_d[1] * yv[1] + (double)hout_d[2] * yv[2];
+            if constexpr (FUSED)
+                dot += (double)hout_d[0] * yv[0] + (double)hout_d[1] * yv[1] + (double)hout_d[2] * yv[2];
+            else
+                dot += (double)yv[0] * yv[0] + (double)yv[1] * yv[1] + (double)yv[2] * yv[2];
         }
     }
     double v[1] = {dot};
-    block_partials<1, C::NTOT>(v, a.partials + (size_t)rhs * ntb, ntb, lb);
+    if (FUSED || a.want_norm) block_partials<1, C::NTOT>(v, a.partials + (size_t)rhs * ntb, ntb, lb);
 }
 
-template <int TX, int TY, int NL, int D, typename T, bool WPAY>
+template <int TX, int TY, int NL, int D, typename T, bool WPAY, int MODE>
 __global__ void __launch_bounds__(TX* TY + 64 * NL, 1) op_kernel_ws(OpArgs<T> a)
 {
-    __shared__ OpSharedWS<TX, TY, NL, D, T, WPAY> sh;
-    op_body_ws<TX, TY, NL, D, T, WPAY>(a, xcd_local_block(), gridDim.x, sh);
+    __shared__ OpSharedWS<TX, TY, NL, D, T, WPAY, MODE> sh;
+    op_body_ws<TX, TY, NL, D, T, WPAY, MODE>(a, xcd_local_block(), gridDim.x, sh);
 }
 
 // Copy of a work-list entry held in scalar registers: the entry is the same
@@ -1783,10 +1833,10 @@ hipError_t launch_op_tiled(hipStream_t st, const OpGeom& g, unsigned grid, const
     case I:                                                                                   \
         if constexpr (MODE == OP_FUSED) {                                                     \
             hipLaunchKernelGGL((op_kernel_ws<kTileShapes[I].tx, kTileShapes[I].ty, kTileShapes[I].nl, \
-                                             ws_depth<T, false>(I), T, false>),                \
+                                             ws_depth<T, false>(I), T, false, OP_FUSED>),      \
                                dim3(grid), dim3(tile_lanes(I)), 0, st, a);                    \
             hipLaunchKernelGGL((op_kernel_ws<kTileShapes[I].tx, kTileShapes[I].ty, kTileShapes[I].nl, \
-                                             ws_depth<T, true>(I), T, true>),                  \
+                                             ws_depth<T, true>(I), T, true, OP_FUSED>),        \
                                dim3(grid), dim3(tile_lanes(I)), 0, st, a);                    \
         } else {                                                                              \
             return hipErrorInvalidValue;                                                      \
@@ -2455,6 +2505,16 @@ hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const in
                         const Tables& t, const double* const x[3], double* const y[3],
                         const double* const add[3], double* partials, double* norm2)
 {
+    if (g.tile < 0 || g.tile >= kNumTiles) return hipErrorInvalidValue;
+    if (is_ws(g.tile)) {
+        // the wave-specialised operator: its dictionaries, rows of whole
+        // 16-byte chunks and 16-byte aligned node vectors
+        if (!t.ws.dict || !t.ws.map || t.ws.tile != g.tile || t.ws.tiles_x != g.tiles_x ||
+            t.ws.tiles_y != g.tiles_y || t.ws.kz != g.kz || !ws_supported(d, g.tile, 8))
+            return hipErrorInvalidValue;
+        for (int c = 0; c < 3; ++c)
+            if (((uintptr_t)x[c] | (add ? (uintptr_t)add[c] : 0)) % 16 != 0) return hipErrorInvalidValue;
+    }
     OpArgs<double> a = {};
     a.d = d;
     a.tiles_x = g.tiles_x;
@@ -2469,7 +2529,24 @@ hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const in
     }
     a.partials = partials;
     a.want_norm = norm2 != nullptr;
-    hipError_t e = launch_op_tiled<OP_APPLY, double>(st, g, (unsigned)g.blocks, a);
+    a.wsdict = t.ws.dict;
+    a.wsmap = t.ws.map;
+    a.nrhs = 1;
+    if (is_ws(g.tile)) {
+        static_assert(kNumTiles == 6 && is_ws(5), "the one wave-specialised shape");
+        constexpr int TX = kTileShapes[5].tx, TY = kTileShapes[5].ty, NL = kTileShapes[5].nl,
+                      DA = kTileShapes[5].d;  // the operator's ring carries x alone: one depth serves both forms
+        if (add)
+            hipLaunchKernelGGL((op_kernel_ws<TX, TY, NL, DA, double, true, OP_APPLY>), dim3(g.blocks),
+                               dim3(tile_lanes(5)), 0, st, a);
+        else
+            hipLaunchKernelGGL((op_kernel_ws<TX, TY, NL, DA, double, false, OP_APPLY>), dim3(g.blocks),
+                               dim3(tile_lanes(5)), 0, st, a);
+    } else {
+        hipError_t e = launch_op_tiled<OP_APPLY, double>(st, g, (unsigned)g.blocks, a);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (norm2)
         hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,

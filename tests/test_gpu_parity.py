@@ -863,6 +863,27 @@ def test_sweep_with_many_phases_per_row_matches_oracle(E, orc, tile):
         assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
 
 
+def test_wave_specialised_operator_gives_the_true_residual(E, orc):
+    """With the wave-specialised shape forced (autotune = 2), the residual
+    sweep (y = A w + b, the true residual of the stopping test) runs in its
+    wave-specialised form: the relative true residual the GPU reports equals
+    the oracle's ||A w + b|| / ||b|| of the returned w, in FP64 and in mixed
+    precision (whose refinement cycles each take one)."""
+    ms = _small_poly((68, 29, 21), 131, grains=20)
+    P = orc.Problem.from_micro(ms)
+    b, _ = P.load(ms.strain[0])
+    for precision in (E.PREC_FP64, E.PREC_MIXED):
+        say("case: wave-specialised residual sweep, precision", precision)
+        with E.Context.from_micro(ms, tile=5, autotune=2, precision=precision) as ctx:
+            st, info = ctx.solve(1e-6, 20000)
+            assert st == E.OK
+            assert info["apply_tile"][:2] == [64, 6] and info["op_shape"] == 5
+            w = ctx.solution(0)
+        rel = np.linalg.norm(P.apply(w) + b) / np.linalg.norm(b)
+        assert 0 < rel <= 1e-6
+        assert abs(info["relres_true"][0] - rel) <= 1e-6 * rel, (info["relres_true"][0], rel)
+
+
 def test_wave_specialised_shape_needs_whole_chunks(E):
     """Forcing a wave-specialised shape on a grid whose rows are not a whole
     number of 16-byte chunks is refused at setup (before any device work)."""
