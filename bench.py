@@ -99,6 +99,9 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=160, help="edge of the oracle's sample grid")
     ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations timed (0 = automatic)")
+    ap.add_argument("--cpu-tts", action="store_true",
+                    help="also time the oracle's own solves of the benchmark problem to the tolerance, every "
+                         "load case, threaded (grids of at most 2^21 nodes) and serial (at most 2^18)")
     ap.add_argument("--no-stream-probe", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
@@ -312,6 +315,33 @@ def cpu_baseline(workload: str, edge: int, iters: int, n_full: int, gpu_iters, t
         out["extrapolation"] = (f"time to solution of the full grid ({n_full} voxels) extrapolated from the "
                                 f"sample: s/iteration x {n_full / ms.n:.3g} (voxel ratio) x {gpu_iters} (the "
                                 f"GPU's FP64 iterations to the tolerance); not a measured solve")
+    return out
+
+
+def cpu_time_to_solution(ms, tol: float, criterion: str, gpu: dict) -> dict:
+    """The oracle's time to solution of the benchmark problem itself (same
+    grid, phases, stiffnesses, load cases and stopping rule), every load case
+    solved in turn, on the host's cores (OpenMP build) and on one core, beside
+    the GPU's time for the same solves."""
+    import oracle
+    mode = 1 if criterion == "paper" else 0
+    out = {"grid": list(ms.shape), "cases": int(ms.nrhs), "tol": tol, "criterion": criterion,
+           "cpu_model": cpu_model(), "gpu": gpu}
+    legs = [("serial", 1)] if ms.n <= (1 << 18) else []  # one core: small grids only
+    threads = host_threads()
+    if threads > 1 and oracle.threaded_available():
+        legs.insert(0, ("threaded", threads))
+    for name, nt in legs:
+        phase = ms.phase.cpu().numpy() if hasattr(ms.phase, "cpu") else np.asarray(ms.phase)  # device-generated maps
+        P = oracle.Problem(ms.shape, phase, np.asarray(ms.C), threads=nt if name == "threaded" else 0)
+        t0 = time.perf_counter()
+        iters = []
+        for r in range(ms.nrhs):
+            res = P.solve(ms.strain[r], tol=tol, mode=mode)
+            iters.append(int(res["iters"]))
+            print(f"# oracle {name}: case {r} solved in {iters[-1]} iterations", file=sys.stderr, flush=True)
+        out[name] = {"threads": nt, "time_to_solution_s": round(time.perf_counter() - t0, 3), "iters": iters}
+        del P
     return out
 
 
@@ -579,6 +609,15 @@ def main(argv=None):
         else:
             skipped.append("cpu baseline")
             out["skipped"] = skipped
+    if args.cpu_tts:
+        if ms.n > (1 << 21):
+            out["cpu_time_to_solution"] = {"error": "grid above 2^21 nodes: the oracle's full solve is not timed"}
+        elif head in tts_out:
+            t = tts_out[head]
+            out["cpu_time_to_solution"] = cpu_time_to_solution(
+                ms, args.tol, args.criterion,
+                {"precision": head, "time_to_solution_s": t["time_to_solution_s"], "iters": t["iters"]})
+            note("cpu time to solution done")
     out["wall_s"] = round(elapsed(), 1)
     print(json.dumps(out), flush=True)
 

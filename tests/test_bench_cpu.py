@@ -63,3 +63,16 @@ def test_cpu_baseline_reports_both_legs_and_the_extrapolation():
     assert abs(s["extrapolated_time_to_solution_s"] - s["s_per_iter"] * 8 * 123) <= 0.1 + 1e-3 * s["s_per_iter"] * 984
     if "threaded" in out:
         assert out["threaded"]["threads"] > 1 and out["cores"] == out["threaded"]["threads"]
+
+
+def test_cpu_time_to_solution_solves_every_case():
+    """The oracle's own solves of the benchmark problem: every load case to
+    the tolerance, serial (and threaded where OpenMP is built), with the GPU
+    figures passed through."""
+    from paper_2602_07354_amd import synth
+    ms = synth.eshelby_inclusion(8)
+    out = bench.cpu_time_to_solution(ms, 1e-8, "residual", {"time_to_solution_s": 0.01})
+    assert out["cases"] == ms.nrhs and out["gpu"]["time_to_solution_s"] == 0.01
+    assert out["serial"]["time_to_solution_s"] > 0 and len(out["serial"]["iters"]) == ms.nrhs
+    if "threaded" in out:
+        assert out["threaded"]["iters"] == out["serial"]["iters"]
