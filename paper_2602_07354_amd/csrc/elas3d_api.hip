@@ -470,27 +470,29 @@ int autotune(elas3d_ctx* c, const FieldsT<T>& f0, size_t rs, int r0, int R, cons
 // Geometry of the residual and refinement sweeps (one operator application
 // each, FP64): with options.autotune = 1, the fastest of the candidate
 // workgroup shapes and z-chunkings on the live grid (cached per process by
-// device and grid), timed as y = A w into the FP64 operator-output field of
-// case 0 (no finalize, so no scalar changes; y is rewritten by the first
-// direction sweep); with 2, the forced geometry of options.tile / zchunk
-// (64x8 lanes when that shape exists for the fused sweep only).
-// The reduction order of ||y||^2 follows the geometry; y itself does not
-// depend on it.
-std::map<std::array<int, 4>, std::pair<e3d::OpGeom, e3d::OpGeom>> g_apply_cache;  // (apply, refine)
+// device and grid), timed as y = A x + b, as those sweeps run, with x dense
+// stand-in data in the FP64 direction buffer that the first direction sweep
+// writes before reading, and y the FP64 operator-output field of case 0 (no
+// finalize, so no scalar changes; y is rewritten by the first direction
+// sweep); with 2, the forced geometry of options.tile / zchunk
+// (64x8 lanes when a wave-specialised box holds more phases than its
+// dictionary).  The reduction order of ||y||^2 follows the geometry; y itself
+// does not depend on it.
+// Cached: the fastest shape and the fastest classic one, the fallback for a
+// microstructure whose phases do not fit the wave-specialised dictionaries.
+std::map<std::array<int, 4>, std::pair<e3d::OpGeom, e3d::OpGeom>> g_apply_cache;
 
 int autotune_apply(elas3d_ctx* c)
 {
     const Dims& d = c->d;
     if (c->opt.autotune == 2) {
-        // the forced shape (its phase dictionaries were built at setup); the
-        // refinement sweep takes 64x8 in place of the wave-specialised shape
+        // the forced shape (its phase dictionaries were built at setup)
         c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, c->opt.tile);
-        c->geom_refine = e3d::is_ws(c->opt.tile) ? e3d::op_geometry(d, c->opt.zchunk, 4) : c->geom_apply;
         if (e3d::is_ws(c->opt.tile)) {
             bool fits = true;
             int rc = ws_prepare(c, c->geom_apply, fits);
             if (rc) return rc;
-            if (!fits) c->geom_apply = c->geom_refine;
+            if (!fits) c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, 4);
         }
         c->apply_tuned = 1;
         return 0;
@@ -513,13 +515,14 @@ int autotune_apply(elas3d_ctx* c)
             int rc = ws_prepare(c, hit.first, fits);
             if (rc) return rc;
             c->geom_apply = fits ? hit.first : hit.second;
-            c->geom_refine = hit.second;
             c->apply_tuned = 1;
             return 0;
         }
     }
     Fields f = c->fields(0);
-    const double* x[3] = {f.w[0], f.w[1], f.w[2]};
+    // h1 is contiguous over its three components
+    HIPCHK(c, e3d::launch_tuning_fill(c->stream, f.h1[0], 3 * c->N()));
+    const double* x[3] = {f.h1[0], f.h1[1], f.h1[2]};
     double* y[3] = {f.Ah[0], f.Ah[1], f.Ah[2]};
     hipEvent_t ev[2];
     HIPCHK(c, hipEventCreate(&ev[0]));
@@ -536,7 +539,7 @@ int autotune_apply(elas3d_ctx* c)
             if (rc) break;
             if (!fits) continue;  // a box with more phases than a dictionary holds
             const e3d::Tables t = c->tables_for(g);
-            auto launch = [&] { return e3d::launch_apply(c->stream, d, g, c->phase, t, x, y, nullptr, c->partials, nullptr); };
+            auto launch = [&] { return e3d::launch_apply(c->stream, d, g, c->phase, t, x, y, f.b, c->partials, nullptr); };
             hipError_t e = launch();  // warm-up
             for (int k = 0; k < 3 && e == hipSuccess; ++k) {
                 if (k == 0) e = hipEventRecord(ev[0], c->stream);
@@ -554,7 +557,7 @@ int autotune_apply(elas3d_ctx* c)
                 best = ms;
                 best_g = g;
             }
-            if (!e3d::is_ws(tile) && ms < best_classic) {  // the refinement sweep has no wave-specialised form
+            if (!e3d::is_ws(tile) && ms < best_classic) {
                 best_classic = ms;
                 best_cg = g;
             }
@@ -564,7 +567,6 @@ int autotune_apply(elas3d_ctx* c)
     hipEventDestroy(ev[1]);
     if (rc) return rc;
     c->geom_apply = best_g;
-    c->geom_refine = best_cg;
     c->apply_tuned = 1;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_apply_cache[key] = {best_g, best_cg};
@@ -822,7 +824,7 @@ int refine_launch(elas3d_ctx* c, int r, int q)
     double* w[3] = {f64.w[0], f64.w[1], f64.w[2]};
     const float* dc[3] = {f32.w[0], f32.w[1], f32.w[2]};
     float* r32[3] = {f32.g[0], f32.g[1], f32.g[2]};
-    HIPCHK(c, e3d::launch_refine(c->stream, c->d, c->geom_refine, c->phase, c->tables(), w, dc, f64.b, r32,
+    HIPCHK(c, e3d::launch_refine(c->stream, c->d, c->geom_apply, c->phase, c->tables_for(c->geom_apply), w, dc, f64.b, r32,
                                  c->partials, c->dscratch + 4 + 2 * q));
     // {||r||^2, ||r||^2}: the norms of the next inner run
     HIPCHK(c, hipMemcpyAsync(c->dscratch + 5 + 2 * q, c->dscratch + 4 + 2 * q, sizeof(double),
@@ -1120,7 +1122,6 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->bytes = need;
     c->geom = e3d::op_geometry(c->d, 0);
     c->geom_apply = c->geom;
-    c->geom_refine = c->geom;
     for (int q = 0; q < 2; ++q) {
         c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, opt.tile);
         c->upd_blocks[q] = opt.update_blocks > 0 ? opt.update_blocks : default_update_blocks(c->d.n);

@@ -240,6 +240,8 @@ hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const i
                          const double* const b[3], float* const r[3], double* partials,
                          double* norm2);
 hipError_t launch_to_float(hipStream_t st, const double* src, float* dst, size_t n);
+// n values in [-1e-3, 1e-3) from a hash of the index (stand-in data for timing)
+hipError_t launch_tuning_fill(hipStream_t st, double* p, size_t n);
 // y = A x (+ add when add[0] != nullptr); ||y||^2 into *norm2 when norm2 != nullptr.
 // APPLY and REFINE run with any workgroup shape (the geometry g).
 hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const int32_t* phase,

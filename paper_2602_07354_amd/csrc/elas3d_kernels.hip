@@ -861,6 +861,20 @@ __global__ void __launch_bounds__(kBlock) add_correction_kernel(Dims d, double* 
     }
 }
 
+// Dense stand-in data for timing a sweep: element i gets a value in
+// [-1e-3, 1e-3) from a 64-bit integer hash of i (SplitMix64's finaliser), so
+// that the timed sweep reads non-zero, varied node values as in a solve.
+__global__ void __launch_bounds__(kBlock) tuning_fill_kernel(double* __restrict__ p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        unsigned long long z = i + 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        p[i] = ((double)(z >> 11) * 0x1.0p-53 - 0.5) * 2e-3;
+    }
+}
+
 // dst = (float) src, n elements.
 __global__ void __launch_bounds__(kBlock) to_float_kernel(const double* __restrict__ src,
                                                           float* __restrict__ dst, size_t n)
@@ -920,7 +934,7 @@ struct OpArgs {
     int want_norm;
     size_t rs;  // FUSED: elements between consecutive RHS of the batch
     int nrhs;   // FUSED: RHS in the batch (workgroup -> (tile, rhs))
-    // wave-specialised FUSED: phase dictionaries of the launch geometry
+    // wave-specialised sweeps: phase dictionaries of the launch geometry
     const int32_t* wsdict;
     const uint8_t* wsmap;
 };
@@ -931,7 +945,8 @@ struct OpArgs {
 //            buffer), Ah = A h_new and the partial h_new.Ah (FP64); when w
 //            owes two steps (WPAY), also w -= lambda_prev h_prev (the
 //            buffer's old content) and w -= lambda h_old, in that order.
-// OP_REFINE: y = A (x + xd) + add in FP64, stored as FP32, ||y||^2.
+// OP_REFINE: y = A (x + xd) + add in FP64, stored as FP32, ||y||^2 (the
+//            wave-specialised form reads x after xd has been added to it).
 #ifndef E3D_OP_MIN_WAVES
 #define E3D_OP_MIN_WAVES 1
 #endif
@@ -1289,8 +1304,8 @@ struct WsCfg {
     static constexpr int CH = 16 / (int)sizeof(T);  // elements per chunk
     static constexpr int NCH = TX / CH + 1;         // chunks per patch row
     static constexpr int LY = TY + 1;               // patch rows
-    // OP_FUSED: z (3 components) and h_old (3); OP_APPLY: x (3)
-    static constexpr bool APPLY = MODE == OP_APPLY;
+    // OP_FUSED: z (3 components) and h_old (3); OP_APPLY and OP_REFINE: x (3)
+    static constexpr bool APPLY = MODE != OP_FUSED;
     static constexpr int NF = APPLY ? 3 : 6;
     static constexpr int QN = NF * LY * NCH;        // node chunks per plane
     static constexpr int NIN = (QN + 63) / 64;      // loader instructions of node chunks
@@ -1465,7 +1480,10 @@ struct WsCopier {
 
 // MODE OP_FUSED: the direction + operator sweep (WPAY: the form that pays
 // w's two owed steps).  MODE OP_APPLY (FP64): y = A x, plus the added vector
-// when WPAY, with the optional ||y||^2 partials; one right-hand side.
+// when WPAY, with the optional ||y||^2 partials; one right-hand side.  MODE
+// OP_REFINE: the same operator with the added vector, y stored in FP32 and
+// ||y||^2 from the FP64 values (the refinement residual, once the FP32
+// correction has been added to x).
 template <int TX, int TY, int NL, int D, typename T, bool WPAY, int MODE>
 __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int nblocks,
                                            OpSharedWS<TX, TY, NL, D, T, WPAY, MODE>& sh)
@@ -1474,7 +1492,9 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
     using R = T;
     constexpr int NT = C::NT, LY = C::LY, NCH = C::NCH, CH = C::CH;
     constexpr bool FUSED = MODE == OP_FUSED;
-    static_assert(FUSED || (MODE == OP_APPLY && sizeof(T) == 8), "the fused sweep, or the FP64 operator");
+    constexpr bool REFINE = MODE == OP_REFINE;
+    static_assert(FUSED || ((MODE == OP_APPLY || (REFINE && WPAY)) && sizeof(T) == 8),
+                  "the fused sweep, or the FP64 operator");
 
     int ntb = nblocks, rhs = 0, lb = lbr;
     R gam = R(0);
@@ -1484,6 +1504,7 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
     T* hnew[3] = {nullptr, nullptr, nullptr};
     T* wdst[3] = {nullptr, nullptr, nullptr};
     T* ydst[3];
+    float* yrdst[3];
     if constexpr (FUSED) {
         ntb = nblocks / a.nrhs;  // tile blocks per RHS
         rhs = lbr / ntb;
@@ -1510,6 +1531,7 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
             nf[c] = reinterpret_cast<const T*>(a.x[c]);
             of[c] = reinterpret_cast<const T*>(a.add[c]);
             ydst[c] = reinterpret_cast<T*>(a.yd[c]);
+            yrdst[c] = a.yr[c];
         }
     }
 
@@ -1638,9 +1660,15 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
             }
             {
                 const size_t pk = (size_t)wrapk(ku - 2) * plane;
-                const int off = emit ? own * (int)sizeof(T) : kDropOffset;
+                if constexpr (REFINE) {
+                    const int off = emit ? own * (int)sizeof(float) : kDropOffset;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) plane_store(yv[c], plane_rsrc(ydst[c], pk, plane), off);
+                    for (int c = 0; c < 3; ++c) plane_store((float)yv[c], plane_rsrc(yrdst[c], pk, plane), off);
+                } else {
+                    const int off = emit ? own * (int)sizeof(T) : kDropOffset;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) plane_store(yv[c], plane_rsrc(ydst[c], pk, plane), off);
+                }
             }
             const int slot = (s + 1) % D;
             R Cu[21];
@@ -1703,7 +1731,10 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
             for (int c = 0; c < 3; ++c) {
                 yv[c] = mine_d[c] + SF[b][c][tid + TX];
                 if constexpr (!FUSED) yv[c] += hout_d[c];
-                ydst[c][idx] = yv[c];
+                if constexpr (REFINE)
+                    yrdst[c][idx] = (float)yv[c];
+                else
+                    ydst[c][idx] = yv[c];
             }
             if constexpr (FUSED)
                 dot += (double)hout_d[0] * yv[0] + (double)hout_d[1] * yv[1] + (double)hout_d[2] * yv[2];
@@ -2560,6 +2591,15 @@ hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const i
                          const double* const b[3], float* const r[3], double* partials,
                          double* norm2)
 {
+    if (g.tile < 0 || g.tile >= kNumTiles) return hipErrorInvalidValue;
+    const bool ws = is_ws(g.tile);
+    if (ws) {
+        if (!t.ws.dict || !t.ws.map || t.ws.tile != g.tile || t.ws.tiles_x != g.tiles_x ||
+            t.ws.tiles_y != g.tiles_y || t.ws.kz != g.kz || !ws_supported(d, g.tile, 8))
+            return hipErrorInvalidValue;
+        for (int c = 0; c < 3; ++c)
+            if (((uintptr_t)w[c] | (uintptr_t)b[c]) % 16 != 0) return hipErrorInvalidValue;
+    }
     OpArgs<double> a = {};
     a.d = d;
     a.tiles_x = g.tiles_x;
@@ -2575,14 +2615,40 @@ hipError_t launch_refine(hipStream_t st, const Dims& d, const OpGeom& g, const i
     }
     a.partials = partials;
     a.want_norm = 1;
-    hipError_t e = launch_op_tiled<OP_REFINE, double>(st, g, (unsigned)g.blocks, a);
+    a.wsdict = t.ws.dict;
+    a.wsmap = t.ws.map;
+    a.nrhs = 1;
+    const int nb = sweep_blocks(d.n, 4096);
+    if (ws) {
+        // w + d is formed once, in place, and the operator reads it: the
+        // same FP64 sums as the classic sweep forms at every node it reads
+        hipLaunchKernelGGL(add_correction_kernel, dim3(nb), dim3(kBlock), 0, st, d, w[0], w[1], w[2],
+                           dcorr[0], dcorr[1], dcorr[2]);
+        constexpr int TX = kTileShapes[5].tx, TY = kTileShapes[5].ty, NL = kTileShapes[5].nl,
+                      DA = kTileShapes[5].d;
+        hipLaunchKernelGGL((op_kernel_ws<TX, TY, NL, DA, double, true, OP_REFINE>), dim3(g.blocks),
+                           dim3(tile_lanes(5)), 0, st, a);
+    } else {
+        hipError_t e = launch_op_tiled<OP_REFINE, double>(st, g, (unsigned)g.blocks, a);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(kFinThreads), 0, st, (int)FIN_STORE,
                        (const double*)partials, g.blocks, g.blocks, (Scalars*)nullptr, norm2,
                        (const double*)nullptr, 0);
-    const int nb = sweep_blocks(d.n, 4096);
-    hipLaunchKernelGGL(add_correction_kernel, dim3(nb), dim3(kBlock), 0, st, d, w[0], w[1], w[2],
-                       dcorr[0], dcorr[1], dcorr[2]);
+    if (!ws)
+        hipLaunchKernelGGL(add_correction_kernel, dim3(nb), dim3(kBlock), 0, st, d, w[0], w[1], w[2],
+                           dcorr[0], dcorr[1], dcorr[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_tuning_fill(hipStream_t st, double* p, size_t n)
+{
+    size_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(tuning_fill_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, p, n);
     return hipGetLastError();
 }
 

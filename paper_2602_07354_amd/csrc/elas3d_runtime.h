@@ -55,7 +55,6 @@ struct elas3d_ctx {
     // geometry of the residual and refinement sweeps of elas3d_solve (the
     // default, or the autotuned choice)
     e3d::OpGeom geom_apply{};
-    e3d::OpGeom geom_refine{};  // the refinement sweep (classic shapes only)
     int apply_tuned = 0;
     // direction+operator sweep and update grid per precision (0 FP64, 1 FP32),
     // the defaults or the autotuned choice

@@ -865,10 +865,12 @@ def test_sweep_with_many_phases_per_row_matches_oracle(E, orc, tile):
 
 def test_wave_specialised_operator_gives_the_true_residual(E, orc):
     """With the wave-specialised shape forced (autotune = 2), the residual
-    sweep (y = A w + b, the true residual of the stopping test) runs in its
-    wave-specialised form: the relative true residual the GPU reports equals
-    the oracle's ||A w + b|| / ||b|| of the returned w, in FP64 and in mixed
-    precision (whose refinement cycles each take one)."""
+    sweep (y = A w + b, the true residual of the stopping test) and the mixed
+    refinement sweep (w += d, then r = A w + b stored in FP32 with ||r||^2 in
+    FP64) run in their wave-specialised forms: the relative true residual the
+    GPU reports equals the oracle's ||A w + b|| / ||b|| of the returned w, in
+    FP64 and in mixed precision (whose refinement cycles each take one), and
+    mixed precision refined to 1e-12 reaches the FP64 oracle's solution."""
     ms = _small_poly((68, 29, 21), 131, grains=20)
     P = orc.Problem.from_micro(ms)
     b, _ = P.load(ms.strain[0])
@@ -882,6 +884,25 @@ def test_wave_specialised_operator_gives_the_true_residual(E, orc):
         rel = np.linalg.norm(P.apply(w) + b) / np.linalg.norm(b)
         assert 0 < rel <= 1e-6
         assert abs(info["relres_true"][0] - rel) <= 1e-6 * rel, (info["relres_true"][0], rel)
+    say("case: wave-specialised refinement sweep to 1e-12")
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    with E.Context.from_micro(ms, tile=5, autotune=2, precision=E.PREC_MIXED) as ctx:
+        st, info = ctx.solve(1e-12, 20000)
+        say("mixed", info["iters"][0], "inner iterations,", info["restarts"][0], "cycles, fallback",
+            info["fp64_fallback"][0])
+        assert st == E.OK and info["fp64_fallback"][0] == 0 and info["restarts"][0] >= 1
+        assert info["apply_tile"][:2] == [64, 6]
+        w = ctx.solution(0)
+        out = ctx.stress(0)
+    rel = np.linalg.norm(P.apply(w) + b) / np.linalg.norm(b)
+    # at 1e-12 the two residuals differ by rounding of order 1e-16 ||b||
+    assert rel <= 1.05e-12 and abs(info["relres_true"][0] - rel) <= 1e-2 * rel, (info["relres_true"][0], rel)
+    assert _rel(out["sigma"], so) <= 1e-8
+    active = np.any(np.abs(P.precond()).reshape(ms.n, 9) > 0, axis=1)
+    d1 = w[:, active] - w[:, active].mean(axis=1, keepdims=True)
+    d0 = ro["w"][:, active] - ro["w"][:, active].mean(axis=1, keepdims=True)
+    assert _rel(d1, d0) <= 1e-8
 
 
 def test_wave_specialised_shape_needs_whole_chunks(E):

@@ -48,7 +48,7 @@ def test_iteration_sweeps_use_no_scratch_and_fit_their_occupancy(tmp_path):
         assert v.get("vgpr_spill_count", 0) == 0, (name, v)
         assert v["vgpr_count"] <= 256, (name, v)
     ws = {n: v for n, v in sweeps.items() if "op_kernel_ws" in n}
-    assert len(ws) == 6, sorted(ws)  # fused: light and paying forms, FP64 and FP32; FP64 operator with and without add
+    assert len(ws) == 7, sorted(ws)  # fused: light and paying forms, FP64 and FP32; FP64 operator with and without add; refinement
     for name, v in ws.items():
         # 8 wavefronts (6 compute + 2 loaders) per CU: 2 per SIMD, at most 256 VGPRs each, and
         # the ring, row exchange and dictionary inside the 160 KB of LDS
