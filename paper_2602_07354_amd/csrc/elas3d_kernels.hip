@@ -75,13 +75,15 @@ __device__ __forceinline__ void adj8(R* v)
             }
 }
 
-// t = C[sup,sup] e for a support of the 6 Voigt components.
-template <int N, typename R>
+// t = C[sup,sup] e for a support of the 6 Voigt components; a row r whose
+// bit is set in ACC adds to the value t[r] holds on entry (its chain of FMAs
+// starts there).
+template <int N, unsigned ACC = 0u, typename R>
 __device__ __forceinline__ void contract(const R* Cu, const int (&sup)[N], const R* e, R* t)
 {
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        R acc = Cu[ut(sup[r], sup[0])] * e[0];
+        R acc = ((ACC >> r) & 1u) ? fma(Cu[ut(sup[r], sup[0])], e[0], t[r]) : Cu[ut(sup[r], sup[0])] * e[0];
 #pragma unroll
         for (int c = 1; c < N; ++c) acc = fma(Cu[ut(sup[r], sup[c])], e[c], acc);
         t[r] = acc;
@@ -95,21 +97,17 @@ enum { MX = 1, MY = 2, MXY = 3, MZ = 4, MXZ = 5, MYZ = 6, MXYZ = 7 };
 //   1/2 [ (1/16) e1^T C e1 + (1/48) sum_{X,Y,Z} e^T C e + (1/144) sum_{YZ,XZ,XY} e^T C e ]
 // (coefficient scales 1/4, 1/2, 1 of the transform times the L2 weights 1,
 // 1/12, 1/144 of the modes), so with Cs = C/16 the linear modes carry an
-// extra 1/3 and the bilinear ones 1/9.
-//
-// modal_core: H[c][mu] (slots MX..MXYZ, unscaled) -> G[c][mu] = dE/dH (slot 0
-// is not written and must be treated as 0).  H is scaled in place.
+// extra weight 1/3 and the bilinear ones 1/9.  Each class of modes reads and
+// writes its own slots of H and G (constant: MX, MY, MZ; linear: MXY, MXZ,
+// MYZ; bilinear: MXYZ), so the weights can be applied to G afterwards.
+constexpr double kLinearWeight = 1.0 / 3.0, kBilinearWeight = 1.0 / 9.0;
+
+// modal_core: H[c][mu] (slots MX..MXYZ) -> G[c][mu] = dE/dH before the mode
+// weights (slots MXY, MXZ, MYZ still to be multiplied by 1/3 and MXYZ by
+// 1/9; slot 0 is not written and must be treated as 0).
 template <typename R>
-__device__ __forceinline__ void modal_core(const R* Cs, R (&H)[3][8], R (&G)[3][8])
+__device__ __forceinline__ void modal_core(const R* Cs, const R (&H)[3][8], R (&G)[3][8])
 {
-    const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        H[c][MXY] *= third;
-        H[c][MXZ] *= third;
-        H[c][MYZ] *= third;
-        H[c][MXYZ] *= ninth;
-    }
     // constant mode: full 6-component strain
     {
         constexpr int sup[6] = {0, 1, 2, 3, 4, 5};
@@ -145,24 +143,30 @@ __device__ __forceinline__ void modal_core(const R* Cs, R (&H)[3][8], R (&G)[3][
         constexpr int sup[5] = {0, 2, 3, 4, 5};
         const R e[5] = {H[0][MXY], H[2][MYZ], H[1][MYZ], H[0][MYZ] + H[2][MXY], H[1][MXY]};
         R t[5];
-        contract<5>(Cs, sup, e, t);
-        G[0][MXY] += t[0];
+        t[0] = G[0][MXY];
+        t[4] = G[1][MXY];
+        contract<5, 0x11u>(Cs, sup, e, t);
+        G[0][MXY] = t[0];
         G[2][MYZ] = t[1];
         G[1][MYZ] = t[2];
         G[0][MYZ] = t[3];
         G[2][MXY] += t[3];
-        G[1][MXY] += t[4];
+        G[1][MXY] = t[4];
     }
     // Z mode: (xx, yy, yz, xz, xy)
     {
         constexpr int sup[5] = {0, 1, 3, 4, 5};
         const R e[5] = {H[0][MXZ], H[1][MYZ], H[2][MYZ], H[2][MXZ], H[0][MYZ] + H[1][MXZ]};
         R t[5];
-        contract<5>(Cs, sup, e, t);
-        G[0][MXZ] += t[0];
-        G[1][MYZ] += t[1];
-        G[2][MYZ] += t[2];
-        G[2][MXZ] += t[3];
+        t[0] = G[0][MXZ];
+        t[1] = G[1][MYZ];
+        t[2] = G[2][MYZ];
+        t[3] = G[2][MXZ];
+        contract<5, 0x0Fu>(Cs, sup, e, t);
+        G[0][MXZ] = t[0];
+        G[1][MYZ] = t[1];
+        G[2][MYZ] = t[2];
+        G[2][MXZ] = t[3];
         G[0][MYZ] += t[4];
         G[1][MXZ] += t[4];
     }
@@ -180,21 +184,21 @@ __device__ __forceinline__ void modal_core(const R* Cs, R (&H)[3][8], R (&G)[3][
     {
         constexpr int sup[3] = {1, 3, 5};
         const R e[3] = {H[1][MXYZ], H[2][MXYZ], H[0][MXYZ]};
-        R t[3];
-        contract<3>(Cs, sup, e, t);
-        G[1][MXYZ] += t[0];
-        G[2][MXYZ] += t[1];
-        G[0][MXYZ] += t[2];
+        R t[3] = {G[1][MXYZ], G[2][MXYZ], G[0][MXYZ]};
+        contract<3, 0x7u>(Cs, sup, e, t);
+        G[1][MXYZ] = t[0];
+        G[2][MXYZ] = t[1];
+        G[0][MXYZ] = t[2];
     }
     // XY mode: (zz, yz, xz)
     {
         constexpr int sup[3] = {2, 3, 4};
         const R e[3] = {H[2][MXYZ], H[1][MXYZ], H[0][MXYZ]};
-        R t[3];
-        contract<3>(Cs, sup, e, t);
-        G[2][MXYZ] += t[0];
-        G[1][MXYZ] += t[1];
-        G[0][MXYZ] += t[2];
+        R t[3] = {G[2][MXYZ], G[1][MXYZ], G[0][MXYZ]};
+        contract<3, 0x7u>(Cs, sup, e, t);
+        G[2][MXYZ] = t[0];
+        G[1][MXYZ] = t[1];
+        G[0][MXYZ] = t[2];
     }
 }
 
@@ -208,9 +212,14 @@ __device__ __forceinline__ void element_force(const R* Cs, R (&u)[3][8], R (&f)[
     fwd8(u[2]);
     R g[3][8];
     modal_core(Cs, u, g);
+    const R lw = R(kLinearWeight), bw = R(kBilinearWeight);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         g[c][0] = R(0);
+        g[c][MXY] *= lw;
+        g[c][MXZ] *= lw;
+        g[c][MYZ] *= lw;
+        g[c][MXYZ] *= bw;
         adj8(g[c]);
 #pragma unroll
         for (int a = 0; a < 8; ++a) f[c][a] = g[c][a];
@@ -259,17 +268,19 @@ __device__ __forceinline__ void element_force_faces(const R* Cs, const R (&L)[3]
         H[c][MXYZ] = U[c][3] - L[c][3];
     }
     modal_core(Cs, H, G);
+    const R lw = R(kLinearWeight), bw = R(kBilinearWeight);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        // adjoint of the z stage (slot 0 of G is zero)
+        // adjoint of the z stage (slot 0 of G is zero), with the mode weights
         FL[c][0] = -G[c][MZ];
         FU[c][0] = G[c][MZ];
-        FL[c][1] = G[c][MX] - G[c][MXZ];
-        FU[c][1] = G[c][MX] + G[c][MXZ];
-        FL[c][2] = G[c][MY] - G[c][MYZ];
-        FU[c][2] = G[c][MY] + G[c][MYZ];
-        FL[c][3] = G[c][MXY] - G[c][MXYZ];
-        FU[c][3] = G[c][MXY] + G[c][MXYZ];
+        FL[c][1] = fma(-lw, G[c][MXZ], G[c][MX]);
+        FU[c][1] = fma(lw, G[c][MXZ], G[c][MX]);
+        FL[c][2] = fma(-lw, G[c][MYZ], G[c][MY]);
+        FU[c][2] = fma(lw, G[c][MYZ], G[c][MY]);
+        const R b3 = bw * G[c][MXYZ];
+        FL[c][3] = fma(lw, G[c][MXY], -b3);
+        FU[c][3] = fma(lw, G[c][MXY], b3);
     }
 }
 
@@ -1381,6 +1392,21 @@ __device__ __forceinline__ void plane_store(float v, __amdgpu_buffer_rsrc_t r, i
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
 }
 
+// Value of the next lane (lane + 1) of the wavefront, through a DPP
+// wavefront shift by one lane (a VALU move, no LDS round trip like a lane
+// permute); lane 63 gets 0.
+__device__ __forceinline__ float next_lane(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double next_lane(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x130, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x130, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Copy duties of one loader wavefront in the wave-specialised sweep: the
 // source of each of its PER_W direct-to-LDS instructions of a ring slot
 // (instruction j = cw + NL i of the slot layout above), the plane and layer
@@ -1640,7 +1666,10 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
         }
         R hprev[3] = {R(0), R(0), R(0)};
         R mine_d[3] = {R(0), R(0), R(0)}, hout_d[3] = {R(0), R(0), R(0)};
-        for (int s = 0; s < nsteps; ++s) {
+        // one plane step; the loop below runs two per trip, so the values a
+        // step hands to the next (lo, carry and the delayed outputs) change
+        // registers between the two instead of being copied back every step
+        auto step = [&](const int s) {
             const int b = s & 1;
             const int ku = k0 + s;
             __syncthreads();  // plane ku in slot (s + 1) % D; forces of step s - 1 in SF[b ^ 1]
@@ -1687,8 +1716,8 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
                     for (int q = 0; q < 4; ++q) F[q] = carry[c][q] + FL[c][q];
                     face_adj(F, v);
                     // own node: v3 + the x neighbour's v2; row below: v1 + the x neighbour's v0
-                    mine[c] = v[3] + __shfl_down(v[2], 1);
-                    SF[b][c][tid] = v[1] + __shfl_down(v[0], 1);
+                    mine[c] = v[3] + next_lane(v[2]);
+                    SF[b][c][tid] = v[1] + next_lane(v[0]);
                 }
             }
             const R* wb = reinterpret_cast<const R*>(sh.ring[slot] + C::W_OFF);
@@ -1721,7 +1750,13 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
                 hout_d[c] = hprev[c];
                 hprev[c] = ov[c];
             }
+        };
+        int s = 0;
+        for (; s + 1 < nsteps; s += 2) {
+            step(s);
+            step(s + 1);
         }
+        if (s < nsteps) step(s);
         __syncthreads();
         if (nsteps > 1 && out_ok) {
             const int b = (nsteps - 1) & 1;

@@ -630,6 +630,20 @@ def test_fixed_z_chunking_matches_oracle(E, orc):
             assert st == E.OK and info["op_tile"] == [64, 8, min(zc, 21)]
             assert abs(info["iters"][0] - ro["iters"]) <= 2
             assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
+    # the wave-specialised sweep takes its plane steps two per loop trip:
+    # chunks of an odd and an even number of steps (zchunk + 1), and a grid
+    # whose last chunk is shorter than the others
+    say("case: fixed z chunking, wave-specialised")
+    ms = _small_poly((38, 29, 21), 47, grains=15)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    for zc in (1, 2, 4, 21):
+        with E.Context.from_micro(ms, tile=5, zchunk=zc, autotune=2) as ctx:
+            st, info = ctx.solve(1e-12, 20000)
+            assert st == E.OK and info["op_tile"] == [64, 6, zc] and info["apply_tile"] == [64, 6, zc]
+            assert abs(info["iters"][0] - ro["iters"]) <= 2
+            assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
 
 
 def test_update_sweep_forms_are_bitwise_equal(E, orc):
