@@ -1337,12 +1337,20 @@ struct WsCfg {
     static constexpr int PH_OFF = NIN * 64 * 16;    // byte offset of the phase ranks in a slot
     static constexpr int W_OFF = (NIN + NIP) * 64 * 16;  // byte offset of w / the older direction
     // dictionary rows: kCoefStride elements each, in 16-byte chunks
-    static constexpr int CHR = kCoefStride * (int)sizeof(T) / 16;
-    static constexpr int NCI = kWsDict * CHR / 64;  // loader instructions of the rows
+    // dictionary rows in LDS: RS elements apart (FP64 22, FP32 28), so that
+    // the 16-byte reads of lanes on rows of different phases fall on
+    // different banks unless the rows' ranks differ by a multiple of 8; CHR
+    // chunks per row in LDS, of which the first CHG hold the table's
+    static constexpr int RS = sizeof(T) == 8 ? 22 : 28;
+    static constexpr int CHR = RS * (int)sizeof(T) / 16;
+    static constexpr int CHG = kCoefStride * (int)sizeof(T) / 16;
+    static constexpr int NCI = (kWsDict * CHR + 63) / 64;  // loader instructions of the rows
+    static constexpr int CCB = NCI * 1024;                 // their bytes in LDS
     static_assert(TX == 64, "one wavefront per row of the tile");
     static_assert(NT % 64 == 0, "whole wavefronts");
     static_assert(LAYER % 16 == 0 && QP <= 64, "a layer of ranks in one instruction");
-    static_assert(kCoefStride * sizeof(T) % 16 == 0 && kWsDict * CHR % 64 == 0, "whole dictionary instructions");
+    static_assert(kCoefStride * sizeof(T) % 16 == 0 && RS * sizeof(T) % 16 == 0 && RS >= 21,
+                  "rows of whole 16-byte chunks holding the 21 coefficients");
     static_assert(kWsDict <= 256, "ranks are bytes");
     static_assert(NL >= 1 && D >= 3, "loader wavefronts and a ring of at least three planes");
     // vmcnt that lets D - 2 planes of a loader wavefront stay in flight
@@ -1355,7 +1363,7 @@ struct OpSharedWS {
     using C = WsCfg<TX, TY, NL, D, T, WPAY, MODE>;
     alignas(16) char ring[D][C::SLOT];
     T sf[2][3][C::NT];
-    alignas(16) T cc[kWsDict][kCoefStride];  // the dictionary's stiffness rows
+    alignas(16) char cc[C::CCB];  // the dictionary's stiffness rows, C::RS elements apart
 };
 
 // s_waitcnt on the vector-memory counter only (gfx9 encoding: vmcnt in bits
@@ -1495,8 +1503,10 @@ struct WsCopier {
         for (int m = 0; m < (C::NCI + C::NLOAD - 1) / C::NLOAD; ++m) {
             const int i = cw + C::NLOAD * m;
             if (i < C::NCI) {
+                // chunk g of the LDS rows; the tail of the last instruction
+                // and the padding chunks of a row copy a chunk of the row
                 const int g = 64 * i + lane;
-                const int r = g / C::CHR, q = g - r * C::CHR;
+                const int r = min(g / C::CHR, kWsDict - 1), q = min(g - r * C::CHR, C::CHG - 1);
                 const T* row = coef + (size_t)dict[r] * kCoefStride + q * C::CH;
                 __builtin_amdgcn_global_load_lds((const void*)row, (void*)(ccb + (size_t)i * 1024), 16, 0, 0);
             }
@@ -1583,7 +1593,7 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
         // ---------------------------------------------------------- loader
         WsCopier<C, T> cp;
         cp.init(a, nf, of, lb, (tid - NT) >> 6, lane, xa, xw, j0, k0, nsteps);
-        cp.issue_dict(reinterpret_cast<char*>(&sh.cc[0][0]));
+        cp.issue_dict(sh.cc);
 #pragma unroll
         for (int u = 0; u < D; ++u) cp.issue(sh.ring[u % D], u);
         wait_vmcnt<C::WAIT0>();  // plane 0 landed
@@ -1650,7 +1660,7 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
             return (int)reinterpret_cast<const uint8_t*>(sh.ring[slot] + C::PH_OFF)[eph];
         };
         auto read_coef = [&](int rank, R (&Cx)[21]) {
-            const R* row = sh.cc[rank];
+            const R* row = reinterpret_cast<const R*>(sh.cc) + rank * C::RS;
 #pragma unroll
             for (int q = 0; q < 21; ++q) Cx[q] = row[q];
         };
