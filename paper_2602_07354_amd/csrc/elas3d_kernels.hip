@@ -1674,6 +1674,11 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
             R ov[3], oh[3];
             read_plane(0, lo, ov, oh);
         }
+        // a step reads the next step's coefficients when it ends (the
+        // dictionary rows never change), so a wavefront that reaches the
+        // barrier early has them read while the others still compute
+        R Cn[21];
+        read_coef(rank, Cn);
         R hprev[3] = {R(0), R(0), R(0)};
         R mine_d[3] = {R(0), R(0), R(0)}, hout_d[3] = {R(0), R(0), R(0)};
         // one plane step; the loop below runs two per trip, so the values a
@@ -1711,7 +1716,8 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
             }
             const int slot = (s + 1) % D;
             R Cu[21];
-            read_coef(rank, Cu);
+#pragma unroll
+            for (int q = 0; q < 21; ++q) Cu[q] = Cn[q];
             rank = slot_rank(slot);
             R up[3][4], ov[3], oh[3];
             read_plane(slot, up, ov, oh);
@@ -1760,6 +1766,7 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
                 hout_d[c] = hprev[c];
                 hprev[c] = ov[c];
             }
+            read_coef(rank, Cn);
         };
         int s = 0;
         for (; s + 1 < nsteps; s += 2) {
