@@ -253,7 +253,7 @@ def _oracle_sample(workload: str, edge: int):
     return generate.workload(workload, scale=edge)
 
 
-def _oracle_rate(P, strain, b, minv, iters: int, target_s: float):
+def _oracle_rate(P, strain, b, minv, iters: int, target_s: float, label: str = "oracle"):
     """Seconds per PCG iteration of the oracle: after one untimed run (cold
     caches), the time of a run of 1 + k iterations minus that of a run of 1
     (both pay the same start-up preconditioner apply, closing true residual
@@ -266,6 +266,8 @@ def _oracle_rate(P, strain, b, minv, iters: int, target_s: float):
     t_one = time.perf_counter() - t0
     if iters <= 0:  # about target_s of iterations
         iters = int(min(50, max(2, round(target_s / max(1e-3, t_one - 0.5 * t_warm)))))
+    print(f"# {label}: a run of 1 iteration took {t_one:.2f} s; timing a run of {1 + iters}", file=sys.stderr,
+          flush=True)
     t0 = time.perf_counter()
     r = P.solve(strain, tol=0.0, maxit=1 + iters, b=b, minv=minv)
     t_k = time.perf_counter() - t0
@@ -301,7 +303,9 @@ def cpu_baseline(workload: str, edge: int, iters: int, n_full: int, gpu_iters, t
         b, _ = P.load(strain)
         minv = P.precond()
         t_setup = time.perf_counter() - t0
-        s_it, k, spent = _oracle_rate(P, strain, b, minv, iters, scale * (4.0 if name == "threaded" else 8.0))
+        print(f"# oracle {name} ({nt} threads) on {ms.shape}: setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+        s_it, k, spent = _oracle_rate(P, strain, b, minv, iters, scale * (4.0 if name == "threaded" else 8.0),
+                                      f"oracle {name}")
         leg = {"value": round(3.0 * ms.n / s_it / 1e9, 5), "threads": nt, "iters": k,
                "s_per_iter": round(s_it, 4), "setup_s": round(t_setup, 2), "timed_s": round(spent, 2)}
         if gpu_iters:
