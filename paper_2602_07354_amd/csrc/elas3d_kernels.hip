@@ -916,6 +916,25 @@ __device__ __forceinline__ int xcd_map(const int b, const int nb)
 
 __device__ __forceinline__ int xcd_local_block() { return xcd_map(blockIdx.x, gridDim.x); }
 
+// The wave-specialised sweep runs one workgroup per CU, so each XCD holds a
+// band of kCusPerXcd consecutive tiles at a time.  This bijection hands the
+// XCDs adjacent bands at the same time (groups of kXcds bands of W logical
+// workgroups; the tail of nb that fills no whole group keeps the
+// contiguous map): the halo rows two bands share are then read by two XCDs
+// at about the same time, and the second read is served by the memory-side
+// cache shared by all XCDs instead of HBM.
+constexpr int kCusPerXcd = 32;  // MI355X: 256 CUs in 8 XCDs
+__device__ __forceinline__ int xcd_band_map(const int b, const int nb, const int W)
+{
+    if (!E3D_XCD_REMAP || nb < kXcds) return b;
+    const int full = nb / (kXcds * W) * (kXcds * W);
+    if (b < full) {
+        const int x = b % kXcds, j = b / kXcds;
+        return (j / W) * (kXcds * W) + x * W + (j % W);
+    }
+    return full + xcd_map(b - full, nb - full);
+}
+
 // Operator sweep modes.
 enum OpMode { OP_APPLY = 0, OP_FUSED = 1, OP_REFINE = 2 };
 
@@ -1802,7 +1821,7 @@ template <int TX, int TY, int NL, int D, typename T, bool WPAY, int MODE>
 __global__ void __launch_bounds__(TX* TY + 64 * NL, 1) op_kernel_ws(OpArgs<T> a)
 {
     __shared__ OpSharedWS<TX, TY, NL, D, T, WPAY, MODE> sh;
-    op_body_ws<TX, TY, NL, D, T, WPAY, MODE>(a, xcd_local_block(), gridDim.x, sh);
+    op_body_ws<TX, TY, NL, D, T, WPAY, MODE>(a, xcd_band_map(blockIdx.x, gridDim.x, kCusPerXcd), gridDim.x, sh);
 }
 
 // Copy of a work-list entry held in scalar registers: the entry is the same

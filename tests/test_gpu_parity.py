@@ -789,6 +789,28 @@ def test_wave_specialised_sweep_matches_oracle(E, orc, tile):
                 assert _rel(ctx.solution(r), ro2["w"]) <= 1e-11, (k, r)
 
 
+def test_wave_specialised_sweep_on_a_grid_of_several_workgroup_groups(E, orc):
+    """A grid with more workgroups than the XCDs hold at once (432 at
+    4-plane chunks: one whole group of 8 x 32 and a tail), so that both parts
+    of the workgroup-to-tile map run: the iterates after k = 1..3 iterations
+    equal the oracle's, for the fused sweep and the residual sweep."""
+    shape = (128, 60, 48)
+    ms = _small_poly(shape, 83, grains=40)
+    P = orc.Problem.from_micro(ms)
+    b, _ = P.load(ms.strain[0])
+    for k in (1, 2, 3):
+        say("case: wave-specialised sweep, several workgroup groups, k =", k)
+        ro = P.solve(ms.strain[0], tol=1e-30, maxit=k)
+        with E.Context.from_micro(ms, tile=5, zchunk=4, autotune=2) as ctx:
+            st, info = ctx.solve(1e-30, k)
+            assert st == E.NOT_CONVERGED and info["iters"][0] == k
+            assert info["op_tile"] == [64, 6, 4] and info["apply_tile"] == [64, 6, 4]
+            w = ctx.solution(0)
+            assert _rel(w, ro["w"]) <= 1e-11, k
+            rel = np.linalg.norm(P.apply(w) + b) / np.linalg.norm(b)
+            assert abs(info["relres_true"][0] - rel) <= 1e-9 * rel, (info["relres_true"][0], rel)
+
+
 def _many_phase_grid(shape, nphase, seed):
     """Every voxel its own random draw among nphase rotated 316L crystals: a
     64-voxel row meets far more distinct phases than a grain structure does."""
