@@ -122,7 +122,10 @@ typedef struct elas3d_options {
                                   workgroup box may hold more than 96
                                   distinct phases, else EBADARG; setup builds
                                   a phase dictionary per workgroup, about
-                                  1.3 bytes per voxel)                        */
+                                  1.3 bytes per voxel); 6 = 64x8 + two loader
+                                  wavefronts, the same for the FP32 sweep of
+                                  mixed precision only (EBADARG in FP64; the
+                                  FP64 sweeps of that context take 64x8)     */
     int32_t zchunk;            /* z planes per workgroup of that sweep when not
                                   autotuned; 0 = automatic (about 4096 workgroups);
                                   values above nz mean nz                            */

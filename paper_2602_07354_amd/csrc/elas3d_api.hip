@@ -201,6 +201,10 @@ int validate_setup(int32_t nx, int32_t ny, int32_t nz, const int32_t* phase, int
         // chunks in every precision the context sweeps in
         const Dims d{nx, ny, nz, (int)n};
         const int elem = o->precision == ELAS3D_PREC_MIXED ? 4 : 8;
+        if (o->autotune != 1 && !e3d::ws_elem_ok(o->tile, elem))
+            return fail(nullptr, ELAS3D_EBADARG,
+                        "options.tile " + std::to_string(o->tile) +
+                            " is a shape of the FP32 sweep only (mixed precision)");
         if (o->autotune != 1 && !e3d::ws_supported(d, o->tile, elem))
             return fail(nullptr, ELAS3D_EBADARG,
                         "options.tile " + std::to_string(o->tile) + " needs nx to be a multiple of " +
@@ -486,9 +490,10 @@ int autotune_apply(elas3d_ctx* c)
 {
     const Dims& d = c->d;
     if (c->opt.autotune == 2) {
-        // the forced shape (its phase dictionaries were built at setup)
-        c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, c->opt.tile);
-        if (e3d::is_ws(c->opt.tile)) {
+        // the forced shape (its phase dictionaries were built at setup; the
+        // FP32-only shape leaves these FP64 sweeps on 64x8 lanes)
+        c->geom_apply = e3d::op_geometry(d, c->opt.zchunk, e3d::ws_elem_ok(c->opt.tile, 8) ? c->opt.tile : 4);
+        if (e3d::is_ws(c->geom_apply.tile)) {
             bool fits = true;
             int rc = ws_prepare(c, c->geom_apply, fits);
             if (rc) return rc;
@@ -1123,7 +1128,9 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     c->geom = e3d::op_geometry(c->d, 0);
     c->geom_apply = c->geom;
     for (int q = 0; q < 2; ++q) {
-        c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, opt.tile);
+        // a forced FP32-only shape leaves the FP64 sweep (the fallback of a
+        // stalled refinement) on 64x8 lanes
+        c->geom_sweep[q] = e3d::op_geometry(c->d, opt.zchunk, e3d::ws_elem_ok(opt.tile, q ? 4 : 8) ? opt.tile : 4);
         c->upd_blocks[q] = opt.update_blocks > 0 ? opt.update_blocks : default_update_blocks(c->d.n);
         c->upd_nt[q] = opt.update_nontemporal;
     }
@@ -1242,9 +1249,10 @@ int elas3d_setup(elas3d_ctx** out, int32_t nx, int32_t ny, int32_t nz, const int
     // (host input arrays must not be read after return)
     SETUPCHK(hipStreamSynchronize(c->stream));
     if (opt.autotune != 1 && e3d::is_ws(opt.tile)) {
-        // the forced wave-specialised shape: its phase dictionaries
+        // the forced wave-specialised shape: its phase dictionaries (the
+        // sweep of the precision that runs it)
         bool fits = true;
-        int rc2 = ws_prepare(c, c->geom_sweep[0], fits);
+        int rc2 = ws_prepare(c, c->geom_sweep[e3d::is_ws(c->geom_sweep[0].tile) ? 0 : 1], fits);
         if (!rc2 && !fits) {
             free_ctx(c);
             return fail(nullptr, ELAS3D_EBADARG,

@@ -140,23 +140,33 @@ struct Tables {
 // element, the phase's rank in it.  It needs rows of whole 16-byte chunks of
 // nodes, 16-byte aligned fields and at most kWsDict distinct phases in every
 // workgroup box (ws_supported, launch_ws_dictionary).
-constexpr int kNumTiles = 6;
+// Shape 6 (64 x 8 compute lanes + 2 loaders) exists for the FP32 sweep only:
+// its ten wavefronts put two computing ones on every SIMD, and in FP64 its
+// ring and row exchange would not fit the LDS of a CU.
+constexpr int kNumTiles = 7;
 struct TileShape {
     int tx, ty;
     int nl, d;  // d > 0: wave-specialised, with nl loader wavefronts and a ring of d planes
+    int elem;   // wave-specialised: 0 for both precisions, 4 for the FP32 sweep only
 };
-constexpr TileShape kTileShapes[kNumTiles] = {{32, 8, 0, 0}, {16, 16, 0, 0}, {64, 4, 0, 0},
-                                              {32, 16, 0, 0}, {64, 8, 0, 0}, {64, 6, 2, 4}};
+constexpr TileShape kTileShapes[kNumTiles] = {{32, 8, 0, 0, 0},  {16, 16, 0, 0, 0}, {64, 4, 0, 0, 0},
+                                              {32, 16, 0, 0, 0}, {64, 8, 0, 0, 0},  {64, 6, 2, 4, 0},
+                                              {64, 8, 2, 4, 4}};
 // True for the wave-specialised shapes (fused sweep only).
 constexpr bool is_ws(int t) { return kTileShapes[t].d > 0; }
 // Lanes of a workgroup of shape t.
 constexpr int tile_lanes(int t) { return kTileShapes[t].tx * kTileShapes[t].ty + 64 * kTileShapes[t].nl; }
+// True when shape t exists for elements of elem_bytes (constexpr: selects
+// the kernels that are built).
+constexpr bool ws_elem_ok(int t, int elem_bytes) { return kTileShapes[t].elem == 0 || kTileShapes[t].elem == elem_bytes; }
 // True when the wave-specialised shape t can run on grid d with elements of
-// elem_bytes: rows of whole 16-byte chunks and planes under 2^27 voxels (its
-// stores address a plane by a 32-bit byte offset).
+// elem_bytes: a shape for that precision, rows of whole 16-byte chunks and
+// planes under 2^27 voxels (its stores address a plane by a 32-bit byte
+// offset).
 inline bool ws_supported(const Dims& d, int t, int elem_bytes)
 {
-    return !is_ws(t) || (d.nx % (16 / elem_bytes) == 0 && (long long)d.nx * d.ny < (1ll << 27));
+    return !is_ws(t) || (ws_elem_ok(t, elem_bytes) && d.nx % (16 / elem_bytes) == 0 &&
+                         (long long)d.nx * d.ny < (1ll << 27));
 }
 
 // Kernel launch geometry of the tiled operator sweep.

@@ -1820,6 +1820,8 @@ __device__ __forceinline__ void op_body_ws(OpArgs<T> a, const int lbr, const int
 template <int TX, int TY, int NL, int D, typename T, bool WPAY, int MODE>
 __global__ void __launch_bounds__(TX* TY + 64 * NL, 1) op_kernel_ws(OpArgs<T> a)
 {
+    static_assert(sizeof(OpSharedWS<TX, TY, NL, D, T, WPAY, MODE>) + 64 * 8 <= 160 * 1024,
+                  "ring, row exchange, dictionary and reduction within a CU's LDS");
     __shared__ OpSharedWS<TX, TY, NL, D, T, WPAY, MODE> sh;
     op_body_ws<TX, TY, NL, D, T, WPAY, MODE>(a, xcd_band_map(blockIdx.x, gridDim.x, kCusPerXcd), gridDim.x, sh);
 }
@@ -1914,11 +1916,13 @@ constexpr int kTX = kTileShapes[0].tx, kTY = kTileShapes[0].ty;
 
 // Ring depth of the wave-specialised sweep: the shape's d planes in FP64,
 // two more for the FP32 sweep (half the bytes per plane); one less for the
-// paying form, whose planes also carry w and the older direction.
+// paying form, whose planes also carry w and the older direction, and one
+// less again for the 8-row shape, whose paying ring of 5 would not fit the
+// LDS (op_kernel_ws checks the total).
 template <typename T, bool WPAY>
 constexpr int ws_depth(int t)
 {
-    return kTileShapes[t].d + (sizeof(T) == 4 ? 2 : 0) - (WPAY ? 1 : 0);
+    return kTileShapes[t].d + (sizeof(T) == 4 ? 2 : 0) - (WPAY ? (kTileShapes[t].ty > 6 ? 2 : 1) : 0);
 }
 
 // Launch of the operator sweep with the workgroup shape of g.tile (the
@@ -1933,7 +1937,7 @@ hipError_t launch_op_tiled(hipStream_t st, const OpGeom& g, unsigned grid, const
         break;
 #define E3D_WS_CASE(I)                                                                        \
     case I:                                                                                   \
-        if constexpr (MODE == OP_FUSED) {                                                     \
+        if constexpr (MODE == OP_FUSED && ws_elem_ok(I, sizeof(T))) {                         \
             hipLaunchKernelGGL((op_kernel_ws<kTileShapes[I].tx, kTileShapes[I].ty, kTileShapes[I].nl, \
                                              ws_depth<T, false>(I), T, false, OP_FUSED>),      \
                                dim3(grid), dim3(tile_lanes(I)), 0, st, a);                    \
@@ -1944,7 +1948,7 @@ hipError_t launch_op_tiled(hipStream_t st, const OpGeom& g, unsigned grid, const
             return hipErrorInvalidValue;                                                      \
         }                                                                                     \
         break;
-    static_assert(kNumTiles == 6, "a launch case per shape");
+    static_assert(kNumTiles == 7, "a launch case per shape");
     switch (g.tile) {
         E3D_OP_CASE(0)
         E3D_OP_CASE(1)
@@ -1952,6 +1956,7 @@ hipError_t launch_op_tiled(hipStream_t st, const OpGeom& g, unsigned grid, const
         E3D_OP_CASE(3)
         E3D_OP_CASE(4)
         E3D_WS_CASE(5)
+        E3D_WS_CASE(6)
         default:
             return hipErrorInvalidValue;
     }
@@ -2265,10 +2270,15 @@ hipError_t launch_ws_dictionary(hipStream_t st, const Dims& d, const OpGeom& g, 
                                 int32_t* dict, uint8_t* map, int* maxcount)
 {
     if (g.tile < 0 || g.tile >= kNumTiles || !is_ws(g.tile) || g.blocks <= 0) return hipErrorInvalidValue;
-    static_assert(kNumTiles == 6 && is_ws(5) && kTileShapes[5].tx == 64 && kTileShapes[5].ty == 6,
-                  "the one wave-specialised shape");
-    hipLaunchKernelGGL((ws_dict_kernel<64, 6>), dim3(g.blocks), dim3(256), 0, st, d, g.tiles_x, g.tiles_y,
-                       g.kz, phase, dict, map, maxcount);
+    static_assert(kNumTiles == 7 && kTileShapes[5].tx == 64 && kTileShapes[5].ty == 6 &&
+                      kTileShapes[6].tx == 64 && kTileShapes[6].ty == 8,
+                  "a dictionary kernel per wave-specialised shape");
+    if (g.tile == 6)
+        hipLaunchKernelGGL((ws_dict_kernel<64, 8>), dim3(g.blocks), dim3(256), 0, st, d, g.tiles_x, g.tiles_y,
+                           g.kz, phase, dict, map, maxcount);
+    else
+        hipLaunchKernelGGL((ws_dict_kernel<64, 6>), dim3(g.blocks), dim3(256), 0, st, d, g.tiles_x, g.tiles_y,
+                           g.kz, phase, dict, map, maxcount);
     return hipGetLastError();
 }
 
@@ -2635,7 +2645,7 @@ hipError_t launch_apply(hipStream_t st, const Dims& d, const OpGeom& g, const in
     a.wsmap = t.ws.map;
     a.nrhs = 1;
     if (is_ws(g.tile)) {
-        static_assert(kNumTiles == 6 && is_ws(5), "the one wave-specialised shape");
+        static_assert(kNumTiles == 7 && is_ws(5) && ws_elem_ok(5, 8), "the FP64 wave-specialised shape");
         constexpr int TX = kTileShapes[5].tx, TY = kTileShapes[5].ty, NL = kTileShapes[5].nl,
                       DA = kTileShapes[5].d;  // the operator's ring carries x alone: one depth serves both forms
         if (add)

@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EBADARG", "ENOMEM", "EDEVICE", "EORDER",
     "PREC_FP64", "PREC_MIXED", "CONV_RESIDUAL", "CONV_PAPER", "PRECOND_BLOCK_JACOBI",
-    "PRECOND_NONE", "TILE_SHAPES", "WS_TILES", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
+    "PRECOND_NONE", "TILE_SHAPES", "WS_TILES", "WS_FP32_ONLY", "Options", "Info", "Elas3dError", "lib", "LIB_PATH", "options_init",
     "setup", "solve", "stress", "apply", "get_load", "get_precond", "get_solution",
     "device_bytes", "destroy", "last_error", "version", "Context", "EXPORTS", "von_mises",
     "generate_grains", "generate_grains_static", "carve_pores", "PORE_STRIDE", "Group", "stream_bandwidth",
@@ -34,10 +34,12 @@ CONV_RESIDUAL, CONV_PAPER = 0, 1
 PRECOND_BLOCK_JACOBI, PRECOND_NONE = 0, 1
 MAX_RHS = 6
 # workgroup shapes (compute lanes in x, y) of the direction+operator sweep, by
-# options.tile; 5 adds two loader wavefronts (nx a multiple of 2, of 4 in mixed
-# precision; at most 96 distinct phases per workgroup box)
-TILE_SHAPES = ((32, 8), (16, 16), (64, 4), (32, 16), (64, 8), (64, 6))
-WS_TILES = (5,)
+# options.tile; 5 and 6 add two loader wavefronts (nx a multiple of 2, of 4 in
+# mixed precision; at most 96 distinct phases per workgroup box), and 6 is for
+# the FP32 sweep of mixed precision only
+TILE_SHAPES = ((32, 8), (16, 16), (64, 4), (32, 16), (64, 8), (64, 6), (64, 8))
+WS_TILES = (5, 6)
+WS_FP32_ONLY = (6,)  # wave-specialised shapes of the FP32 sweep only
 # doubles per pore of elas3d_carve_pores: centre 3, semi-axes 3, R row-major 9
 PORE_STRIDE = 15
 

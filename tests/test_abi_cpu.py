@@ -102,7 +102,7 @@ def test_setup_rejects_bad_options(E):
     shape, phase, C, strain = _good()
     for kw in ({"precision": 7}, {"convergence": 3}, {"preconditioner": -1},
                {"poll_interval": -2}, {"hbm_budget_bytes": -1.0}, {"inner_tol": 2.0},
-               {"tile": 6}, {"tile": -1}, {"zchunk": -3}, {"update_blocks": -1},
+               {"tile": 7}, {"tile": -1}, {"zchunk": -3}, {"update_blocks": -1},
                {"update_blocks": 32769}, {"update_nontemporal": 2}):
         with pytest.raises(E.Elas3dError) as ei:
             E.setup(shape, phase, C, strain, E.options_init(**kw))
@@ -121,6 +121,18 @@ def test_setup_rejects_a_forced_shape_the_grid_cannot_run(E):
         with pytest.raises(E.Elas3dError) as ei:
             E.setup(shape, phase, C, strain, E.options_init(**kw))
         assert ei.value.code == E.EBADARG and "multiple" in str(ei.value)
+
+
+def test_setup_rejects_the_fp32_only_shape_in_fp64(E):
+    """Shape 6 (64x8 lanes + two loaders) is built for the FP32 sweep only:
+    forcing it on an FP64 context is refused before any device call."""
+    from paper_2602_07354_amd import synth
+    C = synth.isotropic_stiffness(200, .3)[None]
+    strain = np.array([[1e-3, 0, 0, 0, 0, 0]])
+    assert E.WS_FP32_ONLY == (6,) and 6 in E.WS_TILES
+    with pytest.raises(E.Elas3dError) as ei:
+        E.setup((8, 4, 4), np.zeros(128, np.int32), C, strain, E.options_init(tile=6))
+    assert ei.value.code == E.EBADARG and "FP32 sweep only" in str(ei.value)
 
 
 def test_null_context_calls_are_rejected(E):

@@ -644,6 +644,18 @@ def test_fixed_z_chunking_matches_oracle(E, orc):
             assert st == E.OK and info["op_tile"] == [64, 6, zc] and info["apply_tile"] == [64, 6, zc]
             assert abs(info["iters"][0] - ro["iters"]) <= 2
             assert _rel(ctx.stress(0)["sigma"], so) <= 1e-8
+    # the FP32-only 64x8 shape in mixed precision (its FP64 sweeps on 64x8 lanes)
+    ms = _small_poly((40, 29, 21), 47, grains=15)
+    P = orc.Problem.from_micro(ms)
+    ro = P.solve(ms.strain[0], tol=1e-12)
+    so, _ = P.stress(ms.strain[0], ro["w"])
+    for zc in (1, 2, 21):
+        say("case: fixed z chunking, FP32 64x8 shape, zchunk", zc)
+        with E.Context.from_micro(ms, tile=6, zchunk=zc, autotune=2, precision=E.PREC_MIXED) as ctx:
+            st, info = ctx.solve(1e-10, 20000)
+            assert st == E.OK and info["op_tile"] == [64, 8, zc] and info["op_shape"] == 6
+            assert info["apply_tile"] == [64, 8, zc]
+            assert _rel(ctx.stress(0)["sigma"], so) <= 1e-7
 
 
 def test_update_sweep_forms_are_bitwise_equal(E, orc):
@@ -746,7 +758,7 @@ def test_breakdown_matches_oracle(E, orc, case, poll):
         assert _rel(w, ro["w"]) <= 1e-10
 
 
-@pytest.mark.parametrize("tile", [5])
+@pytest.mark.parametrize("tile", [5, 6])
 def test_wave_specialised_sweep_matches_oracle(E, orc, tile):
     """The wave-specialised fused sweep (loader wavefronts streaming node
     planes into an LDS ring): solves to the oracle's solution in FP64 and
@@ -760,7 +772,7 @@ def test_wave_specialised_sweep_matches_oracle(E, orc, tile):
         P = orc.Problem.from_micro(ms)
         ro = P.solve(ms.strain[0], tol=1e-12)
         so, _ = P.stress(ms.strain[0], ro["w"])
-        for precision in (E.PREC_FP64, E.PREC_MIXED):
+        for precision in ((E.PREC_MIXED,) if tile in E.WS_FP32_ONLY else (E.PREC_FP64, E.PREC_MIXED)):
             with E.Context.from_micro(ms, tile=tile, precision=precision) as ctx:
                 st, info = ctx.solve(1e-12 if precision == E.PREC_FP64 else 1e-10, 20000)
                 assert st == E.OK
@@ -769,6 +781,8 @@ def test_wave_specialised_sweep_matches_oracle(E, orc, tile):
                     assert abs(info["iters"][0] - ro["iters"]) <= 2
                 out = ctx.stress(0)
             assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
+    if tile in E.WS_FP32_ONLY:
+        return  # (the iterates below are FP64's)
     say("case: wave-specialised sweep iterates, tile", tile)
     shape = (20, 19, 23)
     ms = _small_poly(shape, 29)
@@ -829,7 +843,7 @@ def test_sweep_with_many_phases_per_box(E, orc):
     the classic sweep on it: test_sweep_with_many_phases_per_row_matches_oracle.)"""
     ms = _many_phase_grid((72, 13, 11), 300, 7)
     for tile in E.WS_TILES:
-        for prec in (E.PREC_FP64, E.PREC_MIXED):
+        for prec in ((E.PREC_MIXED,) if tile in E.WS_FP32_ONLY else (E.PREC_FP64, E.PREC_MIXED)):
             with pytest.raises(E.Elas3dError) as ei:
                 E.Context.from_micro(ms, tile=tile, precision=prec)
             assert ei.value.code == E.EBADARG and "distinct phases" in str(ei.value)
@@ -842,16 +856,18 @@ def test_sweep_with_many_phases_per_box(E, orc):
         assert _rel(ctx.solution(0), ro["w"]) <= 1e-9
 
 
-@pytest.mark.parametrize("tile", [5])
+@pytest.mark.parametrize("tile", [5, 6])
 def test_wave_specialised_sweep_with_a_full_dictionary(E, orc, tile):
     """Every voxel draws one of exactly 96 phases (a workgroup box holds all
     of them: the phase dictionary is full, ranks 0..95 in use): the
     wave-specialised sweep's iterates after k = 1..3 iterations equal the
-    oracle's, and the FP64 and mixed-precision solves reach its stress."""
+    oracle's, and the FP64 and mixed-precision solves reach its stress (the
+    FP32-only shape: the mixed-precision solve)."""
     ms = _many_phase_grid((72, 13, 11), 96, 11)
     assert len(np.unique(ms.phase)) == 96
     P = orc.Problem.from_micro(ms)
-    for k in range(1, 4):
+    fp64 = tile not in E.WS_FP32_ONLY
+    for k in range(1, 4) if fp64 else ():
         say("case: full dictionary, iterations", k)
         ro = P.solve(ms.strain[0], tol=1e-30, maxit=k)
         with E.Context.from_micro(ms, tile=tile) as ctx:
@@ -860,7 +876,7 @@ def test_wave_specialised_sweep_with_a_full_dictionary(E, orc, tile):
             assert _rel(ctx.solution(0), ro["w"]) <= 1e-11, k
     ro = P.solve(ms.strain[0], tol=1e-12)
     so, _ = P.stress(ms.strain[0], ro["w"])
-    for precision in (E.PREC_FP64, E.PREC_MIXED):
+    for precision in (E.PREC_FP64, E.PREC_MIXED) if fp64 else (E.PREC_MIXED,):
         say("case: full dictionary, converged, precision", precision)
         with E.Context.from_micro(ms, tile=tile, precision=precision) as ctx:
             st, info = ctx.solve(1e-12 if precision == E.PREC_FP64 else 1e-10, 20000)
