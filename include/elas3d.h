@@ -97,8 +97,8 @@ typedef struct elas3d_options {
                                   when timing is on); default 1                      */
     int32_t autotune;          /* nonzero: before the first iteration of each
                                   precision, time the candidate workgroup shapes
-                                  (options.tile's list; 5 where the grid and
-                                  its phases allow)
+                                  (options.tile's list; 5, and 6 for the FP32
+                                  sweep, where the grid and its phases allow)
                                   and z-chunkings
                                   (about 2048 to 16384 workgroups) of the
                                   direction+operator sweep and
