@@ -55,9 +55,9 @@ KERNEL_SOURCES = ("paper_2602_07354_amd/csrc/elas3d_kernels.hip", "paper_2602_07
 # write h_new and Ah (4 x 3 values + the phase); every other iteration it
 # also pays the two steps w owes (read w and the older direction, write w:
 # 3 x 3 values).  Per launch: 5.5 vectors + the phase, which the classic
-# shapes read as a 4-byte id and the wave-specialised one as a 1-byte rank
+# shapes read as a 4-byte id and the wave-specialised ones as a 1-byte rank
 # in its workgroup's phase dictionary.
-WS_SHAPES = (5,)  # options.tile of the wave-specialised shape
+WS_SHAPES = (5, 6)  # options.tile of the wave-specialised shapes
 
 
 def operator_bytes_per_node(precision: str, shape: int) -> float:
