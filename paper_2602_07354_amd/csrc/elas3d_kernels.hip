@@ -1358,8 +1358,10 @@ struct WsCfg {
     // dictionary rows: kCoefStride elements each, in 16-byte chunks
     // dictionary rows in LDS: RS elements apart (FP64 22, FP32 28), so that
     // the 16-byte reads of lanes on rows of different phases fall on
-    // different banks unless the rows' ranks differ by a multiple of 8; CHR
-    // chunks per row in LDS, of which the first CHG hold the table's
+    // different banks unless the rows' ranks differ by a multiple of 8.  CHR
+    // 16-byte chunks per LDS row, copied from the first of the CHG chunks of
+    // a table row (kCoefStride elements); an LDS row longer than the table's
+    // (FP32) repeats its last chunk as padding
     static constexpr int RS = sizeof(T) == 8 ? 22 : 28;
     static constexpr int CHR = RS * (int)sizeof(T) / 16;
     static constexpr int CHG = kCoefStride * (int)sizeof(T) / 16;
