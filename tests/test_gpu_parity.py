@@ -782,6 +782,20 @@ def test_wave_specialised_sweep_matches_oracle(E, orc, tile):
                 out = ctx.stress(0)
             assert _rel(out["sigma"], so) <= (1e-8 if precision == E.PREC_FP64 else 1e-7)
     if tile in E.WS_FP32_ONLY:
+        # two load cases batched in lockstep (case-major workgroups of one
+        # launch) in mixed precision: each reaches the oracle's stress
+        say("case: FP32-only shape, two load cases batched")
+        shape = (40, 19, 23)
+        ms2 = synth.polycrystal(shape, 12, 37, [dict(kind="sphere", fraction=0.02, median=1.5, sigma=0.3)],
+                                synth.unit_load_cases()[[1, 5]])
+        P2 = orc.Problem.from_micro(ms2)
+        with E.Context.from_micro(ms2, batched=1, tile=tile, precision=E.PREC_MIXED) as ctx:
+            st, info = ctx.solve(1e-10, 20000)
+            assert st == E.OK and info["op_shape"] == tile
+            for r in range(2):
+                ro2 = P2.solve(ms2.strain[r], tol=1e-12)
+                so2, _ = P2.stress(ms2.strain[r], ro2["w"])
+                assert _rel(ctx.stress(r)["sigma"], so2) <= 1e-7, r
         return  # (the iterates below are FP64's)
     say("case: wave-specialised sweep iterates, tile", tile)
     shape = (20, 19, 23)
